@@ -1,0 +1,200 @@
+"""Benchmark: one full max-flow solve per step on one MI355X.
+
+A step is the whole hot path on one synthetic graph already resident in HBM:
+residual-graph build (bidirectional CSR), preflow, vertex-centric push-relabel
+sweeps with on-GPU global relabels until no active vertex can reach the sink,
+the canonical min-cut side, the second phase that returns stranded excess to
+the source, and the per-arc flow decode.  The default workload is the R-MAT
+scale-22 graph (4,194,304 vertices, edge factor 16, a/b/c/d =
+.57/.19/.19/.05, duplicates and self-loops removed, capacities U[1,1000],
+s = max out-degree, t = max in-degree vertex other than s), the synthetic
+stand-in for the paper's large social-network max-flow inputs.
+
+Prints ONE JSON line.  value = arc-scans per second over the whole timed
+solve (residual entries examined by the sweeps / wall time); ms_per_step is
+the solve time.  "roofline" prices the dominant kernel (the sweep tile
+kernel) by its algorithmic bytes per launch over its HIP-event-timed average
+launch duration against the 8 TB/s HBM peak.  "cpu_baseline" times the CPU
+oracle (FIFO push-relabel) on a bounded sample: the same R-MAT recipe at
+scale 20.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes of the sweep tile kernel (bidirectional CSR):
+#   per arc-scan   12 B: entry {column, residual} 8 B + height of the column 4 B
+#   per queued u   24 B: queue slot 4 + row bounds 8 + e(u) 8 + h(u) 4
+#   per push       52 B: two residual atomics (2 x 8 B read+write), two excess
+#                        atomics (2 x 16 B read+write), mate index 4 B
+#   per relabel     4 B: height write
+B_SCAN, B_QUEUED, B_PUSH, B_RELABEL = 12, 24, 52, 4
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(scale: int = 20):
+    import oracle
+    from paper_2404_00270_amd import workloads as W
+
+    g = W.rmat(scale, 16, 0.57, 0.19, 0.19, 1, 1000, 3)
+    t0 = time.perf_counter()
+    r = oracle.fifo_pr(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+    dt = time.perf_counter() - t0
+    return {
+        "value": r.arc_scans / dt,
+        "unit": "arc-scans/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"oracle FIFO push-relabel (single thread) on the same R-MAT recipe at scale {scale} "
+                  f"(V={g.V}, E={g.E}): {dt:.2f} s, {r.arc_scans} arc-scans, value {r.value}",
+        "solve_s": dt,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat", choices=["plain", "bipartite", "rmat", "grid"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-flows", action="store_true", help="value and cut only (skips the second phase)")
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--gr-every", type=int, default=0)
+    ap.add_argument("--split", type=int, default=0)
+    ap.add_argument("--blocks", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build measures a single MI355X.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2404_00270_amd import workloads as W
+    from paper_2404_00270_amd import wbpr
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    g = W.CONFIGS[args.workload]()
+    log(f"[bench] generated {g.name}: V={g.V} E={g.E} in {time.perf_counter() - t0:.1f}s")
+
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    cap = torch.from_numpy(g.cap).to(dev)
+    value = torch.zeros(1, dtype=torch.int64, device=dev)
+    flow = None if args.no_flows else torch.zeros(max(g.E, 1), dtype=torch.int32, device=dev)
+    side = torch.zeros(g.V, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    solver = wbpr.Solver(0, lanes_per_vertex=args.lanes, gr_every_sweeps=args.gr_every, split_degree=args.split,
+                         grid_blocks=args.blocks, time_kernels=1, max_wall_ms=300_000)
+
+    def step():
+        return solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)
+
+    for i in range(args.warmup):
+        st = step()
+        log(f"[bench] warmup {i}: {st['ms_total']:.1f} ms value={int(value.item())}")
+
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        stats.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for i, st in enumerate(stats):
+        log(f"[bench] step {i}: total {st['ms_total']:.1f} ms (build {st['ms_build']:.1f}, phase1 {st['ms_phase1']:.1f}, "
+            f"phase2 {st['ms_phase2']:.1f}, decode {st['ms_decode']:.2f}) sweeps={st['sweeps']} "
+            f"gr={st['global_relabels']} scans={st['arc_scans']} pushes={st['pushes']} relabels={st['relabels']}")
+    flow_value = int(value.item())
+
+    ms_per_step = elapsed * 1000.0 / args.steps
+    scans = sum(st["arc_scans"] for st in stats)
+    arc_scans_per_s = scans / elapsed
+
+    # dominant kernel: sweep tile kernel, per-launch average from HIP events
+    launches = sum(st["sweep_kernel_launches"] for st in stats)
+    kern_ms = sum(st["ms_sweep_kernels"] for st in stats)
+    tile_bytes = sum(B_SCAN * st["tile_arc_scans"] + B_QUEUED * st["tile_queued"] + B_PUSH * st["tile_pushes"]
+                     + B_RELABEL * st["tile_relabels"] for st in stats) if stats and "tile_arc_scans" in stats[0] else \
+        sum(B_SCAN * st["arc_scans"] + B_QUEUED * st["queued"] + B_PUSH * st["pushes"] + B_RELABEL * st["relabels"]
+            for st in stats)
+    roofline = None
+    if launches > 0 and kern_ms > 0:
+        per_launch_bytes = tile_bytes / launches
+        avg_launch_s = kern_ms / 1000.0 / launches
+        achieved = per_launch_bytes / avg_launch_s / 1e9
+        roofline = {
+            "kernel": "k_sweep_tile",
+            "bound": "hbm",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": None,
+            "launches": launches,
+            "avg_launch_us": round(avg_launch_s * 1e6, 3),
+            "algorithmic_bytes_per_launch": round(per_launch_bytes, 1),
+        }
+
+    out = {
+        "metric": "max-flow solve time & arc-scans/s (GB/s vs HBM peak); batched solves/s + p99",
+        "value": arc_scans_per_s,
+        "unit": "arc-scans/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": g.name,
+            "V": g.V,
+            "E": g.E,
+            "M": stats[-1]["M"] if stats else None,
+            "s": g.s,
+            "t": g.t,
+            "max_flow": flow_value,
+            "flows": not args.no_flows,
+            "lanes_per_vertex": stats[-1]["lanes_per_vertex"] if stats else None,
+            "split_degree": stats[-1]["split_degree"] if stats else None,
+            "gr_every_sweeps": stats[-1]["gr_every_sweeps"] if stats else None,
+            "sweeps_per_solve": stats[-1]["sweeps"] if stats else None,
+            "global_relabels_per_solve": stats[-1]["global_relabels"] if stats else None,
+            "ms_build": stats[-1]["ms_build"] if stats else None,
+            "ms_phase1": stats[-1]["ms_phase1"] if stats else None,
+            "ms_phase2": stats[-1]["ms_phase2"] if stats else None,
+            "ms_decode": stats[-1]["ms_decode"] if stats else None,
+        },
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline and args.workload == "rmat":
+        log("[bench] timing the CPU oracle on the bounded sample")
+        out["cpu_baseline"] = cpu_baseline()
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,157 @@
+/*
+ * wbpr.h -- C ABI of the MI355X (gfx950) workload-balanced push-relabel
+ * maximum-flow library.
+ *
+ * Problem (paper, section 2.1): a directed graph G(V,E) in which every arc
+ * (u,v) carries an integer capacity c(u,v) >= 0, a source s and a sink t.
+ * The library returns the maximum s-t flow value, one maximum flow (the flow
+ * on every input arc) and the canonical minimum cut: side[v] = 1 iff v can
+ * still reach t in the residual graph of a maximum flow (the sink side).
+ * This set is the same for every maximum flow, so it is bit-comparable.
+ *
+ * Method (paper, Algorithm 1 and Algorithm 2, sections 2.2 and 3): the
+ * lock-free push-relabel algorithm with the vertex-centric two-level
+ * parallelism: each sweep compacts the active vertices (e(u) > 0,
+ * h(u) < |V|) into an active-vertex queue, a group of lanes scans each queued
+ * vertex's residual arcs in the bidirectional CSR (section 3.2) for the
+ * minimum-height residual neighbour, and one lane pushes (atomic updates of
+ * residuals and excesses) or relabels.  A global relabel (backward BFS from
+ * the sink in the residual graph, section 2.2) resets heights periodically;
+ * it runs on the GPU.  Everything is exact integer arithmetic: capacities
+ * and residuals int32, excesses and flow values int64.
+ *
+ * Graph input (all entry points):
+ *   row_ptr  int64[V+1], row_ptr[0] = 0, non-decreasing, row_ptr[V] = E
+ *   col      int32[E],  0 <= col[i] < V       (arc i = (u, col[i]) for
+ *                                               row_ptr[u] <= i < row_ptr[u+1])
+ *   cap      int32[E],  cap[i] >= 0
+ * Parallel arcs, antiparallel arcs, zero capacities and self-loops are all
+ * allowed (a self-loop always carries flow 0).  Limits: 2 <= V < 2^30,
+ * E < 2^30, at most 2^31-1 merged residual entries, and for every vertex
+ * pair c(u->v) + c(v->u) summed over parallel arcs must fit in int32
+ * (WBPR_EOVERFLOW otherwise).
+ *
+ * Outputs: value int64; arc_flow int32[E] (0 <= f <= cap, conserved at every
+ * v not in {s,t}); cut_side uint8[V] (0 = source side, 1 = sink side).
+ *
+ * Errors: every function returns an int status (WBPR_OK = 0).  On failure
+ * wbpr_last_error() gives a message for the calling thread.  No exception
+ * or abort crosses the ABI.  Output buffers are unspecified after a failure.
+ */
+#ifndef WBPR_H
+#define WBPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum wbpr_status {
+    WBPR_OK = 0,
+    WBPR_EINVAL = 1,     /* bad argument or malformed graph */
+    WBPR_ENOMEM = 2,     /* device or host allocation failed */
+    WBPR_ETOOBIG = 3,    /* graph exceeds a size limit or the admission budget */
+    WBPR_ETIMEOUT = 4,   /* max_sweeps / max_wall_ms watchdog fired */
+    WBPR_EDEVICE = 5,    /* HIP runtime error */
+    WBPR_EAGAIN = 6,     /* result not ready yet (server polling) */
+    WBPR_EOVERFLOW = 7,  /* merged pair capacity does not fit in int32 */
+    WBPR_EINTERNAL = 8   /* internal consistency check failed (a bug) */
+};
+
+/* Graph in CSR.  Pointers are host or device memory depending on the entry
+ * point (see each function).  The caller owns them; the library only reads
+ * them during the call (or until the stream work completes for
+ * wbpr_solve_device). */
+typedef struct wbpr_csr {
+    int32_t V;
+    int64_t E;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const int32_t *cap;
+} wbpr_csr;
+
+enum wbpr_layout { WBPR_LAYOUT_AUTO = 0, WBPR_LAYOUT_BCSR = 1 };
+
+/* Tuning knobs.  Zero means "choose automatically" for every field.  None of
+ * them changes the results, only the speed. */
+typedef struct wbpr_options {
+    int32_t layout;            /* enum wbpr_layout */
+    int32_t lanes_per_vertex;  /* lanes scanning one queued vertex: 4,8,16,32,64 */
+    int32_t split_degree;      /* rows longer than this are split over waves */
+    int32_t gr_every_sweeps;   /* sweeps between global relabels */
+    int64_t max_sweeps;        /* watchdog on total sweeps (0 = none) */
+    int32_t max_wall_ms;       /* watchdog on wall time (0 = none) */
+    int32_t grid_blocks;       /* workgroups per sweep launch */
+    int32_t time_kernels;      /* 1: time every sweep-tile launch with HIP
+                                  events (fills ms_sweep_kernels) */
+    int32_t push_mode;         /* 1: one push per visit to the minimum-height
+                                  residual neighbour, exactly Algorithms 1-2;
+                                  0 or 2: full discharge per visit (push along
+                                  every lower residual arc, then relabel) */
+    int32_t reserved[6];
+} wbpr_options;
+
+/* Per-solve counters and timings (filled when a non-NULL pointer is given). */
+typedef struct wbpr_stats {
+    int64_t value;
+    int64_t V, E, M;               /* vertices, input arcs, merged residual entries */
+    int64_t sweeps;                /* sweep launches executed (both phases) */
+    int64_t global_relabels;       /* global relabels (both phases) */
+    int64_t pushes, relabels;      /* push / relabel operations (both phases) */
+    int64_t arc_scans;             /* residual entries examined by sweeps */
+    int64_t queued;                /* sum of active-queue lengths over sweeps */
+    int64_t bfs_scans;             /* entries examined by global relabels */
+    int64_t phase2_sweeps;
+    int32_t lanes_per_vertex, split_degree, gr_every_sweeps, grid_blocks;
+    double ms_build, ms_phase1, ms_phase2, ms_decode, ms_total;
+    double ms_sweep_kernels;       /* GPU time of the sweep-tile launches (events) */
+    int64_t sweep_kernel_launches; /* sweep-tile launches timed */
+    int64_t tile_arc_scans, tile_pushes, tile_relabels, tile_queued;  /* sweep-tile kernel share */
+    int64_t nonempty_sweeps;       /* sweeps that found a non-empty queue */
+} wbpr_stats;
+
+typedef struct wbpr_ctx wbpr_ctx;
+
+/* Library version string (static storage). */
+const char *wbpr_version(void);
+
+/* Message for the last failing call on this thread (static thread-local
+ * storage, valid until the next failing call on the same thread). */
+const char *wbpr_last_error(void);
+
+/* gcnArchName of device `dev` into buf (NUL-terminated, truncated to n). */
+int wbpr_device_arch(int dev, char *buf, size_t n);
+
+/* Create a context on HIP device `device`.  `opt` may be NULL (defaults).
+ * The context owns a growable device arena, a stream and pinned staging
+ * buffers; it is not thread-safe.  *out receives the handle. */
+int wbpr_ctx_create(int device, const wbpr_options *opt, wbpr_ctx **out);
+void wbpr_ctx_destroy(wbpr_ctx *ctx);
+
+/* Replace the context's options (NULL restores the defaults). */
+int wbpr_ctx_set_options(wbpr_ctx *ctx, const wbpr_options *opt);
+
+/* Solve one instance from HOST memory.  `g` points to host arrays; they are
+ * copied to the device before work starts and may be freed after return.
+ * value: required; arc_flow (int32[E]) and cut_side (uint8[V]) may be NULL
+ * (then the second phase and the decode are skipped).  Synchronous. */
+int wbpr_solve(wbpr_ctx *ctx, const wbpr_csr *g, int32_t s, int32_t t, int64_t *value,
+               int32_t *arc_flow, uint8_t *cut_side, wbpr_stats *stats);
+
+/* Solve one instance whose CSR arrays are already in DEVICE memory (e.g.
+ * torch tensors).  Outputs are DEVICE pointers: dev_value int64[1]
+ * (required), dev_arc_flow int32[E] and dev_cut_side uint8[V] (nullable).
+ * Work is ordered after prior work on `stream` (a hipStream_t; NULL = the
+ * context's own stream) and the call returns once the results are written
+ * (the solver reads small status words back to drive its loop). */
+int wbpr_solve_device(wbpr_ctx *ctx, const wbpr_csr *dev_g, int32_t s, int32_t t, void *stream,
+                      int64_t *dev_value, int32_t *dev_arc_flow, uint8_t *dev_cut_side,
+                      wbpr_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WBPR_H */

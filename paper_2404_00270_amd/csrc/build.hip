@@ -1,0 +1,257 @@
+// Residual-graph builder: CSR of input arcs -> bidirectional CSR (paper,
+// section 3.2).  Each row u holds one entry per distinct neighbour v that is
+// joined to u by an arc in either direction, columns ascending.  Parallel and
+// antiparallel input arcs are merged: entry (u,v) starts with residual
+// sum c(u->v) and its mate (v,u) with sum c(v->u).  The paper finds the mate
+// by binary search in row v; here the builder records it once in rev[]
+// (constant-time mate access, paid for with 4 bytes per entry).
+//
+// Pipeline, entirely on the GPU:
+//   1. validate + emit two keys per arc: (u,v) forward and (v,u) backward,
+//      payload = arc index * 2 + direction; self-loops get the largest key
+//   2. stable radix sort on (row, column)
+//   3. group heads -> unique entry ids (scan), row counts, merged capacities
+//   4. row pointers (scan), mates and arc->entry map, parallel-arc prefixes
+#include "wb_common.h"
+#include "wb_internal.h"
+
+namespace wb {
+
+static int bits_for(int64_t n) {
+  int b = 1;
+  while ((1ll << b) < n) b++;
+  return b;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t residual_bytes(int32_t V, int64_t E) {
+  int64_t Mc = 2 * E > 0 ? 2 * E : 1;
+  return align256(sizeof(int32_t) * ((size_t)V + 1)) + align256(sizeof(int2) * Mc) + 2 * align256(sizeof(int32_t) * Mc) +
+         2 * align256(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
+}
+
+void residual_carve(Residual *res, int32_t V, int64_t E, void *mem) {
+  char *p = (char *)mem;
+  int64_t Mc = 2 * E > 0 ? 2 * E : 1;
+  res->V = V;
+  res->E = E;
+  res->M_cap = Mc;
+  res->rptr = (int32_t *)p; p += align256(sizeof(int32_t) * ((size_t)V + 1));
+  res->ent = (int2 *)p; p += align256(sizeof(int2) * Mc);
+  res->rev = (int32_t *)p; p += align256(sizeof(int32_t) * Mc);
+  res->cap0 = (int32_t *)p; p += align256(sizeof(int32_t) * Mc);
+  res->arc2ent = (int32_t *)p; p += align256(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
+  res->pbefore = (int32_t *)p;
+}
+
+namespace {
+struct Scratch {
+  uint64_t *k0, *k1;
+  uint32_t *v0, *v1;
+  int32_t *head, *hx, *wpos, *gstart, *rowcnt, *hist, *stemp;
+  int64_t *pcap, *stemp64;
+  unsigned long long *capacc;
+};
+
+size_t carve_scratch(int32_t V, int64_t E, void *mem, Scratch *s) {
+  int64_t N = 2 * E > 0 ? 2 * E : 1;
+  int64_t hn = radix_hist_elems(N);
+  int64_t st = scan_temp_elems(hn > N + 1 ? hn : (N > V + 1 ? N : V + 1)) + 2;
+  char *base = (char *)mem, *p = base;
+  auto take = [&](size_t bytes) { char *q = p; p += align256(bytes); return (void *)q; };
+  s->k0 = (uint64_t *)take(8 * N);
+  s->k1 = (uint64_t *)take(8 * N);
+  s->v0 = (uint32_t *)take(4 * N);
+  s->v1 = (uint32_t *)take(4 * N);
+  s->head = (int32_t *)take(4 * N);
+  s->hx = (int32_t *)take(4 * N);
+  s->wpos = (int32_t *)take(4 * N);
+  s->gstart = (int32_t *)take(4 * N);
+  s->rowcnt = (int32_t *)take(4 * ((size_t)V + 1));
+  s->hist = (int32_t *)take(4 * (size_t)hn);
+  s->stemp = (int32_t *)take(4 * (size_t)st);
+  s->pcap = (int64_t *)take(8 * N);
+  s->stemp64 = (int64_t *)take(8 * (size_t)st);
+  s->capacc = (unsigned long long *)take(8 * N);
+  return (size_t)(p - base);
+}
+}  // namespace
+
+size_t build_scratch_bytes(int32_t V, int64_t E) {
+  Scratch s;
+  return carve_scratch(V, E, nullptr, &s) + 256;
+}
+
+constexpr int BT = 256;
+
+static unsigned grid_for(int64_t n, int per_block = BT) {
+  int64_t b = (n + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > 65536) b = 65536;
+  return (unsigned)b;
+}
+
+__global__ void k_check_rowptr(const int64_t *rp, int32_t V, int64_t E, BuildStatus *st, int32_t *rowcnt) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= V; v += (int64_t)gridDim.x * blockDim.x) {
+    rowcnt[v] = 0;
+    if (v == 0 && rp[0] != 0) atomicAdd(&st->bad_input, 1);
+    if (v == V && rp[V] != E) atomicAdd(&st->bad_input, 1);
+    if (v < V && rp[v + 1] < rp[v]) atomicAdd(&st->bad_input, 1);
+  }
+}
+
+// Step 1.  Tail of arc i = last row whose start is <= i (binary search).
+__global__ void k_emit_keys(const int64_t *rp, const int32_t *col, const int32_t *cap, int32_t V, int64_t E, int vb,
+                            uint64_t *keys, uint32_t *vals, int32_t *arc2ent, BuildStatus *st) {
+  const uint64_t ALL = (vb * 2 >= 64) ? ~0ull : ((1ull << (2 * vb)) - 1);
+  int nself = 0, bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = V - 1;
+    while (lo < hi) {
+      int32_t mid = lo + (hi - lo + 1) / 2;
+      if (rp[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    uint64_t u = (uint64_t)lo;
+    int32_t vv = col[i];
+    bool ok = vv >= 0 && vv < V;
+    if (!ok || cap[i] < 0) bad++;
+    uint64_t v = ok ? (uint64_t)vv : u;
+    if (u == v) {  // self-loop, or an out-of-range column dropped as one
+      nself++;
+      keys[2 * i] = ALL;
+      keys[2 * i + 1] = ALL;
+      arc2ent[i] = -1;
+    } else {
+      keys[2 * i] = (u << vb) | v;
+      keys[2 * i + 1] = (v << vb) | u;
+      arc2ent[i] = 0;
+    }
+    vals[2 * i] = (uint32_t)(2 * i);
+    vals[2 * i + 1] = (uint32_t)(2 * i + 1);
+  }
+  nself = wave_sum_i32(nself);
+  bad = wave_sum_i32(bad);
+  if (lane() == 0) {
+    if (nself) atomicAdd(&st->nself, nself);
+    if (bad) atomicAdd(&st->bad_input, bad);
+  }
+}
+
+// Step 3a.  head[i] = 1 where a new (row, column) group starts.  Items at or
+// beyond Mraw = 2(E - nself) are self-loop keys and are dropped.
+__global__ void k_heads(const uint64_t *keys, int64_t N, const BuildStatus *st, int32_t *head) {
+  int64_t mraw = N - 2 * (int64_t)st->nself;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    head[i] = (i < mraw && (i == 0 || keys[i] != keys[i - 1])) ? 1 : 0;
+  }
+}
+
+// Step 3b.  Unique id of item i = hx[i] + head[i] - 1.
+__global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, const int32_t *cap,
+                         const BuildStatus *st, const int32_t *head, const int32_t *hx, int2 *ent, int32_t *gstart,
+                         int32_t *rowcnt, unsigned long long *capacc, int32_t *wpos, int64_t *pcap) {
+  int64_t mraw = N - 2 * (int64_t)st->nself;
+  const uint64_t cmask = (1ull << vb) - 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i >= mraw) { pcap[i] = 0; continue; }
+    uint64_t key = keys[i];
+    uint32_t pl = vals[i];
+    int32_t u = hx[i] + head[i] - 1;
+    if (head[i]) {
+      ent[u] = make_int2((int)(key & cmask), 0);
+      gstart[u] = (int32_t)i;
+      capacc[u] = 0;
+      atomicAdd(&rowcnt[key >> vb], 1);
+    }
+    wpos[pl] = (int32_t)i;
+    pcap[i] = (pl & 1u) ? 0 : (int64_t)cap[pl >> 1];
+  }
+}
+
+__global__ void k_capacc(const uint32_t *vals, int64_t N, const int32_t *cap, const BuildStatus *st,
+                         const int32_t *head, const int32_t *hx, unsigned long long *capacc) {
+  int64_t mraw = N - 2 * (int64_t)st->nself;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mraw; i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t pl = vals[i];
+    if (pl & 1u) continue;
+    int32_t u = hx[i] + head[i] - 1;
+    atomicAdd(&capacc[u], (unsigned long long)cap[pl >> 1]);
+  }
+}
+
+// Step 4.  Mates and the arc -> entry map; capacity of earlier parallel arcs.
+__global__ void k_arcs(int64_t E, const int32_t *wpos, const int32_t *head, const int32_t *hx, const int32_t *gstart,
+                       const int64_t *pcap_scanned, int32_t *rev, int32_t *arc2ent, int32_t *pbefore) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+    if (arc2ent[i] < 0) { pbefore[i] = 0; continue; }
+    int32_t pf = wpos[2 * i], pb = wpos[2 * i + 1];
+    int32_t f = hx[pf] + head[pf] - 1;
+    int32_t b = hx[pb] + head[pb] - 1;
+    rev[f] = b;
+    rev[b] = f;
+    arc2ent[i] = f;
+    pbefore[i] = (int32_t)(pcap_scanned[pf] - pcap_scanned[gstart[f]]);
+  }
+}
+
+__global__ void k_caps(const BuildStatus *st, const unsigned long long *capacc, const int32_t *rev, int2 *ent,
+                       int32_t *cap0, BuildStatus *stw) {
+  int64_t M = st->M;
+  int ovf = 0;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = rev[j];
+    if (r < 0 || r >= M) {  // every entry gets a mate; anything else is a bug
+      atomicAdd(&stw->bad_input, 1);
+      continue;
+    }
+    unsigned long long c = capacc[j], cr = capacc[r];
+    if (c + cr > 0x7fffffffull) { ovf++; c = 0; }
+    ent[j].y = (int)c;
+    cap0[j] = (int32_t)c;
+  }
+  ovf = wave_sum_i32(ovf);
+  if (lane() == 0 && ovf) atomicAdd(&stw->overflow, ovf);
+}
+
+hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, Residual *res,
+                          void *scratch, BuildStatus *status_dev, hipStream_t st) {
+  const int32_t V = res->V;
+  const int64_t E = res->E;
+  const int64_t N = 2 * E;
+  Scratch s;
+  carve_scratch(V, E, scratch, &s);
+  hipError_t e = hipMemsetAsync(status_dev, 0, sizeof(BuildStatus), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_check_rowptr, dim3(grid_for(V + 1)), dim3(BT), 0, st, row_ptr, V, E, status_dev, s.rowcnt);
+  if (E == 0) {
+    // no arcs: every row is empty
+    e = excl_scan_i32(s.rowcnt, res->rptr, (int64_t)V + 1, nullptr, s.stemp, st);
+    return e != hipSuccess ? e : hipGetLastError();
+  }
+  const int vb = bits_for(V);
+  hipLaunchKernelGGL(k_emit_keys, dim3(grid_for(E)), dim3(BT), 0, st, row_ptr, col, cap, V, E, vb, s.k0, s.v0,
+                     res->arc2ent, status_dev);
+  int alt = 0;
+  e = radix_sort_u64_u32(s.k0, s.v0, s.k1, s.v1, N, 2 * vb, s.hist, s.stemp, &alt, st);
+  if (e != hipSuccess) return e;
+  uint64_t *keys = alt ? s.k1 : s.k0;
+  uint32_t *vals = alt ? s.v1 : s.v0;
+  hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(BT), 0, st, keys, N, status_dev, s.head);
+  e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_unique, dim3(grid_for(N)), dim3(BT), 0, st, keys, vals, N, vb, cap, status_dev, s.head, s.hx,
+                     res->ent, s.gstart, s.rowcnt, s.capacc, s.wpos, s.pcap);
+  hipLaunchKernelGGL(k_capacc, dim3(grid_for(N)), dim3(BT), 0, st, vals, N, cap, status_dev, s.head, s.hx, s.capacc);
+  e = excl_scan_i64(s.pcap, s.pcap, N, nullptr, s.stemp64, st);
+  if (e != hipSuccess) return e;
+  e = excl_scan_i32(s.rowcnt, res->rptr, (int64_t)V + 1, nullptr, s.stemp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_arcs, dim3(grid_for(E)), dim3(BT), 0, st, E, s.wpos, s.head, s.hx, s.gstart, s.pcap,
+                     res->rev, res->arc2ent, res->pbefore);
+  hipLaunchKernelGGL(k_caps, dim3(grid_for(N)), dim3(BT), 0, st, status_dev, s.capacc, res->rev, res->ent,
+                     res->cap0, status_dev);
+  return hipGetLastError();
+}
+
+}  // namespace wb

@@ -1,0 +1,132 @@
+// Shared device helpers for the HIP max-flow path (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define WB_WAVE 64
+
+// Excess of a terminal carries this bias so that e > 0 never holds for it:
+// the active test e(u) > 0 && h(u) < hcap then excludes s and t with no
+// vertex-id comparison.  |bias| exceeds any reachable sum of int32
+// capacities over < 2^31 arcs.
+#define WB_EXCESS_BIAS (-(1LL << 62))
+
+#define WB_KEY_NONE (~0ull)
+
+namespace wb {
+
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  return (1ull << lane()) - 1ull;
+}
+
+// 64-bit xor shuffle built from two 32-bit lane permutes.
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m) {
+  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  lo = (unsigned)__shfl_xor((int)lo, m, WB_WAVE);
+  hi = (unsigned)__shfl_xor((int)hi, m, WB_WAVE);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int src) {
+  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  lo = (unsigned)__shfl((int)lo, src, WB_WAVE);
+  hi = (unsigned)__shfl((int)hi, src, WB_WAVE);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Minimum over aligned groups of P lanes (P a power of two <= 64).  Every
+// lane of the wave must execute this (converged control flow).
+template <int P>
+__device__ __forceinline__ unsigned long long group_min(unsigned long long k) {
+#pragma unroll
+  for (int m = P >> 1; m > 0; m >>= 1) {
+    unsigned long long o = shfl_xor_u64(k, m);
+    k = o < k ? o : k;
+  }
+  return k;
+}
+
+template <int P>
+__device__ __forceinline__ long long group_sum_i64(long long x) {
+#pragma unroll
+  for (int m = P >> 1; m > 0; m >>= 1) x += (long long)shfl_xor_u64((unsigned long long)x, m);
+  return x;
+}
+
+__device__ __forceinline__ int wave_sum_i32(int x) {
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1) x += __shfl_xor(x, m, WB_WAVE);
+  return x;
+}
+
+// Relaxed device-scope atomics (coherent across the XCDs' L2 caches).
+__device__ __forceinline__ long long atomic_load_i64(const long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int atomic_load_i32(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long atomic_load_u64(const unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long atomic_add_i64(long long *p, long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int atomic_add_i32(int *p, int v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long atomic_add_u64(unsigned long long *p, unsigned long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long atomic_min_u64(unsigned long long *p, unsigned long long v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_store_i32(int *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Wave-aggregated append: lanes with pred set write val into q at
+// consecutive slots reserved by one atomic on *cnt.  Slots at or beyond
+// `cap` are not written; they bump *err instead (a queue can only overflow
+// through a bug, which the host then reports).  Lanes that do not take part
+// may be inactive; the active ones need not be converged beyond that.
+__device__ __forceinline__ void wave_append(bool pred, int val, int *q, int *cnt, int cap, int *err) {
+  unsigned long long m = __ballot(pred);
+  if (m == 0) return;
+  int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane() == leader) base = atomic_add_i32(cnt, __popcll(m));
+  base = __shfl(base, leader, WB_WAVE);
+  if (pred) {
+    int idx = base + __popcll(m & lanemask_lt());
+    if (idx < cap) q[idx] = val;
+    else atomic_add_i32(err, 1);
+  }
+}
+
+// Grid-wide barrier for cooperative launches (all workgroups co-resident).
+// bar[0] counts arrivals, bar[1] is the generation.  Release/acquire fences
+// at device scope make prior global writes visible across XCDs.
+__device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this block's writes
+    unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+}  // namespace wb

@@ -1,0 +1,289 @@
+"""Thin ctypes binding of the C ABI in include/wbpr.h (argument marshalling only).
+
+Every step of the solve runs in the HIP library ``libwbpr.so``; this module
+only converts Python/numpy/torch arguments to pointers.  If the library is
+missing it raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwbpr.so")
+
+WBPR_OK = 0
+WBPR_EINVAL = 1
+WBPR_ENOMEM = 2
+WBPR_ETOOBIG = 3
+WBPR_ETIMEOUT = 4
+WBPR_EDEVICE = 5
+WBPR_EAGAIN = 6
+WBPR_EOVERFLOW = 7
+WBPR_EINTERNAL = 8
+
+STATUS_NAMES = {
+    0: "WBPR_OK", 1: "WBPR_EINVAL", 2: "WBPR_ENOMEM", 3: "WBPR_ETOOBIG", 4: "WBPR_ETIMEOUT",
+    5: "WBPR_EDEVICE", 6: "WBPR_EAGAIN", 7: "WBPR_EOVERFLOW", 8: "WBPR_EINTERNAL",
+}
+
+# Every symbol declared in include/wbpr.h.
+EXPORTS = (
+    "wbpr_version", "wbpr_last_error", "wbpr_device_arch", "wbpr_ctx_create", "wbpr_ctx_destroy",
+    "wbpr_ctx_set_options", "wbpr_solve", "wbpr_solve_device",
+)
+
+
+class wbpr_csr(ctypes.Structure):
+    _fields_ = [
+        ("V", ctypes.c_int32),
+        ("E", ctypes.c_int64),
+        ("row_ptr", ctypes.c_void_p),
+        ("col", ctypes.c_void_p),
+        ("cap", ctypes.c_void_p),
+    ]
+
+
+class wbpr_options(ctypes.Structure):
+    _fields_ = [
+        ("layout", ctypes.c_int32),
+        ("lanes_per_vertex", ctypes.c_int32),
+        ("split_degree", ctypes.c_int32),
+        ("gr_every_sweeps", ctypes.c_int32),
+        ("max_sweeps", ctypes.c_int64),
+        ("max_wall_ms", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
+        ("time_kernels", ctypes.c_int32),
+        ("push_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class wbpr_stats(ctypes.Structure):
+    _fields_ = [
+        ("value", ctypes.c_int64),
+        ("V", ctypes.c_int64),
+        ("E", ctypes.c_int64),
+        ("M", ctypes.c_int64),
+        ("sweeps", ctypes.c_int64),
+        ("global_relabels", ctypes.c_int64),
+        ("pushes", ctypes.c_int64),
+        ("relabels", ctypes.c_int64),
+        ("arc_scans", ctypes.c_int64),
+        ("queued", ctypes.c_int64),
+        ("bfs_scans", ctypes.c_int64),
+        ("phase2_sweeps", ctypes.c_int64),
+        ("lanes_per_vertex", ctypes.c_int32),
+        ("split_degree", ctypes.c_int32),
+        ("gr_every_sweeps", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32),
+        ("ms_build", ctypes.c_double),
+        ("ms_phase1", ctypes.c_double),
+        ("ms_phase2", ctypes.c_double),
+        ("ms_decode", ctypes.c_double),
+        ("ms_total", ctypes.c_double),
+        ("ms_sweep_kernels", ctypes.c_double),
+        ("sweep_kernel_launches", ctypes.c_int64),
+        ("tile_arc_scans", ctypes.c_int64),
+        ("tile_pushes", ctypes.c_int64),
+        ("tile_relabels", ctypes.c_int64),
+        ("tile_queued", ctypes.c_int64),
+        ("nonempty_sweeps", ctypes.c_int64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class WbprError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def _init_torch_first():
+    """PyTorch-ROCm ships its own HIP runtime; libwbpr.so links the system one.
+    Both share the process's GPU address space (so device pointers pass
+    freely), but torch's runtime fails to start once the other one has
+    claimed the device first.  So when torch is present, start it first."""
+    try:
+        import torch
+    except Exception:
+        return
+    try:
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except Exception:
+        pass
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libwbpr.so and declare every entry point; raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    _init_torch_first()
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.wbpr_version.restype = ctypes.c_char_p
+    lib.wbpr_version.argtypes = []
+    lib.wbpr_last_error.restype = ctypes.c_char_p
+    lib.wbpr_last_error.argtypes = []
+    lib.wbpr_device_arch.restype = ctypes.c_int
+    lib.wbpr_device_arch.argtypes = [ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+    lib.wbpr_ctx_create.restype = ctypes.c_int
+    lib.wbpr_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(wbpr_options), ctypes.POINTER(vp)]
+    lib.wbpr_ctx_destroy.restype = None
+    lib.wbpr_ctx_destroy.argtypes = [vp]
+    lib.wbpr_ctx_set_options.restype = ctypes.c_int
+    lib.wbpr_ctx_set_options.argtypes = [vp, ctypes.POINTER(wbpr_options)]
+    lib.wbpr_solve.restype = ctypes.c_int
+    lib.wbpr_solve.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, i32, vp, vp, vp, ctypes.POINTER(wbpr_stats)]
+    lib.wbpr_solve_device.restype = ctypes.c_int
+    lib.wbpr_solve_device.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, i32, vp, vp, vp, vp,
+                                      ctypes.POINTER(wbpr_stats)]
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != WBPR_OK:
+        raise WbprError(rc, wbpr_last_error())
+
+
+def wbpr_version() -> str:
+    return load_library().wbpr_version().decode()
+
+
+def wbpr_last_error() -> str:
+    return load_library().wbpr_last_error().decode(errors="replace")
+
+
+def wbpr_device_arch(dev: int = 0) -> str:
+    buf = ctypes.create_string_buffer(128)
+    _check(load_library().wbpr_device_arch(dev, buf, 128))
+    return buf.value.decode()
+
+
+def make_options(**kw) -> wbpr_options:
+    o = wbpr_options()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def wbpr_ctx_create(device: int = 0, **options) -> int:
+    lib = load_library()
+    h = ctypes.c_void_p()
+    opt = make_options(**options) if options else None
+    _check(lib.wbpr_ctx_create(device, ctypes.byref(opt) if opt is not None else None, ctypes.byref(h)))
+    return h.value
+
+
+def wbpr_ctx_destroy(ctx: int) -> None:
+    load_library().wbpr_ctx_destroy(ctx)
+
+
+def wbpr_ctx_set_options(ctx: int, **options) -> None:
+    opt = make_options(**options)
+    _check(load_library().wbpr_ctx_set_options(ctx, ctypes.byref(opt)))
+
+
+@dataclass
+class Result:
+    value: int
+    flow: np.ndarray | None
+    side: np.ndarray | None
+    stats: dict
+
+
+def wbpr_solve(ctx: int, V: int, row_ptr, col, cap, s: int, t: int, want_flow: bool = True,
+               want_side: bool = True, return_code: bool = False):
+    """Solve from host arrays; returns Result (or the raw status when return_code)."""
+    lib = load_library()
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    k = np.ascontiguousarray(cap, dtype=np.int32)
+    E = int(c.shape[0])
+    g = wbpr_csr(V, E, rp.ctypes.data, c.ctypes.data if E else None, k.ctypes.data if E else None)
+    value = ctypes.c_int64(0)
+    flow = np.zeros(max(E, 1), np.int32) if want_flow else None
+    side = np.zeros(max(V, 1), np.uint8) if want_side else None
+    st = wbpr_stats()
+    rc = lib.wbpr_solve(ctx, ctypes.byref(g), s, t, ctypes.addressof(value),
+                        flow.ctypes.data if flow is not None else None,
+                        side.ctypes.data if side is not None else None, ctypes.byref(st))
+    if return_code:
+        return rc
+    _check(rc)
+    return Result(int(value.value), flow[:E] if flow is not None else None,
+                  side[:V] if side is not None else None, st.as_dict())
+
+
+def wbpr_solve_device(ctx: int, V: int, E: int, row_ptr_ptr: int, col_ptr: int, cap_ptr: int, s: int, t: int,
+                      stream: int, value_ptr: int, flow_ptr: int | None, side_ptr: int | None) -> dict:
+    """Solve from device pointers (e.g. torch tensor data_ptr()); returns the stats dict."""
+    lib = load_library()
+    g = wbpr_csr(V, E, row_ptr_ptr, col_ptr, cap_ptr)
+    st = wbpr_stats()
+    _check(lib.wbpr_solve_device(ctx, ctypes.byref(g), s, t, stream or None, value_ptr, flow_ptr or None,
+                                 side_ptr or None, ctypes.byref(st)))
+    return st.as_dict()
+
+
+class Solver:
+    """Context-owning convenience wrapper around the C ABI."""
+
+    def __init__(self, device: int = 0, **options):
+        self.ctx = wbpr_ctx_create(device, **options)
+
+    def set_options(self, **options):
+        wbpr_ctx_set_options(self.ctx, **options)
+
+    def solve(self, g, want_flow: bool = True, want_side: bool = True) -> Result:
+        return wbpr_solve(self.ctx, g.V, g.row_ptr, g.col, g.cap, g.s, g.t, want_flow, want_side)
+
+    def solve_tensors(self, V, row_ptr, col, cap, s, t, value, flow=None, side=None) -> dict:
+        """Device-resident solve on torch tensors (torch supplies the memory).
+
+        torch's streams belong to torch's own HIP runtime, so they are not
+        passed down: torch's pending work is synchronised first, the library
+        runs on its context stream, and the call returns with the outputs
+        written."""
+        import torch
+
+        for x in (row_ptr, col, cap, value, flow, side):
+            if x is not None and (not x.is_cuda or not x.is_contiguous()):
+                raise ValueError("tensors must be contiguous device tensors")
+        torch.cuda.synchronize(row_ptr.device)
+        return wbpr_solve_device(self.ctx, V, int(col.shape[0]), row_ptr.data_ptr(), col.data_ptr(),
+                                 cap.data_ptr(), s, t, 0, value.data_ptr(),
+                                 flow.data_ptr() if flow is not None else None,
+                                 side.data_ptr() if side is not None else None)
+
+    def close(self):
+        if self.ctx:
+            wbpr_ctx_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,72 @@
+"""CPU-only checks of the C-ABI library: it loads, exports every function that
+include/wbpr.h declares, and the binding's structs match the header sizes.
+No compute call is made (there is no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2404_00270_amd import wbpr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wbpr.h")
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(wbpr_[a-z_]+)\s*\(", src)))
+
+
+def test_library_present_and_exports_every_declared_symbol():
+    lib = wbpr.load_library()
+    names = header_functions()
+    assert names, "no declarations found"
+    for n in names:
+        assert hasattr(lib, n), f"missing export {n}"
+    assert set(names) == set(wbpr.EXPORTS)
+
+
+def test_version_string():
+    assert "gfx950" in wbpr.wbpr_version()
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Compile a probe against include/wbpr.h with gcc and compare sizes/offsets."""
+    import subprocess
+
+    probe = tmp_path / "probe.c"
+    probe.write_text(r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "wbpr.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(wbpr_csr), sizeof(wbpr_options), sizeof(wbpr_stats));
+  printf("%zu %zu %zu\n", offsetof(wbpr_options, max_sweeps), offsetof(wbpr_options, time_kernels),
+         offsetof(wbpr_stats, ms_build));
+  printf("%zu %zu\n", offsetof(wbpr_stats, lanes_per_vertex), offsetof(wbpr_stats, sweep_kernel_launches));
+  return 0;
+}
+""")
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(probe), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    sizes = list(map(int, out))
+    assert sizes[0:3] == [ctypes.sizeof(wbpr.wbpr_csr), ctypes.sizeof(wbpr.wbpr_options),
+                          ctypes.sizeof(wbpr.wbpr_stats)]
+    assert sizes[3] == wbpr.wbpr_options.max_sweeps.offset
+    assert sizes[4] == wbpr.wbpr_options.time_kernels.offset
+    assert sizes[5] == wbpr.wbpr_stats.ms_build.offset
+    assert sizes[6] == wbpr.wbpr_stats.lanes_per_vertex.offset
+    assert sizes[7] == wbpr.wbpr_stats.sweep_kernel_launches.offset
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(ImportError):
+        wbpr._lib_backup = wbpr._lib
+        try:
+            wbpr._lib = None
+            wbpr.load_library(str(tmp_path / "nope.so"))
+        finally:
+            wbpr._lib = wbpr._lib_backup

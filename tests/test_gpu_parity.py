@@ -1,0 +1,232 @@
+"""GPU parity: the HIP solver (through the C ABI) against the CPU oracle.
+
+Exact comparisons: flow value (int64) and the canonical sink-side vector
+(vertices that reach t in the residual graph) must equal the oracle's bit for
+bit; the returned per-arc flow is not unique, so it must pass the oracle's
+certificate (capacity bounds, conservation, value == capacity of the
+returned cut).  Full-size workloads compare against tests/golden values
+written by tests/golden/make_golden.py (oracle only).
+"""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_00270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "workload_values.json")
+WATCHDOG = dict(max_wall_ms=120_000)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def solver():
+    from paper_2404_00270_amd import wbpr
+
+    s = wbpr.Solver(0, **WATCHDOG)
+    yield s
+    s.close()
+
+
+def check_against_oracle(g, res, ref=None):
+    if ref is None:
+        ref = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+    value, side, cutcap = ref
+    assert res.value == value, (g.name, res.value, value)
+    if res.side is not None:
+        assert np.array_equal(res.side, side), (g.name, int(res.side.sum()), int(side.sum()))
+    if res.flow is not None:
+        c = oracle.check(g.V, g.row_ptr, g.col, g.cap, g.s, g.t, res.flow)
+        assert c.feasible, (g.name, c.code, c.bad)
+        assert c.value == value
+        assert c.cut_capacity == value
+        assert np.array_equal(c.side, side)
+
+
+def test_device_arch():
+    from paper_2404_00270_amd import wbpr
+
+    assert wbpr.wbpr_device_arch(0).startswith("gfx950")
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_small_multigraphs(solver, seed):
+    rng = np.random.default_rng(seed)
+    V = int(rng.integers(2, 40))
+    E = int(rng.integers(0, 6 * V))
+    g = W.multigraph(V, E, cmax=int(rng.integers(0, 30)), seed=5000 + seed)
+    say(f"[small] seed={seed} V={V} E={E}")
+    check_against_oracle(g, solver.solve(g))
+
+
+@pytest.mark.parametrize("V,E,seed", [(100, 600, 1), (1000, 8000, 2), (3000, 40000, 3), (20000, 100000, 4)])
+def test_random_graphs_ragged(solver, V, E, seed):
+    g = W.random_graph(V, E, 1, 100, seed)
+    say(f"[random] V={V} E={E} seed={seed}")
+    check_against_oracle(g, solver.solve(g))
+
+
+def test_degenerate_cases(solver):
+    cases = [
+        W.from_arcs(2, [], 0, 1, "no-arcs"),
+        W.from_arcs(2, [(0, 1, 7)], 0, 1, "single-arc"),
+        W.from_arcs(2, [(0, 1, 7), (0, 1, 5), (0, 0, 9), (1, 0, 4), (1, 1, 3)], 0, 1, "parallel+loops"),
+        W.from_arcs(4, [(0, 1, 5), (1, 2, 5), (3, 1, 7)], 0, 3, "sink-unreachable"),
+        W.from_arcs(4, [(1, 2, 5), (2, 3, 5)], 0, 3, "source-isolated"),
+        W.from_arcs(5, [(0, 1, 0), (1, 4, 3), (0, 2, 3), (2, 4, 0)], 0, 4, "zero-caps"),
+        W.from_arcs(3, [(0, 1, 3), (1, 0, 3), (1, 2, 2), (2, 1, 9)], 2, 0, "reverse-roles"),
+        W.from_arcs(8, [(0, 2 + i, 2**31 - 1) for i in range(6)] + [(2 + i, 1, 2**31 - 1) for i in range(6)], 0, 1,
+                    "int64-excess"),
+    ]
+    for g in cases:
+        say(f"[degenerate] {g.name}")
+        check_against_oracle(g, solver.solve(g))
+
+
+def test_long_path_and_star(solver):
+    n = 3000
+    g = W.from_arcs(n, [(i, i + 1, 1 + (i * 7919) % 50) for i in range(n - 1)], 0, n - 1, "path")
+    say("[path]")
+    check_against_oracle(g, solver.solve(g))
+    k = 5000  # hub rows far longer than the split threshold
+    arcs = [(0, 2 + i, 1 + i % 9) for i in range(k)] + [(2 + i, 1, 1 + (i * 31) % 7) for i in range(k)]
+    g = W.from_arcs(k + 2, arcs, 0, 1, "star")
+    say("[star]")
+    check_against_oracle(g, solver.solve(g))
+
+
+@pytest.mark.parametrize("lanes", [4, 8, 16, 32, 64])
+def test_every_tile_width_and_split_path(solver, lanes):
+    g = W.bipartite(3000, 2000, 40000, 2.1, 11)
+    ref = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+    for mode in (1, 2):
+        for split in (0, 1, 7):
+            say(f"[tiles] lanes={lanes} split={split} push_mode={mode}")
+            solver.set_options(lanes_per_vertex=lanes, split_degree=split, push_mode=mode, **WATCHDOG)
+            try:
+                check_against_oracle(g, solver.solve(g), ref)
+            finally:
+                solver.set_options(**WATCHDOG)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_paper_single_push_mode(solver, seed):
+    """Algorithms 1-2 as printed: one push to the minimum-height neighbour per visit."""
+    rng = np.random.default_rng(100 + seed)
+    V = int(rng.integers(2, 60))
+    g = W.multigraph(V, int(rng.integers(0, 8 * V)), cmax=int(rng.integers(0, 40)), seed=7000 + seed)
+    say(f"[paper-mode] seed={seed} V={V}")
+    solver.set_options(push_mode=1, **WATCHDOG)
+    try:
+        check_against_oracle(g, solver.solve(g))
+    finally:
+        solver.set_options(**WATCHDOG)
+
+
+@pytest.mark.parametrize("K", [1, 3, 64])
+def test_global_relabel_frequency(solver, K):
+    g = W.random_graph(2000, 16000, 1, 100, 21)
+    say(f"[gr] K={K}")
+    solver.set_options(gr_every_sweeps=K, **WATCHDOG)
+    try:
+        check_against_oracle(g, solver.solve(g))
+    finally:
+        solver.set_options(**WATCHDOG)
+
+
+def test_value_only_and_repeatability(solver):
+    g = W.config_plain()
+    ref = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+    sides = set()
+    for rep in range(5):
+        say(f"[repeat] {rep}")
+        r = solver.solve(g, want_flow=(rep % 2 == 0), want_side=True)
+        check_against_oracle(g, r, ref)
+        sides.add(hashlib.sha256(r.side.tobytes()).hexdigest())
+    assert len(sides) == 1
+    r = solver.solve(g, want_flow=False, want_side=False)
+    assert r.value == ref[0]
+
+
+def test_error_paths(solver):
+    from paper_2404_00270_amd import wbpr
+
+    g = W.config_plain()
+    ctx = solver.ctx
+    rc = wbpr.wbpr_solve(ctx, g.V, g.row_ptr, g.col, g.cap, 5, 5, return_code=True)
+    assert rc == wbpr.WBPR_EINVAL
+    rc = wbpr.wbpr_solve(ctx, g.V, g.row_ptr, g.col, g.cap, 0, g.V, return_code=True)
+    assert rc == wbpr.WBPR_EINVAL
+    bad = g.col.copy()
+    bad[17] = g.V + 3  # detected on the device
+    rc = wbpr.wbpr_solve(ctx, g.V, g.row_ptr, bad, g.cap, g.s, g.t, return_code=True)
+    assert rc == wbpr.WBPR_EINVAL
+    neg = g.cap.copy()
+    neg[5] = -1
+    rc = wbpr.wbpr_solve(ctx, g.V, g.row_ptr, g.col, neg, g.s, g.t, return_code=True)
+    assert rc == wbpr.WBPR_EINVAL
+    rp = g.row_ptr.copy()
+    rp[10], rp[11] = rp[11], rp[10]
+    if rp[10] != rp[11]:
+        rc = wbpr.wbpr_solve(ctx, g.V, rp, g.col, g.cap, g.s, g.t, return_code=True)
+        assert rc == wbpr.WBPR_EINVAL
+    ovf = W.from_arcs(3, [(0, 1, 2**31 - 1), (1, 0, 5), (1, 2, 4)], 0, 2)
+    rc = wbpr.wbpr_solve(ctx, ovf.V, ovf.row_ptr, ovf.col, ovf.cap, 0, 2, return_code=True)
+    assert rc == wbpr.WBPR_EOVERFLOW
+    # the context still works after errors
+    check_against_oracle(g, solver.solve(g))
+
+
+def test_device_resident_path_torch(solver):
+    import torch
+
+    g = W.random_graph(5000, 40000, 1, 100, 31)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    cap = torch.from_numpy(g.cap).to(dev)
+    value = torch.zeros(1, dtype=torch.int64, device=dev)
+    flow = torch.zeros(g.E, dtype=torch.int32, device=dev)
+    side = torch.zeros(g.V, dtype=torch.uint8, device=dev)
+    solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)
+    torch.cuda.synchronize()
+
+    class R:
+        pass
+
+    r = R()
+    r.value, r.flow, r.side = int(value.item()), flow.cpu().numpy(), side.cpu().numpy()
+    check_against_oracle(g, r)
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("name", ["plain", "bipartite", "grid", "rmat"])
+def test_full_size_workloads(solver, name):
+    gold = _golden()[name]
+    say(f"[full] generating {name}")
+    g = W.CONFIGS[name]()
+    assert g.sha256() == gold["graph_sha256"], "workload generator drifted"
+    say(f"[full] solving {name} V={g.V} E={g.E}")
+    r = solver.solve(g)
+    say(f"[full] {name} value={r.value} stats={ {k: r.stats[k] for k in ('sweeps', 'global_relabels', 'ms_total')} }")
+    assert r.value == gold["value"]
+    assert int(r.side.sum()) == gold["sink_side_size"]
+    assert hashlib.sha256(r.side.tobytes()).hexdigest() == gold["sink_side_sha256"]
+    c = oracle.check(g.V, g.row_ptr, g.col, g.cap, g.s, g.t, r.flow)
+    assert c.feasible and c.value == gold["value"] and c.cut_capacity == gold["cut_capacity"]
+    assert np.array_equal(c.side, r.side)
