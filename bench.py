@@ -31,13 +31,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes of the sweep tile kernel (bidirectional CSR):
-#   per arc-scan   12 B: entry {column, residual} 8 B + height of the column 4 B
-#   per queued u   24 B: queue slot 4 + row bounds 8 + e(u) 8 + h(u) 4
-#   per push       52 B: two residual atomics (2 x 8 B read+write), two excess
-#                        atomics (2 x 16 B read+write), mate index 4 B
-#   per relabel     4 B: height write
+# Algorithmic bytes per unit of work (bidirectional CSR, int32 residuals,
+# int64 excesses, int32 heights):
+#   sweep kernels  per arc-scan 12 B: entry {column, residual} 8 B + height of
+#                  the column 4 B; per queued vertex 24 B: queue slot 4 + row
+#                  bounds 8 + e(u) 8 + h(u) 4; per push 52 B: two residual
+#                  atomics (2 x 8 B read+write), two excess atomics (2 x 16 B
+#                  read+write), mate index 4 B; per relabel 4 B.
+#   global relabel per top-down entry 12 B (entry 8 + head height 4); per
+#                  bottom-up entry 9 B (entry 8 + visit code 1); per vertex
+#                  and launch 17 B (height reset 4 + visit reset 1 + queue
+#                  rebuild reads e 8 + h 4).
 B_SCAN, B_QUEUED, B_PUSH, B_RELABEL = 12, 24, 52, 4
+B_BFS_TD, B_BFS_BU, B_BFS_V = 12, 9, 17
+KERNELS = ["k_sweep_tile", "k_sweep_tile<64> (medium rows)", "k_sweep_block (long rows)", "k_global_relabel"]
+
+
+def kernel_bytes(st, k):
+    if k < 3:
+        return (B_SCAN * st["kernel_arc_scans"][k] + B_QUEUED * st["kernel_queued"][k]
+                + B_PUSH * st["kernel_pushes"][k] + B_RELABEL * st["kernel_relabels"][k])
+    td = st["bfs_topdown_scans"]
+    bu = st["bfs_scans"] - td
+    return B_BFS_TD * td + B_BFS_BU * bu + B_BFS_V * st["V"] * st["kernel_launches"][3]
 
 
 def log(*a):
@@ -74,6 +90,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--gr-every", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
+    ap.add_argument("--block-degree", type=int, default=0)
+    ap.add_argument("--push-mode", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
     args = ap.parse_args()
 
@@ -103,7 +121,8 @@ def main():
     torch.cuda.synchronize()
 
     solver = wbpr.Solver(0, lanes_per_vertex=args.lanes, gr_every_sweeps=args.gr_every, split_degree=args.split,
-                         grid_blocks=args.blocks, time_kernels=1, max_wall_ms=300_000)
+                         block_degree=args.block_degree, push_mode=args.push_mode, grid_blocks=args.blocks,
+                         time_kernels=1, max_wall_ms=300_000)
 
     def step():
         return solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)
@@ -129,20 +148,25 @@ def main():
     scans = sum(st["arc_scans"] for st in stats)
     arc_scans_per_s = scans / elapsed
 
-    # dominant kernel: sweep tile kernel, per-launch average from HIP events
-    launches = sum(st["sweep_kernel_launches"] for st in stats)
-    kern_ms = sum(st["ms_sweep_kernels"] for st in stats)
-    tile_bytes = sum(B_SCAN * st["tile_arc_scans"] + B_QUEUED * st["tile_queued"] + B_PUSH * st["tile_pushes"]
-                     + B_RELABEL * st["tile_relabels"] for st in stats) if stats and "tile_arc_scans" in stats[0] else \
-        sum(B_SCAN * st["arc_scans"] + B_QUEUED * st["queued"] + B_PUSH * st["pushes"] + B_RELABEL * st["relabels"]
-            for st in stats)
+    # per-kernel breakdown from HIP events; the roofline prices the kernel
+    # with the largest share of GPU time
+    kernels = []
+    for k in range(4):
+        ms = sum(st["kernel_ms"][k] for st in stats)
+        launches = sum(st["kernel_launches"][k] for st in stats)
+        nbytes = sum(kernel_bytes(st, k) for st in stats)
+        kernels.append({"kernel": KERNELS[k], "ms": round(ms, 3), "launches": launches,
+                        "algorithmic_GB": round(nbytes / 1e9, 4),
+                        "GBps": round(nbytes / (ms / 1e3) / 1e9, 2) if ms > 0 else None})
+    dom = max(range(4), key=lambda k: kernels[k]["ms"])
     roofline = None
-    if launches > 0 and kern_ms > 0:
-        per_launch_bytes = tile_bytes / launches
-        avg_launch_s = kern_ms / 1000.0 / launches
+    if kernels[dom]["launches"] > 0 and kernels[dom]["ms"] > 0:
+        launches = kernels[dom]["launches"]
+        per_launch_bytes = sum(kernel_bytes(st, dom) for st in stats) / launches
+        avg_launch_s = kernels[dom]["ms"] / 1e3 / launches
         achieved = per_launch_bytes / avg_launch_s / 1e9
         roofline = {
-            "kernel": "k_sweep_tile",
+            "kernel": KERNELS[dom],
             "bound": "hbm",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
@@ -185,8 +209,10 @@ def main():
             "ms_phase1": stats[-1]["ms_phase1"] if stats else None,
             "ms_phase2": stats[-1]["ms_phase2"] if stats else None,
             "ms_decode": stats[-1]["ms_decode"] if stats else None,
+            "block_degree": stats[-1]["block_degree"] if stats else None,
         },
         "roofline": roofline,
+        "kernels": kernels,
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline and args.workload == "rmat":

@@ -79,37 +79,48 @@ enum wbpr_layout { WBPR_LAYOUT_AUTO = 0, WBPR_LAYOUT_BCSR = 1 };
 typedef struct wbpr_options {
     int32_t layout;            /* enum wbpr_layout */
     int32_t lanes_per_vertex;  /* lanes scanning one queued vertex: 4,8,16,32,64 */
-    int32_t split_degree;      /* rows longer than this are split over waves */
+    int32_t split_degree;      /* rows longer than this get one wave each */
     int32_t gr_every_sweeps;   /* sweeps between global relabels */
     int64_t max_sweeps;        /* watchdog on total sweeps (0 = none) */
     int32_t max_wall_ms;       /* watchdog on wall time (0 = none) */
     int32_t grid_blocks;       /* workgroups per sweep launch */
-    int32_t time_kernels;      /* 1: time every sweep-tile launch with HIP
-                                  events (fills ms_sweep_kernels) */
+    int32_t time_kernels;      /* 1: time every sweep and global-relabel
+                                  launch with HIP events (kernel_ms) */
     int32_t push_mode;         /* 1: one push per visit to the minimum-height
                                   residual neighbour, exactly Algorithms 1-2;
                                   0 or 2: full discharge per visit (push along
                                   every lower residual arc, then relabel) */
-    int32_t reserved[6];
+    int32_t block_degree;      /* rows longer than this get one workgroup each */
+    int32_t reserved[5];
 } wbpr_options;
 
 /* Per-solve counters and timings (filled when a non-NULL pointer is given). */
 typedef struct wbpr_stats {
     int64_t value;
     int64_t V, E, M;               /* vertices, input arcs, merged residual entries */
-    int64_t sweeps;                /* sweep launches executed (both phases) */
+    int64_t sweeps;                /* sweeps executed (both phases) */
     int64_t global_relabels;       /* global relabels (both phases) */
     int64_t pushes, relabels;      /* push / relabel operations (both phases) */
     int64_t arc_scans;             /* residual entries examined by sweeps */
     int64_t queued;                /* sum of active-queue lengths over sweeps */
     int64_t bfs_scans;             /* entries examined by global relabels */
     int64_t phase2_sweeps;
-    int32_t lanes_per_vertex, split_degree, gr_every_sweeps, grid_blocks;
-    double ms_build, ms_phase1, ms_phase2, ms_decode, ms_total;
-    double ms_sweep_kernels;       /* GPU time of the sweep-tile launches (events) */
-    int64_t sweep_kernel_launches; /* sweep-tile launches timed */
-    int64_t tile_arc_scans, tile_pushes, tile_relabels, tile_queued;  /* sweep-tile kernel share */
     int64_t nonempty_sweeps;       /* sweeps that found a non-empty queue */
+    int64_t gr_levels;             /* BFS levels summed over global relabels */
+    int32_t lanes_per_vertex, split_degree, block_degree, gr_every_sweeps, grid_blocks, gr_blocks;
+    double ms_build, ms_phase1, ms_phase2, ms_decode, ms_total;
+    /* Per-kernel breakdown.  Index 0: short-row sweep kernel (tiles of
+     * lanes_per_vertex lanes), 1: medium-row sweep kernel (one wave per
+     * row), 2: long-row sweep kernel (one workgroup per row), 3: global
+     * relabel.  kernel_ms / kernel_launches are filled only with
+     * time_kernels (HIP events around every launch). */
+    double kernel_ms[4];
+    int64_t kernel_launches[4];
+    int64_t kernel_arc_scans[4];
+    int64_t kernel_pushes[4];
+    int64_t kernel_relabels[4];
+    int64_t kernel_queued[4];
+    int64_t bfs_topdown_scans;     /* share of bfs_scans examined top-down */
 } wbpr_stats;
 
 typedef struct wbpr_ctx wbpr_ctx;

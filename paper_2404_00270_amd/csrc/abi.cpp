@@ -58,6 +58,7 @@ wb::SolveConfig to_config(const wbpr_options *o) {
   c.grid_blocks = o->grid_blocks;
   c.time_kernels = o->time_kernels != 0;
   c.push_mode = o->push_mode;
+  c.block_degree = o->block_degree;
   return c;
 }
 
@@ -66,7 +67,8 @@ int check_options(const wbpr_options *o) {
   int P = o->lanes_per_vertex;
   if (P != 0 && P != 4 && P != 8 && P != 16 && P != 32 && P != 64)
     return fail(WBPR_EINVAL, "lanes_per_vertex must be 0, 4, 8, 16, 32 or 64");
-  if (o->split_degree < 0 || o->gr_every_sweeps < 0 || o->max_sweeps < 0 || o->max_wall_ms < 0 || o->grid_blocks < 0)
+  if (o->split_degree < 0 || o->block_degree < 0 || o->gr_every_sweeps < 0 || o->max_sweeps < 0 ||
+      o->max_wall_ms < 0 || o->grid_blocks < 0)
     return fail(WBPR_EINVAL, "negative option");
   if (o->layout != WBPR_LAYOUT_AUTO && o->layout != WBPR_LAYOUT_BCSR) return fail(WBPR_EINVAL, "unknown layout");
   if (o->push_mode < 0 || o->push_mode > 2) return fail(WBPR_EINVAL, "push_mode must be 0, 1 or 2");
@@ -82,7 +84,8 @@ struct wbpr_ctx {
   DevBuf res, scratch, state, input, output, status;
   long long *pinned = nullptr;  // 64 words of pinned host memory
   int gr_blocks[7] = {0, 0, 0, 0, 0, 0, 0};
-  hipEvent_t (*ev)[2] = nullptr;
+  hipEvent_t (*ev)[4] = nullptr;
+  hipEvent_t (*gev)[2] = nullptr;
 };
 
 extern "C" {
@@ -137,11 +140,14 @@ void wbpr_ctx_destroy(wbpr_ctx *c) {
   c->output.release();
   c->status.release();
   if (c->ev) {
-    for (int i = 0; i < wb::State::kMaxEvents; i++) {
-      hipEventDestroy(c->ev[i][0]);
-      hipEventDestroy(c->ev[i][1]);
-    }
+    for (int i = 0; i < wb::State::kMaxSweeps; i++)
+      for (int k = 0; k < 4; k++) hipEventDestroy(c->ev[i][k]);
     delete[] c->ev;
+  }
+  if (c->gev) {
+    for (int i = 0; i < wb::State::kMaxGR; i++)
+      for (int k = 0; k < 2; k++) hipEventDestroy(c->gev[i][k]);
+    delete[] c->gev;
   }
   if (c->pinned) hipHostFree(c->pinned);
   if (c->stream) hipStreamDestroy(c->stream);
@@ -200,15 +206,18 @@ int solve_dev(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, hipStream_t 
   wb::State S;
   wb::state_carve(&S, g->V, res.M_cap, chunk, c->state.p);
   if (c->cfg.time_kernels && !c->ev) {
-    c->ev = new (std::nothrow) hipEvent_t[wb::State::kMaxEvents][2];
-    if (!c->ev) return fail(WBPR_ENOMEM, "event table");
-    for (int i = 0; i < wb::State::kMaxEvents; i++) {
-      hipEventCreate(&c->ev[i][0]);
-      hipEventCreate(&c->ev[i][1]);
-    }
+    c->ev = new (std::nothrow) hipEvent_t[wb::State::kMaxSweeps][4];
+    c->gev = new (std::nothrow) hipEvent_t[wb::State::kMaxGR][2];
+    if (!c->ev || !c->gev) return fail(WBPR_ENOMEM, "event table");
+    for (int i = 0; i < wb::State::kMaxSweeps; i++)
+      for (int k = 0; k < 4; k++) hipEventCreate(&c->ev[i][k]);
+    for (int i = 0; i < wb::State::kMaxGR; i++)
+      for (int k = 0; k < 2; k++) hipEventCreate(&c->gev[i][k]);
   }
   S.ev = c->ev;
+  S.gev = c->gev;
   S.ev_count = 0;
+  S.gev_count = 0;
   wb::SolveReport rep;
   std::string err;
   int rc = wb::solve_on_device(c->cfg, res, S, s, t, c->gr_blocks, st, c->pinned, dvalue, dflow, dside, g->cap, &rep,
@@ -228,28 +237,27 @@ int solve_dev(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, hipStream_t 
     stats->arc_scans = rep.arc_scans;
     stats->queued = rep.queued;
     stats->bfs_scans = rep.bfs_scans;
-    stats->tile_arc_scans = rep.tile_arc_scans;
-    stats->tile_pushes = rep.tile_pushes;
-    stats->tile_relabels = rep.tile_relabels;
-    stats->tile_queued = rep.tile_queued;
     stats->nonempty_sweeps = rep.nonempty_sweeps;
+    stats->gr_levels = rep.gr_levels;
+    stats->bfs_topdown_scans = rep.bfs_topdown_scans;
     stats->lanes_per_vertex = rep.lanes;
     stats->split_degree = rep.split_degree;
+    stats->block_degree = rep.block_degree;
     stats->gr_every_sweeps = c->cfg.gr_every_sweeps > 0 ? c->cfg.gr_every_sweeps : 16;
     stats->grid_blocks = c->cfg.grid_blocks > 0 ? c->cfg.grid_blocks : 1024;
+    stats->gr_blocks = rep.gr_blocks;
     stats->ms_build = std::chrono::duration<double, std::milli>(t1 - t0).count();
     stats->ms_phase1 = rep.ms_phase1;
     stats->ms_phase2 = rep.ms_phase2;
     stats->ms_decode = rep.ms_decode;
     stats->ms_total = std::chrono::duration<double, std::milli>(t2 - t0).count();
-    if (c->cfg.time_kernels) {
-      double tot = 0;
-      for (int i = 0; i < S.ev_count; i++) {
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, c->ev[i][0], c->ev[i][1]) == hipSuccess) tot += ms;
-      }
-      stats->ms_sweep_kernels = tot;
-      stats->sweep_kernel_launches = S.ev_count;
+    for (int k = 0; k < 4; k++) {
+      stats->kernel_ms[k] = rep.k_ms[k];
+      stats->kernel_launches[k] = rep.k_launches[k];
+      stats->kernel_arc_scans[k] = rep.k_scans[k];
+      stats->kernel_pushes[k] = rep.k_pushes[k];
+      stats->kernel_relabels[k] = rep.k_relabels[k];
+      stats->kernel_queued[k] = rep.k_queued[k];
     }
   }
   if (stats) {

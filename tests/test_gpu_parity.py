@@ -111,9 +111,10 @@ def test_every_tile_width_and_split_path(solver, lanes):
     g = W.bipartite(3000, 2000, 40000, 2.1, 11)
     ref = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
     for mode in (1, 2):
-        for split in (0, 1, 7):
-            say(f"[tiles] lanes={lanes} split={split} push_mode={mode}")
-            solver.set_options(lanes_per_vertex=lanes, split_degree=split, push_mode=mode, **WATCHDOG)
+        for split, block in ((0, 0), (1, 2), (7, 60), (3, 3)):
+            say(f"[tiles] lanes={lanes} split={split} block={block} push_mode={mode}")
+            solver.set_options(lanes_per_vertex=lanes, split_degree=split, block_degree=block, push_mode=mode,
+                               **WATCHDOG)
             try:
                 check_against_oracle(g, solver.solve(g), ref)
             finally:
