@@ -12,11 +12,18 @@ stand-in for the paper's large social-network max-flow inputs.
 
 Prints ONE JSON line.  value = arc-scans per second over the whole timed
 solve (residual entries examined by the sweeps / wall time); ms_per_step is
-the solve time.  "roofline" prices the dominant kernel (the sweep tile
-kernel) by its algorithmic bytes per launch over its HIP-event-timed average
-launch duration against the 8 TB/s HBM peak.  "cpu_baseline" times the CPU
-oracle (FIFO push-relabel) on a bounded sample: the same R-MAT recipe at
-scale 20.
+the solve time.  The timed steps run exactly as a caller would (sweep
+batches replayed as captured hipGraphs, no events).  "roofline" prices the
+kernel with the largest share of GPU time by its algorithmic bytes per
+launch over its average launch duration; durations come from HIP events
+recorded on the library's stream around every launch of extra instrumented
+solves of the same graph, run right after the timed region (events cannot
+sit between the kernels of a captured batch).  "cpu_baseline" times the
+CPU oracle (FIFO push-relabel) on a bounded sample: the same R-MAT recipe at
+scale 20.  "batched" solves a sample of the batched stream (instances with
+log-uniform V in [256, 65536], out-degree 8, capacities U[1,100]) once as a
+single batch and once as one-at-a-time solves of the same instances, checks
+the results are identical, and reports solves/s of both.
 """
 from __future__ import annotations
 
@@ -79,20 +86,119 @@ def cpu_baseline(scale: int = 20):
     }
 
 
+def kernel_table(stats):
+    kernels = []
+    for k in range(4):
+        ms = sum(st["kernel_ms"][k] for st in stats)
+        launches = sum(st["kernel_launches"][k] for st in stats)
+        nbytes = sum(kernel_bytes(st, k) for st in stats)
+        kernels.append({"kernel": KERNELS[k], "ms": round(ms, 3), "launches": launches,
+                        "algorithmic_GB": round(nbytes / 1e9, 4),
+                        "GBps": round(nbytes / (ms / 1e3) / 1e9, 2) if ms > 0 else None})
+    return kernels
+
+
+def roofline_of(stats, kernels):
+    dom = max(range(4), key=lambda k: kernels[k]["ms"])
+    if kernels[dom]["launches"] == 0 or kernels[dom]["ms"] <= 0:
+        return None
+    launches = kernels[dom]["launches"]
+    per_launch_bytes = sum(kernel_bytes(st, dom) for st in stats) / launches
+    avg_launch_s = kernels[dom]["ms"] / 1e3 / launches
+    achieved = per_launch_bytes / avg_launch_s / 1e9
+    return {
+        "kernel": KERNELS[dom],
+        "bound": "hbm",
+        "achieved": round(achieved, 2),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5),
+        "traffic": None,
+        "launches": launches,
+        "avg_launch_us": round(avg_launch_s * 1e6, 3),
+        "algorithmic_bytes_per_launch": round(per_launch_bytes, 1),
+    }
+
+
+def batched_leg(solver, n, dev):
+    """One batch of n stream instances vs n one-at-a-time solves (same outputs)."""
+    import numpy as np
+    import torch
+
+    from paper_2404_00270_amd import workloads as W
+    from paper_2404_00270_amd import wbpr
+
+    gs = [W.batch_instance(i) for i in range(n)]
+    Vs = [g.V for g in gs]
+    Es = [g.E for g in gs]
+    rp = torch.from_numpy(np.concatenate([g.row_ptr for g in gs]).astype(np.int64)).to(dev)
+    col = torch.from_numpy(np.concatenate([g.col for g in gs]).astype(np.int32)).to(dev)
+    cap = torch.from_numpy(np.concatenate([g.cap for g in gs]).astype(np.int32)).to(dev)
+    Vt, Et = sum(Vs), sum(Es)
+    vals = [torch.zeros(n, dtype=torch.int64, device=dev) for _ in range(2)]
+    flows = [torch.zeros(max(Et, 1), dtype=torch.int32, device=dev) for _ in range(2)]
+    sides = [torch.zeros(Vt, dtype=torch.uint8, device=dev) for _ in range(2)]
+    ro = np.concatenate([[0], np.cumsum([v + 1 for v in Vs])])
+    eo = np.concatenate([[0], np.cumsum(Es)])
+    vo = np.concatenate([[0], np.cumsum(Vs)])
+    torch.cuda.synchronize()
+
+    def one_at_a_time():
+        for i, g in enumerate(gs):
+            wbpr.wbpr_solve_device(solver.ctx, g.V, g.E, rp.data_ptr() + 8 * int(ro[i]),
+                                   col.data_ptr() + 4 * int(eo[i]), cap.data_ptr() + 4 * int(eo[i]), g.s, g.t, 0,
+                                   vals[0].data_ptr() + 8 * i, flows[0].data_ptr() + 4 * int(eo[i]),
+                                   sides[0].data_ptr() + int(vo[i]))
+
+    def batch():
+        return wbpr.wbpr_solve_batch_device(solver.ctx, Vs, Es, [g.s for g in gs], [g.t for g in gs], rp.data_ptr(),
+                                            col.data_ptr(), cap.data_ptr(), 0, vals[1].data_ptr(),
+                                            flows[1].data_ptr(), sides[1].data_ptr())
+
+    batch()  # warm: arena sized for the batch
+    one_at_a_time()
+    t0 = time.perf_counter()
+    one_at_a_time()
+    t_single = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st = batch()
+    t_batch = time.perf_counter() - t0
+    same = bool(torch.equal(vals[0], vals[1]) and torch.equal(sides[0], sides[1]))
+    return {
+        "instances": n,
+        "V_total": Vt,
+        "E_total": Et,
+        "batched_solves_per_s": n / t_batch,
+        "single_solves_per_s": n / t_single,
+        "speedup": t_single / t_batch,
+        "batched_ms": t_batch * 1e3,
+        "single_ms": t_single * 1e3,
+        "identical_values_and_cuts": same,
+        "batched_rounds": st["global_relabels"],
+        "batched_sweeps": st["sweeps"],
+        "sample": f"batch_instance(0..{n - 1}): V log-uniform [256, 65536], out-degree 8, caps U[1,100]; "
+                  "flows, cut sides and values written by both legs",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--kernel-steps", type=int, default=1, help="instrumented solves for the per-kernel roofline")
     ap.add_argument("--workload", default="rmat", choices=["plain", "bipartite", "rmat", "grid"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
     ap.add_argument("--no-flows", action="store_true", help="value and cut only (skips the second phase)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--gr-every", type=int, default=0)
+    ap.add_argument("--gr-permille", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--block-degree", type=int, default=0)
     ap.add_argument("--push-mode", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
+    ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -100,7 +206,6 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2404_00270_amd import workloads as W
@@ -120,9 +225,10 @@ def main():
     side = torch.zeros(g.V, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
-    solver = wbpr.Solver(0, lanes_per_vertex=args.lanes, gr_every_sweeps=args.gr_every, split_degree=args.split,
-                         block_degree=args.block_degree, push_mode=args.push_mode, grid_blocks=args.blocks,
-                         time_kernels=1, max_wall_ms=300_000)
+    opts = dict(lanes_per_vertex=args.lanes, gr_every_sweeps=args.gr_every, gr_work_permille=args.gr_permille,
+                split_degree=args.split, block_degree=args.block_degree, push_mode=args.push_mode,
+                grid_blocks=args.blocks, no_graph=int(args.no_graph), max_wall_ms=300_000)
+    solver = wbpr.Solver(0, **opts)
 
     def step():
         return solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)
@@ -139,44 +245,25 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     for i, st in enumerate(stats):
-        log(f"[bench] step {i}: total {st['ms_total']:.1f} ms (build {st['ms_build']:.1f}, phase1 {st['ms_phase1']:.1f}, "
-            f"phase2 {st['ms_phase2']:.1f}, decode {st['ms_decode']:.2f}) sweeps={st['sweeps']} "
-            f"gr={st['global_relabels']} scans={st['arc_scans']} pushes={st['pushes']} relabels={st['relabels']}")
+        log(f"[bench] step {i}: total {st['ms_total']:.1f} ms (build {st['ms_build']:.1f}, solve {st['ms_phase1']:.1f}) "
+            f"sweeps={st['sweeps']} gr={st['global_relabels']} scans={st['arc_scans']} pushes={st['pushes']} "
+            f"relabels={st['relabels']} graph={st['use_graph']}")
     flow_value = int(value.item())
-
     ms_per_step = elapsed * 1000.0 / args.steps
     scans = sum(st["arc_scans"] for st in stats)
     arc_scans_per_s = scans / elapsed
 
-    # per-kernel breakdown from HIP events; the roofline prices the kernel
-    # with the largest share of GPU time
-    kernels = []
-    for k in range(4):
-        ms = sum(st["kernel_ms"][k] for st in stats)
-        launches = sum(st["kernel_launches"][k] for st in stats)
-        nbytes = sum(kernel_bytes(st, k) for st in stats)
-        kernels.append({"kernel": KERNELS[k], "ms": round(ms, 3), "launches": launches,
-                        "algorithmic_GB": round(nbytes / 1e9, 4),
-                        "GBps": round(nbytes / (ms / 1e3) / 1e9, 2) if ms > 0 else None})
-    dom = max(range(4), key=lambda k: kernels[k]["ms"])
-    roofline = None
-    if kernels[dom]["launches"] > 0 and kernels[dom]["ms"] > 0:
-        launches = kernels[dom]["launches"]
-        per_launch_bytes = sum(kernel_bytes(st, dom) for st in stats) / launches
-        avg_launch_s = kernels[dom]["ms"] / 1e3 / launches
-        achieved = per_launch_bytes / avg_launch_s / 1e9
-        roofline = {
-            "kernel": KERNELS[dom],
-            "bound": "hbm",
-            "achieved": round(achieved, 2),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5),
-            "traffic": None,
-            "launches": launches,
-            "avg_launch_us": round(avg_launch_s * 1e6, 3),
-            "algorithmic_bytes_per_launch": round(per_launch_bytes, 1),
-        }
+    # instrumented solves: HIP events around every launch on the library's stream
+    kstats = []
+    if args.kernel_steps > 0:
+        solver.set_options(**opts, time_kernels=1)
+        for i in range(args.kernel_steps):
+            kstats.append(step())
+            log(f"[bench] instrumented {i}: total {kstats[-1]['ms_total']:.1f} ms kernel_ms={kstats[-1]['kernel_ms']}")
+        solver.set_options(**opts)
+        assert int(value.item()) == flow_value
+    kernels = kernel_table(kstats) if kstats else None
+    roofline = roofline_of(kstats, kernels) if kstats else None
 
     out = {
         "metric": "max-flow solve time & arc-scans/s (GB/s vs HBM peak); batched solves/s + p99",
@@ -202,19 +289,23 @@ def main():
             "flows": not args.no_flows,
             "lanes_per_vertex": stats[-1]["lanes_per_vertex"] if stats else None,
             "split_degree": stats[-1]["split_degree"] if stats else None,
+            "block_degree": stats[-1]["block_degree"] if stats else None,
             "gr_every_sweeps": stats[-1]["gr_every_sweeps"] if stats else None,
             "sweeps_per_solve": stats[-1]["sweeps"] if stats else None,
             "global_relabels_per_solve": stats[-1]["global_relabels"] if stats else None,
             "ms_build": stats[-1]["ms_build"] if stats else None,
-            "ms_phase1": stats[-1]["ms_phase1"] if stats else None,
-            "ms_phase2": stats[-1]["ms_phase2"] if stats else None,
-            "ms_decode": stats[-1]["ms_decode"] if stats else None,
-            "block_degree": stats[-1]["block_degree"] if stats else None,
+            "ms_solve": stats[-1]["ms_phase1"] if stats else None,
+            "hipgraph": bool(stats[-1]["use_graph"]) if stats else None,
         },
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": None,
+        "batched": None,
     }
+    if args.batch > 0:
+        log(f"[bench] batched leg: {args.batch} stream instances")
+        out["batched"] = batched_leg(solver, args.batch, dev)
+        log(f"[bench] batched: {out['batched']}")
     if not args.no_cpu_baseline and args.workload == "rmat":
         log("[bench] timing the CPU oracle on the bounded sample")
         out["cpu_baseline"] = cpu_baseline()

@@ -80,7 +80,8 @@ typedef struct wbpr_options {
     int32_t layout;            /* enum wbpr_layout */
     int32_t lanes_per_vertex;  /* lanes scanning one queued vertex: 4,8,16,32,64 */
     int32_t split_degree;      /* rows longer than this get one wave each */
-    int32_t gr_every_sweeps;   /* sweeps between global relabels */
+    int32_t gr_every_sweeps;   /* fixed sweeps between global relabels
+                                  (0 = adaptive, at most 64) */
     int64_t max_sweeps;        /* watchdog on total sweeps (0 = none) */
     int32_t max_wall_ms;       /* watchdog on wall time (0 = none) */
     int32_t grid_blocks;       /* workgroups per sweep launch */
@@ -91,7 +92,13 @@ typedef struct wbpr_options {
                                   0 or 2: full discharge per visit (push along
                                   every lower residual arc, then relabel) */
     int32_t block_degree;      /* rows longer than this get one workgroup each */
-    int32_t reserved[5];
+    int32_t gr_work_permille;  /* with gr_every_sweeps = 0: a round of sweeps
+                                  ends once relabels since the last global
+                                  relabel have scanned this many thousandths
+                                  of (V + M) entries (0 = 1000) */
+    int32_t no_graph;          /* 1: launch sweeps one by one instead of
+                                  replaying a captured hipGraph */
+    int32_t reserved[3];
 } wbpr_options;
 
 /* Per-solve counters and timings (filled when a non-NULL pointer is given). */
@@ -121,6 +128,8 @@ typedef struct wbpr_stats {
     int64_t kernel_relabels[4];
     int64_t kernel_queued[4];
     int64_t bfs_topdown_scans;     /* share of bfs_scans examined top-down */
+    int32_t instances;             /* instances solved by the call */
+    int32_t use_graph;             /* sweep batches replayed as a hipGraph */
 } wbpr_stats;
 
 typedef struct wbpr_ctx wbpr_ctx;
@@ -160,6 +169,29 @@ int wbpr_solve(wbpr_ctx *ctx, const wbpr_csr *g, int32_t s, int32_t t, int64_t *
 int wbpr_solve_device(wbpr_ctx *ctx, const wbpr_csr *dev_g, int32_t s, int32_t t, void *stream,
                       int64_t *dev_value, int32_t *dev_arc_flow, uint8_t *dev_cut_side,
                       wbpr_stats *stats);
+
+/* Batched solve: n independent instances of uneven size, resident together
+ * in one device arena and solved as a disjoint union, so one sweep and one
+ * global relabel serve all of them (the sweep batch is replayed as a captured
+ * hipGraph).  Results per instance are exactly those of separate solves.
+ *
+ * DEVICE variant: the n CSRs are packed back to back in device memory:
+ * instance i contributes V[i] + 1 row pointers (local, starting at 0), E[i]
+ * columns (local ids 0..V[i]-1) and E[i] capacities.  V, E, s, t are HOST
+ * arrays [n] (local s, t).  Outputs are DEVICE arrays packed the same way:
+ * dev_values int64[n] (required), dev_flows int32[sum E] and dev_sides
+ * uint8[sum V] (nullable).  Limits: sum V < 2^30, 2 * sum E < 2^31.
+ * Synchronous with respect to `stream` (NULL = the context's stream). */
+int wbpr_solve_batch_device(wbpr_ctx *ctx, int32_t n, const int32_t *V, const int64_t *E, const int32_t *s,
+                            const int32_t *t, const int64_t *dev_row_ptr, const int32_t *dev_col,
+                            const int32_t *dev_cap, void *stream, int64_t *dev_values, int32_t *dev_flows,
+                            uint8_t *dev_sides, wbpr_stats *stats);
+
+/* HOST variant: graphs[i] are host CSRs (copied before work starts),
+ * s[i], t[i] local; values int64[n] (required); flows (nullable) holds n
+ * pointers to int32[E_i]; sides (nullable) holds n pointers to uint8[V_i]. */
+int wbpr_solve_batch(wbpr_ctx *ctx, int32_t n, const wbpr_csr *graphs, const int32_t *s, const int32_t *t,
+                     int64_t *values, int32_t *const *flows, uint8_t *const *sides, wbpr_stats *stats);
 
 #ifdef __cplusplus
 }

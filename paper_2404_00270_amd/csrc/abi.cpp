@@ -1,16 +1,18 @@
-// C ABI (include/wbpr.h): argument validation, the device arena, host<->device
-// staging and translation of internal status into wbpr_status codes.
+// C ABI (include/wbpr.h): argument validation, host<->device staging and
+// translation of internal status into wbpr_status codes.  Every solve runs on
+// the context's engine (engine.hip).
 #include <hip/hip_runtime.h>
 
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/wbpr.h"
-#include "wb_internal.h"
-#include "wb_solver.h"
+#include "wb_engine.h"
 
 namespace {
 
@@ -52,13 +54,15 @@ wb::SolveConfig to_config(const wbpr_options *o) {
   if (!o) return c;
   c.lanes_per_vertex = o->lanes_per_vertex;
   c.split_degree = o->split_degree;
+  c.block_degree = o->block_degree;
   c.gr_every_sweeps = o->gr_every_sweeps;
+  c.gr_work_permille = o->gr_work_permille;
   c.max_sweeps = o->max_sweeps;
   c.max_wall_ms = o->max_wall_ms;
   c.grid_blocks = o->grid_blocks;
   c.time_kernels = o->time_kernels != 0;
   c.push_mode = o->push_mode;
-  c.block_degree = o->block_degree;
+  c.use_graph = o->no_graph == 0;
   return c;
 }
 
@@ -67,12 +71,49 @@ int check_options(const wbpr_options *o) {
   int P = o->lanes_per_vertex;
   if (P != 0 && P != 4 && P != 8 && P != 16 && P != 32 && P != 64)
     return fail(WBPR_EINVAL, "lanes_per_vertex must be 0, 4, 8, 16, 32 or 64");
-  if (o->split_degree < 0 || o->block_degree < 0 || o->gr_every_sweeps < 0 || o->max_sweeps < 0 ||
-      o->max_wall_ms < 0 || o->grid_blocks < 0)
+  if (o->split_degree < 0 || o->block_degree < 0 || o->gr_every_sweeps < 0 || o->gr_work_permille < 0 ||
+      o->max_sweeps < 0 || o->max_wall_ms < 0 || o->grid_blocks < 0)
     return fail(WBPR_EINVAL, "negative option");
   if (o->layout != WBPR_LAYOUT_AUTO && o->layout != WBPR_LAYOUT_BCSR) return fail(WBPR_EINVAL, "unknown layout");
   if (o->push_mode < 0 || o->push_mode > 2) return fail(WBPR_EINVAL, "push_mode must be 0, 1 or 2");
   return WBPR_OK;
+}
+
+void fill_stats(wbpr_stats *st, const wb::EngineStats &r, const wb::SolveConfig &cfg, int64_t V, int64_t E, int64_t M,
+                int32_t n, double ms_build, double ms_solve, double ms_total) {
+  std::memset(st, 0, sizeof(*st));
+  st->V = V;
+  st->E = E;
+  st->M = M;
+  st->sweeps = r.sweeps;
+  st->global_relabels = r.global_relabels;
+  st->pushes = r.pushes;
+  st->relabels = r.relabels;
+  st->arc_scans = r.arc_scans;
+  st->queued = r.queued;
+  st->bfs_scans = r.bfs_scans;
+  st->nonempty_sweeps = r.nonempty_sweeps;
+  st->gr_levels = r.gr_levels;
+  st->lanes_per_vertex = r.lanes;
+  st->split_degree = r.split_degree;
+  st->block_degree = r.block_degree;
+  st->gr_every_sweeps = cfg.gr_every_sweeps;
+  st->grid_blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : 1024;
+  st->gr_blocks = r.gr_blocks;
+  st->ms_build = ms_build;
+  st->ms_phase1 = ms_solve;  // both phases, interleaved per instance
+  st->ms_total = ms_total;
+  for (int k = 0; k < 4; k++) {
+    st->kernel_ms[k] = r.k_ms[k];
+    st->kernel_launches[k] = r.k_launches[k];
+    st->kernel_arc_scans[k] = r.k_scans[k];
+    st->kernel_pushes[k] = r.k_pushes[k];
+    st->kernel_relabels[k] = r.k_relabels[k];
+    st->kernel_queued[k] = r.k_queued[k];
+  }
+  st->bfs_topdown_scans = r.bfs_topdown_scans;
+  st->instances = n;
+  st->use_graph = cfg.use_graph && !cfg.time_kernels;
 }
 
 }  // namespace
@@ -81,16 +122,13 @@ struct wbpr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   wb::SolveConfig cfg;
-  DevBuf res, scratch, state, input, output, status;
-  long long *pinned = nullptr;  // 64 words of pinned host memory
-  int gr_blocks[7] = {0, 0, 0, 0, 0, 0, 0};
-  hipEvent_t (*ev)[4] = nullptr;
-  hipEvent_t (*gev)[2] = nullptr;
+  std::unique_ptr<wb::Engine> engine;
+  DevBuf input, output;
 };
 
 extern "C" {
 
-const char *wbpr_version(void) { return "wbpr-mi355x 0.1 (gfx950, BCSR vertex-centric push-relabel)"; }
+const char *wbpr_version(void) { return "wbpr-mi355x 0.2 (gfx950, BCSR vertex-centric push-relabel, batched engine)"; }
 
 const char *wbpr_last_error(void) { return g_err.c_str(); }
 
@@ -119,12 +157,16 @@ int wbpr_ctx_create(int device, const wbpr_options *opt, wbpr_ctx **out) {
   c->device = device;
   c->cfg = to_config(opt);
   e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&c->pinned, 64 * sizeof(long long), hipHostMallocDefault);
   if (e != hipSuccess) {
     wbpr_ctx_destroy(c);
-    return hip_fail(e, "context setup");
+    return hip_fail(e, "stream");
   }
-  for (int lg = 2; lg <= 6; lg++) c->gr_blocks[lg] = wb::gr_max_blocks(device, 1 << lg);
+  c->engine.reset(new (std::nothrow) wb::Engine(device));
+  if (!c->engine) {
+    wbpr_ctx_destroy(c);
+    return fail(WBPR_ENOMEM, "engine");
+  }
+  c->engine->set_config(c->cfg);
   *out = c;
   return WBPR_OK;
 }
@@ -133,23 +175,9 @@ void wbpr_ctx_destroy(wbpr_ctx *c) {
   if (!c) return;
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
-  c->res.release();
-  c->scratch.release();
-  c->state.release();
+  c->engine.reset();
   c->input.release();
   c->output.release();
-  c->status.release();
-  if (c->ev) {
-    for (int i = 0; i < wb::State::kMaxSweeps; i++)
-      for (int k = 0; k < 4; k++) hipEventDestroy(c->ev[i][k]);
-    delete[] c->ev;
-  }
-  if (c->gev) {
-    for (int i = 0; i < wb::State::kMaxGR; i++)
-      for (int k = 0; k < 2; k++) hipEventDestroy(c->gev[i][k]);
-    delete[] c->gev;
-  }
-  if (c->pinned) hipHostFree(c->pinned);
   if (c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -159,6 +187,7 @@ int wbpr_ctx_set_options(wbpr_ctx *c, const wbpr_options *opt) {
   int rc = check_options(opt);
   if (rc) return rc;
   c->cfg = to_config(opt);
+  c->engine->set_config(c->cfg);
   return WBPR_OK;
 }
 
@@ -166,104 +195,54 @@ int wbpr_ctx_set_options(wbpr_ctx *c, const wbpr_options *opt) {
 
 namespace {
 
-int check_graph_shape(const wbpr_csr *g, int32_t s, int32_t t) {
-  if (!g) return fail(WBPR_EINVAL, "null graph");
-  if (g->V < 2) return fail(WBPR_EINVAL, "V must be at least 2");
-  if (g->V >= (1 << 30)) return fail(WBPR_ETOOBIG, "V must be below 2^30");
-  if (g->E < 0) return fail(WBPR_EINVAL, "negative E");
-  if (g->E >= (1ll << 30)) return fail(WBPR_ETOOBIG, "E must be below 2^30");
-  if (!g->row_ptr || (g->E > 0 && (!g->col || !g->cap))) return fail(WBPR_EINVAL, "null CSR array");
-  if (s < 0 || s >= g->V || t < 0 || t >= g->V) return fail(WBPR_EINVAL, "s or t out of range");
+int check_shape(int32_t V, int64_t E, int32_t s, int32_t t) {
+  if (V < 2) return fail(WBPR_EINVAL, "V must be at least 2");
+  if (V >= (1 << 30)) return fail(WBPR_ETOOBIG, "V must be below 2^30");
+  if (E < 0) return fail(WBPR_EINVAL, "negative E");
+  if (E >= (1ll << 30)) return fail(WBPR_ETOOBIG, "E must be below 2^30");
+  if (s < 0 || s >= V || t < 0 || t >= V) return fail(WBPR_EINVAL, "s or t out of range");
   if (s == t) return fail(WBPR_EINVAL, "s == t");
   return WBPR_OK;
 }
 
-// Device-resident solve shared by both entry points.
-int solve_dev(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, hipStream_t st, int64_t *dvalue, int32_t *dflow,
-              uint8_t *dside, wbpr_stats *stats) {
+// Solves a group already packed on the device, from an empty engine.
+int solve_group(wbpr_ctx *c, wb::GroupInput &in, hipStream_t st, wbpr_stats *stats) {
   auto t0 = std::chrono::steady_clock::now();
-  hipError_t e = c->res.ensure(wb::residual_bytes(g->V, g->E));
-  if (e == hipSuccess) e = c->scratch.ensure(wb::build_scratch_bytes(g->V, g->E));
-  if (e == hipSuccess) e = c->status.ensure(sizeof(wb::BuildStatus) + 256);
-  if (e != hipSuccess) return hip_fail(e, "device allocation (graph)");
-  wb::Residual res;
-  wb::residual_carve(&res, g->V, g->E, c->res.p);
-  wb::BuildStatus *bst = (wb::BuildStatus *)c->status.p;
-  e = wb::build_residual(g->row_ptr, g->col, g->cap, &res, c->scratch.p, bst, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->pinned, bst, sizeof(wb::BuildStatus), hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "residual build");
-  wb::BuildStatus hb;
-  std::memcpy(&hb, c->pinned, sizeof(hb));
-  if (hb.bad_input) return fail(WBPR_EINVAL, "malformed CSR (row_ptr not monotone from 0 to E, col out of range, or negative cap)");
-  if (hb.overflow) return fail(WBPR_EOVERFLOW, "c(u->v) + c(v->u) over parallel arcs exceeds INT32_MAX");
-  res.M = hb.M;
-  auto t1 = std::chrono::steady_clock::now();
-
-  const int chunk = 1024;
-  e = c->state.ensure(wb::state_bytes(g->V, res.M_cap, chunk) + wb::misc_bytes() + 4096);
-  if (e != hipSuccess) return hip_fail(e, "device allocation (state)");
-  wb::State S;
-  wb::state_carve(&S, g->V, res.M_cap, chunk, c->state.p);
-  if (c->cfg.time_kernels && !c->ev) {
-    c->ev = new (std::nothrow) hipEvent_t[wb::State::kMaxSweeps][4];
-    c->gev = new (std::nothrow) hipEvent_t[wb::State::kMaxGR][2];
-    if (!c->ev || !c->gev) return fail(WBPR_ENOMEM, "event table");
-    for (int i = 0; i < wb::State::kMaxSweeps; i++)
-      for (int k = 0; k < 4; k++) hipEventCreate(&c->ev[i][k]);
-    for (int i = 0; i < wb::State::kMaxGR; i++)
-      for (int k = 0; k < 2; k++) hipEventCreate(&c->gev[i][k]);
+  int64_t Vt = 0, Et = 0;
+  for (int i = 0; i < in.n; i++) {
+    Vt += in.V[i];
+    Et += in.E[i];
   }
-  S.ev = c->ev;
-  S.gev = c->gev;
-  S.ev_count = 0;
-  S.gev_count = 0;
-  wb::SolveReport rep;
+  if (Vt >= (1ll << 30) || 2 * Et >= (1ll << 31) - 1) return fail(WBPR_ETOOBIG, "batch exceeds the 32-bit index limits");
+  wb::Engine &eng = *c->engine;
+  if (!eng.idle()) return fail(WBPR_EAGAIN, "context busy");
   std::string err;
-  int rc = wb::solve_on_device(c->cfg, res, S, s, t, c->gr_blocks, st, c->pinned, dvalue, dflow, dside, g->cap, &rep,
-                               &err);
+  int rc = eng.reserve(Vt, 2 * Et, Et, in.n, Vt, Et, in.n, &err);
   if (rc) return fail(rc, err);
+  eng.reset_stats();
+  rc = eng.admit(in, st, &err);
+  if (rc) return fail(rc, err);
+  const int64_t M = eng.last_build_M();
+  auto t1 = std::chrono::steady_clock::now();
+  std::vector<wb::Finished> done;
+  rc = eng.run_to_completion(st, &done, &err);
+  if (rc) {
+    eng.abandon(st);  // leave the engine empty for the next call
+    return fail(rc, err);
+  }
   auto t2 = std::chrono::steady_clock::now();
   if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    stats->V = g->V;
-    stats->E = g->E;
-    stats->M = res.M;
-    stats->sweeps = rep.sweeps;
-    stats->phase2_sweeps = rep.phase2_sweeps;
-    stats->global_relabels = rep.global_relabels;
-    stats->pushes = rep.pushes;
-    stats->relabels = rep.relabels;
-    stats->arc_scans = rep.arc_scans;
-    stats->queued = rep.queued;
-    stats->bfs_scans = rep.bfs_scans;
-    stats->nonempty_sweeps = rep.nonempty_sweeps;
-    stats->gr_levels = rep.gr_levels;
-    stats->bfs_topdown_scans = rep.bfs_topdown_scans;
-    stats->lanes_per_vertex = rep.lanes;
-    stats->split_degree = rep.split_degree;
-    stats->block_degree = rep.block_degree;
-    stats->gr_every_sweeps = c->cfg.gr_every_sweeps > 0 ? c->cfg.gr_every_sweeps : 16;
-    stats->grid_blocks = c->cfg.grid_blocks > 0 ? c->cfg.grid_blocks : 1024;
-    stats->gr_blocks = rep.gr_blocks;
-    stats->ms_build = std::chrono::duration<double, std::milli>(t1 - t0).count();
-    stats->ms_phase1 = rep.ms_phase1;
-    stats->ms_phase2 = rep.ms_phase2;
-    stats->ms_decode = rep.ms_decode;
-    stats->ms_total = std::chrono::duration<double, std::milli>(t2 - t0).count();
-    for (int k = 0; k < 4; k++) {
-      stats->kernel_ms[k] = rep.k_ms[k];
-      stats->kernel_launches[k] = rep.k_launches[k];
-      stats->kernel_arc_scans[k] = rep.k_scans[k];
-      stats->kernel_pushes[k] = rep.k_pushes[k];
-      stats->kernel_relabels[k] = rep.k_relabels[k];
-      stats->kernel_queued[k] = rep.k_queued[k];
+    wb::EngineStats r;
+    rc = eng.collect_stats(st, &r, &err);
+    if (rc) return fail(rc, err);
+    const double ms_build = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    const double ms_solve = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    const double ms_total = std::chrono::duration<double, std::milli>(t2 - t0).count();
+    fill_stats(stats, r, c->cfg, Vt, Et, M, in.n, ms_build, ms_solve, ms_total);
+    if (in.n == 1 && in.values) {
+      long long v = 0;
+      if (hipMemcpy(&v, in.values, sizeof(v), hipMemcpyDeviceToHost) == hipSuccess) stats->value = v;
     }
-  }
-  if (stats) {
-    // value for the stats block (one extra 8-byte read)
-    long long v = 0;
-    if (hipMemcpy(&v, dvalue, sizeof(v), hipMemcpyDeviceToHost) == hipSuccess) stats->value = v;
   }
   return WBPR_OK;
 }
@@ -275,49 +254,167 @@ extern "C" {
 int wbpr_solve_device(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, void *stream, int64_t *dev_value,
                       int32_t *dev_arc_flow, uint8_t *dev_cut_side, wbpr_stats *stats) {
   if (!c) return fail(WBPR_EINVAL, "null context");
-  int rc = check_graph_shape(g, s, t);
+  if (!g) return fail(WBPR_EINVAL, "null graph");
+  int rc = check_shape(g->V, g->E, s, t);
   if (rc) return rc;
+  if (!g->row_ptr || (g->E > 0 && (!g->col || !g->cap))) return fail(WBPR_EINVAL, "null CSR array");
   if (!dev_value) return fail(WBPR_EINVAL, "null value pointer");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t st = stream ? (hipStream_t)stream : c->stream;
-  return solve_dev(c, g, s, t, st, dev_value, dev_arc_flow, dev_cut_side, stats);
+  int32_t V = g->V;
+  int64_t E = g->E;
+  wb::GroupInput in;
+  in.n = 1;
+  in.V = &V;
+  in.E = &E;
+  in.s = &s;
+  in.t = &t;
+  in.row_ptr = g->row_ptr;
+  in.col = g->col;
+  in.cap = g->cap;
+  in.values = dev_value;
+  in.flows = dev_arc_flow;
+  in.sides = dev_cut_side;
+  return solve_group(c, in, st, stats);
 }
 
 int wbpr_solve(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int64_t *value, int32_t *arc_flow,
                uint8_t *cut_side, wbpr_stats *stats) {
   if (!c) return fail(WBPR_EINVAL, "null context");
-  int rc = check_graph_shape(g, s, t);
+  if (!g) return fail(WBPR_EINVAL, "null graph");
+  int rc = check_shape(g->V, g->E, s, t);
   if (rc) return rc;
+  if (!g->row_ptr || (g->E > 0 && (!g->col || !g->cap))) return fail(WBPR_EINVAL, "null CSR array");
   if (!value) return fail(WBPR_EINVAL, "null value pointer");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   const int64_t V = g->V, E = g->E;
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  size_t in_bytes = al(8 * (V + 1)) + 2 * al(4 * (E > 0 ? E : 1));
-  size_t out_bytes = al(8) + al(4 * (E > 0 ? E : 1)) + al((size_t)V);
-  e = c->input.ensure(in_bytes);
-  if (e == hipSuccess) e = c->output.ensure(out_bytes);
+  const size_t Ec = (size_t)(E > 0 ? E : 1);
+  e = c->input.ensure(al(8 * (V + 1)) + 2 * al(4 * Ec));
+  if (e == hipSuccess) e = c->output.ensure(al(8) + al(4 * Ec) + al((size_t)V));
   if (e != hipSuccess) return hip_fail(e, "device allocation (staging)");
   char *ip = (char *)c->input.p;
   int64_t *d_rp = (int64_t *)ip;
   int32_t *d_col = (int32_t *)(ip + al(8 * (V + 1)));
-  int32_t *d_cap = (int32_t *)(ip + al(8 * (V + 1)) + al(4 * (E > 0 ? E : 1)));
+  int32_t *d_cap = (int32_t *)(ip + al(8 * (V + 1)) + al(4 * Ec));
   char *op = (char *)c->output.p;
   int64_t *d_val = (int64_t *)op;
   int32_t *d_flow = (int32_t *)(op + al(8));
-  uint8_t *d_side = (uint8_t *)(op + al(8) + al(4 * (E > 0 ? E : 1)));
+  uint8_t *d_side = (uint8_t *)(op + al(8) + al(4 * Ec));
   hipStream_t st = c->stream;
   e = hipMemcpyAsync(d_rp, g->row_ptr, 8 * (V + 1), hipMemcpyHostToDevice, st);
   if (e == hipSuccess && E > 0) e = hipMemcpyAsync(d_col, g->col, 4 * E, hipMemcpyHostToDevice, st);
   if (e == hipSuccess && E > 0) e = hipMemcpyAsync(d_cap, g->cap, 4 * E, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return hip_fail(e, "host to device copy");
   wbpr_csr dg{g->V, g->E, d_rp, d_col, d_cap};
-  rc = solve_dev(c, &dg, s, t, st, d_val, arc_flow ? d_flow : nullptr, cut_side ? d_side : nullptr, stats);
+  rc = wbpr_solve_device(c, &dg, s, t, st, d_val, arc_flow ? d_flow : nullptr, cut_side ? d_side : nullptr, stats);
   if (rc) return rc;
   e = hipMemcpyAsync(value, d_val, 8, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && arc_flow && E > 0) e = hipMemcpyAsync(arc_flow, d_flow, 4 * E, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess && cut_side) e = hipMemcpyAsync(cut_side, d_side, (size_t)V, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "device to host copy");
+  return WBPR_OK;
+}
+
+int wbpr_solve_batch_device(wbpr_ctx *c, int32_t n, const int32_t *V, const int64_t *E, const int32_t *s,
+                            const int32_t *t, const int64_t *dev_row_ptr, const int32_t *dev_col,
+                            const int32_t *dev_cap, void *stream, int64_t *dev_values, int32_t *dev_flows,
+                            uint8_t *dev_sides, wbpr_stats *stats) {
+  if (!c) return fail(WBPR_EINVAL, "null context");
+  if (n < 1) return fail(WBPR_EINVAL, "n must be at least 1");
+  if (!V || !E || !s || !t || !dev_row_ptr || !dev_values) return fail(WBPR_EINVAL, "null argument");
+  int64_t Et = 0;
+  for (int i = 0; i < n; i++) {
+    int rc = check_shape(V[i], E[i], s[i], t[i]);
+    if (rc) {
+      g_err = "instance " + std::to_string(i) + ": " + g_err;
+      return rc;
+    }
+    Et += E[i];
+  }
+  if (Et > 0 && (!dev_col || !dev_cap)) return fail(WBPR_EINVAL, "null CSR array");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  hipStream_t st = stream ? (hipStream_t)stream : c->stream;
+  wb::GroupInput in;
+  in.n = n;
+  in.V = V;
+  in.E = E;
+  in.s = s;
+  in.t = t;
+  in.row_ptr = dev_row_ptr;
+  in.col = dev_col;
+  in.cap = dev_cap;
+  in.values = dev_values;
+  in.flows = dev_flows;
+  in.sides = dev_sides;
+  return solve_group(c, in, st, stats);
+}
+
+int wbpr_solve_batch(wbpr_ctx *c, int32_t n, const wbpr_csr *graphs, const int32_t *s, const int32_t *t,
+                     int64_t *values, int32_t *const *flows, uint8_t *const *sides, wbpr_stats *stats) {
+  if (!c) return fail(WBPR_EINVAL, "null context");
+  if (n < 1 || !graphs || !s || !t || !values) return fail(WBPR_EINVAL, "null argument");
+  std::vector<int32_t> V(n);
+  std::vector<int64_t> E(n);
+  int64_t Vt = 0, Et = 0;
+  for (int i = 0; i < n; i++) {
+    const wbpr_csr &g = graphs[i];
+    int rc = check_shape(g.V, g.E, s[i], t[i]);
+    if (rc) {
+      g_err = "instance " + std::to_string(i) + ": " + g_err;
+      return rc;
+    }
+    if (!g.row_ptr || (g.E > 0 && (!g.col || !g.cap))) return fail(WBPR_EINVAL, "null CSR array");
+    if (flows && !flows[i]) return fail(WBPR_EINVAL, "flows given but flows[i] is null");
+    if (sides && !sides[i]) return fail(WBPR_EINVAL, "sides given but sides[i] is null");
+    V[i] = g.V;
+    E[i] = g.E;
+    Vt += g.V;
+    Et += g.E;
+  }
+  if (Vt + n >= (1ll << 30) || 2 * Et >= (1ll << 31) - 1) return fail(WBPR_ETOOBIG, "batch exceeds the index limits");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t Ec = (size_t)(Et > 0 ? Et : 1);
+  e = c->input.ensure(al(8 * (size_t)(Vt + n)) + 2 * al(4 * Ec));
+  if (e == hipSuccess) e = c->output.ensure(al(8 * (size_t)n) + al(4 * Ec) + al((size_t)Vt));
+  if (e != hipSuccess) return hip_fail(e, "device allocation (staging)");
+  char *ip = (char *)c->input.p;
+  int64_t *d_rp = (int64_t *)ip;
+  int32_t *d_col = (int32_t *)(ip + al(8 * (size_t)(Vt + n)));
+  int32_t *d_cap = (int32_t *)(ip + al(8 * (size_t)(Vt + n)) + al(4 * Ec));
+  char *op = (char *)c->output.p;
+  int64_t *d_val = (int64_t *)op;
+  int32_t *d_flow = (int32_t *)(op + al(8 * (size_t)n));
+  uint8_t *d_side = (uint8_t *)(op + al(8 * (size_t)n) + al(4 * Ec));
+  hipStream_t st = c->stream;
+  int64_t ro = 0, eo = 0;
+  for (int i = 0; i < n && e == hipSuccess; i++) {
+    const wbpr_csr &g = graphs[i];
+    e = hipMemcpyAsync(d_rp + ro, g.row_ptr, 8 * ((size_t)g.V + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && g.E > 0) e = hipMemcpyAsync(d_col + eo, g.col, 4 * (size_t)g.E, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && g.E > 0) e = hipMemcpyAsync(d_cap + eo, g.cap, 4 * (size_t)g.E, hipMemcpyHostToDevice, st);
+    ro += g.V + 1;
+    eo += g.E;
+  }
+  if (e != hipSuccess) return hip_fail(e, "host to device copy");
+  int rc = wbpr_solve_batch_device(c, n, V.data(), E.data(), s, t, d_rp, d_col, d_cap, st, d_val,
+                                   flows ? d_flow : nullptr, sides ? d_side : nullptr, stats);
+  if (rc) return rc;
+  e = hipMemcpyAsync(values, d_val, 8 * (size_t)n, hipMemcpyDeviceToHost, st);
+  int64_t vo = 0;
+  eo = 0;
+  for (int i = 0; i < n && e == hipSuccess; i++) {
+    if (flows && E[i] > 0) e = hipMemcpyAsync(flows[i], d_flow + eo, 4 * (size_t)E[i], hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && sides) e = hipMemcpyAsync(sides[i], d_side + vo, (size_t)V[i], hipMemcpyDeviceToHost, st);
+    vo += V[i];
+    eo += E[i];
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "device to host copy");
   return WBPR_OK;

@@ -25,31 +25,11 @@ static int bits_for(int64_t n) {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t residual_bytes(int32_t V, int64_t E) {
-  int64_t Mc = 2 * E > 0 ? 2 * E : 1;
-  return align256(sizeof(int32_t) * ((size_t)V + 1)) + align256(sizeof(int2) * Mc) + 2 * align256(sizeof(int32_t) * Mc) +
-         2 * align256(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
-}
-
-void residual_carve(Residual *res, int32_t V, int64_t E, void *mem) {
-  char *p = (char *)mem;
-  int64_t Mc = 2 * E > 0 ? 2 * E : 1;
-  res->V = V;
-  res->E = E;
-  res->M_cap = Mc;
-  res->rptr = (int32_t *)p; p += align256(sizeof(int32_t) * ((size_t)V + 1));
-  res->ent = (int2 *)p; p += align256(sizeof(int2) * Mc);
-  res->rev = (int32_t *)p; p += align256(sizeof(int32_t) * Mc);
-  res->cap0 = (int32_t *)p; p += align256(sizeof(int32_t) * Mc);
-  res->arc2ent = (int32_t *)p; p += align256(sizeof(int32_t) * (size_t)(E > 0 ? E : 1));
-  res->pbefore = (int32_t *)p;
-}
-
 namespace {
 struct Scratch {
   uint64_t *k0, *k1;
   uint32_t *v0, *v1;
-  int32_t *head, *hx, *wpos, *gstart, *rowcnt, *hist, *stemp;
+  int32_t *head, *hx, *wpos, *gstart, *rowcnt, *rptr, *hist, *stemp;
   int64_t *pcap, *stemp64;
   unsigned long long *capacc;
 };
@@ -69,6 +49,7 @@ size_t carve_scratch(int32_t V, int64_t E, void *mem, Scratch *s) {
   s->wpos = (int32_t *)take(4 * N);
   s->gstart = (int32_t *)take(4 * N);
   s->rowcnt = (int32_t *)take(4 * ((size_t)V + 1));
+  s->rptr = (int32_t *)take(4 * ((size_t)V + 1));
   s->hist = (int32_t *)take(4 * (size_t)hn);
   s->stemp = (int32_t *)take(4 * (size_t)st);
   s->pcap = (int64_t *)take(8 * N);
@@ -103,7 +84,7 @@ __global__ void k_check_rowptr(const int64_t *rp, int32_t V, int64_t E, BuildSta
 
 // Step 1.  Tail of arc i = last row whose start is <= i (binary search).
 __global__ void k_emit_keys(const int64_t *rp, const int32_t *col, const int32_t *cap, int32_t V, int64_t E, int vb,
-                            uint64_t *keys, uint32_t *vals, int32_t *arc2ent, BuildStatus *st) {
+                            uint64_t *keys, uint32_t *vals, int32_t *arc2ent, int32_t *acap, BuildStatus *st) {
   const uint64_t ALL = (vb * 2 >= 64) ? ~0ull : ((1ull << (2 * vb)) - 1);
   int nself = 0, bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
@@ -129,6 +110,7 @@ __global__ void k_emit_keys(const int64_t *rp, const int32_t *col, const int32_t
     }
     vals[2 * i] = (uint32_t)(2 * i);
     vals[2 * i + 1] = (uint32_t)(2 * i + 1);
+    acap[i] = cap[i];
   }
   nself = wave_sum_i32(nself);
   bad = wave_sum_i32(bad);
@@ -149,8 +131,8 @@ __global__ void k_heads(const uint64_t *keys, int64_t N, const BuildStatus *st, 
 
 // Step 3b.  Unique id of item i = hx[i] + head[i] - 1.
 __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, const int32_t *cap,
-                         const BuildStatus *st, const int32_t *head, const int32_t *hx, int2 *ent, int32_t *gstart,
-                         unsigned long long *capacc, int32_t *wpos, int64_t *pcap) {
+                         const BuildStatus *st, const int32_t *head, const int32_t *hx, int2 *ent, int32_t vbase,
+                         int32_t *gstart, unsigned long long *capacc, int32_t *wpos, int64_t *pcap) {
   int64_t mraw = N - 2 * (int64_t)st->nself;
   const uint64_t cmask = (1ull << vb) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
@@ -159,7 +141,7 @@ __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, 
     uint32_t pl = vals[i];
     int32_t u = hx[i] + head[i] - 1;
     if (head[i]) {
-      ent[u] = make_int2((int)(key & cmask), 0);
+      ent[u] = make_int2(vbase + (int)(key & cmask), 0);
       gstart[u] = (int32_t)i;
       capacc[u] = 0;
     }
@@ -196,27 +178,35 @@ __global__ void k_rowptr(const uint64_t *keys, int64_t N, int vb, int32_t V, con
   }
 }
 
+// Row bounds in the arena: rows of this build start at entry mbase.
+__global__ void k_rowb(const int32_t *rptr, int32_t V, int32_t vbase, int32_t mbase, int2 *rowb) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < V; x += (int64_t)gridDim.x * blockDim.x)
+    rowb[vbase + x] = make_int2(mbase + rptr[x], mbase + rptr[x + 1]);
+}
+
 // Step 4.  Mates and the arc -> entry map; capacity of earlier parallel arcs.
+// rev, arc2ent and pbefore point at this build's slices of the arena; the
+// stored indices are absolute (local + mbase).
 __global__ void k_arcs(int64_t E, const int32_t *wpos, const int32_t *head, const int32_t *hx, const int32_t *gstart,
-                       const int64_t *pcap_scanned, int32_t *rev, int32_t *arc2ent, int32_t *pbefore) {
+                       const int64_t *pcap_scanned, int32_t mbase, int32_t *rev, int32_t *arc2ent, int32_t *pbefore) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
     if (arc2ent[i] < 0) { pbefore[i] = 0; continue; }
     int32_t pf = wpos[2 * i], pb = wpos[2 * i + 1];
     int32_t f = hx[pf] + head[pf] - 1;
     int32_t b = hx[pb] + head[pb] - 1;
-    rev[f] = b;
-    rev[b] = f;
-    arc2ent[i] = f;
+    rev[f] = mbase + b;
+    rev[b] = mbase + f;
+    arc2ent[i] = mbase + f;
     pbefore[i] = (int32_t)(pcap_scanned[pf] - pcap_scanned[gstart[f]]);
   }
 }
 
-__global__ void k_caps(const BuildStatus *st, const unsigned long long *capacc, const int32_t *rev, int2 *ent,
-                       int32_t *cap0, BuildStatus *stw) {
+__global__ void k_caps(const BuildStatus *st, const unsigned long long *capacc, const int32_t *rev, int32_t mbase,
+                       int2 *ent, int32_t *cap0, BuildStatus *stw) {
   int64_t M = st->M;
   int ovf = 0;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = rev[j];
+    const int32_t r = rev[j] - mbase;
     if (r < 0 || r >= M) {  // every entry gets a mate; anything else is a bug
       atomicAdd(&stw->bad_input, 1);
       continue;
@@ -230,24 +220,30 @@ __global__ void k_caps(const BuildStatus *st, const unsigned long long *capacc, 
   if (lane() == 0 && ovf) atomicAdd(&stw->overflow, ovf);
 }
 
-hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, Residual *res,
-                          void *scratch, BuildStatus *status_dev, hipStream_t st) {
-  const int32_t V = res->V;
-  const int64_t E = res->E;
+hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, int32_t V, int64_t E,
+                          const Arena &A, const Place &pl, void *scratch, BuildStatus *status_dev, hipStream_t st) {
   const int64_t N = 2 * E;
   Scratch s;
   carve_scratch(V, E, scratch, &s);
+  int2 *ent = A.ent + pl.mbase;
+  int32_t *rev = A.rev + pl.mbase;
+  int32_t *cap0 = A.cap0 + pl.mbase;
+  int32_t *arc2ent = A.arc2ent + pl.abase;
+  int32_t *pbefore = A.pbefore + pl.abase;
+  int32_t *acap = A.acap + pl.abase;
   hipError_t e = hipMemsetAsync(status_dev, 0, sizeof(BuildStatus), st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_check_rowptr, dim3(grid_for(V + 1)), dim3(BT), 0, st, row_ptr, V, E, status_dev, s.rowcnt);
   if (E == 0) {
     // no arcs: every row is empty
-    e = excl_scan_i32(s.rowcnt, res->rptr, (int64_t)V + 1, nullptr, s.stemp, st);
-    return e != hipSuccess ? e : hipGetLastError();
+    e = excl_scan_i32(s.rowcnt, s.rptr, (int64_t)V + 1, nullptr, s.stemp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rowb, dim3(grid_for(V)), dim3(BT), 0, st, s.rptr, V, pl.vbase, (int32_t)pl.mbase, A.rowb);
+    return hipGetLastError();
   }
   const int vb = bits_for(V);
-  hipLaunchKernelGGL(k_emit_keys, dim3(grid_for(E)), dim3(BT), 0, st, row_ptr, col, cap, V, E, vb, s.k0, s.v0,
-                     res->arc2ent, status_dev);
+  hipLaunchKernelGGL(k_emit_keys, dim3(grid_for(E)), dim3(BT), 0, st, row_ptr, col, cap, V, E, vb, s.k0, s.v0, arc2ent,
+                     acap, status_dev);
   int alt = 0;
   e = radix_sort_u64_u32(s.k0, s.v0, s.k1, s.v1, N, 2 * vb, s.hist, s.stemp, &alt, st);
   if (e != hipSuccess) return e;
@@ -257,16 +253,17 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
   e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_unique, dim3(grid_for(N)), dim3(BT), 0, st, keys, vals, N, vb, cap, status_dev, s.head, s.hx,
-                     res->ent, s.gstart, s.capacc, s.wpos, s.pcap);
+                     ent, pl.vbase, s.gstart, s.capacc, s.wpos, s.pcap);
   hipLaunchKernelGGL(k_capacc, dim3(grid_for(N)), dim3(BT), 0, st, vals, N, cap, status_dev, s.head, s.hx, s.capacc);
   e = excl_scan_i64(s.pcap, s.pcap, N, nullptr, s.stemp64, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rowptr, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, N, vb, V, status_dev, s.hx,
-                     res->rptr);
+                     s.rptr);
+  hipLaunchKernelGGL(k_rowb, dim3(grid_for(V)), dim3(BT), 0, st, s.rptr, V, pl.vbase, (int32_t)pl.mbase, A.rowb);
   hipLaunchKernelGGL(k_arcs, dim3(grid_for(E)), dim3(BT), 0, st, E, s.wpos, s.head, s.hx, s.gstart, s.pcap,
-                     res->rev, res->arc2ent, res->pbefore);
-  hipLaunchKernelGGL(k_caps, dim3(grid_for(N)), dim3(BT), 0, st, status_dev, s.capacc, res->rev, res->ent,
-                     res->cap0, status_dev);
+                     (int32_t)pl.mbase, rev, arc2ent, pbefore);
+  hipLaunchKernelGGL(k_caps, dim3(grid_for(N)), dim3(BT), 0, st, status_dev, s.capacc, rev, (int32_t)pl.mbase, ent,
+                     cap0, status_dev);
   return hipGetLastError();
 }
 

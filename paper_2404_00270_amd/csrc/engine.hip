@@ -1,0 +1,1093 @@
+// Host engine (wb_engine.h) and its per-instance kernels.
+//
+// Every resident instance owns a contiguous vertex range, entry range and arc
+// range of the arena.  Kernels address vertices and entries by arena id, so
+// the residual graphs of all resident instances form one disjoint union: a
+// sweep or a global relabel serves every instance at once.  Heights carry a
+// per-instance base HCAP - V_i, so "h >= HCAP" means "local height >= V_i"
+// (inactive) for every instance alike (Algorithm 1's deactivation at |V|).
+//
+// Per instance the phases are: 1, maximum preflow (sink t is the BFS root,
+// source s excluded) until no active vertex is left; then the flow value and
+// the cut side are written; 2, if per-arc flows are wanted, the stranded
+// excess returns to s (s is the root, t excluded); then the flows are
+// decoded; 3, done and released.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "../../include/wbpr.h"
+#include "wb_common.h"
+#include "wb_engine.h"
+
+namespace wb {
+
+// ------------------------------------------------------------ range alloc
+void RangeAlloc::reset(int64_t cap) {
+  free_.clear();
+  cap_ = cap;
+  free_total_ = cap;
+  if (cap > 0) free_[0] = cap;
+}
+
+int64_t RangeAlloc::alloc(int64_t n) {
+  if (n <= 0) return 0;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= n) {
+      const int64_t at = it->first, len = it->second;
+      free_.erase(it);
+      if (len > n) free_[at + n] = len - n;
+      free_total_ -= n;
+      return at;
+    }
+  }
+  return -1;
+}
+
+void RangeAlloc::release(int64_t at, int64_t n) {
+  if (n <= 0) return;
+  free_total_ += n;
+  auto it = free_.emplace(at, n).first;
+  auto nx = std::next(it);
+  if (nx != free_.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    free_.erase(nx);
+  }
+  if (it != free_.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      free_.erase(it);
+    }
+  }
+}
+
+void RangeAlloc::shrink(int64_t at, int64_t n_old, int64_t n_new) {
+  if (n_new < n_old) release(at + n_new, n_old - n_new);
+}
+
+int64_t RangeAlloc::largest_free() const {
+  int64_t b = 0;
+  for (const auto &kv : free_) b = std::max(b, kv.second);
+  return b;
+}
+
+// ------------------------------------------------------ per-instance kernels
+struct InstDev {
+  int32_t vbase, V, s, t;  // s, t: arena ids
+  int64_t abase, E;
+  long long *value;
+  int32_t *flow;
+  uint8_t *side;
+};
+
+enum InstKernel { IK_INIT = 0, IK_PREFLOW, IK_VALUE_ZERO, IK_VALUE, IK_SIDE, IK_PHASE2, IK_DECODE, IK_RELEASE, IK_COUNT };
+
+struct InstArgs {
+  const InstDev *L;
+  int2 *rowb;
+  int2 *ent;
+  const int32_t *rev;
+  const int32_t *cap0;
+  const int32_t *arc2ent;
+  const int32_t *pbefore;
+  const int32_t *acap;
+  long long *e;
+  int32_t *h;
+  int32_t *inst_of;
+  const int32_t *slot;  // [n] instance slot of list entry i (IK_INIT)
+};
+
+// blockIdx.y selects the instance of the list; blockIdx.x strides its range.
+__global__ void k_inst(InstArgs a, int which) {
+  const InstDev d = a.L[blockIdx.y];
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  switch (which) {
+    case IK_INIT:
+      for (int64_t x = tid; x < d.V; x += nth) {
+        const int32_t v = d.vbase + (int32_t)x;
+        a.e[v] = v == d.t ? WB_EXCESS_BIAS : 0;
+        a.h[v] = 0;
+        a.inst_of[v] = a.slot[blockIdx.y];
+      }
+      break;
+    case IK_PREFLOW: {  // Algorithm 1, step 0: saturate every residual entry of s
+      const int2 rb = a.rowb[d.s];
+      for (int64_t k = rb.x + tid; k < rb.y; k += nth) {
+        const int2 cr = a.ent[k];
+        if (cr.y > 0) {
+          a.ent[k].y = 0;
+          atomic_add_i32(&a.ent[a.rev[k]].y, cr.y);
+          atomic_add_i64(&a.e[cr.x], (long long)cr.y);
+        }
+      }
+      break;
+    }
+    case IK_VALUE_ZERO:
+      if (tid == 0 && d.value) *d.value = 0;
+      break;
+    case IK_VALUE: {
+      // value = total flow into t = sum over t's row of (c_f(t,w) - c(t,w)):
+      // every push w -> t raised the mate residual c_f(t,w) by the amount
+      // pushed, and nothing is ever pushed out of t
+      __shared__ long long s_part[256 / WB_WAVE];
+      const int2 rb = a.rowb[d.t];
+      long long acc = 0;
+      for (int64_t k = rb.x + tid; k < rb.y; k += nth) acc += (long long)a.ent[k].y - (long long)a.cap0[k];
+      acc = group_sum_i64<WB_WAVE>(acc);
+      if (lane() == 0) s_part[threadIdx.x / WB_WAVE] = acc;
+      __syncthreads();
+      if (threadIdx.x == 0 && d.value) {
+        long long tot = 0;
+        for (int i = 0; i < (int)(blockDim.x / WB_WAVE); i++) tot += s_part[i];
+        if (tot) atomic_add_i64(d.value, tot);
+      }
+      break;
+    }
+    case IK_SIDE:  // sink side: v still reaches t (labelled by the last relabel)
+      if (d.side)
+        for (int64_t x = tid; x < d.V; x += nth) d.side[x] = a.h[d.vbase + x] < HCAP ? 1 : 0;
+      break;
+    case IK_PHASE2:
+      if (tid == 0) a.e[d.s] += WB_EXCESS_BIAS;
+      break;
+    case IK_DECODE:
+      // per-arc flow from the merged net flow of the ordered pair (u,v):
+      // parallel arcs u->v are filled in input order up to their capacities
+      if (d.flow)
+        for (int64_t i = tid; i < d.E; i += nth) {
+          const int32_t j = a.arc2ent[d.abase + i];
+          int32_t f = 0;
+          if (j >= 0) {
+            long long x = (long long)a.cap0[j] - (long long)a.ent[j].y - (long long)a.pbefore[d.abase + i];
+            const long long c = a.acap[d.abase + i];
+            f = (int32_t)(x < 0 ? 0 : (x > c ? c : x));
+          }
+          d.flow[i] = f;
+        }
+      break;
+    case IK_RELEASE:
+      for (int64_t x = tid; x < d.V; x += nth) {
+        const int32_t v = d.vbase + (int32_t)x;
+        a.e[v] = 0;
+        a.h[v] = HCAP;
+        a.inst_of[v] = -1;
+        a.rowb[v] = make_int2(0, 0);
+      }
+      break;
+  }
+}
+
+// Packs n local CSRs into one union CSR: vertex ids offset by voff[i], arcs
+// by eoff[i]; checks each instance's row pointers and columns (bad[i]).
+__global__ void k_union_rows(int32_t n, const int32_t *voff, const int64_t *eoff, const int64_t *rp_packed,
+                             int64_t *rp_union, int32_t *bad) {
+  const int32_t Vt = voff[n];
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= Vt; x += (int64_t)gridDim.x * blockDim.x) {
+    if (x == Vt) {
+      rp_union[x] = eoff[n];
+      continue;
+    }
+    int32_t lo = 0, hi = n - 1;  // last instance with voff <= x
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (voff[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    const int32_t i = lo;
+    const int64_t local = x - voff[i];
+    const int64_t base = (int64_t)voff[i] + i;  // instance i's row pointers start here
+    const int64_t r0 = rp_packed[base + local], r1 = rp_packed[base + local + 1];
+    const int64_t Ei = eoff[i + 1] - eoff[i];
+    bool ok = r0 <= r1 && r0 >= 0 && r1 <= Ei;
+    if (local == 0 && r0 != 0) ok = false;
+    if (x + 1 == voff[i + 1] && r1 != Ei) ok = false;
+    if (!ok) atomic_add_i32(&bad[i], 1);
+    rp_union[x] = eoff[i] + (r0 < 0 ? 0 : (r0 > Ei ? Ei : r0));
+  }
+}
+
+__global__ void k_union_cols(int32_t n, const int32_t *voff, const int64_t *eoff, const int32_t *col_packed,
+                             int32_t *col_union, int32_t *bad) {
+  const int64_t Et = eoff[n];
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < Et; k += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = n - 1;  // last instance with eoff <= k
+    while (lo < hi) {
+      const int32_t mid = (lo + hi + 1) >> 1;
+      if (eoff[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    const int32_t i = lo;
+    const int32_t c = col_packed[k];
+    const int32_t Vi = voff[i + 1] - voff[i];
+    if (c < 0 || c >= Vi) {
+      atomic_add_i32(&bad[i], 1);
+      col_union[k] = voff[i];  // any in-range id; the group is rejected
+    } else {
+      col_union[k] = voff[i] + c;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- layout
+namespace {
+struct MiscLayout {
+  long long stats[16];
+  long long status[4];
+  int32_t err[2];
+  int32_t qcnt[4];
+  int32_t fcnt[4];
+  int32_t chunk_cnt[2];
+  int32_t big_cnt[2];
+  int32_t mid_cnt[2];
+  int32_t bucnt[4];
+  int32_t halt[2];
+  long long rwork;
+  long long rwork_at_gr;
+  unsigned bar[WB_BAR_WORDS];
+  long long fedges[4];
+  int32_t sink;
+  int32_t pad;
+  long long budget;
+};
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int64_t chunk_capacity(int64_t Vcap, int64_t Mcap, int chunk) { return Mcap / chunk + Vcap + 16; }
+
+unsigned grid1d(int64_t n, int threads = 256, int64_t maxb = 65536) {
+  int64_t b = (n + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > maxb) b = maxb;
+  return (unsigned)b;
+}
+
+double gr_beta_env() {
+  static double beta = -1;
+  if (beta < 0) {
+    const char *e = std::getenv("WBPR_GR_BETA");
+    beta = e ? std::atof(e) : 1.0;
+    if (!(beta > 0)) beta = 1.0;
+  }
+  return beta;
+}
+
+int log_level() {
+  static int lvl = -1;
+  if (lvl < 0) {
+    const char *e = std::getenv("WBPR_LOG");
+    lvl = e ? std::atoi(e) : 0;
+  }
+  return lvl;
+}
+
+constexpr int kListKinds = 8;   // separate staging per per-instance kernel kind
+constexpr size_t kPinnedHeader = 4096;
+}  // namespace
+
+size_t Engine::arena_bytes(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap) {
+  const int64_t nch = chunk_capacity(Vcap, Mcap, 1024);
+  size_t b = 0;
+  b += al(8 * (size_t)Vcap);                 // rowb
+  b += al(8 * (size_t)Mcap);                 // ent
+  b += 2 * al(4 * (size_t)Mcap);             // rev, cap0
+  b += 3 * al(4 * (size_t)Ecap);             // arc2ent, pbefore, acap
+  b += al(8 * (size_t)Vcap);                 // e
+  b += 8 * al(4 * (size_t)Vcap);             // h, inst_of, q0, q1, fq0, fq1, mid, big
+  b += al((size_t)Vcap);                     // vis
+  b += 2 * al(4 * (size_t)nch);              // chunk descriptors
+  b += 5 * al(4 * (size_t)ncap);             // active, stranded, roots, root_h, excl
+  b += al(sizeof(InstDev) * (size_t)ncap * kListKinds + 4 * (size_t)ncap);  // lists + slots
+  b += al(sizeof(MiscLayout));
+  return b;
+}
+
+size_t Engine::scratch_bytes(int64_t V, int64_t E, int32_t n) {
+  size_t b = build_scratch_bytes((int32_t)V, E);
+  b += al(8 * ((size_t)V + 1)) + al(4 * (size_t)(E > 0 ? E : 1));  // union CSR
+  b += al(4 * ((size_t)n + 1)) + al(8 * ((size_t)n + 1)) + al(4 * (size_t)n);  // voff, eoff, bad
+  b += al(sizeof(BuildStatus));
+  return b;
+}
+
+Engine::Engine(int device) : device_(device) {
+  for (int lg = 2; lg <= 6; lg++) gr_blocks_[lg] = gr_max_blocks(device, 1 << lg);
+}
+
+Engine::~Engine() {
+  if (graph_exec_) hipGraphExecDestroy(graph_exec_);
+  if (graph_) hipGraphDestroy(graph_);
+  for (auto &e : ev_) hipEventDestroy(e);
+  if (arena_) hipFree(arena_);
+  if (scratch_) hipFree(scratch_);
+  if (pin_) hipHostFree(pin_);
+}
+
+void Engine::set_config(const SolveConfig &cfg) {
+  cfg_ = cfg;
+  if (graph_exec_) hipGraphExecDestroy(graph_exec_);
+  if (graph_) hipGraphDestroy(graph_);
+  graph_exec_ = nullptr;
+  graph_ = nullptr;
+}
+
+int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int64_t sV, int64_t sE, int32_t sn,
+                    std::string *err) {
+  Vcap = std::max<int64_t>(Vcap, 2);
+  Mcap = std::max<int64_t>(Mcap, 2);
+  Ecap = std::max<int64_t>(Ecap, 1);
+  ncap = std::max<int32_t>(ncap, 1);
+  if (Vcap >= (1ll << 30) || Mcap >= (1ll << 31) - 1 || Ecap >= (1ll << 31) - 1) {
+    *err = "arena capacity beyond the 32-bit index limits";
+    return WBPR_ETOOBIG;
+  }
+  const bool grow_arena = Vcap > Vcap_ || Mcap > Mcap_ || Ecap > Ecap_ || ncap > ncap_;
+  if (grow_arena && resident_ > 0) {
+    *err = "arena cannot grow while instances are resident";
+    return WBPR_EAGAIN;
+  }
+  if (grow_arena) {
+    if (graph_exec_) hipGraphExecDestroy(graph_exec_);
+    if (graph_) hipGraphDestroy(graph_);
+    graph_exec_ = nullptr;
+    graph_ = nullptr;
+    Vcap = std::max(Vcap, Vcap_);
+    Mcap = std::max(Mcap, Mcap_);
+    Ecap = std::max(Ecap, Ecap_);
+    ncap = std::max(ncap, ncap_);
+    const size_t bytes = arena_bytes(Vcap, Mcap, Ecap, ncap);
+    if (arena_) hipFree(arena_);
+    arena_ = nullptr;
+    arena_n_ = 0;
+    hipError_t e = hipMalloc(&arena_, bytes);
+    if (e != hipSuccess) {
+      *err = std::string("arena allocation: ") + hipGetErrorString(e);
+      Vcap_ = Mcap_ = Ecap_ = 0;
+      ncap_ = 0;
+      return e == hipErrorOutOfMemory ? WBPR_ENOMEM : WBPR_EDEVICE;
+    }
+    arena_n_ = bytes;
+    Vcap_ = Vcap;
+    Mcap_ = Mcap;
+    Ecap_ = Ecap;
+    ncap_ = ncap;
+    char *p = (char *)arena_;
+    auto take = [&](size_t n) { char *q = p; p += al(n); return (void *)q; };
+    A_.rowb = (int2 *)take(8 * (size_t)Vcap);
+    A_.ent = (int2 *)take(8 * (size_t)Mcap);
+    A_.rev = (int32_t *)take(4 * (size_t)Mcap);
+    A_.cap0 = (int32_t *)take(4 * (size_t)Mcap);
+    A_.arc2ent = (int32_t *)take(4 * (size_t)Ecap);
+    A_.pbefore = (int32_t *)take(4 * (size_t)Ecap);
+    A_.acap = (int32_t *)take(4 * (size_t)Ecap);
+    e_ = (long long *)take(8 * (size_t)Vcap);
+    h_ = (int32_t *)take(4 * (size_t)Vcap);
+    inst_of_ = (int32_t *)take(4 * (size_t)Vcap);
+    q_[0] = (int32_t *)take(4 * (size_t)Vcap);
+    q_[1] = (int32_t *)take(4 * (size_t)Vcap);
+    fq_[0] = (int32_t *)take(4 * (size_t)Vcap);
+    fq_[1] = (int32_t *)take(4 * (size_t)Vcap);
+    mid_ = (int32_t *)take(4 * (size_t)Vcap);
+    big_ = (int32_t *)take(4 * (size_t)Vcap);
+    vis_ = (uint8_t *)take((size_t)Vcap);
+    nchunk_ = chunk_capacity(Vcap, Mcap, chunk_);
+    chunk_w_ = (int32_t *)take(4 * (size_t)nchunk_);
+    chunk_b_ = (int32_t *)take(4 * (size_t)nchunk_);
+    inst_active_ = (int32_t *)take(4 * (size_t)ncap);
+    inst_stranded_ = (int32_t *)take(4 * (size_t)ncap);
+    roots_ = (int32_t *)take(4 * (size_t)ncap);
+    root_h_ = (int32_t *)take(4 * (size_t)ncap);
+    excl_ = (int32_t *)take(4 * (size_t)ncap);
+    inst_list_ = take(sizeof(InstDev) * (size_t)ncap * kListKinds + 4 * (size_t)ncap);
+    misc_ = (long long *)take(sizeof(MiscLayout));
+    MiscLayout *m = reinterpret_cast<MiscLayout *>(misc_);
+    sink_ = &m->sink;
+    budget_ = &m->budget;
+    // free arena: empty rows, inactive vertices, no instance
+    e = hipMemset(arena_, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(inst_of_, 0xff, 4 * (size_t)Vcap);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      *err = std::string("arena init: ") + hipGetErrorString(e);
+      return WBPR_EDEVICE;
+    }
+    valloc_.reset(Vcap);
+    malloc_.reset(Mcap);
+    aalloc_.reset(Ecap);
+    slot_free_.clear();
+    for (int32_t i = ncap - 1; i >= 0; i--) slot_free_.push_back(i);
+    inst_.assign(ncap, Inst());
+    groups_.clear();
+    const size_t pin_need = kPinnedHeader + sizeof(InstDev) * (size_t)ncap * kListKinds + 24 * (size_t)ncap + 4096;
+    if (pin_n_ < pin_need) {
+      if (pin_) hipHostFree(pin_);
+      pin_ = nullptr;
+      pin_n_ = 0;
+      e = hipHostMalloc((void **)&pin_, pin_need, hipHostMallocDefault);
+      if (e != hipSuccess) {
+        *err = std::string("pinned staging: ") + hipGetErrorString(e);
+        return WBPR_ENOMEM;
+      }
+      pin_n_ = pin_need;
+    }
+  }
+  sV_ = std::max(sV_, sV);
+  sE_ = std::max(sE_, sE);
+  sn_ = std::max(sn_, sn);
+  const size_t sbytes = scratch_bytes(sV_, sE_, sn_);
+  if (sbytes > scratch_n_) {
+    if (resident_ > 0 && scratch_) hipDeviceSynchronize();
+    if (scratch_) hipFree(scratch_);
+    scratch_ = nullptr;
+    scratch_n_ = 0;
+    hipError_t e = hipMalloc(&scratch_, sbytes);
+    if (e != hipSuccess) {
+      *err = std::string("scratch allocation: ") + hipGetErrorString(e);
+      return e == hipErrorOutOfMemory ? WBPR_ENOMEM : WBPR_EDEVICE;
+    }
+    scratch_n_ = sbytes;
+  }
+  // tiers from the configuration (defaults from the arena's mean row length
+  // are refined per admission)
+  return 0;
+}
+
+void Engine::launch_inst_kernel(int which, const std::vector<int> &slots, hipStream_t st) {
+  std::vector<InstDev> list;
+  list.reserve(slots.size());
+  for (int sl : slots) {
+    const Inst &I = inst_[sl];
+    InstDev d;
+    d.vbase = I.vbase;
+    d.V = I.V;
+    d.s = I.s;
+    d.t = I.t;
+    d.abase = I.abase;
+    d.E = I.E;
+    d.value = (long long *)I.value;
+    d.flow = I.flow;
+    d.side = I.side;
+    list.push_back(d);
+  }
+  launch_inst_list(which, list, slots, st);
+}
+
+// Per-instance kernel over a list of descriptors.  Each kernel kind has its
+// own pinned and device staging slice; a slice is reused only after the
+// stream has been synchronised (every round and every admission syncs).
+void Engine::launch_inst_list(int which, const std::vector<InstDev> &list, const std::vector<int> &slots,
+                              hipStream_t st) {
+  const int n = (int)list.size();
+  if (n == 0) return;
+  InstDev *hl = reinterpret_cast<InstDev *>(pin_ + kPinnedHeader) + (size_t)which * ncap_;
+  InstDev *dl = reinterpret_cast<InstDev *>(inst_list_) + (size_t)which * ncap_;
+  int32_t *dslot = reinterpret_cast<int32_t *>(reinterpret_cast<InstDev *>(inst_list_) + (size_t)kListKinds * ncap_);
+  int32_t *hslot = reinterpret_cast<int32_t *>(pin_ + kPinnedHeader + sizeof(InstDev) * (size_t)ncap_ * kListKinds);
+  int64_t maxlen = 1;
+  for (int i = 0; i < n; i++) {
+    hl[i] = list[i];
+    if (which == IK_INIT) hslot[i] = slots[i];
+    maxlen = std::max<int64_t>(maxlen, which == IK_DECODE ? list[i].E : list[i].V);
+  }
+  hipMemcpyAsync(dl, hl, sizeof(InstDev) * n, hipMemcpyHostToDevice, st);
+  if (which == IK_INIT) hipMemcpyAsync(dslot, hslot, 4 * (size_t)n, hipMemcpyHostToDevice, st);
+  InstArgs a{dl, A_.rowb, A_.ent, A_.rev, A_.cap0, A_.arc2ent, A_.pbefore, A_.acap, e_, h_, inst_of_, dslot};
+  unsigned bx = which == IK_VALUE_ZERO || which == IK_PHASE2 ? 1u : grid1d(maxlen, 256, 1024);
+  if (which == IK_PREFLOW || which == IK_VALUE) bx = 64;
+  for (int off = 0; off < n; off += 65535) {
+    const int cnt = std::min(65535, n - off);
+    InstArgs b = a;
+    b.L = dl + off;
+    b.slot = dslot + off;
+    hipLaunchKernelGGL(k_inst, dim3(bx, cnt), dim3(256), 0, st, b, which);
+  }
+}
+
+int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
+  if (in.n <= 0) return 0;
+  if (in.n > (int32_t)slot_free_.size()) {
+    *err = "no free instance slot";
+    return WBPR_EAGAIN;
+  }
+  int64_t Vt = 0, Et = 0;
+  for (int i = 0; i < in.n; i++) {
+    Vt += in.V[i];
+    Et += in.E[i];
+  }
+  if (Vt >= (1ll << 30) || 2 * Et >= (1ll << 31) - 1) {
+    *err = "group exceeds the 32-bit index limits";
+    return WBPR_ETOOBIG;
+  }
+  if (Vt > sV_ || Et > sE_ || in.n > sn_) {
+    int rc = reserve(0, 0, 0, 0, Vt, Et, in.n, err);
+    if (rc) return rc;
+  }
+  const int64_t vb = valloc_.alloc(Vt);
+  const int64_t mb = vb < 0 ? -1 : malloc_.alloc(std::max<int64_t>(2 * Et, 1));
+  const int64_t ab = mb < 0 ? -1 : aalloc_.alloc(std::max<int64_t>(Et, 1));
+  if (vb < 0 || mb < 0 || ab < 0) {
+    if (vb >= 0) valloc_.release(vb, Vt);
+    if (mb >= 0) malloc_.release(mb, std::max<int64_t>(2 * Et, 1));
+    *err = "arena full";
+    return WBPR_EAGAIN;
+  }
+  // scratch carve: builder | union rows | union cols | voff | eoff | bad | status
+  char *sp = (char *)scratch_;
+  void *bscratch = sp;
+  sp += al(build_scratch_bytes((int32_t)sV_, sE_));
+  int64_t *rp_union = (int64_t *)sp;
+  sp += al(8 * ((size_t)sV_ + 1));
+  int32_t *col_union = (int32_t *)sp;
+  sp += al(4 * (size_t)(sE_ > 0 ? sE_ : 1));
+  int32_t *voff = (int32_t *)sp;
+  sp += al(4 * ((size_t)sn_ + 1));
+  int64_t *eoff = (int64_t *)sp;
+  sp += al(8 * ((size_t)sn_ + 1));
+  int32_t *bad = (int32_t *)sp;
+  sp += al(4 * (size_t)sn_);
+  BuildStatus *bst = (BuildStatus *)sp;
+
+  const int64_t *rp = in.row_ptr;
+  const int32_t *col = in.col;
+  if (in.n > 1) {
+    // prefix offsets of the instances (host) -> device
+    std::vector<int32_t> voh(in.n + 1);
+    std::vector<int64_t> eoh(in.n + 1);
+    voh[0] = 0;
+    eoh[0] = 0;
+    for (int i = 0; i < in.n; i++) {
+      voh[i + 1] = voh[i] + in.V[i];
+      eoh[i + 1] = eoh[i] + in.E[i];
+    }
+    // the offsets are small; a synchronised copy keeps the staging simple
+    hipError_t e = hipMemcpyAsync(voff, voh.data(), 4 * (size_t)(in.n + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(eoff, eoh.data(), 8 * (size_t)(in.n + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(bad, 0, 4 * (size_t)in.n, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);  // pageable sources
+    if (e != hipSuccess) {
+      valloc_.release(vb, Vt);
+      malloc_.release(mb, std::max<int64_t>(2 * Et, 1));
+      aalloc_.release(ab, std::max<int64_t>(Et, 1));
+      *err = std::string("group offsets: ") + hipGetErrorString(e);
+      return WBPR_EDEVICE;
+    }
+    hipLaunchKernelGGL(k_union_rows, dim3(grid1d(Vt + 1)), dim3(256), 0, st, in.n, voff, eoff, in.row_ptr, rp_union,
+                       bad);
+    if (Et > 0)
+      hipLaunchKernelGGL(k_union_cols, dim3(grid1d(Et)), dim3(256), 0, st, in.n, voff, eoff, in.col, col_union, bad);
+    rp = rp_union;
+    col = col_union;
+  }
+  Place pl;
+  pl.vbase = (int32_t)vb;
+  pl.mbase = mb;
+  pl.abase = ab;
+  hipError_t e = build_residual(rp, col, in.cap, (int32_t)Vt, Et, A_, pl, bscratch, bst, st);
+  BuildStatus hb;
+  if (e == hipSuccess) e = hipMemcpyAsync(pin_, bst, sizeof(BuildStatus), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  int bad_any = 0;
+  if (e == hipSuccess) {
+    std::memcpy(&hb, pin_, sizeof(hb));
+    if (in.n > 1) {
+      std::vector<int32_t> hbad(in.n);
+      hipError_t e2 = hipMemcpy(hbad.data(), bad, 4 * (size_t)in.n, hipMemcpyDeviceToHost);
+      if (e2 != hipSuccess) e = e2;
+      for (int i = 0; i < in.n && e == hipSuccess; i++) bad_any |= hbad[i] != 0;
+    }
+  }
+  auto undo = [&]() {
+    valloc_.release(vb, Vt);
+    malloc_.release(mb, std::max<int64_t>(2 * Et, 1));
+    aalloc_.release(ab, std::max<int64_t>(Et, 1));
+  };
+  if (e != hipSuccess) {
+    undo();
+    *err = std::string("residual build: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  if (hb.bad_input || bad_any || hb.overflow) {
+    // empty the rows written for this group before its ranges are reused
+    hipMemsetAsync(A_.rowb + vb, 0, 8 * (size_t)Vt, st);
+    hipStreamSynchronize(st);
+    undo();
+    if (hb.overflow && !hb.bad_input && !bad_any) {
+      *err = "c(u->v) + c(v->u) over parallel arcs exceeds INT32_MAX";
+      return WBPR_EOVERFLOW;
+    }
+    *err = "malformed CSR (row_ptr not monotone from 0 to E, col out of range, or negative cap)";
+    return WBPR_EINVAL;
+  }
+  const int64_t Mres = std::max<int64_t>(2 * Et, 1);
+  malloc_.shrink(mb, Mres, std::max<int64_t>(hb.M, 1));
+  last_M_ = hb.M;
+  // register the group and its instances
+  int gi = -1;
+  for (int i = 0; i < (int)groups_.size(); i++)
+    if (!groups_[i].used) {
+      gi = i;
+      break;
+    }
+  if (gi < 0) {
+    groups_.push_back(Group());
+    gi = (int)groups_.size() - 1;
+  }
+  Group &G = groups_[gi];
+  G.used = true;
+  G.tag = in.tag;
+  G.vbase = (int32_t)vb;
+  G.V = (int32_t)Vt;
+  G.mbase = mb;
+  G.Mres = std::max<int64_t>(hb.M, 1);
+  G.abase = ab;
+  G.E = Et;
+  G.remaining = in.n;
+  std::vector<int> slots(in.n);
+  int64_t vo = 0, eo = 0;
+  for (int i = 0; i < in.n; i++) {
+    const int sl = slot_free_.back();
+    slot_free_.pop_back();
+    slots[i] = sl;
+    Inst &I = inst_[sl];
+    I.used = true;
+    I.V = in.V[i];
+    I.E = in.E[i];
+    I.vbase = (int32_t)(vb + vo);
+    I.s = I.vbase + in.s[i];
+    I.t = I.vbase + in.t[i];
+    I.abase = ab + eo;
+    I.phase = 1;
+    I.group = gi;
+    I.index = i;
+    I.value = in.values ? in.values + i : nullptr;
+    I.flow = in.flows ? in.flows + eo : nullptr;
+    I.side = in.sides ? in.sides + vo : nullptr;
+    vo += in.V[i];
+    eo += in.E[i];
+  }
+  resident_ += in.n;
+  resident_V_ += Vt;
+  resident_M_ += hb.M;
+  launch_inst_kernel(IK_INIT, slots, st);
+  launch_inst_kernel(IK_PREFLOW, slots, st);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    *err = std::string("instance init: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  return 0;
+}
+
+// Clears the vertices of the listed groups (rows, excess, heights, owner)
+// in one launch, then returns their ranges.  One launch per call: the pinned
+// descriptor slice of a kernel kind is rewritten only after a stream sync.
+void Engine::release_groups(const std::vector<int> &gis, hipStream_t st) {
+  if (gis.empty()) return;
+  std::vector<InstDev> list;
+  for (int gi : gis) {
+    Group &G = groups_[gi];
+    InstDev d;
+    std::memset(&d, 0, sizeof(d));
+    d.vbase = G.vbase;
+    d.V = G.V;
+    list.push_back(d);
+  }
+  launch_inst_list(IK_RELEASE, list, std::vector<int>(list.size(), 0), st);
+  for (int gi : gis) {
+    Group &G = groups_[gi];
+    valloc_.release(G.vbase, G.V);
+    malloc_.release(G.mbase, G.Mres);
+    aalloc_.release(G.abase, std::max<int64_t>(G.E, 1));
+    resident_V_ -= G.V;
+    resident_M_ -= G.Mres;
+    G.used = false;
+  }
+}
+
+int Engine::ensure_graph(hipStream_t st, std::string *err) {
+  if (graph_exec_) return 0;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    *err = std::string("graph capture: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  const int K = cfg_.gr_every_sweeps > 0 ? cfg_.gr_every_sweeps : 64;
+  enqueue_sweeps(st, K);
+  e = hipStreamEndCapture(st, &graph_);
+  if (e == hipSuccess) e = hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    *err = std::string("graph instantiate: ") + hipGetErrorString(e);
+    if (graph_) hipGraphDestroy(graph_);
+    graph_ = nullptr;
+    graph_exec_ = nullptr;
+    return WBPR_EDEVICE;
+  }
+  graph_K_ = K;
+  return 0;
+}
+
+void Engine::enqueue_sweeps(hipStream_t st, int K) {
+  MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+  Graph g{(int32_t)Vcap_, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_};
+  const int sweep_blocks = cfg_.grid_blocks > 0 ? cfg_.grid_blocks : 1024;
+  const int block_blocks = 512;
+  const int mode = cfg_.push_mode == 1 ? 0 : 1;
+  const bool timed = cfg_.time_kernels;
+  for (int j = 0; j < K; j++) {
+    SweepQ q;
+    q.qin = q_[j & 1];
+    q.qin_cnt = &misc->qcnt[j % 3];
+    q.qout = q_[(j + 1) & 1];
+    q.qout_cnt = &misc->qcnt[(j + 1) % 3];
+    q.zero_cnt = &misc->qcnt[(j + 2) % 3];
+    q.mid_v = mid_;
+    q.mid_cnt = &misc->mid_cnt[j & 1];
+    q.big_v = big_;
+    q.big_cnt = &misc->big_cnt[j & 1];
+    q.zero_a = &misc->mid_cnt[(j + 1) & 1];
+    q.zero_b = &misc->big_cnt[(j + 1) & 1];
+    q.t_mid = t_mid_;
+    q.t_big = t_big_;
+    q.mode = mode;
+    q.stats = misc->stats;
+    q.rwork = &misc->rwork;
+    q.halt = &misc->halt[0];
+    q.qcap = (int32_t)Vcap_;
+    q.err = misc->err;
+    SweepQ qw = q;
+    qw.qin = mid_;
+    qw.qin_cnt = &misc->mid_cnt[j & 1];
+    qw.zero_cnt = nullptr;
+    qw.t_mid = 0x7fffffff;
+    qw.t_big = 0x7fffffff;
+    qw.stats = misc->stats + 4;
+    int evb = -1;
+    if (timed) {
+      if (ev_used_ + 4 > (int)ev_.size()) {
+        const size_t old = ev_.size();
+        ev_.resize(old + 1024);
+        for (size_t i = old; i < ev_.size(); i++) hipEventCreate(&ev_[i]);
+      }
+      evb = ev_used_;
+      ev_used_ += 4;
+      ev_marks_.push_back({0, evb});
+      hipEventRecord(ev_[evb], st);
+    }
+    launch_sweep_tile(P_, sweep_blocks, st, g, q);
+    if (timed) hipEventRecord(ev_[evb + 1], st);
+    launch_sweep_tile(64, sweep_blocks, st, g, qw);
+    if (timed) hipEventRecord(ev_[evb + 2], st);
+    launch_sweep_block(block_blocks, st, g, q);
+    if (timed) hipEventRecord(ev_[evb + 3], st);
+    launch_sweep_control(st, q.qout_cnt, &misc->rwork, &misc->rwork_at_gr, budget_, &misc->halt[0]);
+  }
+}
+
+int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err) {
+  if (resident_ == 0) return 0;
+  MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+  // tiers from the resident graphs' mean row length (measured: 4 lanes for
+  // the grid cut, 16 for R-MAT)
+  const double mean_row = resident_V_ > 0 ? (double)resident_M_ / (double)resident_V_ : 1.0;
+  const int P = cfg_.lanes_per_vertex > 0 ? cfg_.lanes_per_vertex : (mean_row <= 10.0 ? 4 : mean_row <= 20.0 ? 8 : 16);
+  const int tm = cfg_.split_degree > 0 ? cfg_.split_degree : 4 * P;
+  const int tb = std::max(tm, cfg_.block_degree > 0 ? cfg_.block_degree : 2048);
+  if (P != P_ || tm != t_mid_ || tb != t_big_) {
+    P_ = P;
+    t_mid_ = tm;
+    t_big_ = tb;
+    bfs_split_ = 8 * P;
+    if (graph_exec_) hipGraphExecDestroy(graph_exec_);
+    if (graph_) hipGraphDestroy(graph_);
+    graph_exec_ = nullptr;
+    graph_ = nullptr;
+  }
+  acc_.lanes = P_;
+  acc_.split_degree = t_mid_;
+  acc_.block_degree = t_big_;
+  // roots / excluded terminals of every resident instance for its phase
+  int32_t *hroots = reinterpret_cast<int32_t *>(pin_ + kPinnedHeader + sizeof(InstDev) * (size_t)ncap_ * kListKinds +
+                                                4 * (size_t)ncap_);
+  int32_t *hrh = hroots + ncap_;
+  int32_t *hex = hrh + ncap_;
+  int nr = 0, sink = -1;
+  for (int i = 0; i < ncap_; i++) {
+    const Inst &I = inst_[i];
+    if (!I.used || I.phase >= 3) continue;
+    hroots[nr] = I.phase == 1 ? I.t : I.s;
+    hrh[nr] = HCAP - I.V;
+    hex[nr] = I.phase == 1 ? I.s : I.t;
+    nr++;
+  }
+  if (nr == 1) sink = hroots[0];
+  const double beta = cfg_.gr_work_permille > 0 ? cfg_.gr_work_permille / 1000.0 : gr_beta_env();
+  long long *hmisc = reinterpret_cast<long long *>(pin_ + 512);
+  hmisc[0] = sink;
+  hmisc[1] = cfg_.gr_every_sweeps > 0 ? (1LL << 62) : (long long)(beta * (double)(resident_V_ + resident_M_));
+  hipMemcpyAsync(roots_, hroots, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(root_h_, hrh, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(excl_, hex, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(sink_, &hmisc[0], 4, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(budget_, &hmisc[1], 8, hipMemcpyHostToDevice, st);
+  hipMemsetAsync(misc->status, 0, sizeof(misc->status), st);
+  hipMemsetAsync(inst_active_, 0, 4 * (size_t)ncap_, st);
+  hipMemsetAsync(inst_stranded_, 0, 4 * (size_t)ncap_, st);
+
+  // the relabel visits vertices up to the end of the highest resident group
+  // (free vertices below it are inactive with empty rows)
+  int64_t vhi = 0;
+  for (const Group &G : groups_)
+    if (G.used) vhi = std::max<int64_t>(vhi, (int64_t)G.vbase + G.V);
+  Graph g{(int32_t)vhi, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_};
+  GRArgs ga;
+  ga.g = g;
+  ga.roots = roots_;
+  ga.root_h = root_h_;
+  ga.nroots = nr;
+  ga.excl = excl_;
+  ga.nexcl = nr;
+  ga.inst_of = inst_of_;
+  ga.inst_active = inst_active_;
+  ga.inst_stranded = inst_stranded_;
+  ga.fq[0] = fq_[0];
+  ga.fq[1] = fq_[1];
+  ga.fcnt = misc->fcnt;
+  ga.vis = vis_;
+  ga.chunk_w = chunk_w_;
+  ga.chunk_b = chunk_b_;
+  ga.chunk_cnt = misc->chunk_cnt;
+  ga.bucnt = misc->bucnt;
+  ga.fedges = misc->fedges;
+  ga.bar = misc->bar;
+  ga.qout = q_[0];
+  ga.qcnt = misc->qcnt;
+  ga.big_cnt = misc->big_cnt;
+  ga.mid_cnt = misc->mid_cnt;
+  ga.stats = misc->stats;
+  ga.status = misc->status;
+  ga.split_deg = bfs_split_;
+  ga.chunk = chunk_;
+  ga.qcap = (int32_t)Vcap_;
+  ga.chunk_cap = (int32_t)std::min<int64_t>(nchunk_, 0x7fffffff);
+  ga.bu_threshold = (int32_t)std::max<int64_t>(resident_V_ / 32, 4096);
+  ga.bu_edges = std::max<long long>(resident_M_ / 16, 65536);
+  ga.err = misc->err;
+  ga.halt = misc->halt;
+  ga.rwork = &misc->rwork;
+  ga.rwork_at_gr = &misc->rwork_at_gr;
+  int lg = 0;
+  while ((1 << lg) < P_) lg++;
+  const int gr_blocks = std::min(gr_blocks_[lg], 1024);
+  acc_.gr_blocks = gr_blocks;
+  if (gr_blocks < 1) {
+    *err = "cooperative launch not possible";
+    return WBPR_EDEVICE;
+  }
+  auto tg0 = std::chrono::steady_clock::now();
+  int evb = -1;
+  if (cfg_.time_kernels) {
+    if (ev_used_ + 2 > (int)ev_.size()) {
+      const size_t old = ev_.size();
+      ev_.resize(old + 1024);
+      for (size_t i = old; i < ev_.size(); i++) hipEventCreate(&ev_[i]);
+    }
+    evb = ev_used_;
+    ev_used_ += 2;
+    ev_marks_.push_back({3, evb});
+    hipEventRecord(ev_[evb], st);
+  }
+  hipError_t he = launch_global_relabel(P_, gr_blocks, st, ga);
+  if (he != hipSuccess) {
+    *err = std::string("global relabel launch: ") + hipGetErrorString(he);
+    return WBPR_EDEVICE;
+  }
+  if (evb >= 0) hipEventRecord(ev_[evb + 1], st);
+  acc_.global_relabels++;
+  // read back: status (4 x i64), err (2 x i32), per-instance counts
+  char *rb = pin_ + 2048;
+  he = hipMemcpyAsync(rb, misc->status, sizeof(misc->status) + sizeof(misc->err), hipMemcpyDeviceToHost, st);
+  int32_t *hact = reinterpret_cast<int32_t *>(pin_ + kPinnedHeader + sizeof(InstDev) * (size_t)ncap_ * kListKinds +
+                                              16 * (size_t)ncap_);
+  int32_t *hstr = hact + ncap_;
+  if (he == hipSuccess) he = hipMemcpyAsync(hact, inst_active_, 4 * (size_t)ncap_, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(hstr, inst_stranded_, 4 * (size_t)ncap_, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipStreamSynchronize(st);
+  if (he != hipSuccess) {
+    *err = std::string("global relabel: ") + hipGetErrorString(he);
+    return WBPR_EDEVICE;
+  }
+  const long long *status = reinterpret_cast<const long long *>(rb);
+  const int32_t *errw = reinterpret_cast<const int32_t *>(rb + sizeof(misc->status));
+  acc_.gr_levels += status[2];
+  if (log_level() > 0) {
+    const double gms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tg0).count();
+    std::fprintf(stderr,
+                 "[wbpr] round %lld: roots=%d active=%lld stranded=%lld bfs_levels=%lld (bottom-up %lld) "
+                 "sweeps+gr+sync=%.3f ms\n",
+                 (long long)acc_.global_relabels, nr, status[0], status[1], status[2], status[3], gms);
+  }
+  if (errw[0] != 0) {
+    *err = "internal queue overflow";
+    return WBPR_EINTERNAL;
+  }
+  // per-instance transitions
+  std::vector<int> fin1, fin2, to2, fin_done;
+  for (int i = 0; i < ncap_; i++) {
+    Inst &I = inst_[i];
+    if (!I.used || I.phase >= 3) continue;
+    if (I.phase == 2 && hstr[i] > 0) {
+      *err = "second phase: excess that cannot return to the source";
+      return WBPR_EINTERNAL;
+    }
+    if (hact[i] != 0) continue;
+    if (I.phase == 1) {
+      fin1.push_back(i);
+      if (I.flow) to2.push_back(i);
+      else fin_done.push_back(i);
+    } else {
+      fin2.push_back(i);
+      fin_done.push_back(i);
+    }
+  }
+  launch_inst_kernel(IK_VALUE_ZERO, fin1, st);
+  launch_inst_kernel(IK_VALUE, fin1, st);
+  launch_inst_kernel(IK_SIDE, fin1, st);
+  launch_inst_kernel(IK_PHASE2, to2, st);
+  launch_inst_kernel(IK_DECODE, fin2, st);
+  for (int i : to2) inst_[i].phase = 2;
+  for (int i : fin_done) inst_[i].phase = 3;
+  // sweeps for the instances still active
+  if (status[0] > 0) {
+    const int K = cfg_.gr_every_sweeps > 0 ? cfg_.gr_every_sweeps : 64;
+    if (cfg_.use_graph && !cfg_.time_kernels) {
+      int rc = ensure_graph(st, err);
+      if (rc) return rc;
+      he = hipGraphLaunch(graph_exec_, st);
+      if (he != hipSuccess) {
+        *err = std::string("graph launch: ") + hipGetErrorString(he);
+        return WBPR_EDEVICE;
+      }
+    } else {
+      enqueue_sweeps(st, K);
+    }
+    acc_.sweeps += K;
+  }
+  he = hipGetLastError();
+  if (he != hipSuccess) {
+    *err = std::string("launch: ") + hipGetErrorString(he);
+    return WBPR_EDEVICE;
+  }
+  // retire finished instances; release groups that have no instance left
+  std::vector<int> empty_groups;
+  for (int i : fin_done) {
+    Inst &I = inst_[i];
+    Group &G = groups_[I.group];
+    done->push_back(Finished{G.tag, I.index, 0});
+    G.remaining--;
+    if (G.remaining == 0) empty_groups.push_back(I.group);
+    I = Inst();
+    slot_free_.push_back(i);
+    resident_--;
+  }
+  release_groups(empty_groups, st);
+  return 0;
+}
+
+int Engine::run_to_completion(hipStream_t st, std::vector<Finished> *done, std::string *err) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t sweeps0 = acc_.sweeps;
+  while (resident_ > 0) {
+    int rc = round(st, done, err);
+    if (rc) return rc;
+    if (cfg_.max_sweeps > 0 && acc_.sweeps - sweeps0 > cfg_.max_sweeps) {
+      *err = "max_sweeps exceeded";
+      return WBPR_ETIMEOUT;
+    }
+    if (cfg_.max_wall_ms > 0 &&
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() > cfg_.max_wall_ms) {
+      *err = "max_wall_ms exceeded";
+      return WBPR_ETIMEOUT;
+    }
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    *err = hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  return 0;
+}
+
+void Engine::abandon(hipStream_t st) {
+  hipStreamSynchronize(st);
+  if (arena_) {
+    hipMemsetAsync(A_.rowb, 0, 8 * (size_t)Vcap_, st);
+    hipMemsetAsync(e_, 0, 8 * (size_t)Vcap_, st);
+    hipMemsetAsync(inst_of_, 0xff, 4 * (size_t)Vcap_, st);
+    hipStreamSynchronize(st);
+  }
+  valloc_.reset(Vcap_);
+  malloc_.reset(Mcap_);
+  aalloc_.reset(Ecap_);
+  slot_free_.clear();
+  for (int32_t i = ncap_ - 1; i >= 0; i--) slot_free_.push_back(i);
+  inst_.assign(ncap_, Inst());
+  groups_.clear();
+  resident_ = 0;
+  resident_V_ = 0;
+  resident_M_ = 0;
+}
+
+void Engine::reset_stats() {
+  acc_ = EngineStats();
+  ev_used_ = 0;
+  ev_marks_.clear();
+  if (misc_) {
+    MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+    hipMemset(misc->stats, 0, sizeof(misc->stats));
+  }
+}
+
+int Engine::collect_stats(hipStream_t st, EngineStats *out, std::string *err) {
+  MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+  long long hs[16];
+  hipError_t e = hipMemcpyAsync(pin_ + 3072, misc->stats, sizeof(hs), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    *err = hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  std::memcpy(hs, pin_ + 3072, sizeof(hs));
+  EngineStats r = acc_;
+  for (int k = 0; k < 3; k++) {
+    r.k_scans[k] = hs[4 * k + 0];
+    r.k_pushes[k] = hs[4 * k + 1];
+    r.k_relabels[k] = hs[4 * k + 2];
+    r.k_queued[k] = hs[4 * k + 3];
+    r.arc_scans += r.k_scans[k];
+    r.pushes += r.k_pushes[k];
+    r.relabels += r.k_relabels[k];
+    r.queued += r.k_queued[k];
+  }
+  r.k_scans[3] = hs[12] + hs[14];
+  r.bfs_scans = hs[12] + hs[14];
+  r.bfs_topdown_scans = hs[12];
+  r.nonempty_sweeps = hs[13];
+  for (const auto &mk : ev_marks_) {
+    if (mk.first == 3) {
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, ev_[mk.second], ev_[mk.second + 1]) == hipSuccess) r.k_ms[3] += ms;
+      r.k_launches[3]++;
+    } else {
+      for (int k = 0; k < 3; k++) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, ev_[mk.second + k], ev_[mk.second + k + 1]) == hipSuccess) r.k_ms[k] += ms;
+        r.k_launches[k]++;
+      }
+    }
+  }
+  *out = r;
+  return 0;
+}
+
+}  // namespace wb

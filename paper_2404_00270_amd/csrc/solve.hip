@@ -37,43 +37,11 @@
 
 #include "wb_common.h"
 #include "wb_internal.h"
-#include "wb_solver.h"
+#include "wb_kernels.h"
 
 namespace wb {
 
-struct Graph {
-  int32_t V;
-  int32_t hcap;
-  const int32_t *rptr;
-  int2 *ent;
-  const int32_t *rev;
-  long long *e;
-  int32_t *h;
-  int32_t sink;  // target of the current phase: its excess is never read, so
-                 // pushes into it skip the excess atomic (-1: none skipped)
-};
 
-struct SweepQ {
-  const int32_t *qin;
-  const int32_t *qin_cnt;
-  int32_t *qout;
-  int32_t *qout_cnt;
-  int32_t *zero_cnt;
-  int32_t *mid_v;       // medium rows deferred to the one-wave tier
-  int32_t *mid_cnt;
-  int32_t *big_v;       // long rows deferred to the workgroup tier
-  int32_t *big_cnt;
-  int32_t *zero_a;      // counters to clear for the next sweep (nullable)
-  int32_t *zero_b;
-  int32_t t_mid;        // rows longer than this go to the one-wave tier
-  int32_t t_big;        // rows longer than this go to the workgroup tier
-  long long *stats;     // per kernel k (0 tile, 1 wave, 2 workgroup): [4k] arc scans, [4k+1] pushes,
-                        // [4k+2] relabels, [4k+3] queued; [12] bfs scans; [13] nonempty sweeps
-  int32_t qcap;      // capacity of every queue and of the long-row list (V)
-  int32_t *err;      // overflow counter (must stay 0)
-  int32_t mode;      // 0: one push to the minimum-height neighbour (Algorithms 1-2)
-                     // 1: full discharge (push along every lower residual arc, then relabel)
-};
 
 // Pushes d along residual entry k of row u into v: the four atomic updates
 // of Algorithm 1 except the decrement of e(u), which the caller applies once
@@ -82,23 +50,36 @@ struct SweepQ {
 __device__ __forceinline__ bool push_entry(const Graph &g, int32_t k, int32_t v, long long d) {
   atomic_add_i32(&g.ent[k].y, -(int32_t)d);
   atomic_add_i32(&g.ent[g.rev[k]].y, (int32_t)d);
-  if (v == g.sink) return false;
+  if (v == *g.sink) return false;
   long long oldv = atomic_add_i64(&g.e[v], d);
   return oldv <= 0 && oldv + d > 0;
 }
 
-__device__ __forceinline__ void flush_stats(long long *stats, long long scans, int pushes, int relabels, long long queued) {
+__device__ __forceinline__ void flush_stats(long long *stats, long long scans, int pushes, int relabels, long long queued,
+                                            long long *rwork_ctr, long long rwork) {
   // one atomic per wave and counter
   scans = (long long)group_sum_i64<WB_WAVE>(scans);
   long long p = group_sum_i64<WB_WAVE>((long long)pushes);
   long long r = group_sum_i64<WB_WAVE>((long long)relabels);
   queued = group_sum_i64<WB_WAVE>(queued);
+  rwork = group_sum_i64<WB_WAVE>(rwork);
   if (lane() == 0) {
     if (scans) atomic_add_i64(&stats[0], scans);
     if (p) atomic_add_i64(&stats[1], p);
     if (r) atomic_add_i64(&stats[2], r);
     if (queued) atomic_add_i64(&stats[3], queued);
+    if (rwork) atomic_add_i64(rwork_ctr, rwork);
   }
+}
+
+// End of a sweep (one thread): stop the rest of this round's sweeps once the
+// queue is empty or the relabelling done since the last global relabel has
+// scanned more than `budget` entries (then fresh exact heights are worth a
+// global relabel).  The flag is read at entry by the next sweeps' kernels,
+// so every workgroup of a kernel sees the same decision.
+__global__ void k_sweep_control(const int32_t *qout_cnt, const long long *rwork, const long long *rwork_at_gr,
+                                const long long *budget, int32_t *halt) {
+  if (*qout_cnt == 0 || *rwork - *rwork_at_gr > *budget) *halt = 1;
 }
 
 template <int P>
@@ -124,7 +105,6 @@ __device__ __forceinline__ long long group_excl_scan_i64(long long x, long long 
   return incl - x;
 }
 
-constexpr int SWEEP_THREADS = 256;
 
 // One visit of a queued vertex by a tile of P lanes (rows up to
 // split_degree).  Paper mode: the tile reduces the packed key
@@ -152,6 +132,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
   const bool defers = q.t_mid != 0x7fffffff;
   const WaveQ wmid{s_mbuf[wl], &s_qcnt[wl][1], q.mid_v, q.mid_cnt, q.qcap, q.err, DEFER_BUF};
   const WaveQ wbig{s_bbuf[wl], &s_qcnt[wl][2], q.big_v, q.big_cnt, q.qcap, q.err, DEFER_BUF};
+  if (*q.halt) return;
   if (blockIdx.x == 0 && threadIdx.x == 0 && q.zero_cnt) {
     *q.zero_cnt = 0;
     *q.zero_a = 0;
@@ -166,7 +147,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
   const int sub = lane() / P;
   const int tl = lane() % P;
   const int tbase = lane() & ~(P - 1);
-  long long scans = 0, queued = 0;
+  long long scans = 0, queued = 0, rwork = 0;
   int pushes = 0, relabels = 0;
   for (int32_t base = wave * TPW; base < n; base += nwaves * TPW) {  // wave-uniform loop
     const int32_t i = base + sub;
@@ -174,8 +155,9 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
     int32_t u = 0, beg = 0, end = 0;
     if (valid) {
       u = q.qin[i];
-      beg = g.rptr[u];
-      end = g.rptr[u + 1];
+      const int2 rb = g.rowb[u];
+      beg = rb.x;
+      end = rb.y;
     }
     const int32_t deg = end - beg;
     const bool split = valid && deg > q.t_mid;
@@ -225,6 +207,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
             if (nh > g.hcap) nh = g.hcap;
             g.h[u] = nh;
             relabels++;
+            rwork += deg;
             app_u = nh < g.hcap;
           }
         }
@@ -285,6 +268,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
             if (nh > g.hcap) nh = g.hcap;
             g.h[u] = nh;
             relabels++;
+            rwork += deg;
             app_u = nh < g.hcap;
           }
         } else {
@@ -299,10 +283,9 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
     waveq_flush(wmid);
     waveq_flush(wbig);
   }
-  flush_stats(q.stats, scans, pushes, relabels, queued);
+  flush_stats(q.stats, scans, pushes, relabels, queued, q.rwork, rwork);
 }
 
-constexpr int BLK = 256;
 constexpr int BLK_WAVES = BLK / WB_WAVE;
 
 // Long rows: one workgroup per queued vertex, same two modes as the tile
@@ -313,15 +296,17 @@ __global__ void __launch_bounds__(BLK) k_sweep_block(Graph g, SweepQ q) {
   __shared__ long long s_wsum[BLK_WAVES];
   __shared__ unsigned long long s_wmin[BLK_WAVES];
   __shared__ long long s_e0;
+  if (*q.halt) return;
   const int32_t nbig = min(*q.big_cnt, q.qcap);
   const int w = threadIdx.x / WB_WAVE;
   if (lane() == 0) s_qcnt[w] = 0;
   const WaveQ wq{s_qbuf[w], &s_qcnt[w], q.qout, q.qout_cnt, q.qcap, q.err};
-  long long scans = 0, queued = 0;
+  long long scans = 0, queued = 0, rwork = 0;
   int pushes = 0, relabels = 0;
   for (int32_t idx = blockIdx.x; idx < nbig; idx += gridDim.x) {
     const int32_t u = q.big_v[idx];
-    const int32_t beg = g.rptr[u], end = g.rptr[u + 1];
+    const int2 rb = g.rowb[u];
+    const int32_t beg = rb.x, end = rb.y;
     const int32_t hu = g.h[u];
     if (threadIdx.x == 0) s_e0 = atomic_load_i64(&g.e[u]);
     __syncthreads();
@@ -406,6 +391,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_block(Graph g, SweepQ q) {
             if (nh > g.hcap) nh = g.hcap;
             g.h[u] = nh;
             relabels++;
+            rwork += end - beg;
             app_u = nh < g.hcap;
           }
         }
@@ -421,6 +407,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_block(Graph g, SweepQ q) {
             if (nh > g.hcap) nh = g.hcap;
             g.h[u] = nh;
             relabels++;
+            rwork += end - beg;
             app_u = nh < g.hcap;
           }
         } else {
@@ -435,36 +422,25 @@ __global__ void __launch_bounds__(BLK) k_sweep_block(Graph g, SweepQ q) {
     __syncthreads();
   }
   waveq_flush(wq);
-  flush_stats(q.stats + 8, scans, pushes, relabels, queued);
+  flush_stats(q.stats + 8, scans, pushes, relabels, queued, q.rwork, rwork);
 }
 
 // ------------------------------------------------------ global relabel
-struct GRArgs {
-  Graph g;
-  int32_t root, excl, root_h;
-  int32_t *fq[2];
-  int32_t *fcnt;      // [3] rotating frontier counters
-  uint8_t *vis;       // [V] 0 unvisited, 1/2 labelled at even/odd distance, 3 excluded
-  int32_t *chunk_w;   // long rows: vertex
-  int32_t *chunk_b;   //            first entry of the chunk
-  int32_t *chunk_cnt; // [2]
-  int32_t *bucnt;     // [3] rotating counts of vertices labelled by bottom-up steps
-  long long *fedges;  // [3] rotating row-length sums of the next frontier
-  unsigned *bar;      // barrier state (WB_BAR_WORDS)
-  int32_t *qout;      // active-vertex queue rebuilt at the end
-  int32_t *qcnt;      // [3] sweep counters: [0] = queue length, [1],[2] zeroed
-  int32_t *big_cnt;   // [2] zeroed
-  long long *stats;
-  long long *status;  // [0] active, [1] stranded, [2] levels, [3] bottom-up levels
-  int32_t split_deg, chunk;
-  int32_t qcap;       // capacity of frontiers and queue (V)
-  int32_t chunk_cap;  // capacity of the chunk descriptor arrays
-  int32_t bu_threshold;    // frontier size above which a level runs bottom-up
-  long long bu_edges;      // frontier row-length sum above which a level runs bottom-up
-  int32_t *err;       // overflow counter (must stay 0)
-};
 
 __device__ __forceinline__ uint8_t dist_code(int32_t d) { return (uint8_t)(1 + (d & 1)); }
+
+// counters[key] += number of lanes with pred and that key; one atomic per
+// distinct key in the wave (consecutive vertices mostly share an instance).
+__device__ __forceinline__ void wave_count_by_key(bool pred, int32_t key, int32_t *counters) {
+  unsigned long long m = __ballot(pred);
+  while (m) {
+    const int leader = __ffsll((long long)m) - 1;
+    const int32_t k = __shfl(key, leader, WB_WAVE);
+    const unsigned long long same = __ballot(pred && key == k);
+    if (lane() == leader) atomic_add_i32(&counters[k], __popcll(same));
+    m &= ~same;
+  }
+}
 
 // Global relabel (section 2.2): backward BFS from the root (the sink in the
 // first phase, the source in the second) over residual arcs v -> w with
@@ -477,8 +453,6 @@ __device__ __forceinline__ uint8_t dist_code(int32_t d) { return (uint8_t)(1 + (
 // can only have residual arcs into distance-L vertices during step L (one at
 // distance L-2 would have made it distance L-1), so "code == code(L)" names
 // the frontier exactly.
-constexpr int GR_THREADS = 1024;
-
 template <int P>
 __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   __shared__ int s_qbuf[GR_THREADS / WB_WAVE][WB_QBUF];
@@ -500,8 +474,9 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     g.h[v] = g.hcap;
     a.vis[v] = 0;
   }
+  for (int64_t j = gtid; j < a.nroots; j += nthreads) a.fq[0][j] = a.roots[j];
   if (gtid == 0) {
-    a.fcnt[0] = 1;
+    a.fcnt[0] = a.nroots;
     a.fcnt[1] = 0;
     a.fcnt[2] = 0;
     a.chunk_cnt[0] = 0;
@@ -517,22 +492,23 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     a.qcnt[2] = 0;
     a.big_cnt[0] = 0;
     a.big_cnt[1] = 0;
-    a.fq[0][0] = a.root;
+    a.mid_cnt[0] = 0;
+    a.mid_cnt[1] = 0;
   }
   grid_barrier(a.bar, nblocks);
-  if (gtid == 0) {
-    g.h[a.root] = a.root_h;
-    a.vis[a.root] = dist_code(0);
-    if (a.excl >= 0) {
-      g.h[a.excl] = g.hcap + 1;
-      a.vis[a.excl] = 3;
-    }
+  for (int64_t j = gtid; j < a.nroots; j += nthreads) {
+    g.h[a.roots[j]] = a.root_h[j];
+    a.vis[a.roots[j]] = dist_code(0);
+  }
+  for (int64_t j = gtid; j < a.nexcl; j += nthreads) {
+    g.h[a.excl[j]] = g.hcap + 1;
+    a.vis[a.excl[j]] = 3;
   }
   grid_barrier(a.bar, nblocks);
 
   long long bscans = 0, buscans = 0;  // entries examined top-down / bottom-up
   int32_t level = 0, bu_levels = 0;
-  int32_t n = 1;
+  int32_t n = min(a.nroots, a.qcap);
   long long nedges = 0;  // row-length sum of the current frontier (0: the root alone)
   bool queue_valid = true;  // the frontier of this level is in fq[level & 1]
   for (;;) {
@@ -560,8 +536,9 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         bool mine = v < g.V && a.vis[v] == 0;
         int32_t beg = 0, end = 0;
         if (mine) {
-          beg = g.rptr[v];
-          end = g.rptr[v + 1];
+          const int2 rb = g.rowb[v];
+          beg = rb.x;
+          end = rb.y;
         }
         if (mine && end - beg > a.split_deg) {
           mine = false;
@@ -617,7 +594,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
       for (int32_t c = wave; c < nc; c += nwaves) {
         const int32_t v = a.chunk_w[c];
         const int32_t cb = a.chunk_b[c];
-        const int32_t ce = min(cb + a.chunk, g.rptr[v + 1]);
+        const int32_t ce = min(cb + a.chunk, g.rowb[v].y);
         if (lane() == 0) buscans += ce - cb;
         for (int32_t kb = cb; kb < ce; kb += WB_WAVE) {
           const int32_t k = kb + lane();
@@ -634,7 +611,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
               if (atomicCAS(&g.h[v], g.hcap, g.h[w] + 1) == g.hcap) {
                 a.vis[v] = nxt;
                 found_cnt++;
-                my_edges += g.rptr[v + 1] - g.rptr[v];
+                my_edges += (g.rowb[v].y - g.rowb[v].x);
               }
             }
             break;
@@ -673,7 +650,8 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         const int32_t i = base + sub;
         if (i < n) {
           const int32_t w = fin[i];
-          const int32_t beg = g.rptr[w], end = g.rptr[w + 1];
+          const int2 rb = g.rowb[w];
+          const int32_t beg = rb.x, end = rb.y;
           const int32_t deg = end - beg;
           if (deg > a.split_deg) {
             if (tl == 0) {
@@ -698,7 +676,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
                 claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
                 if (claimed) {
                   a.vis[v] = nxt;
-                  my_edges += g.rptr[v + 1] - g.rptr[v];
+                  my_edges += (g.rowb[v].y - g.rowb[v].x);
                 }
               }
               waveq_push(wq, claimed, v);
@@ -717,7 +695,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
       for (int32_t c = wave; c < nc; c += nwaves) {
         const int32_t w = a.chunk_w[c];
         const int32_t cb = a.chunk_b[c];
-        const int32_t ce = min(cb + a.chunk, g.rptr[w + 1]);
+        const int32_t ce = min(cb + a.chunk, g.rowb[w].y);
         const int32_t hw1 = g.h[w] + 1;
         if (lane() == 0) bscans += ce - cb;
         for (int32_t k = cb + lane(); k < ce; k += WB_WAVE) {
@@ -727,7 +705,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
             claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
             if (claimed) {
               a.vis[v] = nxt;
-              my_edges += g.rptr[v + 1] - g.rptr[v];
+              my_edges += (g.rowb[v].y - g.rowb[v].x);
             }
           }
           waveq_push(wq, claimed, v);
@@ -745,19 +723,25 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     }
     level++;
   }
-  // rebuild the active-vertex queue; count excess stranded away from the root
+  // rebuild the active-vertex queue; count, per instance, the active
+  // vertices and the excess stranded away from the root
   int stranded = 0;
   {
     WaveQ wq{s_qbuf[wl], &s_qcnt[wl], a.qout, &a.qcnt[0], a.qcap, a.err};
     for (int64_t v0 = gtid - lane(); v0 < g.V; v0 += nthreads) {  // wave-uniform
       const int64_t v = v0 + lane();
-      bool act = false;
+      bool act = false, str = false;
+      int32_t ins = -1;
       if (v < g.V) {
         const long long ev = g.e[v];
         const int32_t hv = g.h[v];
         act = ev > 0 && hv < g.hcap;
-        stranded += (ev > 0 && hv == g.hcap) ? 1 : 0;
+        str = ev > 0 && hv == g.hcap;
+        if (act || str) ins = a.inst_of[v];
       }
+      stranded += str ? 1 : 0;
+      wave_count_by_key(act && ins >= 0, ins, a.inst_active);
+      wave_count_by_key(str && ins >= 0, ins, a.inst_stranded);
       waveq_push(wq, act, (int32_t)v);
     }
     waveq_flush(wq);
@@ -775,96 +759,12 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     a.status[0] = a.qcnt[0];
     a.status[2] = level;
     a.status[3] = bu_levels;
+    *a.halt = 0;
+    *a.rwork_at_gr = *a.rwork;
   }
 }
 
-// ------------------------------------------------------------ small kernels
-__global__ void k_init(Graph g, int32_t t) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.V; v += (int64_t)gridDim.x * blockDim.x) {
-    g.e[v] = (v == t) ? WB_EXCESS_BIAS : 0;
-    g.h[v] = 0;
-  }
-}
-
-// Preflow (Algorithm 1, step 0): every residual entry of s is saturated.
-__global__ void k_preflow(Graph g, int32_t s) {
-  const int32_t beg = g.rptr[s], end = g.rptr[s + 1];
-  for (int64_t k = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < end;
-       k += (int64_t)gridDim.x * blockDim.x) {
-    const int2 cr = g.ent[k];
-    if (cr.y > 0) {
-      g.ent[k].y = 0;
-      atomic_add_i32(&g.ent[g.rev[k]].y, cr.y);
-      atomic_add_i64(&g.e[cr.x], (long long)cr.y);
-    }
-  }
-}
-
-__global__ void k_add_excess(long long *e, int32_t v, long long d) { e[v] += d; }
-
-__global__ void k_zero_i64(long long *out) { out[0] = 0; }
-
-// Flow value = total flow into t = sum over t's row of (c_f(t,w) - c(t,w)):
-// every push w -> t raised the mate residual c_f(t,w) by the pushed amount
-// and nothing ever pushes out of t, so t's excess need not be tracked.
-__global__ void k_value(Graph g, const int32_t *cap0, int32_t t, long long *out) {
-  __shared__ long long s_part[SWEEP_THREADS / WB_WAVE];
-  const int32_t beg = g.rptr[t], end = g.rptr[t + 1];
-  long long acc = 0;
-  for (int64_t k = beg + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < end;
-       k += (int64_t)gridDim.x * blockDim.x)
-    acc += (long long)g.ent[k].y - (long long)cap0[k];
-  acc = group_sum_i64<WB_WAVE>(acc);
-  if (lane() == 0) s_part[threadIdx.x / WB_WAVE] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    long long tot = 0;
-    for (int i = 0; i < SWEEP_THREADS / WB_WAVE; i++) tot += s_part[i];
-    if (tot) atomic_add_i64(out, tot);
-  }
-}
-
-__global__ void k_cut_side(Graph g, uint8_t *side) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < g.V; v += (int64_t)gridDim.x * blockDim.x)
-    side[v] = g.h[v] < g.hcap ? 1 : 0;
-}
-
-// Per-arc flow from the merged net flow of the ordered pair (u,v): parallel
-// arcs u->v are filled in input order up to their capacities.
-__global__ void k_decode(int64_t E, const int32_t *cap, const int32_t *arc2ent, const int32_t *pbefore,
-                         const int32_t *cap0, const int2 *ent, int32_t *flow) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t j = arc2ent[i];
-    int32_t f = 0;
-    if (j >= 0) {
-      const long long net = (long long)cap0[j] - (long long)ent[j].y;
-      long long x = net - (long long)pbefore[i];
-      if (x < 0) x = 0;
-      if (x > cap[i]) x = cap[i];
-      f = (int32_t)x;
-    }
-    flow[i] = f;
-  }
-}
-
-// ------------------------------------------------------------ host driver
-// WBPR_LOG=1 traces every global-relabel round on stderr.
-static int log_level() {
-  static int lvl = -1;
-  if (lvl < 0) {
-    const char *e = std::getenv("WBPR_LOG");
-    lvl = e ? std::atoi(e) : 0;
-  }
-  return lvl;
-}
-
-static unsigned grid1d(int64_t n, int threads = 256, int64_t maxb = 65536) {
-  int64_t b = (n + threads - 1) / threads;
-  if (b < 1) b = 1;
-  if (b > maxb) b = maxb;
-  return (unsigned)b;
-}
-
+// ------------------------------------------------------------ launchers
 typedef void (*TileFn)(Graph, SweepQ);
 typedef void (*GRFn)(GRArgs);
 
@@ -887,6 +787,25 @@ static GRFn gr_fn(int P) {
   }
 }
 
+void launch_sweep_tile(int P, int blocks, hipStream_t st, const Graph &g, const SweepQ &q) {
+  hipLaunchKernelGGL(tile_fn(P), dim3(blocks), dim3(SWEEP_THREADS), 0, st, g, q);
+}
+
+void launch_sweep_block(int blocks, hipStream_t st, const Graph &g, const SweepQ &q) {
+  hipLaunchKernelGGL(k_sweep_block, dim3(blocks), dim3(BLK), 0, st, g, q);
+}
+
+void launch_sweep_control(hipStream_t st, const int32_t *qout_cnt, const long long *rwork, const long long *rwork_at_gr,
+                          const long long *budget, int32_t *halt) {
+  hipLaunchKernelGGL(k_sweep_control, dim3(1), dim3(1), 0, st, qout_cnt, rwork, rwork_at_gr, budget, halt);
+}
+
+hipError_t launch_global_relabel(int P, int blocks, hipStream_t st, GRArgs &a) {
+  void *args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(gr_fn(P)), dim3(blocks), dim3(GR_THREADS), args, 0,
+                                    st);
+}
+
 int gr_max_blocks(int device, int P) {
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(gr_fn(P)), GR_THREADS,
@@ -897,281 +816,6 @@ int gr_max_blocks(int device, int P) {
   // one workgroup per CU: barrier latency grows with the number of
   // workgroups, and 16 waves per CU keep the BFS gathers in flight
   return std::min(per_cu, 1) * prop.multiProcessorCount;
-}
-
-// Long rows met in one BFS level produce at most M/chunk + (number of long
-// rows) <= M/chunk + V chunk descriptors.
-static int64_t chunk_capacity(int32_t V, int64_t Mcap, int chunk) { return Mcap / chunk + V + 16; }
-
-size_t state_bytes(int32_t V, int64_t Mcap, int chunk) {
-  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  int64_t nchunk = chunk_capacity(V, Mcap, chunk);
-  return al(8ull * V) + al(4ull * V) * 7 + al((size_t)V) + al(4ull * nchunk) * 2 + al(4096);
-}
-
-void state_carve(State *s, int32_t V, int64_t Mcap, int chunk, void *mem) {
-  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-  char *p = (char *)mem;
-  int64_t nchunk = chunk_capacity(V, Mcap, chunk);
-  s->e = (long long *)p; p += al(8ull * V);
-  s->h = (int32_t *)p; p += al(4ull * V);
-  s->q[0] = (int32_t *)p; p += al(4ull * V);
-  s->q[1] = (int32_t *)p; p += al(4ull * V);
-  s->fq[0] = (int32_t *)p; p += al(4ull * V);
-  s->fq[1] = (int32_t *)p; p += al(4ull * V);
-  s->big_v = (int32_t *)p; p += al(4ull * V);
-  s->mid_v = (int32_t *)p; p += al(4ull * V);
-  s->vis = (uint8_t *)p; p += al((size_t)V);
-  s->chunk_w = (int32_t *)p; p += al(4ull * nchunk);
-  s->chunk_b = (int32_t *)p; p += al(4ull * nchunk);
-  s->misc = (long long *)p;  // 4 KB of counters
-  s->nchunk_cap = nchunk;
-}
-
-namespace {
-struct MiscLayout {
-  long long stats[16];
-  long long status[4];
-  int32_t err[2];
-  int32_t big_cnt[2];
-  int32_t mid_cnt[2];
-  int32_t bucnt[4];
-  int32_t qcnt[4];
-  int32_t fcnt[4];
-  int32_t chunk_cnt[2];
-  unsigned bar[WB_BAR_WORDS];
-  long long fedges[4];
-};
-}  // namespace
-
-size_t misc_bytes() { return sizeof(MiscLayout); }
-
-static int pick_lanes(const SolveConfig &cfg, int32_t V, int64_t M) {
-  if (cfg.lanes_per_vertex) return cfg.lanes_per_vertex;
-  double avg = V > 0 ? (double)M / (double)V : 1.0;
-  int P = 4;
-  while (P < 64 && P < avg) P <<= 1;
-  return P;
-}
-
-// Runs one phase (sink = root) to completion.  Returns 0 or a wbpr status.
-struct Tiers {
-  int P;           // lanes per short row
-  int32_t t_mid;   // rows longer than this: one wave each
-  int32_t t_big;   // rows longer than this: one workgroup each
-  int32_t bfs_split, chunk;
-};
-
-static int run_phase(const SolveConfig &cfg, const Residual &res, State &S, int32_t root, int32_t excl,
-                     const Tiers &tiers, int gr_blocks, hipStream_t st, long long *pinned, PhaseStats *ps,
-                     bool second_phase, std::string *err) {
-  MiscLayout *misc = reinterpret_cast<MiscLayout *>(S.misc);
-  Graph g{res.V, res.V, res.rptr, res.ent, res.rev, S.e, S.h, root};
-  GRArgs ga;
-  ga.g = g;
-  ga.root = root;
-  ga.excl = excl;
-  ga.root_h = 0;
-  ga.fq[0] = S.fq[0];
-  ga.fq[1] = S.fq[1];
-  ga.fcnt = misc->fcnt;
-  ga.chunk_w = S.chunk_w;
-  ga.chunk_b = S.chunk_b;
-  ga.chunk_cnt = misc->chunk_cnt;
-  ga.bar = misc->bar;
-  ga.qout = S.q[0];
-  ga.qcnt = misc->qcnt;
-  ga.big_cnt = misc->big_cnt;
-  ga.stats = misc->stats;
-  ga.status = misc->status;
-  ga.split_deg = tiers.bfs_split;
-  ga.chunk = tiers.chunk;
-  ga.vis = S.vis;
-  ga.bucnt = misc->bucnt;
-  ga.bu_threshold = std::max<int32_t>(res.V / 32, 4096);
-  ga.bu_edges = std::max<long long>(res.M / 16, 65536);
-  ga.fedges = misc->fedges;
-  ga.qcap = res.V;
-  ga.chunk_cap = (int32_t)std::min<int64_t>(S.nchunk_cap, 0x7fffffff);
-  ga.err = misc->err;
-  TileFn tfn = tile_fn(tiers.P);
-  TileFn wfn = tile_fn(64);
-  GRFn gfn = gr_fn(tiers.P);
-  const int K = cfg.gr_every_sweeps > 0 ? cfg.gr_every_sweeps : 16;
-  const int sweep_blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : 1024;
-  const int block_blocks = 512;
-  const int mode = cfg.push_mode == 1 ? 0 : 1;
-  auto t0 = std::chrono::steady_clock::now();
-  for (;;) {
-    hipError_t he = hipMemsetAsync(misc->status, 0, sizeof(misc->status), st);
-    if (he != hipSuccess) { *err = hipGetErrorString(he); return 5; }
-    void *args[] = {&ga};
-    auto tg0 = std::chrono::steady_clock::now();
-    const bool time_gr = cfg.time_kernels && S.gev_count < State::kMaxGR;
-    if (time_gr) hipEventRecord(S.gev[S.gev_count][0], st);
-    he = hipLaunchCooperativeKernel(reinterpret_cast<const void *>(gfn), dim3(gr_blocks), dim3(GR_THREADS), args, 0,
-                                    st);
-    if (he != hipSuccess) { *err = std::string("global relabel launch: ") + hipGetErrorString(he); return 5; }
-    if (time_gr) hipEventRecord(S.gev[S.gev_count++][1], st);
-    ps->global_relabels++;
-    he = hipMemcpyAsync(pinned, misc->status, sizeof(misc->status) + sizeof(misc->err), hipMemcpyDeviceToHost, st);
-    if (he == hipSuccess) he = hipStreamSynchronize(st);
-    if (he != hipSuccess) { *err = std::string("global relabel: ") + hipGetErrorString(he); return 5; }
-    const long long active = pinned[0];
-    const long long stranded = pinned[1];
-    ps->gr_levels += pinned[2];
-    if (log_level() > 0) {
-      double gms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tg0).count();
-      std::fprintf(stderr,
-                   "[wbpr] phase %d round %lld: active=%lld stranded=%lld bfs_levels=%lld (bottom-up %lld) "
-                   "gr+sync=%.3f ms sweeps so far=%lld\n",
-                   second_phase ? 2 : 1, (long long)ps->global_relabels, active, stranded, pinned[2], pinned[3], gms,
-                   (long long)ps->sweeps);
-    }
-    const int32_t *errw = reinterpret_cast<const int32_t *>(&pinned[4]);
-    if (errw[0] != 0) {
-      *err = "internal queue overflow";
-      return 8;
-    }
-    if (second_phase && stranded > 0) {
-      *err = "second phase: excess that cannot return to the source";
-      return 8;
-    }
-    if (active == 0) break;
-    if (cfg.max_sweeps > 0 && ps->sweeps >= cfg.max_sweeps) { *err = "max_sweeps exceeded"; return 4; }
-    if (cfg.max_wall_ms > 0) {
-      double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-      if (ms > cfg.max_wall_ms) { *err = "max_wall_ms exceeded"; return 4; }
-    }
-    for (int j = 0; j < K; j++) {
-      // short rows: tiles of P lanes; medium and long rows are deferred
-      SweepQ q;
-      q.qin = S.q[j & 1];
-      q.qin_cnt = &misc->qcnt[j % 3];
-      q.qout = S.q[(j + 1) & 1];
-      q.qout_cnt = &misc->qcnt[(j + 1) % 3];
-      q.zero_cnt = &misc->qcnt[(j + 2) % 3];
-      q.mid_v = S.mid_v;
-      q.mid_cnt = &misc->mid_cnt[j & 1];
-      q.big_v = S.big_v;
-      q.big_cnt = &misc->big_cnt[j & 1];
-      q.zero_a = &misc->mid_cnt[(j + 1) & 1];
-      q.zero_b = &misc->big_cnt[(j + 1) & 1];
-      q.t_mid = tiers.t_mid;
-      q.t_big = tiers.t_big;
-      q.mode = mode;
-      q.stats = misc->stats;
-      q.qcap = res.V;
-      q.err = misc->err;
-      // medium rows: one wave each, nothing deferred further
-      SweepQ qw = q;
-      qw.qin = S.mid_v;
-      qw.qin_cnt = &misc->mid_cnt[j & 1];
-      qw.zero_cnt = nullptr;
-      qw.t_mid = 0x7fffffff;
-      qw.t_big = 0x7fffffff;
-      qw.stats = misc->stats + 4;
-      const bool timed = cfg.time_kernels && S.ev_count < State::kMaxSweeps;
-      hipEvent_t *ev = timed ? S.ev[S.ev_count++] : nullptr;
-      if (timed) hipEventRecord(ev[0], st);
-      hipLaunchKernelGGL(tfn, dim3(sweep_blocks), dim3(SWEEP_THREADS), 0, st, g, q);
-      if (timed) hipEventRecord(ev[1], st);
-      hipLaunchKernelGGL(wfn, dim3(sweep_blocks), dim3(SWEEP_THREADS), 0, st, g, qw);
-      if (timed) hipEventRecord(ev[2], st);
-      hipLaunchKernelGGL(k_sweep_block, dim3(block_blocks), dim3(BLK), 0, st, g, q);
-      if (timed) hipEventRecord(ev[3], st);
-      ps->sweeps++;
-    }
-    he = hipGetLastError();
-    if (he != hipSuccess) { *err = std::string("sweep launch: ") + hipGetErrorString(he); return 5; }
-  }
-  return 0;
-}
-
-int solve_on_device(const SolveConfig &cfg, const Residual &res, State &S, int32_t s, int32_t t, const int *gr_blocks_tab,
-                    hipStream_t st, long long *pinned, int64_t *dev_value, int32_t *dev_flow, uint8_t *dev_side,
-                    const int32_t *dev_cap, SolveReport *rep, std::string *err) {
-  Tiers tiers;
-  tiers.P = cfg.lanes_per_vertex > 0 ? cfg.lanes_per_vertex : 8;
-  tiers.t_mid = cfg.split_degree > 0 ? cfg.split_degree : 4 * tiers.P;
-  tiers.t_big = cfg.block_degree > 0 ? cfg.block_degree : std::max<int32_t>(tiers.t_mid, 2048);
-  if (tiers.t_big < tiers.t_mid) tiers.t_big = tiers.t_mid;
-  tiers.bfs_split = 8 * tiers.P;
-  tiers.chunk = 1024;
-  int lg = 0;
-  while ((1 << lg) < tiers.P) lg++;
-  const int gr_blocks = std::min(gr_blocks_tab[lg], 1024);
-  if (gr_blocks < 1) { *err = "cooperative launch not possible"; return 5; }
-  rep->lanes = tiers.P;
-  rep->split_degree = tiers.t_mid;
-  rep->block_degree = tiers.t_big;
-  rep->gr_blocks = gr_blocks;
-  MiscLayout *misc = reinterpret_cast<MiscLayout *>(S.misc);
-  Graph g{res.V, res.V, res.rptr, res.ent, res.rev, S.e, S.h, -1};
-  hipMemsetAsync(S.misc, 0, sizeof(MiscLayout), st);
-  hipLaunchKernelGGL(k_init, dim3(grid1d(res.V)), dim3(256), 0, st, g, t);
-  hipLaunchKernelGGL(k_preflow, dim3(grid1d(res.M > 0 ? res.M : 1, 256, 4096)), dim3(256), 0, st, g, s);
-  auto t0 = std::chrono::steady_clock::now();
-  PhaseStats p1{}, p2{};
-  int rc = run_phase(cfg, res, S, t, s, tiers, gr_blocks, st, pinned, &p1, false, err);
-  if (rc) return rc;
-  hipLaunchKernelGGL(k_zero_i64, dim3(1), dim3(1), 0, st, (long long *)dev_value);
-  hipLaunchKernelGGL(k_value, dim3(256), dim3(SWEEP_THREADS), 0, st, g, res.cap0, t, (long long *)dev_value);
-  if (dev_side) hipLaunchKernelGGL(k_cut_side, dim3(grid1d(res.V)), dim3(256), 0, st, g, dev_side);
-  hipError_t he = hipStreamSynchronize(st);
-  if (he != hipSuccess) { *err = hipGetErrorString(he); return 5; }
-  auto t1 = std::chrono::steady_clock::now();
-  if (dev_flow) {
-    // second phase: return the excess stranded in the source side to s
-    hipLaunchKernelGGL(k_add_excess, dim3(1), dim3(1), 0, st, S.e, s, (long long)WB_EXCESS_BIAS);
-    rc = run_phase(cfg, res, S, s, t, tiers, gr_blocks, st, pinned, &p2, true, err);
-    if (rc) return rc;
-    auto t2 = std::chrono::steady_clock::now();
-    hipLaunchKernelGGL(k_decode, dim3(grid1d(res.E > 0 ? res.E : 1)), dim3(256), 0, st, res.E, dev_cap, res.arc2ent,
-                       res.pbefore, res.cap0, res.ent, dev_flow);
-    he = hipStreamSynchronize(st);
-    if (he != hipSuccess) { *err = hipGetErrorString(he); return 5; }
-    auto t3 = std::chrono::steady_clock::now();
-    rep->ms_phase2 = std::chrono::duration<double, std::milli>(t2 - t1).count();
-    rep->ms_decode = std::chrono::duration<double, std::milli>(t3 - t2).count();
-  }
-  rep->ms_phase1 = std::chrono::duration<double, std::milli>(t1 - t0).count();
-  he = hipMemcpyAsync(pinned, misc->stats, sizeof(misc->stats), hipMemcpyDeviceToHost, st);
-  if (he == hipSuccess) he = hipStreamSynchronize(st);
-  if (he != hipSuccess) { *err = hipGetErrorString(he); return 5; }
-  for (int k = 0; k < 3; k++) {
-    rep->k_scans[k] = pinned[4 * k + 0];
-    rep->k_pushes[k] = pinned[4 * k + 1];
-    rep->k_relabels[k] = pinned[4 * k + 2];
-    rep->k_queued[k] = pinned[4 * k + 3];
-    rep->arc_scans += rep->k_scans[k];
-    rep->pushes += rep->k_pushes[k];
-    rep->relabels += rep->k_relabels[k];
-    rep->queued += rep->k_queued[k];
-  }
-  rep->k_scans[3] = pinned[12] + pinned[14];
-  rep->bfs_topdown_scans = pinned[12];
-  rep->bfs_scans = pinned[12] + pinned[14];
-  rep->nonempty_sweeps = pinned[13];
-  rep->sweeps = p1.sweeps + p2.sweeps;
-  rep->phase2_sweeps = p2.sweeps;
-  rep->global_relabels = p1.global_relabels + p2.global_relabels;
-  rep->gr_levels = p1.gr_levels + p2.gr_levels;
-  if (cfg.time_kernels) {
-    for (int i = 0; i < S.ev_count; i++) {
-      for (int k = 0; k < 3; k++) {
-        float ms = 0;
-        if (hipEventElapsedTime(&ms, S.ev[i][k], S.ev[i][k + 1]) == hipSuccess) rep->k_ms[k] += ms;
-      }
-    }
-    for (int i = 0; i < S.gev_count; i++) {
-      float ms = 0;
-      if (hipEventElapsedTime(&ms, S.gev[i][0], S.gev[i][1]) == hipSuccess) rep->k_ms[3] += ms;
-    }
-    rep->k_launches[0] = rep->k_launches[1] = rep->k_launches[2] = S.ev_count;
-    rep->k_launches[3] = S.gev_count;
-  }
-  return 0;
 }
 
 }  // namespace wb

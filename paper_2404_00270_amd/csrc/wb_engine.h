@@ -1,0 +1,207 @@
+// Host engine: many max-flow instances resident in one device arena, solved
+// together (their residual graphs form a disjoint union, so one sweep and one
+// global relabel serve all of them).  A single solve is an engine holding one
+// instance; a batch admits many at once; the server admits new instances
+// between rounds while others are still running.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "wb_internal.h"
+#include "wb_kernels.h"
+
+namespace wb {
+
+struct SolveConfig {
+  int lanes_per_vertex = 0;   // 0: from the mean row length
+  int split_degree = 0;       // rows longer than this go to the one-wave tier (0: 4 * lanes)
+  int block_degree = 0;       // rows longer than this go to the workgroup tier (0: 2048)
+  int gr_every_sweeps = 0;    // fixed sweeps per round (0: adaptive, at most 64)
+  int gr_work_permille = 0;   // adaptive relabel budget in thousandths of V + M (0: 1000)
+  int64_t max_sweeps = 0;
+  int max_wall_ms = 0;
+  int grid_blocks = 0;        // workgroups per sweep launch (0: 1024)
+  bool time_kernels = false;  // bracket every sweep / relabel launch with events
+  int push_mode = 0;          // 1: single push to the lowest neighbour; 0/2: full discharge
+  bool use_graph = true;      // replay the sweep batch as a captured hipGraph
+};
+
+// Counters of the engine since the last reset_stats().
+struct EngineStats {
+  int lanes = 0, split_degree = 0, block_degree = 0, gr_blocks = 0;
+  int64_t sweeps = 0, phase2_sweeps = 0, global_relabels = 0, gr_levels = 0;
+  int64_t arc_scans = 0, pushes = 0, relabels = 0, queued = 0, bfs_scans = 0, bfs_topdown_scans = 0;
+  int64_t nonempty_sweeps = 0;
+  // per kernel: 0 short-row tiles, 1 medium rows (one wave), 2 long rows (workgroup), 3 global relabel
+  double k_ms[4] = {0, 0, 0, 0};
+  int64_t k_launches[4] = {0, 0, 0, 0};
+  int64_t k_scans[4] = {0, 0, 0, 0}, k_pushes[4] = {0, 0, 0, 0}, k_relabels[4] = {0, 0, 0, 0},
+          k_queued[4] = {0, 0, 0, 0};
+};
+
+// One admission group: n instances whose local CSRs are packed back to back
+// in device memory (instance i: V_i + 1 row pointers, E_i columns and
+// capacities, local vertex ids).  Outputs are device pointers packed the same
+// way (values [n], flows [sum E], sides [sum V]); null = not wanted.
+struct GroupInput {
+  int32_t n = 0;
+  const int32_t *V = nullptr;   // host [n]
+  const int64_t *E = nullptr;   // host [n]
+  const int32_t *s = nullptr;   // host [n], local ids
+  const int32_t *t = nullptr;   // host [n], local ids
+  const int64_t *row_ptr = nullptr;  // device, sum(V_i + 1)
+  const int32_t *col = nullptr;      // device, sum E_i
+  const int32_t *cap = nullptr;      // device, sum E_i
+  int64_t *values = nullptr;         // device [n]
+  int32_t *flows = nullptr;          // device [sum E]
+  uint8_t *sides = nullptr;          // device [sum V]
+  uint64_t tag = 0;                  // caller's id, reported back on completion
+};
+
+struct Finished {
+  uint64_t tag;     // group tag
+  int32_t index;    // instance index inside its group
+  int status;       // 0 ok, else a wbpr status code
+};
+
+// First-fit allocator of half-open index ranges.
+class RangeAlloc {
+ public:
+  void reset(int64_t cap);
+  int64_t alloc(int64_t n);          // -1 when no range fits
+  void release(int64_t at, int64_t n);
+  void shrink(int64_t at, int64_t n_old, int64_t n_new);
+  int64_t largest_free() const;
+  int64_t free_total() const { return free_total_; }
+  int64_t capacity() const { return cap_; }
+
+ private:
+  std::map<int64_t, int64_t> free_;  // start -> length
+  int64_t cap_ = 0, free_total_ = 0;
+};
+
+class Engine {
+ public:
+  explicit Engine(int device);
+  ~Engine();
+  Engine(const Engine &) = delete;
+  Engine &operator=(const Engine &) = delete;
+
+  void set_config(const SolveConfig &cfg);
+  const SolveConfig &config() const { return cfg_; }
+
+  // Device bytes of an arena for the given capacities (footprint formula).
+  static size_t arena_bytes(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap);
+  // Device bytes of the per-admission scratch (builder, union CSR staging).
+  static size_t scratch_bytes(int64_t V, int64_t E, int32_t n);
+
+  // Makes room for at least these capacities; only while nothing is
+  // resident.  Returns 0 or a wbpr status.
+  int reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int64_t scratch_V, int64_t scratch_E,
+              int32_t scratch_n, std::string *err);
+  // Admits a group (builds its residual graphs, preflows them).  Returns 0,
+  // WBPR_EAGAIN when the arena has no room now, or another status.
+  int admit(const GroupInput &in, hipStream_t st, std::string *err);
+  // One round: global relabel of every resident instance, per-instance phase
+  // transitions and outputs, then a batch of sweeps.  Appends finished
+  // instances to *done.
+  int round(hipStream_t st, std::vector<Finished> *done, std::string *err);
+  // Runs rounds until nothing is resident.
+  int run_to_completion(hipStream_t st, std::vector<Finished> *done, std::string *err);
+  // Drops every resident instance (after an error) and clears the arena.
+  void abandon(hipStream_t st);
+
+  bool idle() const { return resident_ == 0; }
+  int32_t resident() const { return resident_; }
+  int64_t free_vertices() const { return valloc_.largest_free(); }
+  int64_t free_entries() const { return malloc_.largest_free(); }
+  int64_t free_arcs() const { return aalloc_.largest_free(); }
+  int32_t free_slots() const { return (int32_t)slot_free_.size(); }
+  int64_t last_build_M() const { return last_M_; }
+
+  void reset_stats();
+  int collect_stats(hipStream_t st, EngineStats *out, std::string *err);
+
+ private:
+  struct Inst {
+    bool used = false;
+    int32_t V = 0;
+    int64_t E = 0;
+    int32_t vbase = 0, s = 0, t = 0;  // arena ids
+    int64_t abase = 0;
+    int phase = 0;  // 1: max preflow, 2: return excess to s, 3: done
+    int group = -1;
+    int32_t index = 0;
+    int64_t *value = nullptr;
+    int32_t *flow = nullptr;
+    uint8_t *side = nullptr;
+  };
+  struct Group {
+    bool used = false;
+    uint64_t tag = 0;
+    int32_t vbase = 0, V = 0;
+    int64_t mbase = 0, Mres = 0, abase = 0, E = 0;
+    int remaining = 0;
+  };
+
+  int ensure_graph(hipStream_t st, std::string *err);
+  void enqueue_sweeps(hipStream_t st, int K);
+  void launch_inst_kernel(int which, const std::vector<int> &slots, hipStream_t st);
+  void launch_inst_list(int which, const std::vector<struct InstDev> &list, const std::vector<int> &slots,
+                        hipStream_t st);
+  void release_groups(const std::vector<int> &gis, hipStream_t st);
+
+  int device_;
+  SolveConfig cfg_;
+  int gr_blocks_[7] = {0, 0, 0, 0, 0, 0, 0};
+  // device memory
+  void *arena_ = nullptr;
+  size_t arena_n_ = 0;
+  void *scratch_ = nullptr;
+  size_t scratch_n_ = 0;
+  int64_t Vcap_ = 0, Mcap_ = 0, Ecap_ = 0;
+  int32_t ncap_ = 0;
+  int64_t sV_ = 0, sE_ = 0;
+  int32_t sn_ = 0;
+  Arena A_;
+  long long *e_ = nullptr;
+  int32_t *h_ = nullptr, *inst_of_ = nullptr, *q_[2] = {nullptr, nullptr}, *fq_[2] = {nullptr, nullptr};
+  int32_t *mid_ = nullptr, *big_ = nullptr, *chunk_w_ = nullptr, *chunk_b_ = nullptr;
+  uint8_t *vis_ = nullptr;
+  int64_t nchunk_ = 0;
+  int32_t *inst_active_ = nullptr, *inst_stranded_ = nullptr;
+  int32_t *roots_ = nullptr, *root_h_ = nullptr, *excl_ = nullptr;
+  void *inst_list_ = nullptr;  // per-instance kernel descriptors [ncap]
+  long long *misc_ = nullptr;
+  int32_t *sink_ = nullptr;
+  long long *budget_ = nullptr;
+  // pinned host staging
+  char *pin_ = nullptr;
+  size_t pin_n_ = 0;
+  // host bookkeeping
+  RangeAlloc valloc_, malloc_, aalloc_;
+  std::vector<int> slot_free_;
+  std::vector<Inst> inst_;
+  std::vector<Group> groups_;
+  int32_t resident_ = 0;
+  int64_t resident_V_ = 0, resident_M_ = 0;
+  int64_t last_M_ = 0;
+  // tiers and launch shapes (fixed per config)
+  int P_ = 8, t_mid_ = 32, t_big_ = 2048, bfs_split_ = 64, chunk_ = 1024;
+  // captured sweep batch
+  hipGraph_t graph_ = nullptr;
+  hipGraphExec_t graph_exec_ = nullptr;
+  int graph_K_ = 0;
+  // timing
+  std::vector<hipEvent_t> ev_;
+  int ev_used_ = 0;
+  std::vector<std::pair<int, int>> ev_marks_;  // (kernel, first event index)
+  EngineStats acc_;
+};
+
+}  // namespace wb

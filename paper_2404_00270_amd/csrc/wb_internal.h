@@ -16,18 +16,22 @@ hipError_t radix_sort_u64_u32(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t
                               int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st);
 
 // ---- residual graph: bidirectional CSR with merged entries and explicit
-// mate indices (build.hip)
-struct Residual {
-  int32_t V = 0;
-  int64_t E = 0;               // input arcs
-  int64_t M = 0;               // merged residual entries (host copy, after build)
-  int64_t M_cap = 0;           // capacity of the entry arrays (2E)
-  int32_t *rptr = nullptr;     // [V+1] row offsets into ent
-  int2 *ent = nullptr;         // [M] {neighbour column, residual capacity}
-  int32_t *rev = nullptr;      // [M] index of the mate entry (v,u) of (u,v)
-  int32_t *cap0 = nullptr;     // [M] merged forward capacity, sum of c(u->v)
-  int32_t *arc2ent = nullptr;  // [E] entry of input arc i, -1 for self-loops
-  int32_t *pbefore = nullptr;  // [E] capacity of earlier parallel arcs (u,v)
+// mate indices, in a device arena shared by all instances (build.hip)
+struct Arena {
+  int2 *rowb = nullptr;        // [Vcap] row bounds {first entry, end entry}
+  int2 *ent = nullptr;         // [Mcap] {neighbour column, residual capacity}
+  int32_t *rev = nullptr;      // [Mcap] index of the mate entry (v,u) of (u,v)
+  int32_t *cap0 = nullptr;     // [Mcap] merged forward capacity, sum of c(u->v)
+  int32_t *arc2ent = nullptr;  // [Ecap] entry of input arc i, -1 for self-loops
+  int32_t *pbefore = nullptr;  // [Ecap] capacity of earlier parallel arcs (u,v)
+  int32_t *acap = nullptr;     // [Ecap] input capacity of arc i
+};
+
+// Where one build lands in the arena.
+struct Place {
+  int32_t vbase = 0;  // arena id of local vertex 0
+  int64_t mbase = 0;  // first arena entry
+  int64_t abase = 0;  // first arena arc slot
 };
 
 // Status words the builder leaves in device memory.
@@ -38,16 +42,14 @@ struct BuildStatus {
   int32_t M;          // merged entries
 };
 
-// Bytes of the Residual arrays for V vertices and E arcs.
-size_t residual_bytes(int32_t V, int64_t E);
-// Carves the Residual arrays out of `mem` (residual_bytes() long).
-void residual_carve(Residual *res, int32_t V, int64_t E, void *mem);
-// Device scratch needed by build_residual.
+// Device scratch needed by build_residual for V vertices and E arcs.
 size_t build_scratch_bytes(int32_t V, int64_t E);
 
-// CSR (device) -> residual graph.  Enqueues everything on `st`; the host
-// learns M, validation and overflow results from *status_dev afterwards.
-hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, Residual *res,
-                          void *scratch, BuildStatus *status_dev, hipStream_t st);
+// CSR (device, local ids 0..V-1) -> residual rows in the arena at `pl`:
+// uses at most 2E entries from pl.mbase and E arc slots from pl.abase.
+// Enqueues everything on `st`; the host learns M and the validation results
+// from *status_dev afterwards.
+hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, int32_t V, int64_t E,
+                          const Arena &A, const Place &pl, void *scratch, BuildStatus *status_dev, hipStream_t st);
 
 }  // namespace wb

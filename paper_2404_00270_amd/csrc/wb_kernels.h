@@ -1,0 +1,103 @@
+// Kernel argument blocks and launch wrappers of the sweep and global-relabel
+// kernels (solve.hip), shared with the host engine (engine.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "wb_common.h"
+
+namespace wb {
+
+constexpr int SWEEP_THREADS = 256;
+constexpr int BLK = 256;
+constexpr int GR_THREADS = 1024;
+// Height cap: a vertex of instance i has height hcap - V_i + (local height);
+// local height >= V_i, i.e. h >= hcap, means inactive; hcap + 1 marks the
+// terminal a phase never labels.
+constexpr int32_t HCAP = 1 << 30;
+
+struct Graph {
+  int32_t V;             // arena vertices
+  int32_t hcap;          // height cap: h >= hcap is inactive
+  const int2 *rowb;      // row bounds {first entry, end entry}
+  int2 *ent;
+  const int32_t *rev;
+  long long *e;
+  int32_t *h;
+  const int32_t *sink;   // target whose excess is never read, so pushes into
+                         // it skip the excess atomic (-1: none skipped)
+};
+
+struct SweepQ {
+  const int32_t *qin;
+  const int32_t *qin_cnt;
+  int32_t *qout;
+  int32_t *qout_cnt;
+  int32_t *zero_cnt;
+  int32_t *mid_v;       // medium rows deferred to the one-wave tier
+  int32_t *mid_cnt;
+  int32_t *big_v;       // long rows deferred to the workgroup tier
+  int32_t *big_cnt;
+  int32_t *zero_a;      // counters to clear for the next sweep (nullable)
+  int32_t *zero_b;
+  int32_t t_mid;        // rows longer than this go to the one-wave tier
+  int32_t t_big;        // rows longer than this go to the workgroup tier
+  long long *stats;     // per kernel k (0 tile, 1 wave, 2 workgroup): [4k] arc scans, [4k+1] pushes,
+                        // [4k+2] relabels, [4k+3] queued; [12] bfs scans; [13] nonempty sweeps
+  long long *rwork;     // running sum of row lengths scanned by relabels
+  const int32_t *halt;  // set by k_sweep_control: the rest of this round's sweeps do nothing
+  int32_t qcap;      // capacity of every queue and of the long-row list (V)
+  int32_t *err;      // overflow counter (must stay 0)
+  int32_t mode;      // 0: one push to the minimum-height neighbour (Algorithms 1-2)
+                     // 1: full discharge (push along every lower residual arc, then relabel)
+};
+
+struct GRArgs {
+  Graph g;
+  const int32_t *roots;    // [nroots] BFS sources (the phase's target of every instance)
+  const int32_t *root_h;   // [nroots] their heights (per-instance base hcap - V_i)
+  int32_t nroots;
+  const int32_t *excl;     // [nexcl] terminals that are never labelled
+  int32_t nexcl;
+  const int32_t *inst_of;  // [V] instance slot of every arena vertex (-1: free)
+  int32_t *inst_active;    // per instance: active vertices after this relabel
+  int32_t *inst_stranded;  // per instance: excess vertices that cannot reach the root
+  int32_t *fq[2];
+  int32_t *fcnt;      // [3] rotating frontier counters
+  uint8_t *vis;       // [V] 0 unvisited, 1/2 labelled at even/odd distance, 3 excluded
+  int32_t *chunk_w;   // long rows: vertex
+  int32_t *chunk_b;   //            first entry of the chunk
+  int32_t *chunk_cnt; // [2]
+  int32_t *bucnt;     // [3] rotating counts of vertices labelled by bottom-up steps
+  long long *fedges;  // [3] rotating row-length sums of the next frontier
+  unsigned *bar;      // barrier state (WB_BAR_WORDS)
+  int32_t *qout;      // active-vertex queue rebuilt at the end
+  int32_t *qcnt;      // [3] sweep counters: [0] = queue length, [1],[2] zeroed
+  int32_t *big_cnt;   // [2] zeroed
+  int32_t *mid_cnt;   // [2] zeroed
+  long long *stats;
+  long long *status;  // [0] active, [1] stranded, [2] levels, [3] bottom-up levels
+  int32_t split_deg, chunk;
+  int32_t qcap;       // capacity of frontiers and queue (V)
+  int32_t chunk_cap;  // capacity of the chunk descriptor arrays
+  int32_t bu_threshold;    // frontier size above which a level runs bottom-up
+  long long bu_edges;      // frontier row-length sum above which a level runs bottom-up
+  int32_t *err;       // overflow counter (must stay 0)
+  int32_t *halt;          // sweep halt flag, cleared here
+  const long long *rwork; // relabel work so far ...
+  long long *rwork_at_gr; // ... snapshot at this global relabel
+};
+
+// Sweep kernels: tiles of P lanes (P = 4..64), one workgroup per long row,
+// and the one-thread round control.
+void launch_sweep_tile(int P, int blocks, hipStream_t st, const Graph &g, const SweepQ &q);
+void launch_sweep_block(int blocks, hipStream_t st, const Graph &g, const SweepQ &q);
+void launch_sweep_control(hipStream_t st, const int32_t *qout_cnt, const long long *rwork, const long long *rwork_at_gr,
+                          const long long *budget, int32_t *halt);
+// Cooperative global relabel (all workgroups co-resident).
+hipError_t launch_global_relabel(int P, int blocks, hipStream_t st, GRArgs &a);
+// Co-resident workgroup limit of the global relabel for P lanes.
+int gr_max_blocks(int device, int P);
+
+}  // namespace wb

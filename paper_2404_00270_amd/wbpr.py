@@ -33,7 +33,7 @@ STATUS_NAMES = {
 # Every symbol declared in include/wbpr.h.
 EXPORTS = (
     "wbpr_version", "wbpr_last_error", "wbpr_device_arch", "wbpr_ctx_create", "wbpr_ctx_destroy",
-    "wbpr_ctx_set_options", "wbpr_solve", "wbpr_solve_device",
+    "wbpr_ctx_set_options", "wbpr_solve", "wbpr_solve_device", "wbpr_solve_batch", "wbpr_solve_batch_device",
 )
 
 
@@ -59,7 +59,9 @@ class wbpr_options(ctypes.Structure):
         ("time_kernels", ctypes.c_int32),
         ("push_mode", ctypes.c_int32),
         ("block_degree", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("gr_work_permille", ctypes.c_int32),
+        ("no_graph", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -97,6 +99,8 @@ class wbpr_stats(ctypes.Structure):
         ("kernel_relabels", ctypes.c_int64 * 4),
         ("kernel_queued", ctypes.c_int64 * 4),
         ("bfs_topdown_scans", ctypes.c_int64),
+        ("instances", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
@@ -159,6 +163,12 @@ def load_library(path: str = LIB_PATH):
     lib.wbpr_solve_device.restype = ctypes.c_int
     lib.wbpr_solve_device.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, i32, vp, vp, vp, vp,
                                       ctypes.POINTER(wbpr_stats)]
+    lib.wbpr_solve_batch.restype = ctypes.c_int
+    lib.wbpr_solve_batch.argtypes = [vp, i32, ctypes.POINTER(wbpr_csr), vp, vp, vp, vp, vp,
+                                     ctypes.POINTER(wbpr_stats)]
+    lib.wbpr_solve_batch_device.restype = ctypes.c_int
+    lib.wbpr_solve_batch_device.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                            ctypes.POINTER(wbpr_stats)]
     _lib = lib
     return lib
 
@@ -250,6 +260,63 @@ def wbpr_solve_device(ctx: int, V: int, E: int, row_ptr_ptr: int, col_ptr: int, 
     return st.as_dict()
 
 
+@dataclass
+class BatchResult:
+    values: np.ndarray           # int64[n]
+    flows: list | None           # n arrays int32[E_i]
+    sides: list | None           # n arrays uint8[V_i]
+    stats: dict
+
+
+def wbpr_solve_batch(ctx: int, graphs, want_flow: bool = True, want_side: bool = True,
+                     return_code: bool = False):
+    """Batched solve from host graphs (objects with V, row_ptr, col, cap, s, t)."""
+    lib = load_library()
+    n = len(graphs)
+    keep = []
+    arr = (wbpr_csr * n)()
+    for i, g in enumerate(graphs):
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+        c = np.ascontiguousarray(g.col, dtype=np.int32)
+        k = np.ascontiguousarray(g.cap, dtype=np.int32)
+        keep += [rp, c, k]
+        E = int(c.shape[0])
+        arr[i] = wbpr_csr(g.V, E, rp.ctypes.data, c.ctypes.data if E else None, k.ctypes.data if E else None)
+    s = np.array([g.s for g in graphs], dtype=np.int32)
+    t = np.array([g.t for g in graphs], dtype=np.int32)
+    values = np.zeros(n, np.int64)
+    flows = [np.zeros(max(int(np.asarray(g.col).shape[0]), 1), np.int32) for g in graphs] if want_flow else None
+    sides = [np.zeros(g.V, np.uint8) for g in graphs] if want_side else None
+    fp = (ctypes.c_void_p * n)(*[f.ctypes.data for f in flows]) if flows is not None else None
+    sp = (ctypes.c_void_p * n)(*[x.ctypes.data for x in sides]) if sides is not None else None
+    st = wbpr_stats()
+    rc = lib.wbpr_solve_batch(ctx, n, arr, s.ctypes.data, t.ctypes.data, values.ctypes.data,
+                              ctypes.cast(fp, ctypes.c_void_p) if fp is not None else None,
+                              ctypes.cast(sp, ctypes.c_void_p) if sp is not None else None, ctypes.byref(st))
+    if return_code:
+        return rc
+    _check(rc)
+    if flows is not None:
+        flows = [f[: int(np.asarray(g.col).shape[0])] for f, g in zip(flows, graphs)]
+    return BatchResult(values, flows, sides, st.as_dict())
+
+
+def wbpr_solve_batch_device(ctx: int, V, E, s, t, row_ptr_ptr: int, col_ptr: int, cap_ptr: int, stream: int,
+                            values_ptr: int, flows_ptr: int | None, sides_ptr: int | None) -> dict:
+    """Batched solve from packed device arrays; V, E, s, t are host sequences."""
+    lib = load_library()
+    n = len(V)
+    Va = np.ascontiguousarray(V, dtype=np.int32)
+    Ea = np.ascontiguousarray(E, dtype=np.int64)
+    sa = np.ascontiguousarray(s, dtype=np.int32)
+    ta = np.ascontiguousarray(t, dtype=np.int32)
+    st = wbpr_stats()
+    _check(lib.wbpr_solve_batch_device(ctx, n, Va.ctypes.data, Ea.ctypes.data, sa.ctypes.data, ta.ctypes.data,
+                                       row_ptr_ptr, col_ptr or None, cap_ptr or None, stream or None, values_ptr,
+                                       flows_ptr or None, sides_ptr or None, ctypes.byref(st)))
+    return st.as_dict()
+
+
 class Solver:
     """Context-owning convenience wrapper around the C ABI."""
 
@@ -261,6 +328,9 @@ class Solver:
 
     def solve(self, g, want_flow: bool = True, want_side: bool = True) -> Result:
         return wbpr_solve(self.ctx, g.V, g.row_ptr, g.col, g.cap, g.s, g.t, want_flow, want_side)
+
+    def solve_batch(self, graphs, want_flow: bool = True, want_side: bool = True) -> BatchResult:
+        return wbpr_solve_batch(self.ctx, graphs, want_flow, want_side)
 
     def solve_tensors(self, V, row_ptr, col, cap, s, t, value, flow=None, side=None) -> dict:
         """Device-resident solve on torch tensors (torch supplies the memory).

@@ -1,0 +1,192 @@
+"""GPU parity of batched solves: many instances resident in one arena, solved
+by shared sweeps and one multi-root global relabel per round.
+
+Every instance of a batch must give exactly what the oracle gives for it
+alone (value, canonical sink side, a certified per-arc flow), whatever the
+mix of sizes, the sweep batching (captured graph or direct launches, fixed or
+adaptive relabel frequency) and the outputs asked for.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_00270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+WATCHDOG = dict(max_wall_ms=120_000)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def solver():
+    from paper_2404_00270_amd import wbpr
+
+    s = wbpr.Solver(0, **WATCHDOG)
+    yield s
+    s.close()
+
+
+def _mixed_batch(seed, n_small=12, n_stream=6, vmax=4096):
+    rng = np.random.default_rng(seed)
+    gs = []
+    for i in range(n_small):
+        V = int(rng.integers(2, 50))
+        gs.append(W.multigraph(V, int(rng.integers(0, 6 * V)), cmax=int(rng.integers(0, 30)),
+                               seed=90_000 + 100 * seed + i))
+    for i in range(n_stream):
+        gs.append(W.batch_instance(7 * seed + i, vmin=64, vmax=vmax))
+    gs.append(W.from_arcs(2, [], 0, 1, "no-arcs"))
+    gs.append(W.from_arcs(4, [(1, 2, 5), (2, 3, 5)], 0, 3, "source-isolated"))
+    order = rng.permutation(len(gs))
+    return [gs[k] for k in order]
+
+
+def _check_batch(gs, res, refs=None):
+    for i, g in enumerate(gs):
+        value, side, cutcap = refs[i] if refs else oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+        assert res.values[i] == value, (i, g.name, int(res.values[i]), value)
+        if res.sides is not None:
+            assert np.array_equal(res.sides[i], side), (i, g.name)
+        if res.flows is not None:
+            c = oracle.check(g.V, g.row_ptr, g.col, g.cap, g.s, g.t, res.flows[i])
+            assert c.feasible, (i, g.name, c.code, c.bad)
+            assert c.value == value and c.cut_capacity == value
+            assert np.array_equal(c.side, side)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_mixed_batch_matches_oracle(solver, seed):
+    gs = _mixed_batch(seed)
+    say(f"[batch] seed={seed} n={len(gs)} V={sum(g.V for g in gs)} E={sum(g.E for g in gs)}")
+    res = solver.solve_batch(gs)
+    assert res.stats["instances"] == len(gs)
+    _check_batch(gs, res)
+
+
+def test_batch_outputs_subsets(solver):
+    gs = _mixed_batch(11)
+    refs = [oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t) for g in gs]
+    for wf, ws in ((False, False), (False, True), (True, False)):
+        say(f"[batch-out] flows={wf} sides={ws}")
+        res = solver.solve_batch(gs, want_flow=wf, want_side=ws)
+        assert (res.flows is None) == (not wf) and (res.sides is None) == (not ws)
+        _check_batch(gs, res, refs)
+
+
+@pytest.mark.parametrize("opts", [
+    dict(no_graph=1),
+    dict(gr_every_sweeps=3),
+    dict(gr_every_sweeps=1, no_graph=1),
+    dict(gr_work_permille=1),
+    dict(gr_work_permille=20, push_mode=1),
+    dict(time_kernels=1),
+    dict(lanes_per_vertex=4, split_degree=3, block_degree=9),
+])
+def test_batch_launch_variants(solver, opts):
+    gs = _mixed_batch(21, n_small=6, n_stream=4)
+    refs = [oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t) for g in gs]
+    say(f"[batch-variant] {opts}")
+    solver.set_options(**opts, **WATCHDOG)
+    try:
+        _check_batch(gs, solver.solve_batch(gs), refs)
+    finally:
+        solver.set_options(**WATCHDOG)
+
+
+@pytest.mark.parametrize("permille", [1, 30, 1000])
+def test_single_solve_relabel_budget(solver, permille):
+    """Early halts of the sweep batch (tiny relabel budget) keep parity."""
+    g = W.random_graph(4000, 40000, 1, 100, 41)
+    ref = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+    say(f"[budget] permille={permille}")
+    for no_graph in (0, 1):
+        solver.set_options(gr_work_permille=permille, no_graph=no_graph, **WATCHDOG)
+        try:
+            r = solver.solve(g)
+        finally:
+            solver.set_options(**WATCHDOG)
+        assert r.value == ref[0]
+        assert np.array_equal(r.side, ref[1])
+        c = oracle.check(g.V, g.row_ptr, g.col, g.cap, g.s, g.t, r.flow)
+        assert c.feasible and c.value == ref[0]
+
+
+def test_batch_of_one_equals_single(solver):
+    g = W.batch_instance(3)
+    a = solver.solve(g)
+    b = solver.solve_batch([g])
+    assert a.value == int(b.values[0])
+    assert np.array_equal(a.side, b.sides[0])
+
+
+def test_back_to_back_batches_reuse_arena(solver):
+    """A larger batch, then a smaller one, then a single solve on one context."""
+    big = _mixed_batch(31, n_small=8, n_stream=8, vmax=8192)
+    small = _mixed_batch(32, n_small=3, n_stream=1)
+    for gs in (big, small):
+        say(f"[reuse] n={len(gs)}")
+        _check_batch(gs, solver.solve_batch(gs))
+    g = W.config_plain()
+    r = solver.solve(g)
+    assert r.value == oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)[0]
+
+
+def test_batch_bad_instance_rejected(solver):
+    from paper_2404_00270_amd import wbpr
+
+    gs = _mixed_batch(41, n_small=4, n_stream=2)
+    bad = gs[2]
+    if bad.E == 0:
+        bad = gs[3] if gs[3].E else W.multigraph(10, 30, seed=5)
+        gs[2] = bad
+    col = bad.col.copy()
+    col[0] = bad.V  # out of range for its own instance, in range for the union
+    gs_bad = list(gs)
+    gs_bad[2] = W.Graph(bad.V, bad.row_ptr, col, bad.cap, bad.s, bad.t, "bad-col")
+    rc = wbpr.wbpr_solve_batch(solver.ctx, gs_bad, return_code=True)
+    assert rc == wbpr.WBPR_EINVAL
+    gs_st = list(gs)
+    gs_st[1] = W.Graph(gs[1].V, gs[1].row_ptr, gs[1].col, gs[1].cap, 0, 0, "s==t")
+    rc = wbpr.wbpr_solve_batch(solver.ctx, gs_st, return_code=True)
+    assert rc == wbpr.WBPR_EINVAL
+    _check_batch(gs, solver.solve_batch(gs))
+
+
+def test_batch_device_packed_torch(solver):
+    import torch
+
+    from paper_2404_00270_amd import wbpr
+
+    gs = _mixed_batch(51, n_small=5, n_stream=3)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(np.concatenate([g.row_ptr for g in gs]).astype(np.int64)).to(dev)
+    col = torch.from_numpy(np.concatenate([g.col for g in gs]).astype(np.int32)).to(dev)
+    cap = torch.from_numpy(np.concatenate([g.cap for g in gs]).astype(np.int32)).to(dev)
+    n = len(gs)
+    values = torch.zeros(n, dtype=torch.int64, device=dev)
+    flows = torch.zeros(max(1, sum(g.E for g in gs)), dtype=torch.int32, device=dev)
+    sides = torch.zeros(sum(g.V for g in gs), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    wbpr.wbpr_solve_batch_device(solver.ctx, [g.V for g in gs], [g.E for g in gs], [g.s for g in gs],
+                                 [g.t for g in gs], rp.data_ptr(), col.data_ptr(), cap.data_ptr(), 0,
+                                 values.data_ptr(), flows.data_ptr(), sides.data_ptr())
+    torch.cuda.synchronize()
+    hv, hf, hs = values.cpu().numpy(), flows.cpu().numpy(), sides.cpu().numpy()
+
+    class R:
+        pass
+
+    r = R()
+    r.values = hv
+    eo = np.cumsum([0] + [g.E for g in gs])
+    vo = np.cumsum([0] + [g.V for g in gs])
+    r.flows = [hf[eo[i]:eo[i + 1]] for i in range(n)]
+    r.sides = [hs[vo[i]:vo[i + 1]] for i in range(n)]
+    _check_batch(gs, r)
