@@ -164,6 +164,8 @@ def batched_leg(solver, n, dev):
     st = batch()
     t_batch = time.perf_counter() - t0
     same = bool(torch.equal(vals[0], vals[1]) and torch.equal(sides[0], sides[1]))
+    served = served_leg(solver, gs, rate=2.0 * n / t_single, alone_values=vals[0].cpu().numpy(),
+                        alone_sides=sides[0].cpu().numpy(), vo=vo)
     return {
         "instances": n,
         "V_total": Vt,
@@ -178,6 +180,54 @@ def batched_leg(solver, n, dev):
         "batched_sweeps": st["sweeps"],
         "sample": f"batch_instance(0..{n - 1}): V log-uniform [256, 65536], out-degree 8, caps U[1,100]; "
                   "flows, cut sides and values written by both legs",
+        "served": served,
+    }
+
+
+def served_leg(solver, gs, rate, alone_values, alone_sides, vo, budget=1 << 30, slots=256, seed=5):
+    """Poisson arrivals at `rate` requests/s into the continuous-batching server."""
+    import threading
+
+    import numpy as np
+
+    from paper_2404_00270_amd import wbpr
+
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=len(gs))
+    tickets = [None] * len(gs)
+    with wbpr.Server(solver, hbm_budget_bytes=budget, max_slots=slots) as srv:
+        def producer():
+            t_next = time.perf_counter()
+            for i, g in enumerate(gs):
+                t_next += gaps[i]
+                d = t_next - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(g)
+
+        t0 = time.perf_counter()
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        res = [srv.wait(tk, 300_000) for tk in tickets]
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+    ok = all(r is not None and r.status == 0 for r in res)
+    same = ok and all(int(r.value) == int(alone_values[i]) and
+                      np.array_equal(r.side, alone_sides[vo[i]:vo[i + 1]]) for i, r in enumerate(res))
+    return {
+        "arrival_rate_per_s": rate,
+        "solves_per_s": st["solves_per_s"],
+        "wall_solves_per_s": len(gs) / wall,
+        "p50_ms": st["p50_ms"],
+        "p99_ms": st["p99_ms"],
+        "max_ms": st["max_ms"],
+        "peak_resident": st["peak_resident"],
+        "rounds": st["rounds"],
+        "admissions": st["admissions"],
+        "hbm_budget_bytes": budget,
+        "arena_bytes": st["arena_bytes"],
+        "identical_to_alone": bool(same),
     }
 
 

@@ -57,7 +57,8 @@ enum wbpr_status {
     WBPR_EDEVICE = 5,    /* HIP runtime error */
     WBPR_EAGAIN = 6,     /* result not ready yet (server polling) */
     WBPR_EOVERFLOW = 7,  /* merged pair capacity does not fit in int32 */
-    WBPR_EINTERNAL = 8   /* internal consistency check failed (a bug) */
+    WBPR_EINTERNAL = 8,  /* internal consistency check failed (a bug) */
+    WBPR_ECANCELED = 9   /* server request dropped by wbpr_server_destroy */
 };
 
 /* Graph in CSR.  Pointers are host or device memory depending on the entry
@@ -192,6 +193,98 @@ int wbpr_solve_batch_device(wbpr_ctx *ctx, int32_t n, const int32_t *V, const in
  * pointers to int32[E_i]; sides (nullable) holds n pointers to uint8[V_i]. */
 int wbpr_solve_batch(wbpr_ctx *ctx, int32_t n, const wbpr_csr *graphs, const int32_t *s, const int32_t *t,
                      int64_t *values, int32_t *const *flows, uint8_t *const *sides, wbpr_stats *stats);
+
+/* ------------------------------------------------------------------------
+ * Continuous-batching server.
+ *
+ * Requests (one instance each) arrive at any time from any thread.  A worker
+ * thread owns a device arena of fixed capacity, carved from an HBM budget:
+ * between rounds it admits waiting requests whose residual graphs fit the
+ * free vertex, entry and arc ranges and a free instance slot, and every round
+ * runs one multi-root global relabel and one batch of sweeps over everything
+ * resident, so requests that arrive while others are solving join the same
+ * launches (continuous batching).  Residual state stays on the device until
+ * the instance finishes; the result is then copied back and its ranges are
+ * returned.  Each result is exactly what a separate solve gives.
+ *
+ * Admission footprint of one instance with V vertices and E arcs (bytes of
+ * the arena it occupies while resident, see wbpr_server_footprint):
+ *   57 V + 44 E + ceil(E / 64)
+ *     (rows 8V; entries 16 B per slot, 2E slots; arcs 12E; excess, height,
+ *      queues and visit codes 41V; long-row chunk descriptors 8(V + 2E/1024))
+ * plus outputs 8 + 4E + V and, during admission only, the input staging
+ * 8(V+1) + 8E and the builder scratch.
+ * ---------------------------------------------------------------------- */
+typedef struct wbpr_server wbpr_server;
+
+typedef struct wbpr_server_options {
+    int64_t hbm_budget_bytes;  /* device bytes for the arena, builder scratch,
+                                  input staging and outputs (0 = 1 GiB) */
+    int32_t max_slots;         /* resident instances at most (0 = 256) */
+    int32_t arcs_per_vertex;   /* expected E/V, proportions the arena (0 = 8) */
+    int32_t want_flows;        /* 1: results carry per-arc flows */
+    int32_t want_sides;        /* 1: results carry the cut side */
+    int32_t max_admit;         /* requests admitted per round (0 = no limit) */
+    int32_t reserved[5];
+} wbpr_server_options;
+
+/* One finished request.  arc_flow / cut_side are allocated by the library
+ * (NULL unless asked for) and released by wbpr_result_free. */
+typedef struct wbpr_result {
+    uint64_t ticket;
+    int32_t status;            /* WBPR_OK or this request's error */
+    int32_t V;
+    int64_t E;
+    int64_t value;
+    int32_t *arc_flow;         /* int32[E] */
+    uint8_t *cut_side;         /* uint8[V] */
+    double latency_ms;         /* submit -> result ready */
+    double queue_ms;           /* submit -> admission */
+} wbpr_result;
+
+typedef struct wbpr_server_stats {
+    int64_t submitted, completed, failed, pending, resident;
+    int64_t rounds, admissions, sweeps;
+    double busy_ms;            /* wall time with at least one request in flight */
+    double solves_per_s;       /* completed / busy time */
+    double p50_ms, p99_ms, max_ms;  /* latency over completed requests */
+    int64_t arena_bytes, scratch_bytes, staging_bytes, output_bytes;
+    int64_t Vcap, Mcap, Ecap;
+    int32_t max_slots, peak_resident;
+} wbpr_server_stats;
+
+/* Start a server on ctx's device with ctx's options (copied).  The server has
+ * its own stream, arena and worker thread; ctx must outlive it and may still
+ * be used for plain solves meanwhile.  WBPR_ETOOBIG if the budget cannot hold
+ * a minimal arena. */
+int wbpr_server_create(wbpr_ctx *ctx, const wbpr_server_options *opt, wbpr_server **out);
+
+/* Queue one instance (host CSR, copied before return; the caller may free it
+ * at once).  Checks the CSR on the host (WBPR_EINVAL) and that the instance
+ * can ever be admitted under the budget (WBPR_ETOOBIG).  Thread-safe. */
+int wbpr_server_submit(wbpr_server *srv, const wbpr_csr *g, int32_t s, int32_t t, uint64_t *ticket);
+
+/* Result of `ticket`: WBPR_OK and *out filled (ownership passes to the caller,
+ * the ticket is retired), WBPR_EAGAIN while pending, WBPR_EINVAL for an
+ * unknown ticket.  out->status holds the request's own outcome.
+ * Thread-safe. */
+int wbpr_server_poll(wbpr_server *srv, uint64_t ticket, wbpr_result *out);
+
+/* Like poll, waiting up to timeout_ms (< 0: no limit) for the result. */
+int wbpr_server_wait(wbpr_server *srv, uint64_t ticket, int32_t timeout_ms, wbpr_result *out);
+
+void wbpr_result_free(wbpr_result *r);
+
+/* Counters and latency percentiles since creation.  Thread-safe. */
+int wbpr_server_get_stats(wbpr_server *srv, wbpr_server_stats *out);
+
+/* Arena bytes an instance of V vertices and E arcs occupies while resident
+ * (formula above).  Pure host function. */
+int wbpr_server_footprint(int32_t V, int64_t E, int64_t *bytes);
+
+/* Stop the worker: requests not yet finished complete with WBPR_ECANCELED
+ * (their results can no longer be fetched); frees everything. */
+void wbpr_server_destroy(wbpr_server *srv);
 
 #ifdef __cplusplus
 }

@@ -12,42 +12,29 @@
 #include <vector>
 
 #include "../../include/wbpr.h"
-#include "wb_engine.h"
+#include "wb_ctx.h"
 
-namespace {
-
+namespace wb {
 thread_local std::string g_err;
 
-int fail(int code, const std::string &msg) {
-  g_err = msg;
-  return code;
+int check_shape(int32_t V, int64_t E, int32_t s, int32_t t) {
+  if (V < 2) return fail(WBPR_EINVAL, "V must be at least 2");
+  if (V >= (1 << 30)) return fail(WBPR_ETOOBIG, "V must be below 2^30");
+  if (E < 0) return fail(WBPR_EINVAL, "negative E");
+  if (E >= (1ll << 30)) return fail(WBPR_ETOOBIG, "E must be below 2^30");
+  if (s < 0 || s >= V || t < 0 || t >= V) return fail(WBPR_EINVAL, "s or t out of range");
+  if (s == t) return fail(WBPR_EINVAL, "s == t");
+  return WBPR_OK;
 }
+}  // namespace wb
 
-int hip_fail(hipError_t e, const char *what) {
-  g_err = std::string(what) + ": " + hipGetErrorString(e);
-  return e == hipErrorOutOfMemory ? WBPR_ENOMEM : WBPR_EDEVICE;
-}
+using wb::check_shape;
+using wb::DevBuf;
+using wb::fail;
+using wb::g_err;
+using wb::hip_fail;
 
-// Grow-only device buffer.
-struct DevBuf {
-  void *p = nullptr;
-  size_t n = 0;
-  hipError_t ensure(size_t bytes) {
-    if (bytes == 0) bytes = 256;
-    if (bytes <= n) return hipSuccess;
-    if (p) hipFree(p);
-    p = nullptr;
-    n = 0;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e == hipSuccess) n = bytes;
-    return e;
-  }
-  void release() {
-    if (p) hipFree(p);
-    p = nullptr;
-    n = 0;
-  }
-};
+namespace {
 
 wb::SolveConfig to_config(const wbpr_options *o) {
   wb::SolveConfig c;
@@ -118,14 +105,6 @@ void fill_stats(wbpr_stats *st, const wb::EngineStats &r, const wb::SolveConfig 
 
 }  // namespace
 
-struct wbpr_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  wb::SolveConfig cfg;
-  std::unique_ptr<wb::Engine> engine;
-  DevBuf input, output;
-};
-
 extern "C" {
 
 const char *wbpr_version(void) { return "wbpr-mi355x 0.2 (gfx950, BCSR vertex-centric push-relabel, batched engine)"; }
@@ -194,16 +173,6 @@ int wbpr_ctx_set_options(wbpr_ctx *c, const wbpr_options *opt) {
 }  // extern "C"
 
 namespace {
-
-int check_shape(int32_t V, int64_t E, int32_t s, int32_t t) {
-  if (V < 2) return fail(WBPR_EINVAL, "V must be at least 2");
-  if (V >= (1 << 30)) return fail(WBPR_ETOOBIG, "V must be below 2^30");
-  if (E < 0) return fail(WBPR_EINVAL, "negative E");
-  if (E >= (1ll << 30)) return fail(WBPR_ETOOBIG, "E must be below 2^30");
-  if (s < 0 || s >= V || t < 0 || t >= V) return fail(WBPR_EINVAL, "s or t out of range");
-  if (s == t) return fail(WBPR_EINVAL, "s == t");
-  return WBPR_OK;
-}
 
 // Solves a group already packed on the device, from an empty engine.
 int solve_group(wbpr_ctx *c, wb::GroupInput &in, hipStream_t st, wbpr_stats *stats) {

@@ -123,6 +123,8 @@ class Engine {
   int64_t free_arcs() const { return aalloc_.largest_free(); }
   int32_t free_slots() const { return (int32_t)slot_free_.size(); }
   int64_t last_build_M() const { return last_M_; }
+  int64_t sweeps_run() const { return acc_.sweeps; }
+  int64_t rounds_run() const { return acc_.global_relabels; }
 
   void reset_stats();
   int collect_stats(hipStream_t st, EngineStats *out, std::string *err);

@@ -24,16 +24,19 @@ WBPR_EDEVICE = 5
 WBPR_EAGAIN = 6
 WBPR_EOVERFLOW = 7
 WBPR_EINTERNAL = 8
+WBPR_ECANCELED = 9
 
 STATUS_NAMES = {
     0: "WBPR_OK", 1: "WBPR_EINVAL", 2: "WBPR_ENOMEM", 3: "WBPR_ETOOBIG", 4: "WBPR_ETIMEOUT",
-    5: "WBPR_EDEVICE", 6: "WBPR_EAGAIN", 7: "WBPR_EOVERFLOW", 8: "WBPR_EINTERNAL",
+    5: "WBPR_EDEVICE", 6: "WBPR_EAGAIN", 7: "WBPR_EOVERFLOW", 8: "WBPR_EINTERNAL", 9: "WBPR_ECANCELED",
 }
 
 # Every symbol declared in include/wbpr.h.
 EXPORTS = (
     "wbpr_version", "wbpr_last_error", "wbpr_device_arch", "wbpr_ctx_create", "wbpr_ctx_destroy",
     "wbpr_ctx_set_options", "wbpr_solve", "wbpr_solve_device", "wbpr_solve_batch", "wbpr_solve_batch_device",
+    "wbpr_server_create", "wbpr_server_submit", "wbpr_server_poll", "wbpr_server_wait", "wbpr_result_free",
+    "wbpr_server_get_stats", "wbpr_server_footprint", "wbpr_server_destroy",
 )
 
 
@@ -136,6 +139,44 @@ def _init_torch_first():
         pass
 
 
+class wbpr_server_options(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_int64),
+        ("max_slots", ctypes.c_int32),
+        ("arcs_per_vertex", ctypes.c_int32),
+        ("want_flows", ctypes.c_int32),
+        ("want_sides", ctypes.c_int32),
+        ("max_admit", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 5),
+    ]
+
+
+class wbpr_result(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("V", ctypes.c_int32),
+        ("E", ctypes.c_int64),
+        ("value", ctypes.c_int64),
+        ("arc_flow", ctypes.POINTER(ctypes.c_int32)),
+        ("cut_side", ctypes.POINTER(ctypes.c_uint8)),
+        ("latency_ms", ctypes.c_double),
+        ("queue_ms", ctypes.c_double),
+    ]
+
+
+class wbpr_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "pending", "resident", "rounds",
+                                               "admissions", "sweeps")] + \
+        [(n, ctypes.c_double) for n in ("busy_ms", "solves_per_s", "p50_ms", "p99_ms", "max_ms")] + \
+        [(n, ctypes.c_int64) for n in ("arena_bytes", "scratch_bytes", "staging_bytes", "output_bytes", "Vcap",
+                                       "Mcap", "Ecap")] + \
+        [("max_slots", ctypes.c_int32), ("peak_resident", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 def load_library(path: str = LIB_PATH):
     """Load libwbpr.so and declare every entry point; raises if it is absent."""
     global _lib
@@ -169,6 +210,22 @@ def load_library(path: str = LIB_PATH):
     lib.wbpr_solve_batch_device.restype = ctypes.c_int
     lib.wbpr_solve_batch_device.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                             ctypes.POINTER(wbpr_stats)]
+    lib.wbpr_server_create.restype = ctypes.c_int
+    lib.wbpr_server_create.argtypes = [vp, ctypes.POINTER(wbpr_server_options), ctypes.POINTER(ctypes.c_void_p)]
+    lib.wbpr_server_submit.restype = ctypes.c_int
+    lib.wbpr_server_submit.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, i32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.wbpr_server_poll.restype = ctypes.c_int
+    lib.wbpr_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(wbpr_result)]
+    lib.wbpr_server_wait.restype = ctypes.c_int
+    lib.wbpr_server_wait.argtypes = [vp, ctypes.c_uint64, i32, ctypes.POINTER(wbpr_result)]
+    lib.wbpr_result_free.restype = None
+    lib.wbpr_result_free.argtypes = [ctypes.POINTER(wbpr_result)]
+    lib.wbpr_server_get_stats.restype = ctypes.c_int
+    lib.wbpr_server_get_stats.argtypes = [vp, ctypes.POINTER(wbpr_server_stats)]
+    lib.wbpr_server_footprint.restype = ctypes.c_int
+    lib.wbpr_server_footprint.argtypes = [i32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.wbpr_server_destroy.restype = None
+    lib.wbpr_server_destroy.argtypes = [vp]
     _lib = lib
     return lib
 
@@ -354,6 +411,102 @@ class Solver:
         if self.ctx:
             wbpr_ctx_destroy(self.ctx)
             self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def wbpr_server_footprint(V: int, E: int) -> int:
+    out = ctypes.c_int64()
+    _check(load_library().wbpr_server_footprint(V, E, ctypes.byref(out)))
+    return out.value
+
+
+@dataclass
+class ServedResult:
+    ticket: int
+    status: int
+    value: int
+    flow: np.ndarray | None
+    side: np.ndarray | None
+    latency_ms: float
+    queue_ms: float
+
+
+class Server:
+    """Continuous-batching server on a context's device (thread-safe submit/wait)."""
+
+    def __init__(self, solver: "Solver", hbm_budget_bytes: int = 0, max_slots: int = 0, arcs_per_vertex: int = 0,
+                 want_flows: bool = True, want_sides: bool = True, max_admit: int = 0):
+        lib = load_library()
+        o = wbpr_server_options()
+        o.hbm_budget_bytes = hbm_budget_bytes
+        o.max_slots = max_slots
+        o.arcs_per_vertex = arcs_per_vertex
+        o.want_flows = int(want_flows)
+        o.want_sides = int(want_sides)
+        o.max_admit = max_admit
+        h = ctypes.c_void_p()
+        _check(lib.wbpr_server_create(solver.ctx, ctypes.byref(o), ctypes.byref(h)))
+        self.h = h.value
+        self._solver = solver  # the context must outlive the server
+
+    def submit(self, g, return_code: bool = False):
+        lib = load_library()
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+        c = np.ascontiguousarray(g.col, dtype=np.int32)
+        k = np.ascontiguousarray(g.cap, dtype=np.int32)
+        E = int(c.shape[0])
+        csr = wbpr_csr(g.V, E, rp.ctypes.data, c.ctypes.data if E else None, k.ctypes.data if E else None)
+        tk = ctypes.c_uint64()
+        rc = lib.wbpr_server_submit(self.h, ctypes.byref(csr), g.s, g.t, ctypes.byref(tk))
+        if return_code:
+            return rc, tk.value
+        _check(rc)
+        return tk.value
+
+    def _take(self, r: wbpr_result) -> ServedResult:
+        flow = np.ctypeslib.as_array(r.arc_flow, shape=(r.E,)).copy() if r.arc_flow else None
+        side = np.ctypeslib.as_array(r.cut_side, shape=(r.V,)).copy() if r.cut_side else None
+        out = ServedResult(r.ticket, r.status, r.value, flow, side, r.latency_ms, r.queue_ms)
+        load_library().wbpr_result_free(ctypes.byref(r))
+        return out
+
+    def poll(self, ticket: int):
+        """ServedResult when ready, None while pending."""
+        r = wbpr_result()
+        rc = load_library().wbpr_server_poll(self.h, ticket, ctypes.byref(r))
+        if rc == WBPR_EAGAIN:
+            return None
+        _check(rc)
+        return self._take(r)
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        r = wbpr_result()
+        rc = load_library().wbpr_server_wait(self.h, ticket, timeout_ms, ctypes.byref(r))
+        if rc == WBPR_EAGAIN:
+            return None
+        _check(rc)
+        return self._take(r)
+
+    def stats(self) -> dict:
+        st = wbpr_server_stats()
+        _check(load_library().wbpr_server_get_stats(self.h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def close(self):
+        if self.h:
+            load_library().wbpr_server_destroy(self.h)
+            self.h = None
 
     def __enter__(self):
         return self

@@ -70,3 +70,38 @@ def test_missing_library_fails_loudly(tmp_path):
             wbpr.load_library(str(tmp_path / "nope.so"))
         finally:
             wbpr._lib = wbpr._lib_backup
+
+
+def test_server_struct_layouts_match_header(tmp_path):
+    import subprocess
+
+    probe = tmp_path / "probe_srv.c"
+    probe.write_text(r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "wbpr.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(wbpr_server_options), sizeof(wbpr_result), sizeof(wbpr_server_stats));
+  printf("%zu %zu %zu %zu\n", offsetof(wbpr_result, value), offsetof(wbpr_result, cut_side),
+         offsetof(wbpr_server_stats, p99_ms), offsetof(wbpr_server_stats, peak_resident));
+  return 0;
+}
+""")
+    exe = tmp_path / "probe_srv"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(probe), "-o", str(exe)])
+    got = list(map(int, subprocess.check_output([str(exe)]).decode().split()))
+    assert got == [ctypes.sizeof(wbpr.wbpr_server_options), ctypes.sizeof(wbpr.wbpr_result),
+                   ctypes.sizeof(wbpr.wbpr_server_stats), wbpr.wbpr_result.value.offset,
+                   wbpr.wbpr_result.cut_side.offset, wbpr.wbpr_server_stats.p99_ms.offset,
+                   wbpr.wbpr_server_stats.peak_resident.offset]
+
+
+def test_admission_footprint_formula():
+    """Arena bytes per resident instance: 57 V + 44 E + ceil(E/64) (pure host call)."""
+    for V, E in [(2, 0), (1000, 8000), (65536, 524288), (4194304, 65242560)]:
+        assert wbpr.wbpr_server_footprint(V, E) == 57 * V + 44 * E + (E + 63) // 64
+    # O(V + E): doubling both doubles the footprint up to the rounding term
+    a, b = wbpr.wbpr_server_footprint(10_000, 80_000), wbpr.wbpr_server_footprint(20_000, 160_000)
+    assert abs(b - 2 * a) <= 1
+    with pytest.raises(wbpr.WbprError):
+        wbpr.wbpr_server_footprint(-1, 5)
