@@ -98,6 +98,22 @@ def kernel_table(stats):
     return kernels
 
 
+def measured_traffic(kernel: str, workload: str):
+    """Calibrated HBM bytes per launch from the committed rocprofv3 counter
+    runs, or None when the kernel sources changed since they were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in rec["sources"])).hexdigest()
+    if h != rec["sources_sha256"]:
+        return None
+    return rec["bytes_per_launch"].get(kernel)
+
+
 def roofline_of(stats, kernels):
     dom = max(range(4), key=lambda k: kernels[k]["ms"])
     if kernels[dom]["launches"] == 0 or kernels[dom]["ms"] <= 0:
@@ -249,6 +265,8 @@ def main():
     ap.add_argument("--push-mode", type=int, default=0)
     ap.add_argument("--blocks", type=int, default=0)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -263,6 +281,17 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy > 0:
+        # a plain copy reads and writes exactly n bytes each: the reference
+        # for scaling FETCH_SIZE / WRITE_SIZE counters
+        n = args.calibrate_copy << 20
+        x = torch.ones(n // 4, dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
+        return
     t0 = time.perf_counter()
     g = W.CONFIGS[args.workload]()
     log(f"[bench] generated {g.name}: V={g.V} E={g.E} in {time.perf_counter() - t0:.1f}s")
@@ -314,6 +343,8 @@ def main():
         assert int(value.item()) == flow_value
     kernels = kernel_table(kstats) if kstats else None
     roofline = roofline_of(kstats, kernels) if kstats else None
+    if roofline is not None and args.workload == "rmat":
+        roofline["traffic"] = measured_traffic(roofline["kernel"], "rmat_s22")
 
     out = {
         "metric": "max-flow solve time & arc-scans/s (GB/s vs HBM peak); batched solves/s + p99",
