@@ -51,7 +51,7 @@ HBM_PEAK_GBS = 8000.0
 #                  rebuild reads e 8 + h 4).
 B_SCAN, B_QUEUED, B_PUSH, B_RELABEL = 12, 24, 52, 4
 B_BFS_TD, B_BFS_BU, B_BFS_V = 12, 9, 17
-KERNELS = ["k_sweep_tile", "k_sweep_tile<64> (medium rows)", "k_sweep_block (long rows)", "k_global_relabel"]
+KERNELS = ["k_sweep_tile", "k_sweep_tile<64> (medium rows)", "k_sweep_chunk (long-row chunks)", "k_global_relabel"]
 
 
 def kernel_bytes(st, k):

@@ -79,7 +79,10 @@ enum wbpr_layout { WBPR_LAYOUT_AUTO = 0, WBPR_LAYOUT_BCSR = 1 };
  * them changes the results, only the speed. */
 typedef struct wbpr_options {
     int32_t layout;            /* enum wbpr_layout */
-    int32_t lanes_per_vertex;  /* lanes scanning one queued vertex: 4,8,16,32,64 */
+    int32_t lanes_per_vertex;  /* lanes scanning one queued vertex: 4,8,16,32,64;
+                                  1 = thread-centric (one thread scans a
+                                  whole row, no medium or long tiers: the
+                                  paper's TC baseline) */
     int32_t split_degree;      /* rows longer than this get one wave each */
     int32_t gr_every_sweeps;   /* fixed sweeps between global relabels
                                   (0 = adaptive, at most 64) */
@@ -99,7 +102,12 @@ typedef struct wbpr_options {
                                   of (V + M) entries (0 = 1000) */
     int32_t no_graph;          /* 1: launch sweeps one by one instead of
                                   replaying a captured hipGraph */
-    int32_t reserved[3];
+    int32_t avq_mode;          /* active-vertex queue: 0 or 2 incremental
+                                  (push targets and still-active vertices are
+                                  appended as they go), 1 full scan of every
+                                  vertex at the start of each sweep
+                                  (Algorithm 2 as printed) */
+    int32_t reserved[2];
 } wbpr_options;
 
 /* Per-solve counters and timings (filled when a non-NULL pointer is given). */
@@ -209,9 +217,11 @@ int wbpr_solve_batch(wbpr_ctx *ctx, int32_t n, const wbpr_csr *graphs, const int
  *
  * Admission footprint of one instance with V vertices and E arcs (bytes of
  * the arena it occupies while resident, see wbpr_server_footprint):
- *   57 V + 44 E + ceil(E / 64)
+ *   69 V + 44 E + ceil(E / 32)
  *     (rows 8V; entries 16 B per slot, 2E slots; arcs 12E; excess, height,
- *      queues and visit codes 41V; long-row chunk descriptors 8(V + 2E/1024))
+ *      owner, queues, frontiers, long-row list and counters, visit codes 45V;
+ *      BFS chunk descriptors 8(V + 2E/1024); long-row chunk tasks
+ *      8(V + 2E/1024))
  * plus outputs 8 + 4E + V and, during admission only, the input staging
  * 8(V+1) + 8E and the builder scratch.
  * ---------------------------------------------------------------------- */

@@ -50,14 +50,16 @@ wb::SolveConfig to_config(const wbpr_options *o) {
   c.time_kernels = o->time_kernels != 0;
   c.push_mode = o->push_mode;
   c.use_graph = o->no_graph == 0;
+  c.full_scan = o->avq_mode == 1;
   return c;
 }
 
 int check_options(const wbpr_options *o) {
   if (!o) return WBPR_OK;
   int P = o->lanes_per_vertex;
-  if (P != 0 && P != 4 && P != 8 && P != 16 && P != 32 && P != 64)
-    return fail(WBPR_EINVAL, "lanes_per_vertex must be 0, 4, 8, 16, 32 or 64");
+  if (P != 0 && P != 1 && P != 4 && P != 8 && P != 16 && P != 32 && P != 64)
+    return fail(WBPR_EINVAL, "lanes_per_vertex must be 0, 1, 4, 8, 16, 32 or 64");
+  if (o->avq_mode < 0 || o->avq_mode > 2) return fail(WBPR_EINVAL, "avq_mode must be 0, 1 or 2");
   if (o->split_degree < 0 || o->block_degree < 0 || o->gr_every_sweeps < 0 || o->gr_work_permille < 0 ||
       o->max_sweeps < 0 || o->max_wall_ms < 0 || o->grid_blocks < 0)
     return fail(WBPR_EINVAL, "negative option");
@@ -85,7 +87,7 @@ void fill_stats(wbpr_stats *st, const wb::EngineStats &r, const wb::SolveConfig 
   st->split_degree = r.split_degree;
   st->block_degree = r.block_degree;
   st->gr_every_sweeps = cfg.gr_every_sweeps;
-  st->grid_blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : 1024;
+  st->grid_blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : 2048;
   st->gr_blocks = r.gr_blocks;
   st->ms_build = ms_build;
   st->ms_phase1 = ms_solve;  // both phases, interleaved per instance

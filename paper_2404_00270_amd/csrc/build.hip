@@ -29,7 +29,7 @@ namespace {
 struct Scratch {
   uint64_t *k0, *k1;
   uint32_t *v0, *v1;
-  int32_t *head, *hx, *wpos, *gstart, *rowcnt, *rptr, *hist, *stemp;
+  int32_t *head, *hx, *uid_of, *gstart, *rowcnt, *rptr, *hist, *stemp;
   int64_t *pcap, *stemp64;
   unsigned long long *capacc;
 };
@@ -37,7 +37,7 @@ struct Scratch {
 size_t carve_scratch(int32_t V, int64_t E, void *mem, Scratch *s) {
   int64_t N = 2 * E > 0 ? 2 * E : 1;
   int64_t hn = radix_hist_elems(N);
-  int64_t st = scan_temp_elems(hn > N + 1 ? hn : (N > V + 1 ? N : V + 1)) + 2;
+  int64_t st = scan_temp_elems(hn > N + 1 ? hn : (N + 1 > V + 1 ? N + 1 : V + 1)) + 2;
   char *base = (char *)mem, *p = base;
   auto take = [&](size_t bytes) { char *q = p; p += align256(bytes); return (void *)q; };
   s->k0 = (uint64_t *)take(8 * N);
@@ -46,13 +46,13 @@ size_t carve_scratch(int32_t V, int64_t E, void *mem, Scratch *s) {
   s->v1 = (uint32_t *)take(4 * N);
   s->head = (int32_t *)take(4 * N);
   s->hx = (int32_t *)take(4 * N);
-  s->wpos = (int32_t *)take(4 * N);
-  s->gstart = (int32_t *)take(4 * N);
+  s->uid_of = (int32_t *)take(4 * N);
+  s->gstart = (int32_t *)take(4 * (N + 1));
   s->rowcnt = (int32_t *)take(4 * ((size_t)V + 1));
   s->rptr = (int32_t *)take(4 * ((size_t)V + 1));
   s->hist = (int32_t *)take(4 * (size_t)hn);
   s->stemp = (int32_t *)take(4 * (size_t)st);
-  s->pcap = (int64_t *)take(8 * N);
+  s->pcap = (int64_t *)take(8 * (N + 1));
   s->stemp64 = (int64_t *)take(8 * (size_t)st);
   s->capacc = (unsigned long long *)take(8 * N);
   return (size_t)(p - base);
@@ -129,35 +129,48 @@ __global__ void k_heads(const uint64_t *keys, int64_t N, const BuildStatus *st, 
   }
 }
 
-// Step 3b.  Unique id of item i = hx[i] + head[i] - 1.
+// Step 3b.  Unique id of item i = hx[i] + head[i] - 1.  Group heads write
+// the entry's column and start; every item records its unique id under its
+// payload (arc * 2 + direction) and its forward capacity for the scan.
 __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, const int32_t *cap,
                          const BuildStatus *st, const int32_t *head, const int32_t *hx, int2 *ent, int32_t vbase,
-                         int32_t *gstart, unsigned long long *capacc, int32_t *wpos, int64_t *pcap) {
-  int64_t mraw = N - 2 * (int64_t)st->nself;
+                         int32_t *gstart, int32_t *uid_of, int64_t *pcap) {
+  const int64_t mraw = N - 2 * (int64_t)st->nself;
+  const int32_t M = st->M;
   const uint64_t cmask = (1ull << vb) - 1;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    if (i >= mraw) { pcap[i] = 0; continue; }
-    uint64_t key = keys[i];
-    uint32_t pl = vals[i];
-    int32_t u = hx[i] + head[i] - 1;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= N; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i >= mraw) {
+      pcap[i] = 0;
+      if (i == mraw) gstart[M] = (int32_t)mraw;  // end of the last group
+      continue;
+    }
+    const uint64_t key = keys[i];
+    const uint32_t pl = vals[i];
+    const int32_t u = hx[i] + head[i] - 1;
     if (head[i]) {
       ent[u] = make_int2(vbase + (int)(key & cmask), 0);
       gstart[u] = (int32_t)i;
-      capacc[u] = 0;
     }
-    wpos[pl] = (int32_t)i;
+    uid_of[pl] = u;
     pcap[i] = (pl & 1u) ? 0 : (int64_t)cap[pl >> 1];
   }
 }
 
-__global__ void k_capacc(const uint32_t *vals, int64_t N, const int32_t *cap, const BuildStatus *st,
-                         const int32_t *head, const int32_t *hx, unsigned long long *capacc) {
-  int64_t mraw = N - 2 * (int64_t)st->nself;
+// Step 3b'.  After the scan of pcap (pc[i] = forward capacity of sorted
+// items before i): merged capacity of entry u = forward capacity of its
+// group; capacity of earlier parallel arcs of forward item i = pc[i] - pc of
+// its group's start (the sort is stable, so a group's arcs are in input
+// order).
+__global__ void k_group_caps(const uint32_t *vals, const BuildStatus *st, const int32_t *head, const int32_t *hx,
+                             const int32_t *gstart, const int64_t *pc, unsigned long long *capacc, int32_t *pbefore_arc,
+                             int64_t N) {
+  const int64_t mraw = N - 2 * (int64_t)st->nself;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mraw; i += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t pl = vals[i];
-    if (pl & 1u) continue;
-    int32_t u = hx[i] + head[i] - 1;
-    atomicAdd(&capacc[u], (unsigned long long)cap[pl >> 1]);
+    const int32_t u = hx[i] + head[i] - 1;
+    const int64_t g0 = pc[gstart[u]];
+    if (head[i]) capacc[u] = (unsigned long long)(pc[gstart[u + 1]] - g0);
+    const uint32_t pl = vals[i];
+    if (!(pl & 1u)) pbefore_arc[pl >> 1] = (int32_t)(pc[i] - g0);
   }
 }
 
@@ -184,20 +197,20 @@ __global__ void k_rowb(const int32_t *rptr, int32_t V, int32_t vbase, int32_t mb
     rowb[vbase + x] = make_int2(mbase + rptr[x], mbase + rptr[x + 1]);
 }
 
-// Step 4.  Mates and the arc -> entry map; capacity of earlier parallel arcs.
-// rev, arc2ent and pbefore point at this build's slices of the arena; the
-// stored indices are absolute (local + mbase).
-__global__ void k_arcs(int64_t E, const int32_t *wpos, const int32_t *head, const int32_t *hx, const int32_t *gstart,
-                       const int64_t *pcap_scanned, int32_t mbase, int32_t *rev, int32_t *arc2ent, int32_t *pbefore) {
+// Step 4.  Mates and the arc -> entry map (arc order: sequential reads).
+// rev and arc2ent point at this build's slices of the arena; the stored
+// indices are absolute (local + mbase).
+__global__ void k_arcs(int64_t E, const int32_t *uid_of, int32_t mbase, int32_t *rev, int32_t *arc2ent,
+                       int32_t *pbefore) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
-    if (arc2ent[i] < 0) { pbefore[i] = 0; continue; }
-    int32_t pf = wpos[2 * i], pb = wpos[2 * i + 1];
-    int32_t f = hx[pf] + head[pf] - 1;
-    int32_t b = hx[pb] + head[pb] - 1;
+    if (arc2ent[i] < 0) {
+      pbefore[i] = 0;
+      continue;
+    }
+    const int32_t f = uid_of[2 * i], b = uid_of[2 * i + 1];
     rev[f] = mbase + b;
     rev[b] = mbase + f;
     arc2ent[i] = mbase + f;
-    pbefore[i] = (int32_t)(pcap_scanned[pf] - pcap_scanned[gstart[f]]);
   }
 }
 
@@ -252,16 +265,17 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
   hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(BT), 0, st, keys, N, status_dev, s.head);
   e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_unique, dim3(grid_for(N)), dim3(BT), 0, st, keys, vals, N, vb, cap, status_dev, s.head, s.hx,
-                     ent, pl.vbase, s.gstart, s.capacc, s.wpos, s.pcap);
-  hipLaunchKernelGGL(k_capacc, dim3(grid_for(N)), dim3(BT), 0, st, vals, N, cap, status_dev, s.head, s.hx, s.capacc);
-  e = excl_scan_i64(s.pcap, s.pcap, N, nullptr, s.stemp64, st);
+  hipLaunchKernelGGL(k_unique, dim3(grid_for(N + 1)), dim3(BT), 0, st, keys, vals, N, vb, cap, status_dev, s.head,
+                     s.hx, ent, pl.vbase, s.gstart, s.uid_of, s.pcap);
+  e = excl_scan_i64(s.pcap, s.pcap, N + 1, nullptr, s.stemp64, st);
   if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_group_caps, dim3(grid_for(N)), dim3(BT), 0, st, vals, status_dev, s.head, s.hx, s.gstart, s.pcap,
+                     s.capacc, pbefore, N);
   hipLaunchKernelGGL(k_rowptr, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, N, vb, V, status_dev, s.hx,
                      s.rptr);
   hipLaunchKernelGGL(k_rowb, dim3(grid_for(V)), dim3(BT), 0, st, s.rptr, V, pl.vbase, (int32_t)pl.mbase, A.rowb);
-  hipLaunchKernelGGL(k_arcs, dim3(grid_for(E)), dim3(BT), 0, st, E, s.wpos, s.head, s.hx, s.gstart, s.pcap,
-                     (int32_t)pl.mbase, rev, arc2ent, pbefore);
+  hipLaunchKernelGGL(k_arcs, dim3(grid_for(E)), dim3(BT), 0, st, E, s.uid_of, (int32_t)pl.mbase, rev, arc2ent,
+                     pbefore);
   hipLaunchKernelGGL(k_caps, dim3(grid_for(N)), dim3(BT), 0, st, status_dev, s.capacc, rev, (int32_t)pl.mbase, ent,
                      cap0, status_dev);
   return hipGetLastError();

@@ -241,6 +241,7 @@ struct MiscLayout {
   int32_t chunk_cnt[2];
   int32_t big_cnt[2];
   int32_t mid_cnt[2];
+  int32_t task_cnt[2];
   int32_t bucnt[4];
   int32_t halt[2];
   long long rwork;
@@ -248,13 +249,19 @@ struct MiscLayout {
   unsigned bar[WB_BAR_WORDS];
   long long fedges[4];
   int32_t sink;
-  int32_t pad;
+  int32_t log_n;
   long long budget;
+  int32_t scan_cnt;  // full-scan queue count
+  int32_t span;      // end of the highest resident vertex range
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int64_t chunk_capacity(int64_t Vcap, int64_t Mcap, int chunk) { return Mcap / chunk + Vcap + 16; }
+
+// Long-row chunk tasks of one sweep: every deferred vertex has
+// ceil(deg / CHUNK) <= deg / CHUNK + 1 tasks.
+int64_t task_capacity(int64_t Vcap, int64_t Mcap) { return Vcap + Mcap / CHUNK + 64; }
 
 unsigned grid1d(int64_t n, int threads = 256, int64_t maxb = 65536) {
   int64_t b = (n + threads - 1) / threads;
@@ -283,6 +290,7 @@ int log_level() {
 }
 
 constexpr int kListKinds = 8;   // separate staging per per-instance kernel kind
+constexpr int kSweepLogCap = 16384;  // sweep-log records kept (WBPR_LOG >= 2)
 constexpr size_t kPinnedHeader = 4096;
 }  // namespace
 
@@ -294,12 +302,16 @@ size_t Engine::arena_bytes(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t nca
   b += 2 * al(4 * (size_t)Mcap);             // rev, cap0
   b += 3 * al(4 * (size_t)Ecap);             // arc2ent, pbefore, acap
   b += al(8 * (size_t)Vcap);                 // e
-  b += 8 * al(4 * (size_t)Vcap);             // h, inst_of, q0, q1, fq0, fq1, mid, big
+  b += 5 * al(4 * (size_t)Vcap);             // h, inst_of, q0, q1, mid
+  b += 2 * al(4 * (size_t)Vcap);             // BFS frontiers fq0, fq1
+  b += 2 * al(4 * (size_t)Vcap);             // long-row list, lr_cnt
+  b += 2 * al(4 * (size_t)task_capacity(Vcap, Mcap));  // chunk tasks
   b += al((size_t)Vcap);                     // vis
-  b += 2 * al(4 * (size_t)nch);              // chunk descriptors
+  b += al(8 * (size_t)nch);                  // BFS chunk descriptors (sweeps: lr_key)
   b += 5 * al(4 * (size_t)ncap);             // active, stranded, roots, root_h, excl
   b += al(sizeof(InstDev) * (size_t)ncap * kListKinds + 4 * (size_t)ncap);  // lists + slots
   b += al(sizeof(MiscLayout));
+  b += al(6 * 4 * (size_t)kSweepLogCap);     // sweep log (diagnostics)
   return b;
 }
 
@@ -316,8 +328,7 @@ Engine::Engine(int device) : device_(device) {
 }
 
 Engine::~Engine() {
-  if (graph_exec_) hipGraphExecDestroy(graph_exec_);
-  if (graph_) hipGraphDestroy(graph_);
+  drop_graphs();
   for (auto &e : ev_) hipEventDestroy(e);
   if (arena_) hipFree(arena_);
   if (scratch_) hipFree(scratch_);
@@ -326,10 +337,16 @@ Engine::~Engine() {
 
 void Engine::set_config(const SolveConfig &cfg) {
   cfg_ = cfg;
-  if (graph_exec_) hipGraphExecDestroy(graph_exec_);
-  if (graph_) hipGraphDestroy(graph_);
-  graph_exec_ = nullptr;
-  graph_ = nullptr;
+  drop_graphs();
+  next_K_ = 64;
+}
+
+void Engine::drop_graphs() {
+  for (auto &kv : graphs_) {
+    hipGraphExecDestroy(kv.second.second);
+    hipGraphDestroy(kv.second.first);
+  }
+  graphs_.clear();
 }
 
 int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int64_t sV, int64_t sE, int32_t sn,
@@ -348,10 +365,7 @@ int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int6
     return WBPR_EAGAIN;
   }
   if (grow_arena) {
-    if (graph_exec_) hipGraphExecDestroy(graph_exec_);
-    if (graph_) hipGraphDestroy(graph_);
-    graph_exec_ = nullptr;
-    graph_ = nullptr;
+    drop_graphs();
     Vcap = std::max(Vcap, Vcap_);
     Mcap = std::max(Mcap, Mcap_);
     Ecap = std::max(Ecap, Ecap_);
@@ -386,14 +400,21 @@ int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int6
     inst_of_ = (int32_t *)take(4 * (size_t)Vcap);
     q_[0] = (int32_t *)take(4 * (size_t)Vcap);
     q_[1] = (int32_t *)take(4 * (size_t)Vcap);
+    mid_ = (int32_t *)take(4 * (size_t)Vcap);
     fq_[0] = (int32_t *)take(4 * (size_t)Vcap);
     fq_[1] = (int32_t *)take(4 * (size_t)Vcap);
-    mid_ = (int32_t *)take(4 * (size_t)Vcap);
     big_ = (int32_t *)take(4 * (size_t)Vcap);
+    lr_cnt_ = (int32_t *)take(4 * (size_t)Vcap);
+    tcap_ = task_capacity(Vcap, Mcap);
+    task_u_ = (int32_t *)take(4 * (size_t)tcap_);
+    task_c_ = (int32_t *)take(4 * (size_t)tcap_);
     vis_ = (uint8_t *)take((size_t)Vcap);
     nchunk_ = chunk_capacity(Vcap, Mcap, chunk_);
-    chunk_w_ = (int32_t *)take(4 * (size_t)nchunk_);
-    chunk_b_ = (int32_t *)take(4 * (size_t)nchunk_);
+    chunk_w_ = (int32_t *)take(8 * (size_t)nchunk_);
+    chunk_b_ = chunk_w_ + nchunk_;
+    // the BFS chunk descriptors are idle during sweeps: the long rows'
+    // minimum keys live there
+    lr_key_ = reinterpret_cast<unsigned long long *>(chunk_w_);
     inst_active_ = (int32_t *)take(4 * (size_t)ncap);
     inst_stranded_ = (int32_t *)take(4 * (size_t)ncap);
     roots_ = (int32_t *)take(4 * (size_t)ncap);
@@ -401,6 +422,8 @@ int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int6
     excl_ = (int32_t *)take(4 * (size_t)ncap);
     inst_list_ = take(sizeof(InstDev) * (size_t)ncap * kListKinds + 4 * (size_t)ncap);
     misc_ = (long long *)take(sizeof(MiscLayout));
+    sweep_log_dev_ = (int32_t *)take(6 * 4 * (size_t)kSweepLogCap);
+    sweep_log_ = log_level() >= 2 ? sweep_log_dev_ : nullptr;
     MiscLayout *m = reinterpret_cast<MiscLayout *>(misc_);
     sink_ = &m->sink;
     budget_ = &m->budget;
@@ -705,46 +728,75 @@ void Engine::release_groups(const std::vector<int> &gis, hipStream_t st) {
   }
 }
 
-int Engine::ensure_graph(hipStream_t st, std::string *err) {
-  if (graph_exec_) return 0;
+// Captured batch of K sweeps (one cached graph per K).
+int Engine::ensure_graph(hipStream_t st, int K, hipGraphExec_t *exec, std::string *err) {
+  auto it = graphs_.find(K);
+  if (it != graphs_.end()) {
+    *exec = it->second.second;
+    return 0;
+  }
   hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) {
     *err = std::string("graph capture: ") + hipGetErrorString(e);
     return WBPR_EDEVICE;
   }
-  const int K = cfg_.gr_every_sweeps > 0 ? cfg_.gr_every_sweeps : 64;
   enqueue_sweeps(st, K);
-  e = hipStreamEndCapture(st, &graph_);
-  if (e == hipSuccess) e = hipGraphInstantiate(&graph_exec_, graph_, nullptr, nullptr, 0);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t ge = nullptr;
+  e = hipStreamEndCapture(st, &graph);
+  if (e == hipSuccess) e = hipGraphInstantiate(&ge, graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
     *err = std::string("graph instantiate: ") + hipGetErrorString(e);
-    if (graph_) hipGraphDestroy(graph_);
-    graph_ = nullptr;
-    graph_exec_ = nullptr;
+    if (graph) hipGraphDestroy(graph);
     return WBPR_EDEVICE;
   }
-  graph_K_ = K;
+  graphs_[K] = {graph, ge};
+  *exec = ge;
   return 0;
+}
+
+void Engine::dump_sweep_log(hipStream_t st) {
+  MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+  int32_t n = 0;
+  if (hipMemcpyAsync(&n, &misc->log_n, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return;
+  if (hipStreamSynchronize(st) != hipSuccess) return;
+  n = std::min(n, kSweepLogCap);
+  std::vector<int32_t> rec(6 * (size_t)std::max(n, 1));
+  if (n > 0 && hipMemcpy(rec.data(), sweep_log_dev_, 24 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) return;
+  std::fprintf(stderr, "[wbpr] sweep log: %d sweeps (queue, medium, long, chunk tasks, queue out, relabel work)\n", n);
+  for (int i = 0; i < n; i++)
+    std::fprintf(stderr, "[wbpr] sweep %5d: %9d %8d %7d %8d %9d %11d\n", i, rec[6 * i], rec[6 * i + 1], rec[6 * i + 2],
+                 rec[6 * i + 3], rec[6 * i + 4], rec[6 * i + 5]);
+  hipMemsetAsync(&misc->log_n, 0, 4, st);
 }
 
 void Engine::enqueue_sweeps(hipStream_t st, int K) {
   MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
   Graph g{(int32_t)Vcap_, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_};
-  const int sweep_blocks = cfg_.grid_blocks > 0 ? cfg_.grid_blocks : 1024;
-  const int block_blocks = 512;
+  const int sweep_blocks = cfg_.grid_blocks > 0 ? cfg_.grid_blocks : 2048;
+  const int chunk_blocks = 2048;
   const int mode = cfg_.push_mode == 1 ? 0 : 1;
   const bool timed = cfg_.time_kernels;
+  const bool fs = cfg_.full_scan;
   for (int j = 0; j < K; j++) {
     SweepQ q;
-    q.qin = q_[j & 1];
-    q.qin_cnt = &misc->qcnt[j % 3];
-    q.qout = q_[(j + 1) & 1];
-    q.qout_cnt = &misc->qcnt[(j + 1) % 3];
-    q.zero_cnt = &misc->qcnt[(j + 2) % 3];
+    q.qin = fs ? q_[1] : q_[j & 1];
+    q.qin_cnt = fs ? &misc->scan_cnt : &misc->qcnt[j % 3];
+    q.qout = fs ? q_[0] : q_[(j + 1) & 1];
+    q.qout_cnt = fs ? &misc->qcnt[0] : &misc->qcnt[(j + 1) % 3];
+    q.zero_cnt = fs ? &misc->qcnt[0] : &misc->qcnt[(j + 2) % 3];
+    q.append = fs ? 0 : 1;
     q.mid_v = mid_;
     q.mid_cnt = &misc->mid_cnt[j & 1];
     q.big_v = big_;
     q.big_cnt = &misc->big_cnt[j & 1];
+    q.task_u = task_u_;
+    q.task_c = task_c_;
+    q.task_cnt = &misc->task_cnt[j & 1];
+    q.zero_c = &misc->task_cnt[(j + 1) & 1];
+    q.tcap = (int32_t)std::min<int64_t>(tcap_, 0x7fffffff);
+    q.lr_key = lr_key_;
+    q.lr_cnt = lr_cnt_;
     q.zero_a = &misc->mid_cnt[(j + 1) & 1];
     q.zero_b = &misc->big_cnt[(j + 1) & 1];
     q.t_mid = t_mid_;
@@ -774,13 +826,32 @@ void Engine::enqueue_sweeps(hipStream_t st, int K) {
       ev_marks_.push_back({0, evb});
       hipEventRecord(ev_[evb], st);
     }
+    if (fs)
+      launch_avq_scan(sweep_blocks, st, g, &misc->span, q_[1], &misc->scan_cnt, (int32_t)Vcap_, misc->err,
+                      &misc->halt[0]);
     launch_sweep_tile(P_, sweep_blocks, st, g, q);
     if (timed) hipEventRecord(ev_[evb + 1], st);
     launch_sweep_tile(64, sweep_blocks, st, g, qw);
     if (timed) hipEventRecord(ev_[evb + 2], st);
-    launch_sweep_block(block_blocks, st, g, q);
+    launch_sweep_chunk(0, chunk_blocks, st, g, q);
+    launch_sweep_chunk(1, chunk_blocks, st, g, q);
+    launch_sweep_chunk(2, 64, st, g, q);
     if (timed) hipEventRecord(ev_[evb + 3], st);
-    launch_sweep_control(st, q.qout_cnt, &misc->rwork, &misc->rwork_at_gr, budget_, &misc->halt[0]);
+    SweepCtl ctl;
+    ctl.qin_cnt = q.qin_cnt;
+    ctl.mid_cnt = q.mid_cnt;
+    ctl.big_cnt = q.big_cnt;
+    ctl.task_cnt = q.task_cnt;
+    ctl.qout_cnt = q.qout_cnt;
+    ctl.rwork = &misc->rwork;
+    ctl.rwork_at_gr = &misc->rwork_at_gr;
+    ctl.budget = budget_;
+    ctl.halt = &misc->halt[0];
+    ctl.scan_cnt = fs ? &misc->scan_cnt : nullptr;
+    ctl.log = sweep_log_;
+    ctl.log_n = &misc->log_n;
+    ctl.log_cap = kSweepLogCap;
+    launch_sweep_control(st, ctl);
   }
 }
 
@@ -791,17 +862,15 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   // the grid cut, 16 for R-MAT)
   const double mean_row = resident_V_ > 0 ? (double)resident_M_ / (double)resident_V_ : 1.0;
   const int P = cfg_.lanes_per_vertex > 0 ? cfg_.lanes_per_vertex : (mean_row <= 10.0 ? 4 : mean_row <= 20.0 ? 8 : 16);
-  const int tm = cfg_.split_degree > 0 ? cfg_.split_degree : 4 * P;
-  const int tb = std::max(tm, cfg_.block_degree > 0 ? cfg_.block_degree : 2048);
+  // one lane per vertex is the thread-centric baseline: no medium or long tiers
+  const int tm = P == 1 ? 0x7fffffff : cfg_.split_degree > 0 ? cfg_.split_degree : 4 * P;
+  const int tb = P == 1 ? 0x7fffffff : std::max(tm, cfg_.block_degree > 0 ? cfg_.block_degree : 2048);
   if (P != P_ || tm != t_mid_ || tb != t_big_) {
     P_ = P;
     t_mid_ = tm;
     t_big_ = tb;
     bfs_split_ = 8 * P;
-    if (graph_exec_) hipGraphExecDestroy(graph_exec_);
-    if (graph_) hipGraphDestroy(graph_);
-    graph_exec_ = nullptr;
-    graph_ = nullptr;
+    drop_graphs();
   }
   acc_.lanes = P_;
   acc_.split_degree = t_mid_;
@@ -823,22 +892,24 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   if (nr == 1) sink = hroots[0];
   const double beta = cfg_.gr_work_permille > 0 ? cfg_.gr_work_permille / 1000.0 : gr_beta_env();
   long long *hmisc = reinterpret_cast<long long *>(pin_ + 512);
+  // the relabel and the full-scan queue visit vertices up to the end of the
+  // highest resident group (free vertices below it are inactive, empty rows)
+  int64_t vhi = 0;
+  for (const Group &G : groups_)
+    if (G.used) vhi = std::max<int64_t>(vhi, (int64_t)G.vbase + G.V);
   hmisc[0] = sink;
+  hmisc[2] = vhi;
   hmisc[1] = cfg_.gr_every_sweeps > 0 ? (1LL << 62) : (long long)(beta * (double)(resident_V_ + resident_M_));
   hipMemcpyAsync(roots_, hroots, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
   hipMemcpyAsync(root_h_, hrh, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
   hipMemcpyAsync(excl_, hex, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
   hipMemcpyAsync(sink_, &hmisc[0], 4, hipMemcpyHostToDevice, st);
   hipMemcpyAsync(budget_, &hmisc[1], 8, hipMemcpyHostToDevice, st);
+  hipMemcpyAsync(&misc->span, &hmisc[2], 4, hipMemcpyHostToDevice, st);
   hipMemsetAsync(misc->status, 0, sizeof(misc->status), st);
   hipMemsetAsync(inst_active_, 0, 4 * (size_t)ncap_, st);
   hipMemsetAsync(inst_stranded_, 0, 4 * (size_t)ncap_, st);
 
-  // the relabel visits vertices up to the end of the highest resident group
-  // (free vertices below it are inactive with empty rows)
-  int64_t vhi = 0;
-  for (const Group &G : groups_)
-    if (G.used) vhi = std::max<int64_t>(vhi, (int64_t)G.vbase + G.V);
   Graph g{(int32_t)vhi, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_};
   GRArgs ga;
   ga.g = g;
@@ -864,6 +935,7 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   ga.qcnt = misc->qcnt;
   ga.big_cnt = misc->big_cnt;
   ga.mid_cnt = misc->mid_cnt;
+  ga.task_cnt = misc->task_cnt;
   ga.stats = misc->stats;
   ga.status = misc->status;
   ga.split_deg = bfs_split_;
@@ -876,8 +948,9 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   ga.halt = misc->halt;
   ga.rwork = &misc->rwork;
   ga.rwork_at_gr = &misc->rwork_at_gr;
+  const int Pg = std::max(P_, 4);  // tile width of the relabel's top-down expansion
   int lg = 0;
-  while ((1 << lg) < P_) lg++;
+  while ((1 << lg) < Pg) lg++;
   const int gr_blocks = std::min(gr_blocks_[lg], 1024);
   acc_.gr_blocks = gr_blocks;
   if (gr_blocks < 1) {
@@ -897,7 +970,7 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
     ev_marks_.push_back({3, evb});
     hipEventRecord(ev_[evb], st);
   }
-  hipError_t he = launch_global_relabel(P_, gr_blocks, st, ga);
+  hipError_t he = launch_global_relabel(Pg, gr_blocks, st, ga);
   if (he != hipSuccess) {
     *err = std::string("global relabel launch: ") + hipGetErrorString(he);
     return WBPR_EDEVICE;
@@ -912,6 +985,7 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   int32_t *hstr = hact + ncap_;
   if (he == hipSuccess) he = hipMemcpyAsync(hact, inst_active_, 4 * (size_t)ncap_, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipMemcpyAsync(hstr, inst_stranded_, 4 * (size_t)ncap_, hipMemcpyDeviceToHost, st);
+  if (he == hipSuccess) he = hipMemcpyAsync(rb + 64, &misc->stats[13], 8, hipMemcpyDeviceToHost, st);
   if (he == hipSuccess) he = hipStreamSynchronize(st);
   if (he != hipSuccess) {
     *err = std::string("global relabel: ") + hipGetErrorString(he);
@@ -958,12 +1032,27 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   for (int i : to2) inst_[i].phase = 2;
   for (int i : fin_done) inst_[i].phase = 3;
   // sweeps for the instances still active
+  // sweeps that found work in the last batch: the next batch is sized to
+  // about twice that (a halted sweep slot costs a few microseconds of empty
+  // launches, a needless global relabel far more), growing fourfold while
+  // batches run to their end
+  long long nonempty = 0;
+  std::memcpy(&nonempty, rb + 64, 8);
+  const long long ran = nonempty - last_nonempty_;
+  last_nonempty_ = nonempty;
+  if (last_K_ > 0) {
+    int k = ran >= last_K_ ? 4 * last_K_ : 16;
+    while (k < 2 * ran) k *= 2;
+    next_K_ = std::min(std::max(k, 16), 512);
+  }
   if (status[0] > 0) {
-    const int K = cfg_.gr_every_sweeps > 0 ? cfg_.gr_every_sweeps : 64;
+    const int K = cfg_.gr_every_sweeps > 0 ? cfg_.gr_every_sweeps : next_K_;
+    last_K_ = K;
     if (cfg_.use_graph && !cfg_.time_kernels) {
-      int rc = ensure_graph(st, err);
+      hipGraphExec_t exec = nullptr;
+      int rc = ensure_graph(st, K, &exec, err);
       if (rc) return rc;
-      he = hipGraphLaunch(graph_exec_, st);
+      he = hipGraphLaunch(exec, st);
       if (he != hipSuccess) {
         *err = std::string("graph launch: ") + hipGetErrorString(he);
         return WBPR_EDEVICE;
@@ -1015,6 +1104,7 @@ int Engine::run_to_completion(hipStream_t st, std::vector<Finished> *done, std::
     *err = hipGetErrorString(e);
     return WBPR_EDEVICE;
   }
+  if (sweep_log_) dump_sweep_log(st);
   return 0;
 }
 
@@ -1040,8 +1130,11 @@ void Engine::abandon(hipStream_t st) {
 
 void Engine::reset_stats() {
   acc_ = EngineStats();
+  next_K_ = 64;
+  last_K_ = 0;
   ev_used_ = 0;
   ev_marks_.clear();
+  last_nonempty_ = 0;
   if (misc_) {
     MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
     hipMemset(misc->stats, 0, sizeof(misc->stats));

@@ -141,6 +141,7 @@ constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / WB_WAVE;
 constexpr int RS_ITEMS = 16;
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+static_assert(RS_THREADS == RS_BINS, "one thread per digit in the scatter's set-up");
 
 // hist[d * nblocks + b] = number of items of tile b whose digit is d.
 __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t *keys, int64_t n, int shift, int32_t *hist,
@@ -158,57 +159,93 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t *keys, in
   for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) hist[(int64_t)d * nblocks + blockIdx.x] = cnt[d];
 }
 
-// Stable scatter.  Items are visited in index order (round j, then thread);
-// an item's destination is the scanned base of its (digit, tile) plus the
-// number of earlier items of the tile with the same digit.
+// Stable scatter through LDS.  Items are ranked in index order (round j,
+// then thread) within their digit; the tile is first rearranged in LDS by
+// (digit, rank), then written out so that consecutive threads store
+// consecutive positions of one digit's run (coalesced instead of one
+// scattered store per item).
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                           uint32_t *vout, int64_t n, int shift,
                                                           const int32_t *hist_scanned, int nblocks) {
-  __shared__ int run[RS_BINS];
-  __shared__ int wcnt[RS_WAVES][RS_BINS];
-  for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) {
-    run[d] = hist_scanned[(int64_t)d * nblocks + blockIdx.x];
+  __shared__ uint64_t s_key[RS_TILE];
+  __shared__ uint32_t s_val[RS_TILE];
+  __shared__ int s_gbase[RS_BINS];  // global position of this tile's first item of digit d
+  __shared__ int s_lbase[RS_BINS];  // LDS position of this tile's first item of digit d
+  __shared__ int s_run[RS_BINS];    // items of digit d placed so far
+  __shared__ int s_wcnt[RS_WAVES][RS_BINS];
+  __shared__ int s_wsum[RS_WAVES];
+  const int w = threadIdx.x / WB_WAVE;
+  const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+  const int tile_n = (int)(n - base < RS_TILE ? n - base : RS_TILE);
+  // this tile's digit counts from the scanned histogram (digit-major layout)
+  {
+    const int d = threadIdx.x;  // RS_THREADS == RS_BINS
+    const int64_t idx = (int64_t)d * nblocks + blockIdx.x;
+    const int g0 = hist_scanned[idx];
+    const int64_t last = (int64_t)RS_BINS * nblocks - 1;
+    const int g1 = idx < last ? hist_scanned[idx + 1] : (int)n;
+    const int cnt = g1 - g0;
+    s_gbase[d] = g0;
+    s_run[d] = 0;
 #pragma unroll
-    for (int w = 0; w < RS_WAVES; w++) wcnt[w][d] = 0;
+    for (int ww = 0; ww < RS_WAVES; ww++) s_wcnt[ww][d] = 0;
+    // exclusive prefix of the counts over digits (one workgroup scan)
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < WB_WAVE; o <<= 1) {
+      const int y = __shfl_up(incl, o, WB_WAVE);
+      if (lane() >= o) incl += y;
+    }
+    if (lane() == WB_WAVE - 1) s_wsum[w] = incl;
+    __syncthreads();
+    int off = 0;
+#pragma unroll
+    for (int ww = 0; ww < RS_WAVES; ww++) off += ww < w ? s_wsum[ww] : 0;
+    s_lbase[d] = off + incl - cnt;
   }
   __syncthreads();
-  const int w = threadIdx.x / WB_WAVE;
   const unsigned long long lt = lanemask_lt();
-  int64_t base = (int64_t)blockIdx.x * RS_TILE;
   for (int j = 0; j < RS_ITEMS; j++) {
-    int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
-    bool valid = i < n;
-    uint64_t key = valid ? kin[i] : 0;
-    uint32_t val = valid ? vin[i] : 0;
-    int d = (int)((key >> shift) & (RS_BINS - 1));
-    // lanes of this wave holding the same digit
+    const int li = j * RS_THREADS + threadIdx.x;
+    const bool valid = li < tile_n;
+    const uint64_t key = valid ? kin[base + li] : 0;
+    const uint32_t val = valid ? vin[base + li] : 0;
+    const int d = (int)((key >> shift) & (RS_BINS - 1));
     unsigned long long peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < RS_BITS; b++) {
-      unsigned long long bits = __ballot((d >> b) & 1);
+      const unsigned long long bits = __ballot((d >> b) & 1);
       peers &= ((d >> b) & 1) ? bits : ~bits;
     }
-    int rank = __popcll(peers & lt);
-    bool leader = valid && rank == 0;
-    if (leader) wcnt[w][d] = __popcll(peers);
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) s_wcnt[w][d] = __popcll(peers);
     __syncthreads();
-    int pos = 0;
     if (valid) {
-      pos = run[d] + rank;
-      for (int ww = 0; ww < w; ww++) pos += wcnt[ww][d];
+      int pos = s_lbase[d] + s_run[d] + rank;
+      for (int ww = 0; ww < w; ww++) pos += s_wcnt[ww][d];
+      s_key[pos] = key;
+      s_val[pos] = val;
     }
     __syncthreads();
-    for (int dd = threadIdx.x; dd < RS_BINS; dd += RS_THREADS) {
-      int s = 0;
+    {
+      const int dd = threadIdx.x;
+      int sum = 0;
 #pragma unroll
-      for (int ww = 0; ww < RS_WAVES; ww++) { s += wcnt[ww][dd]; wcnt[ww][dd] = 0; }
-      run[dd] += s;
-    }
-    if (valid) {
-      kout[pos] = key;
-      vout[pos] = val;
+      for (int ww = 0; ww < RS_WAVES; ww++) {
+        sum += s_wcnt[ww][dd];
+        s_wcnt[ww][dd] = 0;
+      }
+      s_run[dd] += sum;
     }
     __syncthreads();
+  }
+  // write out in LDS order: position p of digit d goes to gbase[d] + p - lbase[d]
+  for (int p = threadIdx.x; p < tile_n; p += RS_THREADS) {
+    const uint64_t key = s_key[p];
+    const int d = (int)((key >> shift) & (RS_BINS - 1));
+    const int64_t gp = (int64_t)s_gbase[d] + (p - s_lbase[d]);
+    kout[gp] = key;
+    vout[gp] = s_val[p];
   }
 }
 

@@ -35,7 +35,7 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Arena bytes one instance occupies while resident (header formula).
-int64_t footprint(int64_t V, int64_t E) { return 57 * V + 44 * E + (E + 63) / 64; }
+int64_t footprint(int64_t V, int64_t E) { return 69 * V + 44 * E + (E + 31) / 32; }
 
 // Device output block of a group: values [n], flows [sum E], sides [sum V].
 size_t out_bytes(int32_t n, int64_t E, int64_t V) { return al(8 * (size_t)n) + al(4 * (size_t)std::max<int64_t>(E, 1)) + al((size_t)V); }

@@ -12,7 +12,8 @@
 //     order, until e(u) is spent, then relabels if excess is left (each such
 //     push obeys the relaxed lock-free rule h(u) > h(v), section 2.2).
 //     Rows longer than `split_degree` go to a kernel that gives each of them
-//     a whole workgroup.
+//     one wave; rows longer than `block_degree` are cut into chunks of CHUNK
+//     entries that many workgroups process at once.
 //   * global relabel (section 2.2): backward BFS from the sink in the
 //     residual graph sets h(v) to the residual distance to t; unreached
 //     vertices get the cap and are inactive.  It runs on the GPU as one
@@ -77,9 +78,49 @@ __device__ __forceinline__ void flush_stats(long long *stats, long long scans, i
 // scanned more than `budget` entries (then fresh exact heights are worth a
 // global relabel).  The flag is read at entry by the next sweeps' kernels,
 // so every workgroup of a kernel sees the same decision.
-__global__ void k_sweep_control(const int32_t *qout_cnt, const long long *rwork, const long long *rwork_at_gr,
-                                const long long *budget, int32_t *halt) {
-  if (*qout_cnt == 0 || *rwork - *rwork_at_gr > *budget) *halt = 1;
+// With a sweep log (diagnostics), every sweep that ran appends one record:
+// queue in, medium rows, long rows, second-pass chunk tasks, queue out,
+// relabel work since the last global relabel (saturated to int32).
+__global__ void k_sweep_control(SweepCtl c) {
+  if (*c.halt) return;
+  const int32_t next = c.scan_cnt ? *c.qin_cnt : *c.qout_cnt;  // full scan: this sweep's queue
+  if (c.log) {
+    const int32_t i = *c.log_n;
+    if (i < c.log_cap) {
+      int32_t *r = c.log + 6 * (int64_t)i;
+      const long long rw = *c.rwork - *c.rwork_at_gr;
+      r[0] = *c.qin_cnt;
+      r[1] = *c.mid_cnt;
+      r[2] = *c.big_cnt;
+      r[3] = *c.task_cnt;
+      r[4] = *c.qout_cnt;
+      r[5] = rw > 0x7fffffff ? 0x7fffffff : (int32_t)rw;
+      *c.log_n = i + 1;
+    }
+  }
+  if (next == 0 || *c.rwork - *c.rwork_at_gr > *c.budget) *c.halt = 1;
+  if (c.scan_cnt) *c.scan_cnt = 0;
+}
+
+// Full-scan queue (Algorithm 2's compaction): ballot over a wave, LDS
+// staging, one atomic per flush.
+__global__ void __launch_bounds__(SWEEP_THREADS) k_avq_scan(Graph g, const int32_t *span, int32_t *list, int32_t *cnt,
+                                                            int32_t cap, int32_t *err, const int32_t *halt) {
+  __shared__ int s_qbuf[SWEEP_THREADS / WB_WAVE][WB_QBUF];
+  __shared__ int s_qcnt[SWEEP_THREADS / WB_WAVE];
+  if (*halt) return;
+  const int wl = threadIdx.x / WB_WAVE;
+  if (lane() == 0) s_qcnt[wl] = 0;
+  const WaveQ wq{s_qbuf[wl], &s_qcnt[wl], list, cnt, cap, err};
+  const int64_t n = *span;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane(); v0 < n; v0 += nth) {  // wave-uniform
+    const int64_t v = v0 + lane();
+    bool act = false;
+    if (v < n) act = g.e[v] > 0 && g.h[v] < g.hcap;
+    waveq_push(wq, act, (int32_t)v);
+  }
+  waveq_flush(wq);
 }
 
 template <int P>
@@ -106,6 +147,23 @@ __device__ __forceinline__ long long group_excl_scan_i64(long long x, long long 
 }
 
 
+constexpr int32_t CHUNK_MORE = 1 << 30;  // lr_cnt flag: a chunk left admissible capacity unpushed
+// Bias added to e(u) while the chunks of long row u work on it (discharge
+// mode): pushes into u then never see e(u) <= 0, so only u's last chunk
+// decides whether u is queued again, and the chunks claim excess from e(u)
+// itself.  Excesses of non-terminals stay below 2^61 (at most 2^30 arcs of
+// capacity below 2^31 leave s).
+constexpr long long CHUNK_BIAS = 1ll << 61;
+
+// Defers long row u to the chunk kernel (one lane): resets the vertex's
+// per-sweep chunk state and, in discharge mode, biases its excess.  The chunk
+// kernel runs after this kernel, so it sees both.
+__device__ __forceinline__ void defer_long_row(const SweepQ &q, const Graph &g, int32_t u) {
+  q.lr_key[u] = WB_KEY_NONE;
+  q.lr_cnt[u] = 0;
+  if (q.mode == 1) atomic_add_i64(&g.e[u], CHUNK_BIAS);
+}
+
 // One visit of a queued vertex by a tile of P lanes (rows up to
 // split_degree).  Paper mode: the tile reduces the packed key
 // (height << 32 | row position) over residual entries to its minimum; the
@@ -117,6 +175,7 @@ __device__ __forceinline__ long long group_excl_scan_i64(long long x, long long 
 // if excess is left.
 template <int P>
 __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q) {
+  constexpr int UNROLL = 4;
   constexpr int DEFER_BUF = 128;
   __shared__ int s_qbuf[SWEEP_THREADS / WB_WAVE][WB_QBUF];
   __shared__ int s_mbuf[SWEEP_THREADS / WB_WAVE][DEFER_BUF];
@@ -137,6 +196,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
     *q.zero_cnt = 0;
     *q.zero_a = 0;
     *q.zero_b = 0;
+    *q.zero_c = 0;
     if (*q.qin_cnt > 0) atomic_add_i64(&q.stats[13], 1);
   }
   const int32_t n = min(*q.qin_cnt, q.qcap);
@@ -165,17 +225,25 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
     const bool leader = tl == 0;
     if (defers) {
       waveq_push(wmid, leader && split && deg <= q.t_big, u);
-      waveq_push(wbig, leader && split && deg > q.t_big, u);
+      const bool big = leader && split && deg > q.t_big;
+      if (big) defer_long_row(q, g, u);
+      waveq_push(wbig, big, u);
     }
     bool app_u = false;
     if (q.mode == 0) {
       unsigned long long key = WB_KEY_NONE;
       if (scan) {
-        for (int32_t k = beg + tl; k < end; k += P) {
-          int2 cr = g.ent[k];
-          if (cr.y > 0) {
-            unsigned long long kk = ((unsigned long long)(unsigned)g.h[cr.x] << 32) | (unsigned)(k - beg);
-            key = kk < key ? kk : key;
+        for (int32_t kb = beg + tl; kb < end; kb += UNROLL * P) {
+          int2 cr[UNROLL];
+#pragma unroll
+          for (int j = 0; j < UNROLL; j++) cr[j] = kb + j * P < end ? g.ent[kb + j * P] : make_int2(0, 0);
+#pragma unroll
+          for (int j = 0; j < UNROLL; j++) {
+            if (cr[j].y > 0) {
+              const unsigned long long kk =
+                  ((unsigned long long)(unsigned)g.h[cr[j].x] << 32) | (unsigned)(kb + j * P - beg);
+              key = kk < key ? kk : key;
+            }
           }
         }
       }
@@ -212,7 +280,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
           }
         }
       }
-      waveq_push(wq, app_v, v);
+      waveq_push(wq, q.append && app_v, v);
     } else {
       // full discharge; every lane of a scanning tile iterates the same count
       const int32_t hu = scan ? g.h[u] : 0;
@@ -222,35 +290,46 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
       unsigned long long key = WB_KEY_NONE;  // lowest residual entry not lower than u
       long long nscan = 0;
       if (scan) {
-        for (int32_t kb = beg; kb < end && erem > 0; kb += P) {
-          const int32_t k = kb + tl;
-          long long want = 0;
-          int32_t v = 0;
-          if (k < end) {
-            int2 cr = g.ent[k];
-            if (cr.y > 0) {
-              const int32_t hv = g.h[cr.x];
-              if (hv < hu) {
-                want = cr.y;
-                v = cr.x;
+        // UNROLL slices of P entries per step: their loads and height
+        // gathers are issued together, then the slices are discharged in
+        // row order
+        for (int32_t kb = beg; kb < end && erem > 0; kb += UNROLL * P) {
+          int2 cr[UNROLL];
+          int32_t hv[UNROLL];
+#pragma unroll
+          for (int j = 0; j < UNROLL; j++) {
+            const int32_t k = kb + j * P + tl;
+            cr[j] = k < end ? g.ent[k] : make_int2(0, 0);
+          }
+#pragma unroll
+          for (int j = 0; j < UNROLL; j++) hv[j] = cr[j].y > 0 ? g.h[cr[j].x] : 0;
+#pragma unroll
+          for (int j = 0; j < UNROLL; j++) {
+            const int32_t k = kb + j * P + tl;
+            long long want = 0;
+            int32_t v = 0;
+            if (cr[j].y > 0) {
+              if (hv[j] < hu) {
+                want = cr[j].y;
+                v = cr[j].x;
               } else {
-                unsigned long long kk = ((unsigned long long)(unsigned)hv << 32) | (unsigned)(k - beg);
+                unsigned long long kk = ((unsigned long long)(unsigned)hv[j] << 32) | (unsigned)(k - beg);
                 key = kk < key ? kk : key;
               }
             }
+            long long tot;
+            const long long before = group_excl_scan_i64<P>(want, &tot);
+            long long take = erem - before;
+            take = take < 0 ? 0 : (take > want ? want : take);
+            bool app_v = false;
+            if (take > 0) {
+              app_v = push_entry(g, k, v, take) && g.h[v] < g.hcap;
+              pushes++;
+            }
+            waveq_push(wq, q.append && app_v, v);
+            if (erem > 0 && kb + j * P < end) nscan += P;
+            erem -= tot;
           }
-          long long tot;
-          const long long before = group_excl_scan_i64<P>(want, &tot);
-          long long take = erem - before;
-          take = take < 0 ? 0 : (take > want ? want : take);
-          bool app_v = false;
-          if (take > 0) {
-            app_v = push_entry(g, k, v, take) && g.h[v] < g.hcap;
-            pushes++;
-          }
-          waveq_push(wq, app_v, v);
-          erem -= tot;
-          nscan += P;
         }
       }
       key = group_min<P>(key);
@@ -276,7 +355,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
         }
       }
     }
-    waveq_push(wq, app_u, u);
+    waveq_push(wq, q.append && app_u, u);
   }
   waveq_flush(wq);
   if (defers) {
@@ -288,141 +367,245 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
 
 constexpr int BLK_WAVES = BLK / WB_WAVE;
 
-// Long rows: one workgroup per queued vertex, same two modes as the tile
-// kernel with workgroup-wide reductions and prefix sums through LDS.
-__global__ void __launch_bounds__(BLK) k_sweep_block(Graph g, SweepQ q) {
+// Exclusive prefix sum over the workgroup (BLK threads) in thread order;
+// *total gets the workgroup sum.  Contains two barriers.
+__device__ __forceinline__ long long block_excl_scan_i64(long long x, long long *total, long long *s_wsum) {
+  const int w = threadIdx.x / WB_WAVE;
+  long long wtot;
+  long long before = group_excl_scan_i64<WB_WAVE>(x, &wtot);
+  if (lane() == 0) s_wsum[w] = wtot;
+  __syncthreads();
+  long long off = 0, tot = 0;
+#pragma unroll
+  for (int j = 0; j < BLK_WAVES; j++) {
+    const long long y = s_wsum[j];
+    off += j < w ? y : 0;
+    tot += y;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + off;
+}
+
+// Finishes the visit of long row u (one thread): discharge mode removes the
+// bias from e(u) and re-enqueues u while it keeps excess, after relabelling
+// it (1 + the minimum over the row) when no chunk left admissible capacity
+// unpushed; paper mode pushes to the minimum-key neighbour or relabels
+// (Algorithm 1).  Sets *app_u / *app_v (and *v) for the caller's queue.
+__device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q, int32_t u, int2 rb, int32_t hu,
+                                                unsigned long long kmin, bool more, bool *app_u, bool *app_v,
+                                                int32_t *v, int *pushes, int *relabels, long long *rwork) {
+  const int32_t deg = rb.y - rb.x;
+  if (q.mode == 1) {
+    const long long left = atomic_add_i64(&g.e[u], -CHUNK_BIAS) - CHUNK_BIAS;
+    if (left > 0) {
+      if (more || kmin == WB_KEY_NONE) {
+        *app_u = true;  // admissible capacity left, or nothing residual visible: next sweep
+      } else {
+        int32_t nh = (int32_t)(kmin >> 32) + 1;
+        if (nh > g.hcap) nh = g.hcap;
+        g.h[u] = nh;
+        (*relabels)++;
+        *rwork += deg;
+        *app_u = nh < g.hcap;
+      }
+    }
+  } else if (kmin == WB_KEY_NONE) {
+    *app_u = true;
+  } else {
+    const int32_t hmin = (int32_t)(kmin >> 32);
+    const int32_t k = rb.x + (int32_t)(kmin & 0xffffffffu);
+    if (hu > hmin) {
+      const long long e0 = atomic_load_i64(&g.e[u]);
+      *v = g.ent[k].x;
+      const int32_t rk = atomic_load_i32(&g.ent[k].y);
+      const long long d = e0 < (long long)rk ? e0 : (long long)rk;
+      if (d > 0) {
+        *app_v = push_entry(g, k, *v, d) && g.h[*v] < g.hcap;
+        const long long oldu = atomic_add_i64(&g.e[u], -d);
+        *app_u = oldu - d > 0;
+        (*pushes)++;
+      } else {
+        *app_u = e0 > 0;
+      }
+    } else {
+      int32_t nh = hmin + 1;
+      if (nh > g.hcap) nh = g.hcap;
+      g.h[u] = nh;
+      (*relabels)++;
+      *rwork += deg;
+      *app_u = nh < g.hcap;
+    }
+  }
+}
+
+// Long rows, cut into chunks of CHUNK entries processed by one workgroup
+// each; thread t holds entries 4t .. 4t+3 of its chunk, so thread order is
+// row order.  First pass (FIRST): the first chunk of every deferred row.
+// Discharge mode: the chunk sums its admissible capacity (residual entries
+// whose head is lower than u), claims up to that much from e(u) (one atomic
+// subtract of the sum; what exceeds the excess is given back) and pushes the
+// claim along those entries in row order.  If the chunk's admissible capacity
+// ran out while u still has excess, the rest of the row is needed: the other
+// chunks become tasks of the second pass, which many workgroups process at
+// once, and a third pass finishes those rows; otherwise the first chunk
+// finishes the visit itself (a hub whose excess fits its first chunk costs
+// one chunk, not the whole row).  Chunks fold their lowest non-admissible
+// residual key into the vertex's minimum and flag unpushed admissible
+// capacity, with atomics whose results they do not wait for.  Paper mode:
+// the chunks fold the minimum (height, position) key over all residual
+// entries of the row; the finish pushes to that neighbour or relabels.
+template <bool FIRST>
+__global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
+  constexpr int PER = CHUNK / BLK;
   __shared__ int s_qbuf[BLK_WAVES][WB_QBUF];
   __shared__ int s_qcnt[BLK_WAVES];
   __shared__ long long s_wsum[BLK_WAVES];
   __shared__ unsigned long long s_wmin[BLK_WAVES];
-  __shared__ long long s_e0;
+  __shared__ long long s_take;
   if (*q.halt) return;
-  const int32_t nbig = min(*q.big_cnt, q.qcap);
+  const int32_t ntask = FIRST ? min(*q.big_cnt, q.qcap) : min(*q.task_cnt, q.tcap);
   const int w = threadIdx.x / WB_WAVE;
   if (lane() == 0) s_qcnt[w] = 0;
   const WaveQ wq{s_qbuf[w], &s_qcnt[w], q.qout, q.qout_cnt, q.qcap, q.err};
   long long scans = 0, queued = 0, rwork = 0;
   int pushes = 0, relabels = 0;
-  for (int32_t idx = blockIdx.x; idx < nbig; idx += gridDim.x) {
-    const int32_t u = q.big_v[idx];
+  for (int32_t task = blockIdx.x; task < ntask; task += gridDim.x) {
+    const int32_t u = FIRST ? q.big_v[task] : q.task_u[task];
+    const int32_t c = FIRST ? 0 : q.task_c[task];
     const int2 rb = g.rowb[u];
-    const int32_t beg = rb.x, end = rb.y;
-    const int32_t hu = g.h[u];
-    if (threadIdx.x == 0) s_e0 = atomic_load_i64(&g.e[u]);
-    __syncthreads();
-    const long long e0 = s_e0;
-    long long erem = e0;
+    const int32_t deg = rb.y - rb.x;
+    const int32_t nch = (deg + CHUNK - 1) / CHUNK;
+    const int32_t beg = rb.x + c * CHUNK;
+    const int32_t end = min(rb.y, beg + CHUNK);
+    const int32_t hu = g.h[u];  // written only when u's visit is finished
+    const int32_t k0 = beg + PER * (int32_t)threadIdx.x;
     unsigned long long key = WB_KEY_NONE;
-    long long nscan = 0;
-    for (int32_t kb = beg; kb < end && (q.mode == 0 || erem > 0); kb += BLK) {
-      const int32_t k = kb + threadIdx.x;
-      long long want = 0;
-      int32_t v = 0;
+    int32_t vv[PER];
+    int32_t want[PER];
+    long long mine = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) {
+      const int32_t k = k0 + j;
+      vv[j] = 0;
+      want[j] = 0;
       if (k < end) {
-        int2 cr = g.ent[k];
+        const int2 cr = g.ent[k];
         if (cr.y > 0) {
           const int32_t hv = g.h[cr.x];
-          unsigned long long kk = ((unsigned long long)(unsigned)hv << 32) | (unsigned)(k - beg);
           if (q.mode == 1 && hv < hu) {
-            want = cr.y;
-            v = cr.x;
+            want[j] = cr.y;
+            vv[j] = cr.x;
+            mine += cr.y;
           } else {
+            const unsigned long long kk = ((unsigned long long)(unsigned)hv << 32) | (unsigned)(k - rb.x);
             key = kk < key ? kk : key;
           }
         }
       }
-      nscan += BLK;
-      if (q.mode == 1) {
-        long long wtot;
-        long long before = group_excl_scan_i64<WB_WAVE>(want, &wtot);
-        if (lane() == 0) s_wsum[w] = wtot;
-        __syncthreads();
-        long long off = 0, tot = 0;
-#pragma unroll
-        for (int j = 0; j < BLK_WAVES; j++) {
-          long long x = s_wsum[j];
-          off += j < w ? x : 0;
-          tot += x;
+    }
+    bool short_claim = false;  // (thread 0) admissible capacity left unpushed
+    long long after = 0;       // (thread 0) excess of u left after this chunk's claim
+    if (q.mode == 1) {
+      long long tot;
+      const long long before = block_excl_scan_i64(mine, &tot, s_wsum);
+      if (threadIdx.x == 0) {
+        long long take = 0;
+        if (tot > 0) {
+          const long long avail = atomic_add_i64(&g.e[u], -tot) - CHUNK_BIAS;
+          take = avail < tot ? (avail > 0 ? avail : 0) : tot;
+          if (take < tot) atomic_add_i64(&g.e[u], tot - take);
+          after = avail - take;
+        } else if (FIRST) {
+          after = atomic_load_i64(&g.e[u]) - CHUNK_BIAS;
         }
-        __syncthreads();
-        before += off;
-        long long take = erem - before;
-        take = take < 0 ? 0 : (take > want ? want : take);
+        short_claim = take < tot;
+        s_take = take;
+      }
+      __syncthreads();
+      long long rem = s_take - before;  // claim left for this thread's entries, in row order
+#pragma unroll
+      for (int j = 0; j < PER; j++) {
+        const long long d = rem < 0 ? 0 : (rem > want[j] ? want[j] : rem);
         bool app_v = false;
-        if (take > 0) {
-          app_v = push_entry(g, k, v, take) && g.h[v] < g.hcap;
+        if (d > 0) {
+          app_v = push_entry(g, k0 + j, vv[j], d) && g.h[vv[j]] < g.hcap;
           pushes++;
         }
-        waveq_push(wq, app_v, v);
-        erem -= tot;
+        waveq_push(wq, q.append && app_v, vv[j]);
+        rem -= want[j];
       }
     }
     key = group_min<WB_WAVE>(key);
     if (lane() == 0) s_wmin[w] = key;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int j = 0; j < BLK_WAVES; j++) key = s_wmin[j] < key ? s_wmin[j] : key;
-    }
     bool app_u = false, app_v = false;
     int32_t v = 0;
     if (threadIdx.x == 0) {
-      scans += nscan < (end - beg) ? nscan : (end - beg);
-      queued += 1;
-      if (q.mode == 0) {
-        if (key == WB_KEY_NONE) {
-          app_u = true;
-        } else {
-          const int32_t hmin = (int32_t)(key >> 32);
-          const int32_t k = beg + (int32_t)(key & 0xffffffffu);
-          if (hu > hmin) {
-            v = g.ent[k].x;
-            const int32_t rk = atomic_load_i32(&g.ent[k].y);
-            long long d = e0 < (long long)rk ? e0 : (long long)rk;
-            if (d > 0) {
-              app_v = push_entry(g, k, v, d) && g.h[v] < g.hcap;
-              long long oldu = atomic_add_i64(&g.e[u], -d);
-              app_u = oldu - d > 0;
-              pushes++;
-            } else {
-              app_u = e0 > 0;
-            }
-          } else {
-            int32_t nh = hmin + 1;
-            if (nh > g.hcap) nh = g.hcap;
-            g.h[u] = nh;
-            relabels++;
-            rwork += end - beg;
-            app_u = nh < g.hcap;
-          }
-        }
+      for (int j = 0; j < BLK_WAVES; j++) key = s_wmin[j] < key ? s_wmin[j] : key;
+      scans += end - beg;
+      if (FIRST && (nch == 1 || (q.mode == 1 && (short_claim || after <= 0)))) {
+        // the first chunk settles the visit alone; its minimum covers the
+        // whole row only when the row is one chunk, so a longer row is not
+        // relabelled here (excess that arrived meanwhile waits a sweep)
+        queued += 1;
+        finish_long_row(g, q, u, rb, hu, key, short_claim || nch > 1, &app_u, &app_v, &v, &pushes, &relabels,
+                        &rwork);
       } else {
-        const long long pushed = e0 - (erem > 0 ? erem : 0);
-        long long left = e0;
-        if (pushed > 0) left = atomic_add_i64(&g.e[u], -pushed) - pushed;
-        if (erem > 0) {
-          if (key == WB_KEY_NONE) {
-            app_u = true;
+        if (key != WB_KEY_NONE) atomic_min_u64(&q.lr_key[u], key);
+        if (short_claim) atomic_or_i32(&q.lr_cnt[u], CHUNK_MORE);
+        if (FIRST) {  // the other chunks become second-pass tasks
+          const int32_t base = atomic_add_i32(q.task_cnt, nch - 1);
+          if ((long long)base + nch - 1 > (long long)q.tcap) {
+            atomic_add_i32(q.err, 1);
           } else {
-            int32_t nh = (int32_t)(key >> 32) + 1;
-            if (nh > g.hcap) nh = g.hcap;
-            g.h[u] = nh;
-            relabels++;
-            rwork += end - beg;
-            app_u = nh < g.hcap;
+            for (int32_t cc = 1; cc < nch; cc++) {
+              q.task_u[base + cc - 1] = u;
+              q.task_c[base + cc - 1] = cc;
+            }
           }
-        } else {
-          app_u = left > 0;
         }
       }
     }
     if (w == 0) {
-      waveq_push(wq, app_v, v);
-      waveq_push(wq, app_u, u);
+      waveq_push(wq, q.append && app_v, v);
+      waveq_push(wq, q.append && app_u, u);
     }
-    __syncthreads();
+    __syncthreads();  // s_take, s_wmin and s_wsum are reused by the next task
   }
   waveq_flush(wq);
   flush_stats(q.stats + 8, scans, pushes, relabels, queued, q.rwork, rwork);
+}
+
+// Third pass: one thread finishes each long row whose chunks ran in the
+// second pass (the row's task with chunk index 1 stands for it).
+__global__ void __launch_bounds__(BLK) k_sweep_chunk_finish(Graph g, SweepQ q) {
+  __shared__ int s_qbuf[BLK_WAVES][WB_QBUF];
+  __shared__ int s_qcnt[BLK_WAVES];
+  if (*q.halt) return;
+  const int32_t ntask = min(*q.task_cnt, q.tcap);
+  const int w = threadIdx.x / WB_WAVE;
+  if (lane() == 0) s_qcnt[w] = 0;
+  const WaveQ wq{s_qbuf[w], &s_qcnt[w], q.qout, q.qout_cnt, q.qcap, q.err};
+  long long queued = 0, rwork = 0;
+  int pushes = 0, relabels = 0;
+  const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < ntask; b0 += nth) {  // wave-uniform
+    const int64_t i = b0 + threadIdx.x;
+    bool app_u = false, app_v = false;
+    int32_t u = 0, v = 0;
+    if (i < ntask && q.task_c[i] == 1) {
+      u = q.task_u[i];
+      const int2 rb = g.rowb[u];
+      queued += 1;
+      finish_long_row(g, q, u, rb, g.h[u], atomic_load_u64(&q.lr_key[u]), (q.lr_cnt[u] & CHUNK_MORE) != 0, &app_u,
+                      &app_v, &v, &pushes, &relabels, &rwork);
+    }
+    waveq_push(wq, q.append && app_v, v);
+    waveq_push(wq, q.append && app_u, u);
+  }
+  waveq_flush(wq);
+  flush_stats(q.stats + 8, 0, pushes, relabels, queued, q.rwork, rwork);
 }
 
 // ------------------------------------------------------ global relabel
@@ -494,6 +677,8 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     a.big_cnt[1] = 0;
     a.mid_cnt[0] = 0;
     a.mid_cnt[1] = 0;
+    a.task_cnt[0] = 0;
+    a.task_cnt[1] = 0;
   }
   grid_barrier(a.bar, nblocks);
   for (int64_t j = gtid; j < a.nroots; j += nthreads) {
@@ -770,6 +955,7 @@ typedef void (*GRFn)(GRArgs);
 
 static TileFn tile_fn(int P) {
   switch (P) {
+    case 1: return k_sweep_tile<1>;
     case 4: return k_sweep_tile<4>;
     case 8: return k_sweep_tile<8>;
     case 16: return k_sweep_tile<16>;
@@ -791,13 +977,22 @@ void launch_sweep_tile(int P, int blocks, hipStream_t st, const Graph &g, const 
   hipLaunchKernelGGL(tile_fn(P), dim3(blocks), dim3(SWEEP_THREADS), 0, st, g, q);
 }
 
-void launch_sweep_block(int blocks, hipStream_t st, const Graph &g, const SweepQ &q) {
-  hipLaunchKernelGGL(k_sweep_block, dim3(blocks), dim3(BLK), 0, st, g, q);
+void launch_sweep_chunk(int pass, int blocks, hipStream_t st, const Graph &g, const SweepQ &q) {
+  if (pass == 0)
+    hipLaunchKernelGGL(k_sweep_chunk<true>, dim3(blocks), dim3(BLK), 0, st, g, q);
+  else if (pass == 1)
+    hipLaunchKernelGGL(k_sweep_chunk<false>, dim3(blocks), dim3(BLK), 0, st, g, q);
+  else
+    hipLaunchKernelGGL(k_sweep_chunk_finish, dim3(blocks), dim3(BLK), 0, st, g, q);
 }
 
-void launch_sweep_control(hipStream_t st, const int32_t *qout_cnt, const long long *rwork, const long long *rwork_at_gr,
-                          const long long *budget, int32_t *halt) {
-  hipLaunchKernelGGL(k_sweep_control, dim3(1), dim3(1), 0, st, qout_cnt, rwork, rwork_at_gr, budget, halt);
+void launch_avq_scan(int blocks, hipStream_t st, const Graph &g, const int32_t *span, int32_t *list, int32_t *cnt,
+                     int32_t cap, int32_t *err, const int32_t *halt) {
+  hipLaunchKernelGGL(k_avq_scan, dim3(blocks), dim3(SWEEP_THREADS), 0, st, g, span, list, cnt, cap, err, halt);
+}
+
+void launch_sweep_control(hipStream_t st, const SweepCtl &c) {
+  hipLaunchKernelGGL(k_sweep_control, dim3(1), dim3(1), 0, st, c);
 }
 
 hipError_t launch_global_relabel(int P, int blocks, hipStream_t st, GRArgs &a) {

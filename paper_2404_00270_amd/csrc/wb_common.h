@@ -84,6 +84,14 @@ __device__ __forceinline__ unsigned long long atomic_add_u64(unsigned long long 
 __device__ __forceinline__ unsigned long long atomic_min_u64(unsigned long long *p, unsigned long long v) {
   return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ int atomic_or_i32(int *p, int v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ long long atomic_cas_i64(long long *p, long long expected, long long desired) {
+  __hip_atomic_compare_exchange_strong(p, &expected, desired, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return expected;  // the value found (== the expected one on success)
+}
 __device__ __forceinline__ void atomic_store_i32(int *p, int v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -25,10 +25,11 @@ struct SolveConfig {
   int gr_work_permille = 0;   // adaptive relabel budget in thousandths of V + M (0: 1000)
   int64_t max_sweeps = 0;
   int max_wall_ms = 0;
-  int grid_blocks = 0;        // workgroups per sweep launch (0: 1024)
+  int grid_blocks = 0;        // workgroups per sweep launch (0: 2048)
   bool time_kernels = false;  // bracket every sweep / relabel launch with events
   int push_mode = 0;          // 1: single push to the lowest neighbour; 0/2: full discharge
   bool use_graph = true;      // replay the sweep batch as a captured hipGraph
+  bool full_scan = false;     // rebuild the active queue by a full scan every sweep
 };
 
 // Counters of the engine since the last reset_stats().
@@ -151,12 +152,14 @@ class Engine {
     int remaining = 0;
   };
 
-  int ensure_graph(hipStream_t st, std::string *err);
+  int ensure_graph(hipStream_t st, int K, hipGraphExec_t *exec, std::string *err);
+  void drop_graphs();
   void enqueue_sweeps(hipStream_t st, int K);
   void launch_inst_kernel(int which, const std::vector<int> &slots, hipStream_t st);
   void launch_inst_list(int which, const std::vector<struct InstDev> &list, const std::vector<int> &slots,
                         hipStream_t st);
   void release_groups(const std::vector<int> &gis, hipStream_t st);
+  void dump_sweep_log(hipStream_t st);
 
   int device_;
   SolveConfig cfg_;
@@ -174,12 +177,16 @@ class Engine {
   long long *e_ = nullptr;
   int32_t *h_ = nullptr, *inst_of_ = nullptr, *q_[2] = {nullptr, nullptr}, *fq_[2] = {nullptr, nullptr};
   int32_t *mid_ = nullptr, *big_ = nullptr, *chunk_w_ = nullptr, *chunk_b_ = nullptr;
+  int32_t *task_u_ = nullptr, *task_c_ = nullptr, *lr_cnt_ = nullptr;
+  unsigned long long *lr_key_ = nullptr;
+  int64_t tcap_ = 0;
   uint8_t *vis_ = nullptr;
   int64_t nchunk_ = 0;
   int32_t *inst_active_ = nullptr, *inst_stranded_ = nullptr;
   int32_t *roots_ = nullptr, *root_h_ = nullptr, *excl_ = nullptr;
   void *inst_list_ = nullptr;  // per-instance kernel descriptors [ncap]
   long long *misc_ = nullptr;
+  int32_t *sweep_log_dev_ = nullptr, *sweep_log_ = nullptr;  // log pointer passed to kernels (null: off)
   int32_t *sink_ = nullptr;
   long long *budget_ = nullptr;
   // pinned host staging
@@ -195,10 +202,10 @@ class Engine {
   int64_t last_M_ = 0;
   // tiers and launch shapes (fixed per config)
   int P_ = 8, t_mid_ = 32, t_big_ = 2048, bfs_split_ = 64, chunk_ = 1024;
-  // captured sweep batch
-  hipGraph_t graph_ = nullptr;
-  hipGraphExec_t graph_exec_ = nullptr;
-  int graph_K_ = 0;
+  // captured sweep batches, one per batch length; adaptive batch length
+  std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs_;
+  int next_K_ = 64, last_K_ = 0;
+  long long last_nonempty_ = 0;
   // timing
   std::vector<hipEvent_t> ev_;
   int ev_used_ = 0;

@@ -16,6 +16,8 @@ constexpr int GR_THREADS = 1024;
 // local height >= V_i, i.e. h >= hcap, means inactive; hcap + 1 marks the
 // terminal a phase never labels.
 constexpr int32_t HCAP = 1 << 30;
+// Long rows are cut into tasks of CHUNK entries, one workgroup each.
+constexpr int32_t CHUNK = 1024;
 
 struct Graph {
   int32_t V;             // arena vertices
@@ -37,8 +39,15 @@ struct SweepQ {
   int32_t *zero_cnt;
   int32_t *mid_v;       // medium rows deferred to the one-wave tier
   int32_t *mid_cnt;
-  int32_t *big_v;       // long rows deferred to the workgroup tier
+  int32_t *big_v;       // long rows deferred to the chunk kernel (first chunk)
   int32_t *big_cnt;
+  int32_t *task_u;      // further chunks of long rows: vertex ...
+  int32_t *task_c;      // ... and chunk index within its row
+  int32_t *task_cnt;
+  int32_t tcap;         // capacity of the task arrays (V + M / CHUNK + 64)
+  int32_t *zero_c;      // task counter to clear for the next sweep
+  unsigned long long *lr_key;     // per vertex: minimum (height, position) key over its chunks
+  int32_t *lr_cnt;                // per vertex: CHUNK_MORE when a chunk left admissible capacity unpushed
   int32_t *zero_a;      // counters to clear for the next sweep (nullable)
   int32_t *zero_b;
   int32_t t_mid;        // rows longer than this go to the one-wave tier
@@ -47,10 +56,23 @@ struct SweepQ {
                         // [4k+2] relabels, [4k+3] queued; [12] bfs scans; [13] nonempty sweeps
   long long *rwork;     // running sum of row lengths scanned by relabels
   const int32_t *halt;  // set by k_sweep_control: the rest of this round's sweeps do nothing
-  int32_t qcap;      // capacity of every queue and of the long-row list (V)
+  int32_t qcap;      // capacity of every queue and of the medium-row list (V)
   int32_t *err;      // overflow counter (must stay 0)
   int32_t mode;      // 0: one push to the minimum-height neighbour (Algorithms 1-2)
                      // 1: full discharge (push along every lower residual arc, then relabel)
+  int32_t append;    // 1: append push targets and still-active vertices to qout (incremental
+                     // queue); 0: the next sweep's full scan finds them
+};
+
+// End-of-sweep control (one thread): halt decision and optional log.
+struct SweepCtl {
+  const int32_t *qin_cnt, *mid_cnt, *big_cnt, *task_cnt, *qout_cnt;
+  const long long *rwork, *rwork_at_gr, *budget;
+  int32_t *halt;
+  int32_t *scan_cnt; // nullable: full-scan queue count, cleared here for the next scan
+  int32_t *log;      // nullable: [log_cap][6] per-sweep records
+  int32_t *log_n;
+  int32_t log_cap;
 };
 
 struct GRArgs {
@@ -76,6 +98,7 @@ struct GRArgs {
   int32_t *qcnt;      // [3] sweep counters: [0] = queue length, [1],[2] zeroed
   int32_t *big_cnt;   // [2] zeroed
   int32_t *mid_cnt;   // [2] zeroed
+  int32_t *task_cnt;  // [2] zeroed
   long long *stats;
   long long *status;  // [0] active, [1] stranded, [2] levels, [3] bottom-up levels
   int32_t split_deg, chunk;
@@ -89,12 +112,16 @@ struct GRArgs {
   long long *rwork_at_gr; // ... snapshot at this global relabel
 };
 
-// Sweep kernels: tiles of P lanes (P = 4..64), one workgroup per long row,
+// Sweep kernels: tiles of P lanes (P = 4..64), one workgroup per long-row chunk,
 // and the one-thread round control.
 void launch_sweep_tile(int P, int blocks, hipStream_t st, const Graph &g, const SweepQ &q);
-void launch_sweep_block(int blocks, hipStream_t st, const Graph &g, const SweepQ &q);
-void launch_sweep_control(hipStream_t st, const int32_t *qout_cnt, const long long *rwork, const long long *rwork_at_gr,
-                          const long long *budget, int32_t *halt);
+// pass 0: first chunks of long rows, 1: their other chunks, 2: finish rows of pass 1
+void launch_sweep_chunk(int pass, int blocks, hipStream_t st, const Graph &g, const SweepQ &q);
+void launch_sweep_control(hipStream_t st, const SweepCtl &c);
+// Full-scan active-vertex queue (Algorithm 2): vertices v < *span with
+// e(v) > 0 and h(v) < hcap, appended to list / *cnt.
+void launch_avq_scan(int blocks, hipStream_t st, const Graph &g, const int32_t *span, int32_t *list, int32_t *cnt,
+                     int32_t cap, int32_t *err, const int32_t *halt);
 // Cooperative global relabel (all workgroups co-resident).
 hipError_t launch_global_relabel(int P, int blocks, hipStream_t st, GRArgs &a);
 // Co-resident workgroup limit of the global relabel for P lanes.

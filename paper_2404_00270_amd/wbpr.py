@@ -64,7 +64,8 @@ class wbpr_options(ctypes.Structure):
         ("block_degree", ctypes.c_int32),
         ("gr_work_permille", ctypes.c_int32),
         ("no_graph", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("avq_mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 

@@ -97,9 +97,9 @@ int main(void) {
 
 
 def test_admission_footprint_formula():
-    """Arena bytes per resident instance: 57 V + 44 E + ceil(E/64) (pure host call)."""
+    """Arena bytes per resident instance: 69 V + 44 E + ceil(E/32) (pure host call)."""
     for V, E in [(2, 0), (1000, 8000), (65536, 524288), (4194304, 65242560)]:
-        assert wbpr.wbpr_server_footprint(V, E) == 57 * V + 44 * E + (E + 63) // 64
+        assert wbpr.wbpr_server_footprint(V, E) == 69 * V + 44 * E + (E + 31) // 32
     # O(V + E): doubling both doubles the footprint up to the rounding term
     a, b = wbpr.wbpr_server_footprint(10_000, 80_000), wbpr.wbpr_server_footprint(20_000, 160_000)
     assert abs(b - 2 * a) <= 1

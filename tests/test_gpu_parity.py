@@ -121,6 +121,26 @@ def test_every_tile_width_and_split_path(solver, lanes):
                 solver.set_options(**WATCHDOG)
 
 
+@pytest.mark.parametrize("lanes,avq_mode,push_mode", [
+    (1, 0, 2), (1, 0, 1), (1, 1, 2), (1, 1, 1),   # thread-centric, incremental / full-scan queue
+    (0, 1, 2), (0, 1, 1), (8, 1, 2), (64, 1, 1),  # vertex-centric with the full-scan queue
+])
+def test_thread_centric_and_full_scan_queue(solver, lanes, avq_mode, push_mode):
+    """The paper's baseline (one thread per vertex) and its per-sweep full scan
+    of the active vertices give exactly the oracle's results too."""
+    graphs = [W.bipartite(3000, 2000, 40000, 2.1, 11), W.random_graph(2000, 16000, 1, 100, 21),
+              W.from_arcs(5002, [(0, 2 + i, 1 + i % 9) for i in range(5000)] + [(2 + i, 1, 1 + (i * 31) % 7)
+                                                                                for i in range(5000)], 0, 1, "star")]
+    graphs += [W.multigraph(int(v), int(6 * v), cmax=25, seed=300 + int(v)) for v in (2, 7, 33, 120)]
+    solver.set_options(lanes_per_vertex=lanes, avq_mode=avq_mode, push_mode=push_mode, **WATCHDOG)
+    try:
+        for g in graphs:
+            say(f"[tc/scan] lanes={lanes} avq={avq_mode} push={push_mode} {g.name}")
+            check_against_oracle(g, solver.solve(g))
+    finally:
+        solver.set_options(**WATCHDOG)
+
+
 @pytest.mark.parametrize("seed", range(30))
 def test_paper_single_push_mode(solver, seed):
     """Algorithms 1-2 as printed: one push to the minimum-height neighbour per visit."""
