@@ -203,6 +203,48 @@ int wbpr_solve_batch(wbpr_ctx *ctx, int32_t n, const wbpr_csr *graphs, const int
                      int64_t *values, int32_t *const *flows, uint8_t *const *sides, wbpr_stats *stats);
 
 /* ------------------------------------------------------------------------
+ * Uploaded graphs: build the residual graph once, solve many (s, t) pairs.
+ *
+ * The residual graph (bidirectional CSR with merged parallel/antiparallel
+ * arcs, mates and the arc -> entry map, paper section 3.2) does not depend on
+ * s and t.  An uploaded graph keeps it on the device; every solve resets the
+ * residual capacities from the stored merged capacities and runs the same
+ * path as wbpr_solve without the builder.
+ * ---------------------------------------------------------------------- */
+typedef struct wbpr_graph wbpr_graph;
+
+/* Upload a host CSR (copied; the caller may free it after return) and build
+ * its residual graph on ctx's device with ctx's options (copied).  The
+ * handle owns its own stream and device arena (O(V + E), see
+ * wbpr_server_footprint); ctx may be destroyed afterwards.  Validation as
+ * wbpr_solve (WBPR_EINVAL, WBPR_EOVERFLOW, WBPR_ETOOBIG). */
+int wbpr_graph_upload(wbpr_ctx *ctx, const wbpr_csr *g, wbpr_graph **out);
+
+/* Maximum s-t flow on an uploaded graph; outputs as wbpr_solve (host
+ * buffers, arc_flow and cut_side nullable).  Synchronous; one solve at a time
+ * per handle (not thread-safe).  After a failure other than WBPR_EINVAL the
+ * handle is unusable (every later solve fails) and should be freed. */
+int wbpr_graph_solve(wbpr_graph *gr, int32_t s, int32_t t, int64_t *value, int32_t *arc_flow, uint8_t *cut_side,
+                     wbpr_stats *stats);
+
+void wbpr_graph_free(wbpr_graph *gr);
+
+/* Autotuner: picks the schedule (lanes per vertex, relabel-work budget,
+ * queue mode) for graphs shaped like g.  The graph is uploaded once; each
+ * candidate schedule solves (s, t) once to warm up and once timed (flows
+ * and cut included); every candidate must give the same flow value
+ * (WBPR_EINTERNAL otherwise: results never depend on the schedule).  The
+ * fastest is written to *best (other fields copied from ctx's options) with
+ * its time in *best_ms (nullable), and remembered in ctx for the graph's
+ * shape class (log2 V and log2 of the mean row length); later solves on ctx
+ * whose options leave lanes_per_vertex and gr_work_permille at 0 use the
+ * remembered schedule for graphs of that class.  max_trials bounds the
+ * number of candidates (0 = all, at most 16); include_full_scan adds the
+ * full-scan queue to the candidates. */
+int wbpr_autotune(wbpr_ctx *ctx, const wbpr_csr *g, int32_t s, int32_t t, int32_t max_trials,
+                  int32_t include_full_scan, wbpr_options *best, double *best_ms);
+
+/* ------------------------------------------------------------------------
  * Continuous-batching server.
  *
  * Requests (one instance each) arrive at any time from any thread.  A worker

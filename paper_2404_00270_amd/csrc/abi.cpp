@@ -176,6 +176,43 @@ int wbpr_ctx_set_options(wbpr_ctx *c, const wbpr_options *opt) {
 
 namespace {
 
+int ilog2(int64_t x) {
+  int l = 0;
+  while (x > 1) {
+    x >>= 1;
+    l++;
+  }
+  return l;
+}
+
+// Shape class of a graph for the autotuner's cache.
+std::pair<int, int> shape_class(int64_t V, int64_t E) {
+  return {ilog2(V), ilog2(V > 0 ? (2 * E + V - 1) / V : 1)};
+}
+
+// The context's options, with an autotuned schedule for this shape class when
+// the options leave the schedule to the library.
+wb::SolveConfig effective_config(wbpr_ctx *c, int64_t V, int64_t E) {
+  wb::SolveConfig cfg = c->cfg;
+  if (cfg.lanes_per_vertex == 0 && cfg.gr_work_permille == 0) {
+    auto it = c->tuned.find(shape_class(V, E));
+    if (it != c->tuned.end()) {
+      cfg.lanes_per_vertex = it->second.lanes_per_vertex;
+      cfg.gr_work_permille = it->second.gr_work_permille;
+      cfg.full_scan = it->second.full_scan;
+    }
+  }
+  return cfg;
+}
+
+bool same_schedule(const wb::SolveConfig &a, const wb::SolveConfig &b) {
+  return a.lanes_per_vertex == b.lanes_per_vertex && a.gr_work_permille == b.gr_work_permille &&
+         a.full_scan == b.full_scan && a.split_degree == b.split_degree && a.block_degree == b.block_degree &&
+         a.gr_every_sweeps == b.gr_every_sweeps && a.grid_blocks == b.grid_blocks &&
+         a.time_kernels == b.time_kernels && a.push_mode == b.push_mode && a.use_graph == b.use_graph &&
+         a.max_sweeps == b.max_sweeps && a.max_wall_ms == b.max_wall_ms;
+}
+
 // Solves a group already packed on the device, from an empty engine.
 int solve_group(wbpr_ctx *c, wb::GroupInput &in, hipStream_t st, wbpr_stats *stats) {
   auto t0 = std::chrono::steady_clock::now();
@@ -187,6 +224,8 @@ int solve_group(wbpr_ctx *c, wb::GroupInput &in, hipStream_t st, wbpr_stats *sta
   if (Vt >= (1ll << 30) || 2 * Et >= (1ll << 31) - 1) return fail(WBPR_ETOOBIG, "batch exceeds the 32-bit index limits");
   wb::Engine &eng = *c->engine;
   if (!eng.idle()) return fail(WBPR_EAGAIN, "context busy");
+  const wb::SolveConfig cfg = effective_config(c, Vt, Et);
+  if (!same_schedule(cfg, eng.config())) eng.set_config(cfg);
   std::string err;
   int rc = eng.reserve(Vt, 2 * Et, Et, in.n, Vt, Et, in.n, &err);
   if (rc) return fail(rc, err);
@@ -209,7 +248,7 @@ int solve_group(wbpr_ctx *c, wb::GroupInput &in, hipStream_t st, wbpr_stats *sta
     const double ms_build = std::chrono::duration<double, std::milli>(t1 - t0).count();
     const double ms_solve = std::chrono::duration<double, std::milli>(t2 - t1).count();
     const double ms_total = std::chrono::duration<double, std::milli>(t2 - t0).count();
-    fill_stats(stats, r, c->cfg, Vt, Et, M, in.n, ms_build, ms_solve, ms_total);
+    fill_stats(stats, r, cfg, Vt, Et, M, in.n, ms_build, ms_solve, ms_total);
     if (in.n == 1 && in.values) {
       long long v = 0;
       if (hipMemcpy(&v, in.values, sizeof(v), hipMemcpyDeviceToHost) == hipSuccess) stats->value = v;
@@ -388,6 +427,234 @@ int wbpr_solve_batch(wbpr_ctx *c, int32_t n, const wbpr_csr *graphs, const int32
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "device to host copy");
+  return WBPR_OK;
+}
+
+
+}  // extern "C"
+
+struct wbpr_graph {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  wb::SolveConfig cfg;
+  std::unique_ptr<wb::Engine> engine;
+  int gid = -1;
+  bool broken = false;
+  int32_t V = 0;
+  int64_t E = 0, M = 0;
+  DevBuf output;
+};
+
+extern "C" {
+
+int wbpr_graph_upload(wbpr_ctx *c, const wbpr_csr *g, wbpr_graph **out) {
+  if (!c || !g || !out) return fail(WBPR_EINVAL, "null argument");
+  *out = nullptr;
+  if (g->V < 2) return fail(WBPR_EINVAL, "V must be at least 2");
+  int rc = check_shape(g->V, g->E, 0, 1);
+  if (rc) return rc;
+  if (!g->row_ptr || (g->E > 0 && (!g->col || !g->cap))) return fail(WBPR_EINVAL, "null CSR array");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  std::unique_ptr<wbpr_graph> G(new (std::nothrow) wbpr_graph());
+  if (!G) return fail(WBPR_ENOMEM, "host allocation");
+  G->device = c->device;
+  G->cfg = c->cfg;
+  G->V = g->V;
+  G->E = g->E;
+  e = hipStreamCreateWithFlags(&G->stream, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "stream");
+  auto cleanup = [&](int code) {
+    if (G->stream) hipStreamSynchronize(G->stream);
+    G->engine.reset();
+    G->output.release();
+    if (G->stream) hipStreamDestroy(G->stream);
+    G->stream = nullptr;
+    return code;
+  };
+  G->engine.reset(new (std::nothrow) wb::Engine(G->device));
+  if (!G->engine) return cleanup(fail(WBPR_ENOMEM, "engine"));
+  G->engine->set_config(G->cfg);
+  const int64_t V = g->V, E = g->E;
+  std::string err;
+  rc = G->engine->reserve(V, 2 * E, E, 1, V, E, 1, &err);
+  if (rc) return cleanup(fail(rc, err));
+  // stage the CSR on the device (temporary)
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t Ec = (size_t)(E > 0 ? E : 1);
+  DevBuf input;
+  e = input.ensure(al(8 * (V + 1)) + 2 * al(4 * Ec));
+  if (e != hipSuccess) return cleanup(hip_fail(e, "device allocation (staging)"));
+  char *ip = (char *)input.p;
+  int64_t *d_rp = (int64_t *)ip;
+  int32_t *d_col = (int32_t *)(ip + al(8 * (V + 1)));
+  int32_t *d_cap = (int32_t *)(ip + al(8 * (V + 1)) + al(4 * Ec));
+  e = hipMemcpyAsync(d_rp, g->row_ptr, 8 * (V + 1), hipMemcpyHostToDevice, G->stream);
+  if (e == hipSuccess && E > 0) e = hipMemcpyAsync(d_col, g->col, 4 * E, hipMemcpyHostToDevice, G->stream);
+  if (e == hipSuccess && E > 0) e = hipMemcpyAsync(d_cap, g->cap, 4 * E, hipMemcpyHostToDevice, G->stream);
+  if (e != hipSuccess) {
+    input.release();
+    return cleanup(hip_fail(e, "host to device copy"));
+  }
+  int32_t Vi = g->V, s0 = 0, t0 = 1;
+  int64_t Ei = g->E;
+  wb::GroupInput in;
+  in.n = 1;
+  in.V = &Vi;
+  in.E = &Ei;
+  in.s = &s0;
+  in.t = &t0;
+  in.row_ptr = d_rp;
+  in.col = d_col;
+  in.cap = d_cap;
+  in.keep = true;
+  in.start = false;
+  in.group_out = &G->gid;
+  rc = G->engine->admit(in, G->stream, &err);  // synchronises the stream
+  input.release();
+  if (rc) return cleanup(fail(rc, err));
+  G->M = G->engine->last_build_M();
+  *out = G.release();
+  return WBPR_OK;
+}
+
+int wbpr_graph_solve(wbpr_graph *G, int32_t s, int32_t t, int64_t *value, int32_t *arc_flow, uint8_t *cut_side,
+                     wbpr_stats *stats) {
+  if (!G || !value) return fail(WBPR_EINVAL, "null argument");
+  if (G->broken) return fail(WBPR_EINVAL, "graph handle unusable after an earlier failure");
+  if (s < 0 || s >= G->V || t < 0 || t >= G->V) return fail(WBPR_EINVAL, "s or t out of range");
+  if (s == t) return fail(WBPR_EINVAL, "s == t");
+  hipError_t e = hipSetDevice(G->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t Ec = (size_t)(G->E > 0 ? G->E : 1);
+  e = G->output.ensure(al(8) + al(4 * Ec) + al((size_t)G->V));
+  if (e != hipSuccess) return hip_fail(e, "device allocation (outputs)");
+  char *op = (char *)G->output.p;
+  int64_t *d_val = (int64_t *)op;
+  int32_t *d_flow = (int32_t *)(op + al(8));
+  uint8_t *d_side = (uint8_t *)(op + al(8) + al(4 * Ec));
+  wb::Engine &eng = *G->engine;
+  auto t0 = std::chrono::steady_clock::now();
+  eng.reset_stats();
+  std::string err;
+  int rc = eng.start_instance(G->gid, s, t, d_val, arc_flow ? d_flow : nullptr, cut_side ? d_side : nullptr, 0,
+                              G->stream, &err);
+  if (rc) return fail(rc, err);
+  std::vector<wb::Finished> done;
+  rc = eng.run_to_completion(G->stream, &done, &err);
+  if (rc) {
+    eng.abandon(G->stream);
+    G->broken = true;
+    return fail(rc, err);
+  }
+  auto t1 = std::chrono::steady_clock::now();
+  e = hipMemcpyAsync(value, d_val, 8, hipMemcpyDeviceToHost, G->stream);
+  if (e == hipSuccess && arc_flow && G->E > 0)
+    e = hipMemcpyAsync(arc_flow, d_flow, 4 * (size_t)G->E, hipMemcpyDeviceToHost, G->stream);
+  if (e == hipSuccess && cut_side) e = hipMemcpyAsync(cut_side, d_side, (size_t)G->V, hipMemcpyDeviceToHost, G->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(G->stream);
+  if (e != hipSuccess) return hip_fail(e, "device to host copy");
+  if (stats) {
+    wb::EngineStats r;
+    rc = eng.collect_stats(G->stream, &r, &err);
+    if (rc) return fail(rc, err);
+    const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    fill_stats(stats, r, G->cfg, G->V, G->E, G->M, 1, 0.0, ms, ms);
+    stats->value = *value;
+  }
+  return WBPR_OK;
+}
+
+void wbpr_graph_free(wbpr_graph *G) {
+  if (!G) return;
+  hipSetDevice(G->device);
+  if (G->stream) hipStreamSynchronize(G->stream);
+  G->engine.reset();
+  G->output.release();
+  if (G->stream) hipStreamDestroy(G->stream);
+  delete G;
+}
+
+
+int wbpr_autotune(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int32_t max_trials, int32_t include_full_scan,
+                  wbpr_options *best, double *best_ms) {
+  if (!c || !g || !best) return fail(WBPR_EINVAL, "null argument");
+  if (max_trials < 0) return fail(WBPR_EINVAL, "negative max_trials");
+  int rc = check_shape(g->V, g->E, s, t);
+  if (rc) return rc;
+  struct Cand {
+    int lanes, permille;
+    bool full_scan;
+  };
+  std::vector<Cand> cands;
+  // most promising first, so a small max_trials keeps the likely winners
+  const int lanes_order[] = {8, 16, 4, 32};
+  const int permille_order[] = {1000, 3000, 300};
+  for (int pm : permille_order)
+    for (int l : lanes_order) cands.push_back({l, pm, false});
+  if (include_full_scan)
+    for (int l : {8, 16}) cands.push_back({l, 1000, true});
+  if (max_trials > 0 && (size_t)max_trials < cands.size()) cands.resize((size_t)max_trials);
+  wbpr_graph *G = nullptr;
+  rc = wbpr_graph_upload(c, g, &G);
+  if (rc) return rc;
+  std::vector<int32_t> flow((size_t)(g->E > 0 ? g->E : 1));
+  std::vector<uint8_t> side((size_t)g->V);
+  double bms = 1e300;
+  int bi = -1;
+  int64_t value0 = -1;
+  for (size_t i = 0; i < cands.size(); i++) {
+    wb::SolveConfig cfg = c->cfg;
+    cfg.lanes_per_vertex = cands[i].lanes;
+    cfg.gr_work_permille = cands[i].permille;
+    cfg.full_scan = cands[i].full_scan;
+    cfg.time_kernels = false;
+    G->cfg = cfg;
+    G->engine->set_config(cfg);
+    double ms = 0;
+    for (int rep = 0; rep < 2; rep++) {  // warm-up (graph capture), then timed
+      int64_t v = 0;
+      auto t0 = std::chrono::steady_clock::now();
+      rc = wbpr_graph_solve(G, s, t, &v, flow.data(), side.data(), nullptr);
+      ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (rc) {
+        const std::string msg = g_err;
+        wbpr_graph_free(G);
+        return fail(rc, msg);
+      }
+      if (value0 < 0) value0 = v;
+      if (v != value0) {
+        wbpr_graph_free(G);
+        return fail(WBPR_EINTERNAL, "schedules disagree on the flow value");
+      }
+    }
+    if (ms < bms) {
+      bms = ms;
+      bi = (int)i;
+    }
+  }
+  wbpr_graph_free(G);
+  wb::SolveConfig win = c->cfg;
+  win.lanes_per_vertex = cands[bi].lanes;
+  win.gr_work_permille = cands[bi].permille;
+  win.full_scan = cands[bi].full_scan;
+  c->tuned[shape_class(g->V, g->E)] = win;
+  std::memset(best, 0, sizeof(*best));
+  best->layout = WBPR_LAYOUT_BCSR;
+  best->lanes_per_vertex = win.lanes_per_vertex;
+  best->split_degree = win.split_degree;
+  best->gr_every_sweeps = win.gr_every_sweeps;
+  best->max_sweeps = win.max_sweeps;
+  best->max_wall_ms = win.max_wall_ms;
+  best->grid_blocks = win.grid_blocks;
+  best->time_kernels = win.time_kernels ? 1 : 0;
+  best->push_mode = win.push_mode;
+  best->block_degree = win.block_degree;
+  best->gr_work_permille = win.gr_work_permille;
+  best->no_graph = win.use_graph ? 0 : 1;
+  best->avq_mode = win.full_scan ? 1 : 0;
+  if (best_ms) *best_ms = bms;
   return WBPR_OK;
 }
 

@@ -83,7 +83,9 @@ struct InstDev {
   uint8_t *side;
 };
 
-enum InstKernel { IK_INIT = 0, IK_PREFLOW, IK_VALUE_ZERO, IK_VALUE, IK_SIDE, IK_PHASE2, IK_DECODE, IK_RELEASE, IK_COUNT };
+enum InstKernel {
+  IK_INIT = 0, IK_PREFLOW, IK_VALUE_ZERO, IK_VALUE, IK_SIDE, IK_PHASE2, IK_DECODE, IK_RELEASE, IK_PARK, IK_COUNT
+};
 
 struct InstArgs {
   const InstDev *L;
@@ -170,12 +172,13 @@ __global__ void k_inst(InstArgs a, int which) {
         }
       break;
     case IK_RELEASE:
+    case IK_PARK:  // a kept graph between solves: rows stay, nothing active
       for (int64_t x = tid; x < d.V; x += nth) {
         const int32_t v = d.vbase + (int32_t)x;
         a.e[v] = 0;
         a.h[v] = HCAP;
         a.inst_of[v] = -1;
-        a.rowb[v] = make_int2(0, 0);
+        if (which == IK_RELEASE) a.rowb[v] = make_int2(0, 0);
       }
       break;
   }
@@ -289,7 +292,7 @@ int log_level() {
   return lvl;
 }
 
-constexpr int kListKinds = 8;   // separate staging per per-instance kernel kind
+constexpr int kListKinds = IK_COUNT;  // separate staging per per-instance kernel kind
 constexpr int kSweepLogCap = 16384;  // sweep-log records kept (WBPR_LOG >= 2)
 constexpr size_t kPinnedHeader = 4096;
 }  // namespace
@@ -529,7 +532,11 @@ void Engine::launch_inst_list(int which, const std::vector<InstDev> &list, const
 
 int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
   if (in.n <= 0) return 0;
-  if (in.n > (int32_t)slot_free_.size()) {
+  if (in.keep && in.n != 1) {
+    *err = "only single-instance groups can be kept";
+    return WBPR_EINVAL;
+  }
+  if (in.start && in.n > (int32_t)slot_free_.size()) {
     *err = "no free instance slot";
     return WBPR_EAGAIN;
   }
@@ -665,6 +672,14 @@ int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
   G.Mres = std::max<int64_t>(hb.M, 1);
   G.abase = ab;
   G.E = Et;
+  G.keep = in.keep;
+  if (in.group_out) *in.group_out = gi;
+  resident_V_ += Vt;
+  resident_M_ += hb.M;
+  if (!in.start) {  // built only: instances start later
+    G.remaining = 0;
+    return 0;
+  }
   G.remaining = in.n;
   std::vector<int> slots(in.n);
   int64_t vo = 0, eo = 0;
@@ -690,8 +705,6 @@ int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
     eo += in.E[i];
   }
   resident_ += in.n;
-  resident_V_ += Vt;
-  resident_M_ += hb.M;
   launch_inst_kernel(IK_INIT, slots, st);
   launch_inst_kernel(IK_PREFLOW, slots, st);
   e = hipGetLastError();
@@ -700,6 +713,75 @@ int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
     return WBPR_EDEVICE;
   }
   return 0;
+}
+
+__global__ void k_reset_entries(int2 *ent, const int32_t *cap0, int64_t M) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x)
+    ent[k].y = cap0[k];
+}
+
+bool Engine::has_kept_groups() const {
+  for (const Group &G : groups_)
+    if (G.used && G.keep) return true;
+  return false;
+}
+
+int Engine::start_instance(int gid, int32_t s, int32_t t, int64_t *value, int32_t *flow, uint8_t *side, uint64_t tag,
+                           hipStream_t st, std::string *err) {
+  if (gid < 0 || gid >= (int)groups_.size() || !groups_[gid].used || !groups_[gid].keep) {
+    *err = "no such kept graph";
+    return WBPR_EINVAL;
+  }
+  Group &G = groups_[gid];
+  if (G.remaining != 0) {
+    *err = "the graph is being solved";
+    return WBPR_EAGAIN;
+  }
+  if (s < 0 || s >= G.V || t < 0 || t >= G.V || s == t) {
+    *err = "s or t out of range, or s == t";
+    return WBPR_EINVAL;
+  }
+  if (slot_free_.empty()) {
+    *err = "no free instance slot";
+    return WBPR_EAGAIN;
+  }
+  // residual capacities back to the merged input capacities
+  hipLaunchKernelGGL(k_reset_entries, dim3(grid1d(G.Mres, 256, 16384)), dim3(256), 0, st, A_.ent + G.mbase,
+                     A_.cap0 + G.mbase, G.Mres);
+  const int sl = slot_free_.back();
+  slot_free_.pop_back();
+  Inst &I = inst_[sl];
+  I = Inst();
+  I.used = true;
+  I.V = G.V;
+  I.E = G.E;
+  I.vbase = G.vbase;
+  I.s = G.vbase + s;
+  I.t = G.vbase + t;
+  I.abase = G.abase;
+  I.phase = 1;
+  I.group = gid;
+  I.index = 0;
+  I.value = value;
+  I.flow = flow;
+  I.side = side;
+  G.tag = tag;
+  G.remaining = 1;
+  resident_ += 1;
+  launch_inst_kernel(IK_INIT, std::vector<int>{sl}, st);
+  launch_inst_kernel(IK_PREFLOW, std::vector<int>{sl}, st);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    *err = std::string("instance init: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  return 0;
+}
+
+void Engine::free_group(int gid, hipStream_t st) {
+  if (gid < 0 || gid >= (int)groups_.size() || !groups_[gid].used || groups_[gid].remaining != 0) return;
+  groups_[gid].keep = false;
+  release_groups(std::vector<int>{gid}, st);
 }
 
 // Clears the vertices of the listed groups (rows, excess, heights, owner)
@@ -1069,17 +1151,26 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   }
   // retire finished instances; release groups that have no instance left
   std::vector<int> empty_groups;
+  std::vector<InstDev> parked;
   for (int i : fin_done) {
     Inst &I = inst_[i];
     Group &G = groups_[I.group];
     done->push_back(Finished{G.tag, I.index, 0});
     G.remaining--;
-    if (G.remaining == 0) empty_groups.push_back(I.group);
+    if (G.remaining == 0 && !G.keep) empty_groups.push_back(I.group);
+    if (G.remaining == 0 && G.keep) {
+      InstDev d;
+      std::memset(&d, 0, sizeof(d));
+      d.vbase = G.vbase;
+      d.V = G.V;
+      parked.push_back(d);
+    }
     I = Inst();
     slot_free_.push_back(i);
     resident_--;
   }
   release_groups(empty_groups, st);
+  if (!parked.empty()) launch_inst_list(IK_PARK, parked, std::vector<int>(parked.size(), 0), st);
   return 0;
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <memory>
 #include <string>
 
@@ -57,4 +58,6 @@ struct wbpr_ctx {
   wb::SolveConfig cfg;
   std::unique_ptr<wb::Engine> engine;
   wb::DevBuf input, output;
+  // autotuned schedules by shape class (log2 V, log2 mean row length)
+  std::map<std::pair<int, int>, wb::SolveConfig> tuned;
 };

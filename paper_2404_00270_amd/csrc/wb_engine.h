@@ -62,6 +62,9 @@ struct GroupInput {
   int32_t *flows = nullptr;          // device [sum E]
   uint8_t *sides = nullptr;          // device [sum V]
   uint64_t tag = 0;                  // caller's id, reported back on completion
+  bool keep = false;                 // keep the built group after its instances finish (n == 1)
+  bool start = true;                 // false: build only, start instances later (start_instance)
+  int32_t *group_out = nullptr;      // receives the group id (nullable)
 };
 
 struct Finished {
@@ -112,12 +115,20 @@ class Engine {
   // transitions and outputs, then a batch of sweeps.  Appends finished
   // instances to *done.
   int round(hipStream_t st, std::vector<Finished> *done, std::string *err);
+  // Starts a new solve on a kept group (built with keep = true): resets its
+  // residual capacities from the stored ones (no rebuild), then preflows.
+  // s, t are local ids; outputs are device pointers (value required).
+  int start_instance(int gid, int32_t s, int32_t t, int64_t *value, int32_t *flow, uint8_t *side, uint64_t tag,
+                     hipStream_t st, std::string *err);
+  // Releases a kept group that has no running instance.
+  void free_group(int gid, hipStream_t st);
   // Runs rounds until nothing is resident.
   int run_to_completion(hipStream_t st, std::vector<Finished> *done, std::string *err);
   // Drops every resident instance (after an error) and clears the arena.
   void abandon(hipStream_t st);
 
   bool idle() const { return resident_ == 0; }
+  bool has_kept_groups() const;
   int32_t resident() const { return resident_; }
   int64_t free_vertices() const { return valloc_.largest_free(); }
   int64_t free_entries() const { return malloc_.largest_free(); }
@@ -150,6 +161,7 @@ class Engine {
     int32_t vbase = 0, V = 0;
     int64_t mbase = 0, Mres = 0, abase = 0, E = 0;
     int remaining = 0;
+    bool keep = false;
   };
 
   int ensure_graph(hipStream_t st, int K, hipGraphExec_t *exec, std::string *err);

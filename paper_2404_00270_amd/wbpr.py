@@ -35,6 +35,7 @@ STATUS_NAMES = {
 EXPORTS = (
     "wbpr_version", "wbpr_last_error", "wbpr_device_arch", "wbpr_ctx_create", "wbpr_ctx_destroy",
     "wbpr_ctx_set_options", "wbpr_solve", "wbpr_solve_device", "wbpr_solve_batch", "wbpr_solve_batch_device",
+    "wbpr_graph_upload", "wbpr_graph_solve", "wbpr_graph_free", "wbpr_autotune",
     "wbpr_server_create", "wbpr_server_submit", "wbpr_server_poll", "wbpr_server_wait", "wbpr_result_free",
     "wbpr_server_get_stats", "wbpr_server_footprint", "wbpr_server_destroy",
 )
@@ -211,6 +212,15 @@ def load_library(path: str = LIB_PATH):
     lib.wbpr_solve_batch_device.restype = ctypes.c_int
     lib.wbpr_solve_batch_device.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                             ctypes.POINTER(wbpr_stats)]
+    lib.wbpr_graph_upload.restype = ctypes.c_int
+    lib.wbpr_graph_upload.argtypes = [vp, ctypes.POINTER(wbpr_csr), ctypes.POINTER(ctypes.c_void_p)]
+    lib.wbpr_graph_solve.restype = ctypes.c_int
+    lib.wbpr_graph_solve.argtypes = [vp, i32, i32, vp, vp, vp, ctypes.POINTER(wbpr_stats)]
+    lib.wbpr_graph_free.restype = None
+    lib.wbpr_graph_free.argtypes = [vp]
+    lib.wbpr_autotune.restype = ctypes.c_int
+    lib.wbpr_autotune.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, i32, i32, i32, ctypes.POINTER(wbpr_options),
+                                  ctypes.POINTER(ctypes.c_double)]
     lib.wbpr_server_create.restype = ctypes.c_int
     lib.wbpr_server_create.argtypes = [vp, ctypes.POINTER(wbpr_server_options), ctypes.POINTER(ctypes.c_void_p)]
     lib.wbpr_server_submit.restype = ctypes.c_int
@@ -387,6 +397,20 @@ class Solver:
     def solve(self, g, want_flow: bool = True, want_side: bool = True) -> Result:
         return wbpr_solve(self.ctx, g.V, g.row_ptr, g.col, g.cap, g.s, g.t, want_flow, want_side)
 
+    def autotune(self, g, max_trials: int = 0, include_full_scan: bool = False):
+        """(best options as a dict, best solve ms); also remembered by the context."""
+        lib = load_library()
+        rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+        c = np.ascontiguousarray(g.col, dtype=np.int32)
+        k = np.ascontiguousarray(g.cap, dtype=np.int32)
+        E = int(c.shape[0])
+        csr = wbpr_csr(g.V, E, rp.ctypes.data, c.ctypes.data if E else None, k.ctypes.data if E else None)
+        best = wbpr_options()
+        ms = ctypes.c_double()
+        _check(lib.wbpr_autotune(self.ctx, ctypes.byref(csr), g.s, g.t, max_trials, int(include_full_scan),
+                                 ctypes.byref(best), ctypes.byref(ms)))
+        return {name: getattr(best, name) for name, _ in best._fields_ if name != "reserved"}, ms.value
+
     def solve_batch(self, graphs, want_flow: bool = True, want_side: bool = True) -> BatchResult:
         return wbpr_solve_batch(self.ctx, graphs, want_flow, want_side)
 
@@ -507,6 +531,55 @@ class Server:
     def close(self):
         if self.h:
             load_library().wbpr_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class UploadedGraph:
+    """A graph whose residual form stays on the device: many (s, t) solves
+    without rebuilding it (wbpr_graph_upload / wbpr_graph_solve)."""
+
+    def __init__(self, solver: "Solver", g):
+        lib = load_library()
+        self._rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+        self._col = np.ascontiguousarray(g.col, dtype=np.int32)
+        self._cap = np.ascontiguousarray(g.cap, dtype=np.int32)
+        self.V = int(g.V)
+        self.E = int(self._col.shape[0])
+        csr = wbpr_csr(self.V, self.E, self._rp.ctypes.data, self._col.ctypes.data if self.E else None,
+                       self._cap.ctypes.data if self.E else None)
+        h = ctypes.c_void_p()
+        _check(lib.wbpr_graph_upload(solver.ctx, ctypes.byref(csr), ctypes.byref(h)))
+        self.h = h.value
+        del self._rp, self._col, self._cap  # the library copied them
+
+    def solve(self, s: int, t: int, want_flow: bool = True, want_side: bool = True, return_code: bool = False):
+        lib = load_library()
+        value = ctypes.c_int64()
+        flow = np.zeros(max(self.E, 1), np.int32) if want_flow else None
+        side = np.zeros(self.V, np.uint8) if want_side else None
+        st = wbpr_stats()
+        rc = lib.wbpr_graph_solve(self.h, s, t, ctypes.byref(value), flow.ctypes.data if flow is not None else None,
+                                  side.ctypes.data if side is not None else None, ctypes.byref(st))
+        if return_code:
+            return rc
+        _check(rc)
+        return Result(value.value, flow[: self.E] if flow is not None else None, side, st.as_dict())
+
+    def close(self):
+        if self.h:
+            load_library().wbpr_graph_free(self.h)
             self.h = None
 
     def __enter__(self):

@@ -190,3 +190,47 @@ def test_batch_device_packed_torch(solver):
     r.flows = [hf[eo[i]:eo[i + 1]] for i in range(n)]
     r.sides = [hs[vo[i]:vo[i + 1]] for i in range(n)]
     _check_batch(gs, r)
+
+
+def test_uploaded_graph_many_pairs(solver):
+    """One residual build, many (s, t) solves: each equals the oracle's."""
+    from paper_2404_00270_amd import wbpr
+
+    rng = np.random.default_rng(77)
+    for g0 in (W.random_graph(3000, 24000, 1, 100, 61), W.bipartite(2000, 1500, 20000, 2.1, 62),
+               W.multigraph(40, 200, cmax=20, seed=63)):
+        with wbpr.UploadedGraph(solver, g0) as ug:
+            pairs = [(g0.s, g0.t)] + [tuple(int(x) for x in rng.choice(g0.V, 2, replace=False)) for _ in range(6)]
+            for s_, t_ in pairs:
+                g = W.Graph(g0.V, g0.row_ptr, g0.col, g0.cap, s_, t_, f"{g0.name}[{s_}->{t_}]")
+                say(f"[uploaded] {g.name}")
+                wf = (s_ + t_) % 2 == 0
+                r = ug.solve(s_, t_, want_flow=wf)
+                value, side, _ = oracle.reference(g.V, g.row_ptr, g.col, g.cap, s_, t_)
+                assert r.value == value, (g.name, r.value, value)
+                assert np.array_equal(r.side, side)
+                if wf:
+                    c = oracle.check(g.V, g.row_ptr, g.col, g.cap, s_, t_, r.flow)
+                    assert c.feasible and c.value == value
+            assert ug.solve(0, 0, return_code=True) == wbpr.WBPR_EINVAL
+            assert ug.solve(0, g0.V, return_code=True) == wbpr.WBPR_EINVAL
+            r = ug.solve(g0.s, g0.t)  # still usable after rejected calls
+            assert r.value == oracle.reference(g0.V, g0.row_ptr, g0.col, g0.cap, g0.s, g0.t)[0]
+
+
+def test_autotune_then_tuned_solves(solver):
+    """The autotuner returns a schedule; later automatic solves of that shape use it, exactly."""
+    from paper_2404_00270_amd import wbpr
+
+    g = W.random_graph(6000, 48000, 1, 100, 71)
+    ref = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+    with wbpr.Solver(0, **WATCHDOG) as s2:
+        best, ms = s2.autotune(g, max_trials=6, include_full_scan=True)
+        say(f"[autotune] best={best} ms={ms:.2f}")
+        assert best["lanes_per_vertex"] in (4, 8, 16, 32) and best["gr_work_permille"] > 0 and ms > 0
+        g2 = W.random_graph(6000, 48000, 1, 100, 72)  # same shape class
+        r = s2.solve(g2)
+        assert r.stats["lanes_per_vertex"] == best["lanes_per_vertex"]
+        assert r.value == oracle.reference(g2.V, g2.row_ptr, g2.col, g2.cap, g2.s, g2.t)[0]
+        r = s2.solve(g)
+        assert r.value == ref[0] and np.array_equal(r.side, ref[1])
