@@ -87,7 +87,7 @@ void fill_stats(wbpr_stats *st, const wb::EngineStats &r, const wb::SolveConfig 
   st->split_degree = r.split_degree;
   st->block_degree = r.block_degree;
   st->gr_every_sweeps = cfg.gr_every_sweeps;
-  st->grid_blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : 2048;
+  st->grid_blocks = cfg.grid_blocks > 0 ? cfg.grid_blocks : 1024;
   st->gr_blocks = r.gr_blocks;
   st->ms_build = ms_build;
   st->ms_phase1 = ms_solve;  // both phases, interleaved per instance

@@ -98,7 +98,17 @@ __global__ void k_sweep_control(SweepCtl c) {
       *c.log_n = i + 1;
     }
   }
-  if (next == 0 || *c.rwork - *c.rwork_at_gr > *c.budget) *c.halt = 1;
+  // stagnation: the queue has not reached a new minimum (by 1/64) for 16
+  // sweeps, typically excess circulating among vertices that can no longer
+  // reach the root; only a global relabel marks it stranded
+  bool stagnant = false;
+  if (next < c.stag[0] - (c.stag[0] >> 6)) {
+    c.stag[0] = next;
+    c.stag[1] = 0;
+  } else {
+    stagnant = ++c.stag[1] > 16;
+  }
+  if (next == 0 || stagnant || *c.rwork - *c.rwork_at_gr > *c.budget) *c.halt = 1;
   if (c.scan_cnt) *c.scan_cnt = 0;
 }
 
@@ -946,6 +956,8 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     a.status[3] = bu_levels;
     *a.halt = 0;
     *a.rwork_at_gr = *a.rwork;
+    a.stag[0] = 0x7fffffff;
+    a.stag[1] = 0;
   }
 }
 

@@ -25,7 +25,7 @@ struct SolveConfig {
   int gr_work_permille = 0;   // adaptive relabel budget in thousandths of V + M (0: 1000)
   int64_t max_sweeps = 0;
   int max_wall_ms = 0;
-  int grid_blocks = 0;        // workgroups per sweep launch (0: 2048)
+  int grid_blocks = 0;        // workgroups per sweep launch (0: 1024)
   bool time_kernels = false;  // bracket every sweep / relabel launch with events
   int push_mode = 0;          // 1: single push to the lowest neighbour; 0/2: full discharge
   bool use_graph = true;      // replay the sweep batch as a captured hipGraph
@@ -149,6 +149,7 @@ class Engine {
     int32_t vbase = 0, s = 0, t = 0;  // arena ids
     int64_t abase = 0;
     int phase = 0;  // 1: max preflow, 2: return excess to s, 3: done
+    int32_t maxdeg = 0;  // longest row its sweeps can meet (terminals excluded)
     int group = -1;
     int32_t index = 0;
     int64_t *value = nullptr;
@@ -164,9 +165,10 @@ class Engine {
     bool keep = false;
   };
 
-  int ensure_graph(hipStream_t st, int K, hipGraphExec_t *exec, std::string *err);
+  int ensure_graph(hipStream_t st, int K, int tiers, hipGraphExec_t *exec, std::string *err);
+  int measure_rows(const std::vector<int> &slots, hipStream_t st, std::string *err);
   void drop_graphs();
-  void enqueue_sweeps(hipStream_t st, int K);
+  void enqueue_sweeps(hipStream_t st, int K, int tiers);
   void launch_inst_kernel(int which, const std::vector<int> &slots, hipStream_t st);
   void launch_inst_list(int which, const std::vector<struct InstDev> &list, const std::vector<int> &slots,
                         hipStream_t st);
@@ -214,7 +216,7 @@ class Engine {
   int64_t last_M_ = 0;
   // tiers and launch shapes (fixed per config)
   int P_ = 8, t_mid_ = 32, t_big_ = 2048, bfs_split_ = 64, chunk_ = 1024;
-  // captured sweep batches, one per batch length; adaptive batch length
+  // captured sweep batches, one per (batch length, tiers); adaptive batch length
   std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs_;
   int next_K_ = 64, last_K_ = 0;
   long long last_nonempty_ = 0;

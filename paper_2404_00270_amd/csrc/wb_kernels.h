@@ -70,6 +70,7 @@ struct SweepCtl {
   const long long *rwork, *rwork_at_gr, *budget;
   int32_t *halt;
   int32_t *scan_cnt; // nullable: full-scan queue count, cleared here for the next scan
+  int32_t *stag;     // [2] smallest queue of this round, sweeps since it was reached (reset by the relabel)
   int32_t *log;      // nullable: [log_cap][6] per-sweep records
   int32_t *log_n;
   int32_t log_cap;
@@ -110,6 +111,7 @@ struct GRArgs {
   int32_t *halt;          // sweep halt flag, cleared here
   const long long *rwork; // relabel work so far ...
   long long *rwork_at_gr; // ... snapshot at this global relabel
+  int32_t *stag;          // [2] stagnation state of the sweeps, reset here
 };
 
 // Sweep kernels: tiles of P lanes (P = 4..64), one workgroup per long-row chunk,
