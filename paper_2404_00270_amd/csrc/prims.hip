@@ -159,11 +159,15 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t *keys, in
   for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) hist[(int64_t)d * nblocks + blockIdx.x] = cnt[d];
 }
 
-// Stable scatter through LDS.  Items are ranked in index order (round j,
-// then thread) within their digit; the tile is first rearranged in LDS by
-// (digit, rank), then written out so that consecutive threads store
-// consecutive positions of one digit's run (coalesced instead of one
-// scattered store per item).
+// Stable scatter through LDS.  Wave w of the workgroup owns items
+// [w * RS_ITEMS * 64, (w + 1) * RS_ITEMS * 64) of the tile, read 64 at a
+// time (coalesced).  Phase 1 ranks every item among the earlier items of its
+// wave with the same digit, against wave-private digit counters in LDS (no
+// workgroup barrier between rounds: a wave's LDS accesses stay in order).
+// Then the counters become per-wave offsets within each digit, the tile is
+// placed in LDS in (digit, index) order, and written out so that
+// consecutive threads store consecutive positions of one digit's run.
+// Stable: within a digit, items keep (wave, round, lane) = index order.
 __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                           uint32_t *vout, int64_t n, int shift,
                                                           const int32_t *hist_scanned, int nblocks) {
@@ -171,26 +175,64 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, 
   __shared__ uint32_t s_val[RS_TILE];
   __shared__ int s_gbase[RS_BINS];  // global position of this tile's first item of digit d
   __shared__ int s_lbase[RS_BINS];  // LDS position of this tile's first item of digit d
-  __shared__ int s_run[RS_BINS];    // items of digit d placed so far
   __shared__ int s_wcnt[RS_WAVES][RS_BINS];
   __shared__ int s_wsum[RS_WAVES];
   const int w = threadIdx.x / WB_WAVE;
   const int64_t base = (int64_t)blockIdx.x * RS_TILE;
   const int tile_n = (int)(n - base < RS_TILE ? n - base : RS_TILE);
-  // this tile's digit counts from the scanned histogram (digit-major layout)
   {
     const int d = threadIdx.x;  // RS_THREADS == RS_BINS
-    const int64_t idx = (int64_t)d * nblocks + blockIdx.x;
-    const int g0 = hist_scanned[idx];
-    const int64_t last = (int64_t)RS_BINS * nblocks - 1;
-    const int g1 = idx < last ? hist_scanned[idx + 1] : (int)n;
-    const int cnt = g1 - g0;
-    s_gbase[d] = g0;
-    s_run[d] = 0;
 #pragma unroll
     for (int ww = 0; ww < RS_WAVES; ww++) s_wcnt[ww][d] = 0;
-    // exclusive prefix of the counts over digits (one workgroup scan)
-    int incl = cnt;
+  }
+  __syncthreads();
+  // phase 1: rank within the wave's range
+  volatile int *wc = s_wcnt[w];
+  const unsigned long long lt = lanemask_lt();
+  const int wbase = w * RS_ITEMS * WB_WAVE;
+  uint64_t kk[RS_ITEMS];
+  uint32_t vv[RS_ITEMS];
+  int rr[RS_ITEMS];
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; j++) {
+    const int li = wbase + j * WB_WAVE + lane();
+    const bool valid = li < tile_n;
+    kk[j] = valid ? kin[base + li] : 0;
+    vv[j] = valid ? vin[base + li] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; j++) {
+    const int li = wbase + j * WB_WAVE + lane();
+    const bool valid = li < tile_n;
+    const int d = (int)((kk[j] >> shift) & (RS_BINS - 1));
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < RS_BITS; b++) {
+      const unsigned long long bits = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? bits : ~bits;
+    }
+    const int rank = __popcll(peers & lt);
+    __builtin_amdgcn_wave_barrier();
+    const int before = valid ? wc[d] : 0;
+    __builtin_amdgcn_wave_barrier();
+    rr[j] = before + rank;
+    if (valid && rank == 0) wc[d] = before + __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  // per digit: offsets of the waves, tile total, digit bases
+  {
+    const int d = threadIdx.x;
+    int acc = 0;
+#pragma unroll
+    for (int ww = 0; ww < RS_WAVES; ww++) {
+      const int c = s_wcnt[ww][d];
+      s_wcnt[ww][d] = acc;
+      acc += c;
+    }
+    const int64_t idx = (int64_t)d * nblocks + blockIdx.x;
+    s_gbase[d] = hist_scanned[idx];
+    int incl = acc;
 #pragma unroll
     for (int o = 1; o < WB_WAVE; o <<= 1) {
       const int y = __shfl_up(incl, o, WB_WAVE);
@@ -201,45 +243,22 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, 
     int off = 0;
 #pragma unroll
     for (int ww = 0; ww < RS_WAVES; ww++) off += ww < w ? s_wsum[ww] : 0;
-    s_lbase[d] = off + incl - cnt;
+    s_lbase[d] = off + incl - acc;
   }
   __syncthreads();
-  const unsigned long long lt = lanemask_lt();
+  // phase 2: place the tile in LDS in (digit, index) order
+#pragma unroll
   for (int j = 0; j < RS_ITEMS; j++) {
-    const int li = j * RS_THREADS + threadIdx.x;
-    const bool valid = li < tile_n;
-    const uint64_t key = valid ? kin[base + li] : 0;
-    const uint32_t val = valid ? vin[base + li] : 0;
-    const int d = (int)((key >> shift) & (RS_BINS - 1));
-    unsigned long long peers = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < RS_BITS; b++) {
-      const unsigned long long bits = __ballot((d >> b) & 1);
-      peers &= ((d >> b) & 1) ? bits : ~bits;
+    const int li = wbase + j * WB_WAVE + lane();
+    if (li < tile_n) {
+      const int d = (int)((kk[j] >> shift) & (RS_BINS - 1));
+      const int pos = s_lbase[d] + s_wcnt[w][d] + rr[j];
+      s_key[pos] = kk[j];
+      s_val[pos] = vv[j];
     }
-    const int rank = __popcll(peers & lt);
-    if (valid && rank == 0) s_wcnt[w][d] = __popcll(peers);
-    __syncthreads();
-    if (valid) {
-      int pos = s_lbase[d] + s_run[d] + rank;
-      for (int ww = 0; ww < w; ww++) pos += s_wcnt[ww][d];
-      s_key[pos] = key;
-      s_val[pos] = val;
-    }
-    __syncthreads();
-    {
-      const int dd = threadIdx.x;
-      int sum = 0;
-#pragma unroll
-      for (int ww = 0; ww < RS_WAVES; ww++) {
-        sum += s_wcnt[ww][dd];
-        s_wcnt[ww][dd] = 0;
-      }
-      s_run[dd] += sum;
-    }
-    __syncthreads();
   }
-  // write out in LDS order: position p of digit d goes to gbase[d] + p - lbase[d]
+  __syncthreads();
+  // write out: position p of digit d goes to gbase[d] + p - lbase[d]
   for (int p = threadIdx.x; p < tile_n; p += RS_THREADS) {
     const uint64_t key = s_key[p];
     const int d = (int)((key >> shift) & (RS_BINS - 1));
