@@ -278,6 +278,9 @@ size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int64_t chunk_capacity(int64_t Vcap, int64_t Mcap, int chunk) { return Mcap / chunk + Vcap + 16; }
 
+// The medium-row list doubles as the relabel's four bitmaps.
+int64_t mid_words(int64_t Vcap) { return std::max<int64_t>(Vcap, 4 * ((Vcap + 31) / 32)); }
+
 // Long-row chunk tasks of one sweep: every deferred vertex has
 // ceil(deg / CHUNK) <= deg / CHUNK + 1 tasks.
 int64_t task_capacity(int64_t Vcap, int64_t Mcap) { return Vcap + Mcap / CHUNK + 64; }
@@ -321,7 +324,8 @@ size_t Engine::arena_bytes(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t nca
   b += 2 * al(4 * (size_t)Mcap);             // rev, cap0
   b += 3 * al(4 * (size_t)Ecap);             // arc2ent, pbefore, acap
   b += al(8 * (size_t)Vcap);                 // e
-  b += 5 * al(4 * (size_t)Vcap);             // h, inst_of, q0, q1, mid
+  b += 4 * al(4 * (size_t)Vcap);             // h, inst_of, q0, q1
+  b += al(4 * (size_t)mid_words(Vcap));      // medium-row list (relabel: bitmaps)
   b += 2 * al(4 * (size_t)Vcap);             // BFS frontiers fq0, fq1
   b += 2 * al(4 * (size_t)Vcap);             // long-row list, lr_cnt
   b += 2 * al(4 * (size_t)task_capacity(Vcap, Mcap));  // chunk tasks
@@ -419,7 +423,7 @@ int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int6
     inst_of_ = (int32_t *)take(4 * (size_t)Vcap);
     q_[0] = (int32_t *)take(4 * (size_t)Vcap);
     q_[1] = (int32_t *)take(4 * (size_t)Vcap);
-    mid_ = (int32_t *)take(4 * (size_t)Vcap);
+    mid_ = (int32_t *)take(4 * (size_t)mid_words(Vcap));
     fq_[0] = (int32_t *)take(4 * (size_t)Vcap);
     fq_[1] = (int32_t *)take(4 * (size_t)Vcap);
     big_ = (int32_t *)take(4 * (size_t)Vcap);
@@ -1083,6 +1087,10 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   ga.rwork = &misc->rwork;
   ga.rwork_at_gr = &misc->rwork_at_gr;
   ga.stag = misc->stag;
+  // the medium-row list is idle during a relabel: it holds the bitmaps
+  // (4 x ceil(V/32) words <= V words)
+  ga.bm = reinterpret_cast<uint32_t *>(mid_);
+  ga.bm_words = (int32_t)((Vcap_ + 31) / 32);
   const int Pg = std::max(P_, 4);  // tile width of the relabel's top-down expansion
   int lg = 0;
   while ((1 << lg) < Pg) lg++;

@@ -622,6 +622,11 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk_finish(Graph g, SweepQ q) {
 
 __device__ __forceinline__ uint8_t dist_code(int32_t d) { return (uint8_t)(1 + (d & 1)); }
 
+__device__ __forceinline__ bool bm_test(const uint32_t *bm, int32_t v) { return (bm[v >> 5] >> (v & 31)) & 1u; }
+__device__ __forceinline__ void bm_set(uint32_t *bm, int32_t v) {
+  __hip_atomic_fetch_or(&bm[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // counters[key] += number of lanes with pred and that key; one atomic per
 // distinct key in the wave (consecutive vertices mostly share an instance).
 __device__ __forceinline__ void wave_count_by_key(bool pred, int32_t key, int32_t *counters) {
@@ -667,6 +672,10 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     g.h[v] = g.hcap;
     a.vis[v] = 0;
   }
+  // frontier membership and visited flags as bitmaps (1/32 of a byte array:
+  // they stay in L2 where the per-entry gathers of a level hit them)
+  uint32_t *const bm_vis = a.bm;
+  for (int64_t j = gtid; j < 4 * (int64_t)a.bm_words; j += nthreads) a.bm[j] = 0;
   for (int64_t j = gtid; j < a.nroots; j += nthreads) a.fq[0][j] = a.roots[j];
   if (gtid == 0) {
     a.fcnt[0] = a.nroots;
@@ -694,10 +703,13 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   for (int64_t j = gtid; j < a.nroots; j += nthreads) {
     g.h[a.roots[j]] = a.root_h[j];
     a.vis[a.roots[j]] = dist_code(0);
+    bm_set(bm_vis, a.roots[j]);
+    bm_set(a.bm + a.bm_words, a.roots[j]);  // frontier of level 0
   }
   for (int64_t j = gtid; j < a.nexcl; j += nthreads) {
     g.h[a.excl[j]] = g.hcap + 1;
     a.vis[a.excl[j]] = 3;
+    bm_set(bm_vis, a.excl[j]);
   }
   grid_barrier(a.bar, nblocks);
 
@@ -709,6 +721,12 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   for (;;) {
     if (n == 0) break;
     const uint8_t cur = dist_code(level), nxt = dist_code(level + 1);
+    // frontier bitmaps rotate over three: this level reads bm_in, writes
+    // bm_out (cleared during the previous level) and clears the third
+    const uint32_t *bm_in = a.bm + (int64_t)(1 + level % 3) * a.bm_words;
+    uint32_t *bm_out = a.bm + (int64_t)(1 + (level + 1) % 3) * a.bm_words;
+    uint32_t *bm_clr = a.bm + (int64_t)(1 + (level + 2) % 3) * a.bm_words;
+    for (int64_t j = gtid; j < a.bm_words; j += nthreads) bm_clr[j] = 0;
     int32_t *fout = a.fq[(level + 1) & 1];
     int32_t *fout_cnt = &a.fcnt[(level + 1) % 3];
     long long *fe_out = &a.fedges[(level + 1) % 3];
@@ -758,7 +776,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
             if (k < end) {
               const int2 cr = g.ent[k];
               w = cr.x;
-              hit = cr.y > 0 && a.vis[w] == cur;
+              hit = cr.y > 0 && bm_test(bm_in, w);
             }
             const unsigned long long m = (__ballot(hit) >> tbase) & (P == 64 ? ~0ull : ((1ull << P) - 1));
             if (tl == 0) buscans += min(P, end - kb);
@@ -766,6 +784,8 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
               if (tl == __ffsll((long long)m) - 1) {
                 g.h[v] = g.h[w] + 1;
                 a.vis[v] = nxt;
+                bm_set(bm_vis, (int32_t)v);
+                bm_set(bm_out, (int32_t)v);
                 found_cnt++;
                 my_edges += end - beg;
               }
@@ -798,13 +818,15 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
           if (k < ce) {
             const int2 cr = g.ent[k];
             w = cr.x;
-            hit = cr.y > 0 && a.vis[w] == cur;
+            hit = cr.y > 0 && bm_test(bm_in, w);
           }
           const unsigned long long m = __ballot(hit);
           if (m) {
             if (lane() == __ffsll((long long)m) - 1) {
               if (atomicCAS(&g.h[v], g.hcap, g.h[w] + 1) == g.hcap) {
                 a.vis[v] = nxt;
+                bm_set(bm_vis, v);
+                bm_set(bm_out, v);
                 found_cnt++;
                 my_edges += (g.rowb[v].y - g.rowb[v].x);
               }
@@ -867,10 +889,12 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
             for (int32_t k = beg + tl; k < end; k += P) {
               const int32_t v = g.ent[k].x;
               bool claimed = false;
-              if (g.h[v] == g.hcap && g.ent[g.rev[k]].y > 0) {
+              if (!bm_test(bm_vis, v) && g.ent[g.rev[k]].y > 0) {
                 claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
                 if (claimed) {
                   a.vis[v] = nxt;
+                  bm_set(bm_vis, v);
+                  bm_set(bm_out, v);
                   my_edges += (g.rowb[v].y - g.rowb[v].x);
                 }
               }
@@ -896,10 +920,12 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         for (int32_t k = cb + lane(); k < ce; k += WB_WAVE) {
           const int32_t v = g.ent[k].x;
           bool claimed = false;
-          if (g.h[v] == g.hcap && g.ent[g.rev[k]].y > 0) {
+          if (!bm_test(bm_vis, v) && g.ent[g.rev[k]].y > 0) {
             claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
             if (claimed) {
               a.vis[v] = nxt;
+              bm_set(bm_vis, v);
+              bm_set(bm_out, v);
               my_edges += (g.rowb[v].y - g.rowb[v].x);
             }
           }

@@ -112,6 +112,8 @@ struct GRArgs {
   const long long *rwork; // relabel work so far ...
   long long *rwork_at_gr; // ... snapshot at this global relabel
   int32_t *stag;          // [2] stagnation state of the sweeps, reset here
+  uint32_t *bm;           // 4 bitmaps of bm_words words: visited, then three rotating frontiers
+  int32_t bm_words;       // words per bitmap (>= V / 32)
 };
 
 // Sweep kernels: tiles of P lanes (P = 4..64), one workgroup per long-row chunk,
