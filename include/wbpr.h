@@ -107,7 +107,12 @@ typedef struct wbpr_options {
                                   appended as they go), 1 full scan of every
                                   vertex at the start of each sweep
                                   (Algorithm 2 as printed) */
-    int32_t reserved[2];
+    int32_t gr_stagnation;     /* with gr_every_sweeps = 0: a round of sweeps
+                                  also ends after this many sweeps without a
+                                  new smallest active queue (0 = from the mean
+                                  row length: 32, 8 or 4 for <= 10, <= 20,
+                                  longer) */
+    int32_t reserved[1];
 } wbpr_options;
 
 /* Per-solve counters and timings (filled when a non-NULL pointer is given). */
@@ -230,7 +235,7 @@ int wbpr_graph_solve(wbpr_graph *gr, int32_t s, int32_t t, int64_t *value, int32
 void wbpr_graph_free(wbpr_graph *gr);
 
 /* Autotuner: picks the schedule (lanes per vertex, relabel-work budget,
- * queue mode) for graphs shaped like g.  The graph is uploaded once; each
+ * stagnation window, queue mode) for graphs shaped like g.  The graph is uploaded once; each
  * candidate schedule solves (s, t) once to warm up and once timed (flows
  * and cut included); every candidate must give the same flow value
  * (WBPR_EINTERNAL otherwise: results never depend on the schedule).  The
@@ -239,7 +244,7 @@ void wbpr_graph_free(wbpr_graph *gr);
  * shape class (log2 V and log2 of the mean row length); later solves on ctx
  * whose options leave lanes_per_vertex and gr_work_permille at 0 use the
  * remembered schedule for graphs of that class.  max_trials bounds the
- * number of candidates (0 = all, at most 16); include_full_scan adds the
+ * number of candidates (0 = all, at most 20); include_full_scan adds the
  * full-scan queue to the candidates. */
 int wbpr_autotune(wbpr_ctx *ctx, const wbpr_csr *g, int32_t s, int32_t t, int32_t max_trials,
                   int32_t include_full_scan, wbpr_options *best, double *best_ms);

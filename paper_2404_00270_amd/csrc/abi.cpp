@@ -51,6 +51,7 @@ wb::SolveConfig to_config(const wbpr_options *o) {
   c.push_mode = o->push_mode;
   c.use_graph = o->no_graph == 0;
   c.full_scan = o->avq_mode == 1;
+  c.gr_stagnation = o->gr_stagnation;
   return c;
 }
 
@@ -61,6 +62,7 @@ int check_options(const wbpr_options *o) {
     return fail(WBPR_EINVAL, "lanes_per_vertex must be 0, 1, 4, 8, 16, 32 or 64");
   if (o->avq_mode < 0 || o->avq_mode > 2) return fail(WBPR_EINVAL, "avq_mode must be 0, 1 or 2");
   if (o->split_degree < 0 || o->block_degree < 0 || o->gr_every_sweeps < 0 || o->gr_work_permille < 0 ||
+      o->gr_stagnation < 0 ||
       o->max_sweeps < 0 || o->max_wall_ms < 0 || o->grid_blocks < 0)
     return fail(WBPR_EINVAL, "negative option");
   if (o->layout != WBPR_LAYOUT_AUTO && o->layout != WBPR_LAYOUT_BCSR) return fail(WBPR_EINVAL, "unknown layout");
@@ -199,6 +201,7 @@ wb::SolveConfig effective_config(wbpr_ctx *c, int64_t V, int64_t E) {
     if (it != c->tuned.end()) {
       cfg.lanes_per_vertex = it->second.lanes_per_vertex;
       cfg.gr_work_permille = it->second.gr_work_permille;
+      cfg.gr_stagnation = it->second.gr_stagnation;
       cfg.full_scan = it->second.full_scan;
     }
   }
@@ -207,7 +210,8 @@ wb::SolveConfig effective_config(wbpr_ctx *c, int64_t V, int64_t E) {
 
 bool same_schedule(const wb::SolveConfig &a, const wb::SolveConfig &b) {
   return a.lanes_per_vertex == b.lanes_per_vertex && a.gr_work_permille == b.gr_work_permille &&
-         a.full_scan == b.full_scan && a.split_degree == b.split_degree && a.block_degree == b.block_degree &&
+         a.full_scan == b.full_scan && a.gr_stagnation == b.gr_stagnation && a.split_degree == b.split_degree &&
+         a.block_degree == b.block_degree &&
          a.gr_every_sweeps == b.gr_every_sweeps && a.grid_blocks == b.grid_blocks &&
          a.time_kernels == b.time_kernels && a.push_mode == b.push_mode && a.use_graph == b.use_graph &&
          a.max_sweeps == b.max_sweeps && a.max_wall_ms == b.max_wall_ms;
@@ -584,17 +588,19 @@ int wbpr_autotune(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int32_t 
   int rc = check_shape(g->V, g->E, s, t);
   if (rc) return rc;
   struct Cand {
-    int lanes, permille;
+    int lanes, permille, stag;
     bool full_scan;
   };
   std::vector<Cand> cands;
   // most promising first, so a small max_trials keeps the likely winners
-  const int lanes_order[] = {8, 16, 4, 32};
-  const int permille_order[] = {1000, 3000, 300};
+  const int lanes_order[] = {8, 16, 4};
+  const int stag_order[] = {0, 4, 32};
+  const int permille_order[] = {1000, 300};
   for (int pm : permille_order)
-    for (int l : lanes_order) cands.push_back({l, pm, false});
+    for (int sg : stag_order)
+      for (int l : lanes_order) cands.push_back({l, pm, sg, false});
   if (include_full_scan)
-    for (int l : {8, 16}) cands.push_back({l, 1000, true});
+    for (int l : {8, 16}) cands.push_back({l, 1000, 0, true});
   if (max_trials > 0 && (size_t)max_trials < cands.size()) cands.resize((size_t)max_trials);
   wbpr_graph *G = nullptr;
   rc = wbpr_graph_upload(c, g, &G);
@@ -608,6 +614,7 @@ int wbpr_autotune(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int32_t 
     wb::SolveConfig cfg = c->cfg;
     cfg.lanes_per_vertex = cands[i].lanes;
     cfg.gr_work_permille = cands[i].permille;
+    cfg.gr_stagnation = cands[i].stag;
     cfg.full_scan = cands[i].full_scan;
     cfg.time_kernels = false;
     G->cfg = cfg;
@@ -638,6 +645,7 @@ int wbpr_autotune(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int32_t 
   wb::SolveConfig win = c->cfg;
   win.lanes_per_vertex = cands[bi].lanes;
   win.gr_work_permille = cands[bi].permille;
+  win.gr_stagnation = cands[bi].stag;
   win.full_scan = cands[bi].full_scan;
   c->tuned[shape_class(g->V, g->E)] = win;
   std::memset(best, 0, sizeof(*best));
@@ -654,6 +662,7 @@ int wbpr_autotune(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int32_t 
   best->gr_work_permille = win.gr_work_permille;
   best->no_graph = win.use_graph ? 0 : 1;
   best->avq_mode = win.full_scan ? 1 : 0;
+  best->gr_stagnation = win.gr_stagnation;
   if (best_ms) *best_ms = bms;
   return WBPR_OK;
 }

@@ -86,7 +86,7 @@ __global__ void k_check_rowptr(const int64_t *rp, int32_t V, int64_t E, BuildSta
 __global__ void k_emit_keys(const int64_t *rp, const int32_t *col, const int32_t *cap, int32_t V, int64_t E, int vb,
                             uint64_t *keys, uint32_t *vals, int32_t *arc2ent, int32_t *acap, BuildStatus *st) {
   const uint64_t ALL = (vb * 2 >= 64) ? ~0ull : ((1ull << (2 * vb)) - 1);
-  int nself = 0, bad = 0;
+  int nself = 0, bad = 0, cmax = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
     int32_t lo = 0, hi = V - 1;
     while (lo < hi) {
@@ -111,12 +111,18 @@ __global__ void k_emit_keys(const int64_t *rp, const int32_t *col, const int32_t
     vals[2 * i] = (uint32_t)(2 * i);
     vals[2 * i + 1] = (uint32_t)(2 * i + 1);
     acap[i] = cap[i];
+    cmax = max(cmax, cap[i]);
   }
   nself = wave_sum_i32(nself);
   bad = wave_sum_i32(bad);
+#pragma unroll
+  for (int o = WB_WAVE / 2; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o, WB_WAVE));
   if (lane() == 0) {
     if (nself) atomicAdd(&st->nself, nself);
     if (bad) atomicAdd(&st->bad_input, bad);
+    // one address for the whole grid: skip the atomic unless it raises the
+    // maximum (after the first waves almost every wave skips it)
+    if (cmax > __hip_atomic_load(&st->cmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&st->cmax, cmax);
   }
 }
 
@@ -161,17 +167,29 @@ __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, 
 // group; capacity of earlier parallel arcs of forward item i = pc[i] - pc of
 // its group's start (the sort is stable, so a group's arcs are in input
 // order).
-__global__ void k_group_caps(const uint32_t *vals, const BuildStatus *st, const int32_t *head, const int32_t *hx,
+// A group holds the forward items of arcs u->v and the backward items of arcs
+// v->u, so its size counts every input arc joining the pair.
+__global__ void k_group_caps(const uint32_t *vals, BuildStatus *st, const int32_t *head, const int32_t *hx,
                              const int32_t *gstart, const int64_t *pc, unsigned long long *capacc, int32_t *pbefore_arc,
                              int64_t N) {
   const int64_t mraw = N - 2 * (int64_t)st->nself;
+  int gmax = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mraw; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t u = hx[i] + head[i] - 1;
-    const int64_t g0 = pc[gstart[u]];
-    if (head[i]) capacc[u] = (unsigned long long)(pc[gstart[u + 1]] - g0);
+    const int32_t gs = gstart[u];
+    const int64_t g0 = pc[gs];
+    if (head[i]) {
+      const int32_t ge = gstart[u + 1];
+      capacc[u] = (unsigned long long)(pc[ge] - g0);
+      gmax = max(gmax, ge - gs);
+    }
     const uint32_t pl = vals[i];
     if (!(pl & 1u)) pbefore_arc[pl >> 1] = (int32_t)(pc[i] - g0);
   }
+#pragma unroll
+  for (int o = WB_WAVE / 2; o > 0; o >>= 1) gmax = max(gmax, __shfl_xor(gmax, o, WB_WAVE));
+  if (lane() == 0 && gmax > __hip_atomic_load(&st->maxgroup, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&st->maxgroup, gmax);
 }
 
 // Step 3c.  Row pointers without atomics (rows such as s and t of a grid cut
@@ -217,6 +235,9 @@ __global__ void k_arcs(int64_t E, const int32_t *uid_of, int32_t mbase, int32_t 
 __global__ void k_caps(const BuildStatus *st, const unsigned long long *capacc, const int32_t *rev, int32_t mbase,
                        int2 *ent, int32_t *cap0, BuildStatus *stw) {
   int64_t M = st->M;
+  // c(u->v) + c(v->u) is at most (arcs joining the pair) x (largest
+  // capacity); when that bound fits in int32 the mate's sum need not be read
+  const bool exact = (long long)st->cmax * (long long)st->maxgroup > 0x7fffffffll;
   int ovf = 0;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r = rev[j] - mbase;
@@ -224,8 +245,8 @@ __global__ void k_caps(const BuildStatus *st, const unsigned long long *capacc, 
       atomicAdd(&stw->bad_input, 1);
       continue;
     }
-    unsigned long long c = capacc[j], cr = capacc[r];
-    if (c + cr > 0x7fffffffull) { ovf++; c = 0; }
+    unsigned long long c = capacc[j];
+    if (exact && c + capacc[r] > 0x7fffffffull) { ovf++; c = 0; }
     ent[j].y = (int)c;
     cap0[j] = (int32_t)c;
   }

@@ -986,6 +986,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
     ctl.halt = &misc->halt[0];
     ctl.scan_cnt = fs ? &misc->scan_cnt : nullptr;
     ctl.stag = misc->stag;
+    ctl.stag_window = cfg_.gr_every_sweeps > 0 ? 0x7fffffff : stag_window_;
     ctl.log = sweep_log_;
     ctl.log_n = &misc->log_n;
     ctl.log_cap = kSweepLogCap;
@@ -1003,10 +1004,15 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   // one lane per vertex is the thread-centric baseline: no medium or long tiers
   const int tm = P == 1 ? 0x7fffffff : cfg_.split_degree > 0 ? cfg_.split_degree : 4 * P;
   const int tb = P == 1 ? 0x7fffffff : std::max(tm, cfg_.block_degree > 0 ? cfg_.block_degree : 2048);
-  if (P != P_ || tm != t_mid_ || tb != t_big_) {
+  // stagnation window (measured: R-MAT best at 4, where excess that will be
+  // stranded keeps circulating among hubs; the grid cut at 32, where the
+  // queue shrinks slowly and relabels are long BFSs; bipartite at 8)
+  const int sw = cfg_.gr_stagnation > 0 ? cfg_.gr_stagnation : (mean_row <= 10.0 ? 32 : mean_row <= 20.0 ? 8 : 4);
+  if (P != P_ || tm != t_mid_ || tb != t_big_ || sw != stag_window_) {
     P_ = P;
     t_mid_ = tm;
     t_big_ = tb;
+    stag_window_ = sw;
     bfs_split_ = 8 * P;
     drop_graphs();
   }

@@ -98,15 +98,15 @@ __global__ void k_sweep_control(SweepCtl c) {
       *c.log_n = i + 1;
     }
   }
-  // stagnation: the queue has not reached a new minimum (by 1/64) for 16
-  // sweeps, typically excess circulating among vertices that can no longer
-  // reach the root; only a global relabel marks it stranded
+  // stagnation: the queue has not reached a new minimum (by 1/64) for
+  // stag_window sweeps, typically excess circulating among vertices that can
+  // no longer reach the root; only a global relabel marks it stranded
   bool stagnant = false;
   if (next < c.stag[0] - (c.stag[0] >> 6)) {
     c.stag[0] = next;
     c.stag[1] = 0;
   } else {
-    stagnant = ++c.stag[1] > 16;
+    stagnant = ++c.stag[1] > c.stag_window;
   }
   if (next == 0 || stagnant || *c.rwork - *c.rwork_at_gr > *c.budget) *c.halt = 1;
   if (c.scan_cnt) *c.scan_cnt = 0;

@@ -30,6 +30,7 @@ struct SolveConfig {
   int push_mode = 0;          // 1: single push to the lowest neighbour; 0/2: full discharge
   bool use_graph = true;      // replay the sweep batch as a captured hipGraph
   bool full_scan = false;     // rebuild the active queue by a full scan every sweep
+  int gr_stagnation = 0;      // sweeps without a new smallest queue that end a round (0: by mean row length)
 };
 
 // Counters of the engine since the last reset_stats().
@@ -215,7 +216,7 @@ class Engine {
   int64_t resident_V_ = 0, resident_M_ = 0;
   int64_t last_M_ = 0;
   // tiers and launch shapes (fixed per config)
-  int P_ = 8, t_mid_ = 32, t_big_ = 2048, bfs_split_ = 64, chunk_ = 1024;
+  int P_ = 8, t_mid_ = 32, t_big_ = 2048, bfs_split_ = 64, chunk_ = 1024, stag_window_ = 16;
   // captured sweep batches, one per (batch length, tiers); adaptive batch length
   std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs_;
   int next_K_ = 64, last_K_ = 0;

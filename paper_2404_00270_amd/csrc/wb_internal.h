@@ -40,6 +40,8 @@ struct BuildStatus {
   int32_t overflow;   // merged pair capacity above INT32_MAX
   int32_t nself;      // self-loops
   int32_t M;          // merged entries
+  int32_t cmax;       // largest input capacity
+  int32_t maxgroup;   // most input arcs joining one vertex pair (both directions)
 };
 
 // Device scratch needed by build_residual for V vertices and E arcs.

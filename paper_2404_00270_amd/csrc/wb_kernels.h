@@ -71,6 +71,7 @@ struct SweepCtl {
   int32_t *halt;
   int32_t *scan_cnt; // nullable: full-scan queue count, cleared here for the next scan
   int32_t *stag;     // [2] smallest queue of this round, sweeps since it was reached (reset by the relabel)
+  int32_t stag_window;  // sweeps without a new smallest queue that end the round
   int32_t *log;      // nullable: [log_cap][6] per-sweep records
   int32_t *log_n;
   int32_t log_cap;

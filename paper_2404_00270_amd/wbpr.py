@@ -66,7 +66,8 @@ class wbpr_options(ctypes.Structure):
         ("gr_work_permille", ctypes.c_int32),
         ("no_graph", ctypes.c_int32),
         ("avq_mode", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 2),
+        ("gr_stagnation", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
