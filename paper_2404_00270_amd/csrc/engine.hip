@@ -891,7 +891,7 @@ void Engine::dump_sweep_log(hipStream_t st) {
   int32_t n = 0;
   if (hipMemcpyAsync(&n, &misc->log_n, 4, hipMemcpyDeviceToHost, st) != hipSuccess) return;
   if (hipStreamSynchronize(st) != hipSuccess) return;
-  n = std::min(n, kSweepLogCap);
+  n = std::min(n, kSweepLogCap / 2);
   std::vector<int32_t> rec(6 * (size_t)std::max(n, 1));
   if (n > 0 && hipMemcpy(rec.data(), sweep_log_dev_, 24 * (size_t)n, hipMemcpyDeviceToHost) != hipSuccess) return;
   std::fprintf(stderr, "[wbpr] sweep log: %d sweeps (queue, medium, long, chunk tasks, queue out, relabel work)\n", n);
@@ -989,7 +989,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
     ctl.stag_window = cfg_.gr_every_sweeps > 0 ? 0x7fffffff : stag_window_;
     ctl.log = sweep_log_;
     ctl.log_n = &misc->log_n;
-    ctl.log_cap = kSweepLogCap;
+    ctl.log_cap = kSweepLogCap / 2;
     launch_sweep_control(st, ctl);
   }
 }
@@ -1088,6 +1088,7 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   ga.chunk_cap = (int32_t)std::min<int64_t>(nchunk_, 0x7fffffff);
   ga.bu_threshold = (int32_t)std::max<int64_t>(resident_V_ / 32, 4096);
   ga.bu_edges = std::max<long long>(resident_M_ / 16, 65536);
+  ga.m_total = resident_M_;
   ga.err = misc->err;
   ga.halt = misc->halt;
   ga.rwork = &misc->rwork;
@@ -1097,6 +1098,10 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   // (4 x ceil(V/32) words <= V words)
   ga.bm = reinterpret_cast<uint32_t *>(mid_);
   ga.bm_words = (int32_t)((Vcap_ + 31) / 32);
+  // diagnostics (WBPR_LOG >= 3): per-level timestamps in the sweep-log space
+  // second half of the sweep-log space (the sweep log keeps the first)
+  ga.tlog = log_level() >= 3 ? reinterpret_cast<long long *>(sweep_log_dev_ + 3 * (size_t)kSweepLogCap) : nullptr;
+  ga.tlog_cap = kSweepLogCap / 2;
   const int Pg = std::max(P_, 4);  // tile width of the relabel's top-down expansion
   int lg = 0;
   while ((1 << lg) < Pg) lg++;
@@ -1142,6 +1147,20 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   }
   const long long *status = reinterpret_cast<const long long *>(rb);
   const int32_t *errw = reinterpret_cast<const int32_t *>(rb + sizeof(misc->status));
+  if (ga.tlog) {  // per-level times of this relabel (100 MHz wall clock)
+    const int nl = (int)std::min<long long>(status[2] + 3, ga.tlog_cap);
+    std::vector<long long> t(3 * (size_t)nl);
+    if (hipMemcpy(t.data(), ga.tlog, 24 * (size_t)nl, hipMemcpyDeviceToHost) == hipSuccess) {
+      std::string line = "[wbpr] relabel levels (us, frontier, frontier edges; negative: bottom-up):";
+      for (int i = 1; i < nl; i++) {
+        char buf[96];
+        std::snprintf(buf, sizeof(buf), " [%.1f %lld %lld]", (t[3 * i] - t[3 * (i - 1)]) / 100.0, t[3 * (i - 1) + 1],
+                      t[3 * (i - 1) + 2]);
+        line += buf;
+      }
+      std::fprintf(stderr, "%s\n", line.c_str());
+    }
+  }
   acc_.gr_levels += status[2];
   if (log_level() > 0) {
     const double gms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tg0).count();

@@ -627,6 +627,14 @@ __device__ __forceinline__ void bm_set(uint32_t *bm, int32_t v) {
   __hip_atomic_fetch_or(&bm[v >> 5], 1u << (v & 31), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Running per-wave count for the common case of one key per wave step
+// (wave-uniform): flushed with one atomic when the key changes and at the
+// end, instead of one atomic per wave step on the same counter.
+struct KeyCount {
+  int32_t key = -1;
+  int32_t cnt = 0;
+};
+
 // counters[key] += number of lanes with pred and that key; one atomic per
 // distinct key in the wave (consecutive vertices mostly share an instance).
 __device__ __forceinline__ void wave_count_by_key(bool pred, int32_t key, int32_t *counters) {
@@ -637,6 +645,27 @@ __device__ __forceinline__ void wave_count_by_key(bool pred, int32_t key, int32_
     const unsigned long long same = __ballot(pred && key == k);
     if (lane() == leader) atomic_add_i32(&counters[k], __popcll(same));
     m &= ~same;
+  }
+}
+
+__device__ __forceinline__ void key_count_flush(KeyCount &kc, int32_t *counters) {
+  if (kc.cnt && lane() == 0) atomic_add_i32(&counters[kc.key], kc.cnt);
+  kc.cnt = 0;
+}
+
+__device__ __forceinline__ void key_count_add(bool pred, int32_t key, KeyCount &kc, int32_t *counters) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0) return;
+  const int leader = __ffsll((long long)m) - 1;
+  const int32_t k0 = __shfl(key, leader, WB_WAVE);
+  if (__ballot(pred && key == k0) == m) {
+    if (k0 != kc.key) {
+      key_count_flush(kc, counters);
+      kc.key = k0;
+    }
+    kc.cnt += __popcll(m);
+  } else {
+    wave_count_by_key(pred, key, counters);
   }
 }
 
@@ -668,6 +697,11 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   const int tbase = lane() & ~(P - 1);
   if (lane() == 0) s_qcnt[wl] = 0;
 
+  if (a.tlog && gtid == 0) {
+    a.tlog[0] = (long long)wall_clock64();
+    a.tlog[1] = -2;  // set-up
+    a.tlog[2] = 0;
+  }
   for (int64_t v = gtid; v < g.V; v += nthreads) {
     g.h[v] = g.hcap;
     a.vis[v] = 0;
@@ -717,6 +751,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   int32_t level = 0, bu_levels = 0;
   int32_t n = min(a.nroots, a.qcap);
   long long nedges = 0;  // row-length sum of the current frontier (0: the root alone)
+  long long vedges = 0;  // row-length sum of every vertex labelled so far
   bool queue_valid = true;  // the frontier of this level is in fq[level & 1]
   for (;;) {
     if (n == 0) break;
@@ -737,15 +772,29 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
       a.bucnt[(level + 2) % 3] = 0;
       a.fedges[(level + 2) % 3] = 0;
     }
-    const bool bottom_up = n > a.bu_threshold || nedges > a.bu_edges;
+    // direction: bottom-up while the frontier is large or its rows hold more
+    // than 1/16 of the rows still unvisited (late levels whose frontier is a
+    // few hubs are cheaper bottom-up: little is left to scan)
+    vedges += nedges;
+    const long long unvisited_edges = a.m_total - vedges;
+    const bool bottom_up = n > a.bu_threshold || nedges > a.bu_edges || 16 * nedges > unvisited_edges;
+    if (a.tlog && gtid == 0 && level + 1 < a.tlog_cap) {
+      a.tlog[3 * (level + 1)] = (long long)wall_clock64();
+      a.tlog[3 * (level + 1) + 1] = n;
+      a.tlog[3 * (level + 1) + 2] = bottom_up ? -nedges - 1 : nedges;  // sign: direction
+    }
     if (bottom_up) {
       bu_levels++;
-      // every unvisited vertex with a short row: tile of P lanes, stop at
-      // the first residual arc into the frontier; long rows become chunks
+      // every unvisited vertex looks for a residual arc into the frontier
+      // and stops at the first: one lane per vertex (coalesced visit codes
+      // and row bounds, most rows are short); rows longer than BU_SHORT are
+      // then taken one at a time by the whole wave (the wave's own list, no
+      // global step); rows longer than split_deg become chunks
+      constexpr int32_t BU_SHORT = 32;
       int found_cnt = 0;
       int32_t *ccnt = &a.chunk_cnt[level & 1];
-      for (int64_t vb = (int64_t)wave * TPW; vb < g.V; vb += (int64_t)nwaves * TPW) {
-        const int64_t v = vb + sub;
+      for (int64_t vb = (int64_t)wave * WB_WAVE; vb < g.V; vb += (int64_t)nwaves * WB_WAVE) {  // wave-uniform
+        const int64_t v = vb + lane();
         bool mine = v < g.V && a.vis[v] == 0;
         int32_t beg = 0, end = 0;
         if (mine) {
@@ -753,41 +802,68 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
           beg = rb.x;
           end = rb.y;
         }
-        if (mine && end - beg > a.split_deg) {
+        const int32_t deg = end - beg;
+        if (mine && deg > a.split_deg) {
           mine = false;
-          if (tl == 0) {
-            const int32_t nch = (end - beg + a.chunk - 1) / a.chunk;
-            const int32_t c0 = atomic_add_i32(ccnt, nch);
-            if (c0 + nch <= a.chunk_cap) {
-              for (int32_t j = 0; j < nch; j++) {
-                a.chunk_w[c0 + j] = (int32_t)v;
-                a.chunk_b[c0 + j] = beg + j * a.chunk;
-              }
-            } else {
-              atomic_add_i32(a.err, 1);
+          const int32_t nch = (deg + a.chunk - 1) / a.chunk;
+          const int32_t c0 = atomic_add_i32(ccnt, nch);
+          if (c0 + nch <= a.chunk_cap) {
+            for (int32_t j = 0; j < nch; j++) {
+              a.chunk_w[c0 + j] = (int32_t)v;
+              a.chunk_b[c0 + j] = beg + j * a.chunk;
             }
+          } else {
+            atomic_add_i32(a.err, 1);
           }
         }
-        if (mine) {
-          for (int32_t kb = beg; kb < end; kb += P) {  // tile-uniform trip count
-            const int32_t k = kb + tl;
+        if (mine && deg <= BU_SHORT) {
+          // four entries per step: their loads and bitmap probes overlap
+          int32_t hitw = -1;
+          int32_t k = beg;
+          for (; k < end && hitw < 0; k += 4) {
+            int2 cr[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) cr[j] = k + j < end ? g.ent[k + j] : make_int2(0, 0);
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+              if (hitw < 0 && cr[j].y > 0 && bm_test(bm_in, cr[j].x)) hitw = cr[j].x;
+          }
+          buscans += (k < end ? k : end) - beg;
+          if (hitw >= 0) {
+            g.h[v] = g.h[hitw] + 1;
+            a.vis[v] = nxt;
+            bm_set(bm_vis, (int32_t)v);
+            bm_set(bm_out, (int32_t)v);
+            found_cnt++;
+            my_edges += deg;
+          }
+        }
+        // medium rows of this wave, one after the other with all lanes
+        unsigned long long med = __ballot(mine && deg > BU_SHORT);
+        while (med) {
+          const int src = __ffsll((long long)med) - 1;
+          med &= med - 1;
+          const int32_t mv = (int32_t)(vb + src);
+          const int32_t mb = __shfl(beg, src, WB_WAVE), me = __shfl(end, src, WB_WAVE);
+          for (int32_t kb = mb; kb < me; kb += WB_WAVE) {  // wave-uniform
+            const int32_t k = kb + lane();
             bool hit = false;
             int32_t w = 0;
-            if (k < end) {
+            if (k < me) {
               const int2 cr = g.ent[k];
               w = cr.x;
               hit = cr.y > 0 && bm_test(bm_in, w);
             }
-            const unsigned long long m = (__ballot(hit) >> tbase) & (P == 64 ? ~0ull : ((1ull << P) - 1));
-            if (tl == 0) buscans += min(P, end - kb);
+            const unsigned long long m = __ballot(hit);
+            if (lane() == 0) buscans += min(WB_WAVE, me - kb);
             if (m) {
-              if (tl == __ffsll((long long)m) - 1) {
-                g.h[v] = g.h[w] + 1;
-                a.vis[v] = nxt;
-                bm_set(bm_vis, (int32_t)v);
-                bm_set(bm_out, (int32_t)v);
+              if (lane() == __ffsll((long long)m) - 1) {
+                g.h[mv] = g.h[w] + 1;
+                a.vis[mv] = nxt;
+                bm_set(bm_vis, mv);
+                bm_set(bm_out, mv);
                 found_cnt++;
-                my_edges += end - beg;
+                my_edges += me - mb;
               }
               break;
             }
@@ -848,13 +924,15 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     } else {
       const int32_t *fin = a.fq[level & 1];
       if (!queue_valid) {
-        // the frontier was produced bottom-up: list the vertices of code(L)
+        // the frontier was produced bottom-up: list it from its bitmap (the
+        // visit codes tell distance parity only, which would also list the
+        // vertices two levels back)
         WaveQ wq{s_qbuf[wl], &s_qcnt[wl], a.fq[level & 1], &a.fcnt[level % 3], a.qcap, a.err};
         if (gtid == 0) a.fcnt[level % 3] = 0;
         grid_barrier(a.bar, nblocks);
         for (int64_t v0 = gtid - lane(); v0 < g.V; v0 += nthreads) {
           const int64_t v = v0 + lane();
-          waveq_push(wq, v < g.V && a.vis[v] == cur, (int32_t)v);
+          waveq_push(wq, v < g.V && bm_test(bm_in, (int32_t)v), (int32_t)v);
         }
         waveq_flush(wq);
         grid_barrier(a.bar, nblocks);
@@ -944,11 +1022,17 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     }
     level++;
   }
+  if (a.tlog && gtid == 0 && level + 1 < a.tlog_cap) {
+    a.tlog[3 * (level + 1)] = (long long)wall_clock64();
+    a.tlog[3 * (level + 1) + 1] = -1;  // queue rebuild starts
+    a.tlog[3 * (level + 1) + 2] = 0;
+  }
   // rebuild the active-vertex queue; count, per instance, the active
   // vertices and the excess stranded away from the root
   int stranded = 0;
   {
     WaveQ wq{s_qbuf[wl], &s_qcnt[wl], a.qout, &a.qcnt[0], a.qcap, a.err};
+    KeyCount kc_act, kc_str;
     for (int64_t v0 = gtid - lane(); v0 < g.V; v0 += nthreads) {  // wave-uniform
       const int64_t v = v0 + lane();
       bool act = false, str = false;
@@ -961,10 +1045,12 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         if (act || str) ins = a.inst_of[v];
       }
       stranded += str ? 1 : 0;
-      wave_count_by_key(act && ins >= 0, ins, a.inst_active);
-      wave_count_by_key(str && ins >= 0, ins, a.inst_stranded);
+      key_count_add(act && ins >= 0, ins, kc_act, a.inst_active);
+      key_count_add(str && ins >= 0, ins, kc_str, a.inst_stranded);
       waveq_push(wq, act, (int32_t)v);
     }
+    key_count_flush(kc_act, a.inst_active);
+    key_count_flush(kc_str, a.inst_stranded);
     waveq_flush(wq);
   }
   stranded = wave_sum_i32(stranded);
@@ -977,6 +1063,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   }
   grid_barrier(a.bar, nblocks);
   if (gtid == 0) {
+    if (a.tlog && level + 2 < a.tlog_cap) a.tlog[3 * (level + 2)] = (long long)wall_clock64();
     a.status[0] = a.qcnt[0];
     a.status[2] = level;
     a.status[3] = bu_levels;

@@ -108,6 +108,7 @@ struct GRArgs {
   int32_t chunk_cap;  // capacity of the chunk descriptor arrays
   int32_t bu_threshold;    // frontier size above which a level runs bottom-up
   long long bu_edges;      // frontier row-length sum above which a level runs bottom-up
+  long long m_total;       // entries of all resident rows (unvisited edges = m_total - visited)
   int32_t *err;       // overflow counter (must stay 0)
   int32_t *halt;          // sweep halt flag, cleared here
   const long long *rwork; // relabel work so far ...
@@ -115,6 +116,8 @@ struct GRArgs {
   int32_t *stag;          // [2] stagnation state of the sweeps, reset here
   uint32_t *bm;           // 4 bitmaps of bm_words words: visited, then three rotating frontiers
   int32_t bm_words;       // words per bitmap (>= V / 32)
+  long long *tlog;        // nullable (diagnostics): per level {wall clock, frontier, bottom-up}
+  int32_t tlog_cap;
 };
 
 // Sweep kernels: tiles of P lanes (P = 4..64), one workgroup per long-row chunk,
