@@ -958,7 +958,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
       }
       evb = ev_used_;
       ev_used_ += 4;
-      ev_marks_.push_back({0, evb});
+      ev_marks_.push_back({tiers << 4, evb});  // a sweep; which tiers ran
       hipEventRecord(ev_[evb], st);
     }
     if (fs)
@@ -966,7 +966,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
                       &misc->halt[0]);
     launch_sweep_tile(P_, sweep_blocks, st, g, q);
     if (timed) hipEventRecord(ev_[evb + 1], st);
-    if (tiers & 1) launch_sweep_tile(64, sweep_blocks, st, g, qw);
+    if (tiers & 1) launch_sweep_tile(mid_lanes_, sweep_blocks, st, g, qw);
     if (timed) hipEventRecord(ev_[evb + 2], st);
     if (tiers & 2) {
       launch_sweep_chunk(0, chunk_blocks, st, g, q);
@@ -1354,7 +1354,10 @@ int Engine::collect_stats(hipStream_t st, EngineStats *out, std::string *err) {
       if (hipEventElapsedTime(&ms, ev_[mk.second], ev_[mk.second + 1]) == hipSuccess) r.k_ms[3] += ms;
       r.k_launches[3]++;
     } else {
+      const int tiers = mk.first >> 4;
       for (int k = 0; k < 3; k++) {
+        if (k == 1 && !(tiers & 1)) continue;  // tier not launched in this sweep
+        if (k == 2 && !(tiers & 2)) continue;
         float ms = 0;
         if (hipEventElapsedTime(&ms, ev_[mk.second + k], ev_[mk.second + k + 1]) == hipSuccess) r.k_ms[k] += ms;
         r.k_launches[k]++;
