@@ -247,6 +247,57 @@ def served_leg(solver, gs, rate, alone_values, alone_sides, vo, budget=1 << 30, 
     }
 
 
+def ablation(workloads, dev, steps=2):
+    """The paper's thread-centric / vertex-centric comparison (its Tables 1-2)
+    on the synthetic stand-ins, BCSR layout: one thread per active vertex
+    versus tiles of lanes, each with the paper's full-scan active-vertex queue
+    and with the incremental queue.  Every variant must give the same value."""
+    import torch
+
+    from paper_2404_00270_amd import workloads as W
+    from paper_2404_00270_amd import wbpr
+
+    variants = [
+        ("VC, incremental queue (default)", {}),
+        ("VC, full-scan queue (Algorithm 2)", dict(avq_mode=1)),
+        ("TC, full-scan queue (paper baseline)", dict(lanes_per_vertex=1, avq_mode=1)),
+        ("TC, incremental queue", dict(lanes_per_vertex=1)),
+    ]
+    out = []
+    for name in workloads:
+        g = W.CONFIGS[name]()
+        rp = torch.from_numpy(g.row_ptr).to(dev)
+        col = torch.from_numpy(g.col).to(dev)
+        cap = torch.from_numpy(g.cap).to(dev)
+        value = torch.zeros(1, dtype=torch.int64, device=dev)
+        flow = torch.zeros(max(g.E, 1), dtype=torch.int32, device=dev)
+        side = torch.zeros(g.V, dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        row = {"workload": g.name}
+        values = set()
+        for label, opts in variants:
+            solver = wbpr.Solver(0, max_wall_ms=60_000, **opts)
+            try:
+                solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)  # warm-up
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)
+                torch.cuda.synchronize()
+                row[label] = round((time.perf_counter() - t0) * 1000.0 / steps, 2)
+                values.add(int(value.item()))
+            except wbpr.WbprError as e:
+                row[label] = f"not finished: {e}"
+            finally:
+                solver.close()
+            log(f"[ablation] {g.name} {label}: {row[label]}")
+        row["same_value"] = len(values) == 1
+        tc, vc = row.get("TC, full-scan queue (paper baseline)"), row.get("VC, full-scan queue (Algorithm 2)")
+        if isinstance(tc, float) and isinstance(vc, float):
+            row["paper_speedup_vc_over_tc"] = round(tc / vc, 2)
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +318,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of this many MiB (HBM counter calibration)")
+    ap.add_argument("--ablation", default="", metavar="W1,W2",
+                    help="only run the thread-centric / vertex-centric comparison on these workloads")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -281,6 +334,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.ablation:
+        print(json.dumps({"ablation": ablation(args.ablation.split(","), dev)}), flush=True)
+        return
     if args.calibrate_copy > 0:
         # a plain copy reads and writes exactly n bytes each: the reference
         # for scaling FETCH_SIZE / WRITE_SIZE counters

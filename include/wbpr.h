@@ -80,9 +80,13 @@ enum wbpr_layout { WBPR_LAYOUT_AUTO = 0, WBPR_LAYOUT_BCSR = 1 };
 typedef struct wbpr_options {
     int32_t layout;            /* enum wbpr_layout */
     int32_t lanes_per_vertex;  /* lanes scanning one queued vertex: 4,8,16,32,64;
-                                  1 = thread-centric (one thread scans a
-                                  whole row, no medium or long tiers: the
-                                  paper's TC baseline) */
+                                  1 = thread-centric: one thread scans a
+                                  whole row and, unless split_degree or
+                                  block_degree is set, there are no medium
+                                  or long tiers (the paper's TC baseline).
+                                  0 = automatic: one lane when no row is
+                                  longer than 16, else 4, 8 or 16 by the
+                                  mean row length */
     int32_t split_degree;      /* rows longer than this get one wave each */
     int32_t gr_every_sweeps;   /* fixed sweeps between global relabels
                                   (0 = adaptive, at most 64) */
