@@ -8,8 +8,12 @@
 //
 // Pipeline, entirely on the GPU:
 //   1. validate + emit two keys per arc: (u,v) forward and (v,u) backward,
-//      payload = arc index * 2 + direction; self-loops get the largest key
-//   2. stable radix sort on (row, column)
+//      payload = arc index * 2 + direction; forward keys first, in arc order
+//   2. sorted (row, column) sequence of all keys: when every input row lists
+//      its columns in non-decreasing order (the common case), the forward
+//      keys are sorted already and the backward keys need only a stable sort
+//      on their row (the head of the arc), then the two are merged; else a
+//      stable radix sort of all keys on (row, column), self-loops last
 //   3. group heads -> unique entry ids (scan), row counts, merged capacities
 //   4. row pointers (scan), mates and arc->entry map, parallel-arc prefixes
 #include "wb_common.h"
@@ -83,10 +87,13 @@ __global__ void k_check_rowptr(const int64_t *rp, int32_t V, int64_t E, BuildSta
 }
 
 // Step 1.  Tail of arc i = last row whose start is <= i (binary search).
+// keys[i] = (u,v), keys[E + i] = (v,u); a self-loop (or an out-of-range
+// column, dropped as one) gets (u,u) in both, which keeps a column-sorted row
+// sorted; the full-sort path turns them into the largest key.  Also checks
+// that every row's columns are non-decreasing.
 __global__ void k_emit_keys(const int64_t *rp, const int32_t *col, const int32_t *cap, int32_t V, int64_t E, int vb,
                             uint64_t *keys, uint32_t *vals, int32_t *arc2ent, int32_t *acap, BuildStatus *st) {
-  const uint64_t ALL = (vb * 2 >= 64) ? ~0ull : ((1ull << (2 * vb)) - 1);
-  int nself = 0, bad = 0, cmax = 0;
+  int nself = 0, bad = 0, cmax = 0, unsorted = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
     int32_t lo = 0, hi = V - 1;
     while (lo < hi) {
@@ -97,51 +104,124 @@ __global__ void k_emit_keys(const int64_t *rp, const int32_t *col, const int32_t
     int32_t vv = col[i];
     bool ok = vv >= 0 && vv < V;
     if (!ok || cap[i] < 0) bad++;
+    if (i > rp[lo] && col[i - 1] > vv) unsorted++;
     uint64_t v = ok ? (uint64_t)vv : u;
-    if (u == v) {  // self-loop, or an out-of-range column dropped as one
-      nself++;
-      keys[2 * i] = ALL;
-      keys[2 * i + 1] = ALL;
-      arc2ent[i] = -1;
-    } else {
-      keys[2 * i] = (u << vb) | v;
-      keys[2 * i + 1] = (v << vb) | u;
-      arc2ent[i] = 0;
-    }
-    vals[2 * i] = (uint32_t)(2 * i);
-    vals[2 * i + 1] = (uint32_t)(2 * i + 1);
+    if (u == v) nself++;
+    keys[i] = (u << vb) | v;
+    keys[E + i] = (v << vb) | u;
+    arc2ent[i] = u == v ? -1 : 0;
+    vals[i] = (uint32_t)(2 * i);
+    vals[E + i] = (uint32_t)(2 * i + 1);
     acap[i] = cap[i];
     cmax = max(cmax, cap[i]);
   }
   nself = wave_sum_i32(nself);
   bad = wave_sum_i32(bad);
+  unsorted = wave_sum_i32(unsorted);
 #pragma unroll
   for (int o = WB_WAVE / 2; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o, WB_WAVE));
   if (lane() == 0) {
     if (nself) atomicAdd(&st->nself, nself);
     if (bad) atomicAdd(&st->bad_input, bad);
+    if (unsorted) atomicAdd(&st->unsorted, unsorted);
     // one address for the whole grid: skip the atomic unless it raises the
     // maximum (after the first waves almost every wave skips it)
     if (cmax > __hip_atomic_load(&st->cmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&st->cmax, cmax);
   }
 }
 
-// Step 3a.  head[i] = 1 where a new (row, column) group starts.  Items at or
-// beyond Mraw = 2(E - nself) are self-loop keys and are dropped.
-__global__ void k_heads(const uint64_t *keys, int64_t N, const BuildStatus *st, int32_t *head) {
-  int64_t mraw = N - 2 * (int64_t)st->nself;
+// Full-sort path: self-loop keys (u,u) become the largest key, so the sort
+// puts them last where the later steps drop them.
+__global__ void k_selfloops_last(uint64_t *keys, int64_t N, int vb) {
+  const uint64_t ALL = (vb * 2 >= 64) ? ~0ull : ((1ull << (2 * vb)) - 1);
+  const uint64_t cmask = (1ull << vb) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
-    head[i] = (i < mraw && (i == 0 || keys[i] != keys[i - 1])) ? 1 : 0;
+    const uint64_t k = keys[i];
+    if ((k >> vb) == (k & cmask)) keys[i] = ALL;
+  }
+}
+
+// Sorted-rows path: merge two sorted runs a [0, n) and b [0, n) into out
+// (merge path; equal keys take a first).  A workgroup makes MERGE_TILE
+// outputs: two threads find the tile's split of a and b by a binary search
+// along its first and last diagonal, the workgroup stages both input ranges
+// in LDS (coalesced), and each thread finds its own MERGE_ITEMS outputs by a
+// short search in LDS and merges them from there.
+constexpr int MERGE_THREADS = 256;
+constexpr int MERGE_ITEMS = 8;
+constexpr int MERGE_TILE = MERGE_THREADS * MERGE_ITEMS;
+
+// smallest i in [max(0, d - nb), min(d, na)] with a[i] > b[d - i - 1]
+template <typename K>
+__device__ __forceinline__ int64_t merge_split(const K *a, int64_t na, const K *b, int64_t nb, int64_t d) {
+  int64_t lo = d > nb ? d - nb : 0, hi = d < na ? d : na;
+  while (lo < hi) {
+    const int64_t i = (lo + hi) >> 1;
+    if (a[i] <= b[d - i - 1]) lo = i + 1; else hi = i;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(MERGE_THREADS) k_merge(const uint64_t *ka, const uint32_t *va, const uint64_t *kb,
+                                                         const uint32_t *vb, int64_t n, uint64_t *ko, uint32_t *vo) {
+  __shared__ uint64_t s_k[MERGE_TILE];
+  __shared__ uint32_t s_v[MERGE_TILE];
+  __shared__ int64_t s_split[2];
+  const int64_t total = 2 * n;
+  for (int64_t d0 = (int64_t)blockIdx.x * MERGE_TILE; d0 < total; d0 += (int64_t)gridDim.x * MERGE_TILE) {
+    const int64_t d1 = d0 + MERGE_TILE < total ? d0 + MERGE_TILE : total;
+    if (threadIdx.x < 2) s_split[threadIdx.x] = merge_split(ka, n, kb, n, threadIdx.x == 0 ? d0 : d1);
+    __syncthreads();
+    const int64_t i0 = s_split[0], i1 = s_split[1];
+    const int na = (int)(i1 - i0), nb = (int)((d1 - i1) - (d0 - i0));
+    const int64_t j0 = d0 - i0;
+    for (int x = threadIdx.x; x < na + nb; x += MERGE_THREADS) {
+      if (x < na) {
+        s_k[x] = ka[i0 + x];
+        s_v[x] = va[i0 + x];
+      } else {
+        s_k[x] = kb[j0 + x - na];
+        s_v[x] = vb[j0 + x - na];
+      }
+    }
+    __syncthreads();
+    const int dl = threadIdx.x * MERGE_ITEMS;
+    if (dl < na + nb) {
+      const uint64_t *A = s_k, *B = s_k + na;
+      int i = (int)merge_split(A, na, B, nb, dl), j = dl - i;
+      const int end = dl + MERGE_ITEMS < na + nb ? dl + MERGE_ITEMS : na + nb;
+      for (int o = dl; o < end; o++) {
+        const bool take_a = j >= nb || (i < na && A[i] <= B[j]);
+        const int src = take_a ? i++ : na + j++;
+        ko[d0 + o] = s_k[src];
+        vo[d0 + o] = s_v[src];
+      }
+    }
+    __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+// Self-loop items: after the full sort they are the last 2 nself items
+// (dropped by mraw); on the sorted-rows path they stay inline with key (u,u)
+// and every step skips them.
+__device__ __forceinline__ bool self_key(uint64_t k, int vb) { return (k >> vb) == (k & ((1ull << vb) - 1)); }
+
+// Step 3a.  head[i] = 1 where a new (row, column) group starts.
+__global__ void k_heads(const uint64_t *keys, int64_t N, int vb, bool inline_self, const BuildStatus *st,
+                        int32_t *head) {
+  int64_t mraw = inline_self ? N : N - 2 * (int64_t)st->nself;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    head[i] = (i < mraw && (i == 0 || keys[i] != keys[i - 1]) && !(inline_self && self_key(keys[i], vb))) ? 1 : 0;
   }
 }
 
 // Step 3b.  Unique id of item i = hx[i] + head[i] - 1.  Group heads write
 // the entry's column and start; every item records its unique id under its
 // payload (arc * 2 + direction) and its forward capacity for the scan.
-__global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, const int32_t *cap,
-                         const BuildStatus *st, const int32_t *head, const int32_t *hx, int2 *ent, int32_t vbase,
-                         int32_t *gstart, int32_t *uid_of, int64_t *pcap) {
-  const int64_t mraw = N - 2 * (int64_t)st->nself;
+__global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, bool inline_self,
+                         const int32_t *cap, const BuildStatus *st, const int32_t *head, const int32_t *hx, int2 *ent,
+                         int32_t vbase, int32_t *gstart, int32_t *uid_of, int64_t *pcap) {
+  const int64_t mraw = inline_self ? N : N - 2 * (int64_t)st->nself;
   const int32_t M = st->M;
   const uint64_t cmask = (1ull << vb) - 1;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= N; i += (int64_t)gridDim.x * blockDim.x) {
@@ -151,6 +231,10 @@ __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, 
       continue;
     }
     const uint64_t key = keys[i];
+    if (inline_self && self_key(key, vb)) {
+      pcap[i] = 0;
+      continue;
+    }
     const uint32_t pl = vals[i];
     const int32_t u = hx[i] + head[i] - 1;
     if (head[i]) {
@@ -169,12 +253,13 @@ __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, 
 // order).
 // A group holds the forward items of arcs u->v and the backward items of arcs
 // v->u, so its size counts every input arc joining the pair.
-__global__ void k_group_caps(const uint32_t *vals, BuildStatus *st, const int32_t *head, const int32_t *hx,
-                             const int32_t *gstart, const int64_t *pc, unsigned long long *capacc, int32_t *pbefore_arc,
-                             int64_t N) {
-  const int64_t mraw = N - 2 * (int64_t)st->nself;
+__global__ void k_group_caps(const uint64_t *keys, int vb, bool inline_self, const uint32_t *vals, BuildStatus *st,
+                             const int32_t *head, const int32_t *hx, const int32_t *gstart, const int64_t *pc,
+                             unsigned long long *capacc, int32_t *pbefore_arc, int64_t N) {
+  const int64_t mraw = inline_self ? N : N - 2 * (int64_t)st->nself;
   int gmax = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mraw; i += (int64_t)gridDim.x * blockDim.x) {
+    if (inline_self && self_key(keys[i], vb)) continue;
     const int32_t u = hx[i] + head[i] - 1;
     const int32_t gs = gstart[u];
     const int64_t g0 = pc[gs];
@@ -195,9 +280,9 @@ __global__ void k_group_caps(const uint32_t *vals, BuildStatus *st, const int32_
 // Step 3c.  Row pointers without atomics (rows such as s and t of a grid cut
 // hold millions of entries): rptr[x] = number of merged entries in rows < x
 // = number of group heads before the first sorted key of row >= x.
-__global__ void k_rowptr(const uint64_t *keys, int64_t N, int vb, int32_t V, const BuildStatus *st, const int32_t *hx,
-                         int32_t *rptr) {
-  const int64_t mraw = N - 2 * (int64_t)st->nself;
+__global__ void k_rowptr(const uint64_t *keys, int64_t N, int vb, bool inline_self, int32_t V, const BuildStatus *st,
+                         const int32_t *hx, int32_t *rptr) {
+  const int64_t mraw = inline_self ? N : N - 2 * (int64_t)st->nself;
   for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= V; x += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t target = (uint64_t)x << vb;
     int64_t lo = 0, hi = mraw;  // first position with key >= target
@@ -278,22 +363,49 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
   const int vb = bits_for(V);
   hipLaunchKernelGGL(k_emit_keys, dim3(grid_for(E)), dim3(BT), 0, st, row_ptr, col, cap, V, E, vb, s.k0, s.v0, arc2ent,
                      acap, status_dev);
-  int alt = 0;
-  e = radix_sort_u64_u32(s.k0, s.v0, s.k1, s.v1, N, 2 * vb, s.hist, s.stemp, &alt, st);
+  // which path: the host needs the row-order check (and the self-loop count)
+  BuildStatus hs;
+  e = hipMemcpyAsync(&hs, status_dev, sizeof(hs), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
-  uint64_t *keys = alt ? s.k1 : s.k0;
-  uint32_t *vals = alt ? s.v1 : s.v0;
-  hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(BT), 0, st, keys, N, status_dev, s.head);
+  const bool inline_self = hs.unsorted == 0;
+  uint64_t *keys;
+  uint32_t *vals;
+  if (inline_self) {
+    // backward keys: stable sort on their row bits only (emitted in arc
+    // order, so equal rows stay ordered by the arc's tail), then merge with
+    // the forward keys, which are sorted already
+    int alt = 0;
+    e = radix_sort_u64_u32(s.k0 + E, s.v0 + E, s.k1 + E, s.v1 + E, E, vb, s.hist, s.stemp, &alt, st, vb);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(s.k1, s.k0, 8 * (size_t)E, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s.v1, s.v0, 4 * (size_t)E, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && !alt) e = hipMemcpyAsync(s.k1 + E, s.k0 + E, 8 * (size_t)E, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && !alt) e = hipMemcpyAsync(s.v1 + E, s.v0 + E, 4 * (size_t)E, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_merge, dim3(grid_for((N + MERGE_TILE - 1) / MERGE_TILE, 1)), dim3(MERGE_THREADS), 0, st, s.k1,
+                       s.v1, s.k1 + E, s.v1 + E, E, s.k0, s.v0);
+    keys = s.k0;
+    vals = s.v0;
+  } else {
+    if (hs.nself > 0) hipLaunchKernelGGL(k_selfloops_last, dim3(grid_for(N)), dim3(BT), 0, st, s.k0, N, vb);
+    int alt = 0;
+    e = radix_sort_u64_u32(s.k0, s.v0, s.k1, s.v1, N, 2 * vb, s.hist, s.stemp, &alt, st);
+    if (e != hipSuccess) return e;
+    keys = alt ? s.k1 : s.k0;
+    vals = alt ? s.v1 : s.v0;
+  }
+  hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(BT), 0, st, keys, N, vb, inline_self, status_dev, s.head);
   e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_unique, dim3(grid_for(N + 1)), dim3(BT), 0, st, keys, vals, N, vb, cap, status_dev, s.head,
-                     s.hx, ent, pl.vbase, s.gstart, s.uid_of, s.pcap);
+  hipLaunchKernelGGL(k_unique, dim3(grid_for(N + 1)), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev,
+                     s.head, s.hx, ent, pl.vbase, s.gstart, s.uid_of, s.pcap);
   e = excl_scan_i64(s.pcap, s.pcap, N + 1, nullptr, s.stemp64, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_group_caps, dim3(grid_for(N)), dim3(BT), 0, st, vals, status_dev, s.head, s.hx, s.gstart, s.pcap,
-                     s.capacc, pbefore, N);
-  hipLaunchKernelGGL(k_rowptr, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, N, vb, V, status_dev, s.hx,
-                     s.rptr);
+  hipLaunchKernelGGL(k_group_caps, dim3(grid_for(N)), dim3(BT), 0, st, keys, vb, inline_self, vals, status_dev, s.head,
+                     s.hx, s.gstart, s.pcap, s.capacc, pbefore, N);
+  hipLaunchKernelGGL(k_rowptr, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, N, vb, inline_self, V,
+                     status_dev, s.hx, s.rptr);
   hipLaunchKernelGGL(k_rowb, dim3(grid_for(V)), dim3(BT), 0, st, s.rptr, V, pl.vbase, (int32_t)pl.mbase, A.rowb);
   hipLaunchKernelGGL(k_arcs, dim3(grid_for(E)), dim3(BT), 0, st, E, s.uid_of, (int32_t)pl.mbase, rev, arc2ent,
                      pbefore);

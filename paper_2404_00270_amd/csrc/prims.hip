@@ -270,17 +270,18 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_scatter(const uint64_t *kin, 
 
 int64_t radix_hist_elems(int64_t n) { return (int64_t)RS_BINS * ((n + RS_TILE - 1) / RS_TILE); }
 
-// Sorts (k0,v0) on the low `bits` bits of the key; (k1,v1) is scratch of the
-// same size.  *result_in_alt is set when the sorted data ends in (k1,v1).
+// Sorts (k0,v0) stably on key bits [shift0, shift0 + bits); (k1,v1) is
+// scratch of the same size.  *result_in_alt is set when the sorted data ends
+// in (k1,v1).
 hipError_t radix_sort_u64_u32(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int bits,
-                              int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st) {
+                              int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st, int shift0) {
   *result_in_alt = 0;
   if (n <= 1) return hipSuccess;
   int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
   int64_t hn = (int64_t)RS_BINS * nblocks;
   uint64_t *ka = k0, *kb = k1;
   uint32_t *va = v0, *vb = v1;
-  for (int shift = 0; shift < bits; shift += RS_BITS) {
+  for (int shift = shift0; shift < shift0 + bits; shift += RS_BITS) {
     hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, st, ka, n, shift, hist, nblocks);
     hipError_t e = excl_scan_i32(hist, hist, hn, nullptr, scan_temp, st);
     if (e != hipSuccess) return e;

@@ -13,7 +13,7 @@ hipError_t excl_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *to
 hipError_t excl_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, int64_t *temp, hipStream_t st);
 int64_t radix_hist_elems(int64_t n);
 hipError_t radix_sort_u64_u32(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int bits,
-                              int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st);
+                              int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st, int shift0 = 0);
 
 // ---- residual graph: bidirectional CSR with merged entries and explicit
 // mate indices, in a device arena shared by all instances (build.hip)
@@ -42,6 +42,8 @@ struct BuildStatus {
   int32_t M;          // merged entries
   int32_t cmax;       // largest input capacity
   int32_t maxgroup;   // most input arcs joining one vertex pair (both directions)
+  int32_t unsorted;   // rows whose columns are not non-decreasing
+  int32_t pad;
 };
 
 // Device scratch needed by build_residual for V vertices and E arcs.
