@@ -8,14 +8,16 @@
 //
 // Pipeline, entirely on the GPU:
 //   1. validate + emit two keys per arc: (u,v) forward and (v,u) backward,
-//      payload = arc index * 2 + direction; forward keys first, in arc order
+//      payload = arc index (forward) or E + arc index (backward)
 //   2. sorted (row, column) sequence of all keys: when every input row lists
 //      its columns in non-decreasing order (the common case), the forward
 //      keys are sorted already and the backward keys need only a stable sort
 //      on their row (the head of the arc), then the two are merged; else a
 //      stable radix sort of all keys on (row, column), self-loops last
-//   3. group heads -> unique entry ids (scan), row counts, merged capacities
-//   4. row pointers (scan), mates and arc->entry map, parallel-arc prefixes
+//   3. group heads -> unique entry ids (scan), merged capacities (scan of
+//      the forward arcs' capacities, differenced at group bounds)
+//   4. row pointers, mates and arc->entry map, parallel-arc prefixes; the
+//      pairwise int32 overflow check runs only if some entry holds >= 2^30
 #include "wb_common.h"
 #include "wb_internal.h"
 
@@ -35,7 +37,6 @@ struct Scratch {
   uint32_t *v0, *v1;
   int32_t *head, *hx, *uid_of, *gstart, *rowcnt, *rptr, *hist, *stemp;
   int64_t *pcap, *stemp64;
-  unsigned long long *capacc;
 };
 
 size_t carve_scratch(int32_t V, int64_t E, void *mem, Scratch *s) {
@@ -58,7 +59,6 @@ size_t carve_scratch(int32_t V, int64_t E, void *mem, Scratch *s) {
   s->stemp = (int32_t *)take(4 * (size_t)st);
   s->pcap = (int64_t *)take(8 * (N + 1));
   s->stemp64 = (int64_t *)take(8 * (size_t)st);
-  s->capacc = (unsigned long long *)take(8 * N);
   return (size_t)(p - base);
 }
 }  // namespace
@@ -86,47 +86,70 @@ __global__ void k_check_rowptr(const int64_t *rp, int32_t V, int64_t E, BuildSta
   }
 }
 
-// Step 1.  Tail of arc i = last row whose start is <= i (binary search).
-// keys[i] = (u,v), keys[E + i] = (v,u); a self-loop (or an out-of-range
-// column, dropped as one) gets (u,u) in both, which keeps a column-sorted row
-// sorted; the full-sort path turns them into the largest key.  Also checks
-// that every row's columns are non-decreasing.
-__global__ void k_emit_keys(const int64_t *rp, const int32_t *col, const int32_t *cap, int32_t V, int64_t E, int vb,
-                            uint64_t *keys, uint32_t *vals, int32_t *arc2ent, int32_t *acap, BuildStatus *st) {
-  int nself = 0, bad = 0, cmax = 0, unsorted = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
-    int32_t lo = 0, hi = V - 1;
-    while (lo < hi) {
-      int32_t mid = lo + (hi - lo + 1) / 2;
-      if (rp[mid] <= i) lo = mid; else hi = mid - 1;
-    }
-    uint64_t u = (uint64_t)lo;
-    int32_t vv = col[i];
-    bool ok = vv >= 0 && vv < V;
-    if (!ok || cap[i] < 0) bad++;
-    if (i > rp[lo] && col[i - 1] > vv) unsorted++;
-    uint64_t v = ok ? (uint64_t)vv : u;
-    if (u == v) nself++;
-    keys[i] = (u << vb) | v;
-    keys[E + i] = (v << vb) | u;
-    arc2ent[i] = u == v ? -1 : 0;
-    vals[i] = (uint32_t)(2 * i);
-    vals[E + i] = (uint32_t)(2 * i + 1);
-    acap[i] = cap[i];
-    cmax = max(cmax, cap[i]);
-  }
-  nself = wave_sum_i32(nself);
-  bad = wave_sum_i32(bad);
-  unsorted = wave_sum_i32(unsorted);
+// Sum (MAX false) or maximum over the workgroup, returned in thread 0.
+// Every thread of the workgroup calls it; blockDim.x <= BT.
+template <bool MAX>
+__device__ int block_reduce_i32(int x) {
+  __shared__ int s_part[BT / WB_WAVE];
 #pragma unroll
-  for (int o = WB_WAVE / 2; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o, WB_WAVE));
-  if (lane() == 0) {
+  for (int o = WB_WAVE / 2; o > 0; o >>= 1) {
+    const int y = __shfl_xor(x, o, WB_WAVE);
+    x = MAX ? max(x, y) : x + y;
+  }
+  __syncthreads();  // a previous call may still read s_part
+  if (lane() == 0) s_part[threadIdx.x / WB_WAVE] = x;
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int w = 1; w < (int)(blockDim.x / WB_WAVE); w++) x = MAX ? max(x, s_part[w]) : x + s_part[w];
+  return x;
+}
+
+// Step 1a.  Row of every arc without a per-arc search: cnt[rp[u]] += 1 for
+// each row u >= 1 that starts inside [0, E); the inclusive prefix sum of cnt
+// at arc i then counts the rows u >= 1 that start at or before i, which is
+// the row of i (empty rows share a start and are counted, so the last of
+// them wins, as it must).  The count stays below V whatever rp holds.
+__global__ void k_row_marks(const int64_t *rp, int32_t V, int64_t E, int32_t *cnt) {
+  for (int64_t u = 1 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < V; u += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = rp[u];
+    if (p >= 0 && p < E) atomicAdd(&cnt[p], 1);
+  }
+}
+
+// Step 1b.  Forward key (u,v) goes to fkeys[i], backward key (v,u) to
+// bkeys[i], with u = row_of[i]; a self-loop (or an out-of-range column,
+// dropped as one) gets (u,u) in both, which keeps a column-sorted row
+// sorted; the full-sort path turns them into the largest key.  Also checks
+// that every row's columns are non-decreasing.  Counters are reduced per
+// workgroup, one atomic per workgroup and status word.
+__global__ void k_emit_keys(const int64_t *rp, const int32_t *row_of, const int32_t *col, const int32_t *cap,
+                            int32_t V, int64_t E, int vb, uint64_t *fkeys, uint32_t *fvals, uint64_t *bkeys,
+                            uint32_t *bvals, int32_t *arc2ent, int32_t *acap, BuildStatus *st) {
+  int nself = 0, bad = 0, unsorted = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t r = row_of[i];
+    const uint64_t u = (uint64_t)r;
+    const int32_t vv = col[i];
+    const int32_t c = cap[i];
+    const bool ok = vv >= 0 && vv < V;
+    if (!ok || c < 0) bad++;
+    if (i > rp[r] && col[i - 1] > vv) unsorted++;
+    const uint64_t v = ok ? (uint64_t)vv : u;
+    if (u == v) nself++;
+    fkeys[i] = (u << vb) | v;
+    bkeys[i] = (v << vb) | u;
+    arc2ent[i] = u == v ? -1 : 0;
+    fvals[i] = (uint32_t)i;
+    bvals[i] = (uint32_t)(E + i);
+    acap[i] = c;
+  }
+  nself = block_reduce_i32<false>(nself);
+  bad = block_reduce_i32<false>(bad);
+  unsorted = block_reduce_i32<false>(unsorted);
+  if (threadIdx.x == 0) {
     if (nself) atomicAdd(&st->nself, nself);
     if (bad) atomicAdd(&st->bad_input, bad);
     if (unsorted) atomicAdd(&st->unsorted, unsorted);
-    // one address for the whole grid: skip the atomic unless it raises the
-    // maximum (after the first waves almost every wave skips it)
-    if (cmax > __hip_atomic_load(&st->cmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&st->cmax, cmax);
   }
 }
 
@@ -146,7 +169,8 @@ __global__ void k_selfloops_last(uint64_t *keys, int64_t N, int vb) {
 // outputs: two threads find the tile's split of a and b by a binary search
 // along its first and last diagonal, the workgroup stages both input ranges
 // in LDS (coalesced), and each thread finds its own MERGE_ITEMS outputs by a
-// short search in LDS and merges them from there.
+// short search in LDS and records where each comes from; the workgroup then
+// writes the tile out in order (coalesced).
 constexpr int MERGE_THREADS = 256;
 constexpr int MERGE_ITEMS = 8;
 constexpr int MERGE_TILE = MERGE_THREADS * MERGE_ITEMS;
@@ -166,7 +190,9 @@ __global__ void __launch_bounds__(MERGE_THREADS) k_merge(const uint64_t *ka, con
                                                          const uint32_t *vb, int64_t n, uint64_t *ko, uint32_t *vo) {
   __shared__ uint64_t s_k[MERGE_TILE];
   __shared__ uint32_t s_v[MERGE_TILE];
+  __shared__ uint16_t s_src[MERGE_TILE];
   __shared__ int64_t s_split[2];
+  static_assert(MERGE_TILE <= 65536, "LDS source index is 16-bit");
   const int64_t total = 2 * n;
   for (int64_t d0 = (int64_t)blockIdx.x * MERGE_TILE; d0 < total; d0 += (int64_t)gridDim.x * MERGE_TILE) {
     const int64_t d1 = d0 + MERGE_TILE < total ? d0 + MERGE_TILE : total;
@@ -192,10 +218,14 @@ __global__ void __launch_bounds__(MERGE_THREADS) k_merge(const uint64_t *ka, con
       const int end = dl + MERGE_ITEMS < na + nb ? dl + MERGE_ITEMS : na + nb;
       for (int o = dl; o < end; o++) {
         const bool take_a = j >= nb || (i < na && A[i] <= B[j]);
-        const int src = take_a ? i++ : na + j++;
-        ko[d0 + o] = s_k[src];
-        vo[d0 + o] = s_v[src];
+        s_src[o] = (uint16_t)(take_a ? i++ : na + j++);
       }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < na + nb; x += MERGE_THREADS) {
+      const int src = s_src[x];
+      ko[d0 + x] = s_k[src];
+      vo[d0 + x] = s_v[src];
     }
     __syncthreads();  // LDS is reused by the next tile
   }
@@ -219,11 +249,11 @@ __global__ void k_heads(const uint64_t *keys, int64_t N, int vb, bool inline_sel
 // the entry's column and start; every item records its unique id under its
 // payload (arc * 2 + direction) and its forward capacity for the scan.
 __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, bool inline_self,
-                         const int32_t *cap, const BuildStatus *st, const int32_t *head, const int32_t *hx, int2 *ent,
-                         int32_t vbase, int32_t *gstart, int32_t *uid_of, int64_t *pcap) {
+                         const int32_t *cap, const BuildStatus *st, const int32_t *head, const int32_t *hx,
+                         int32_t *gstart, int32_t *uid_of, int64_t *pcap) {
   const int64_t mraw = inline_self ? N : N - 2 * (int64_t)st->nself;
   const int32_t M = st->M;
-  const uint64_t cmask = (1ull << vb) - 1;
+  const uint32_t E = (uint32_t)(N / 2);  // payloads below E are forward arcs
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= N; i += (int64_t)gridDim.x * blockDim.x) {
     if (i >= mraw) {
       pcap[i] = 0;
@@ -237,12 +267,9 @@ __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, 
     }
     const uint32_t pl = vals[i];
     const int32_t u = hx[i] + head[i] - 1;
-    if (head[i]) {
-      ent[u] = make_int2(vbase + (int)(key & cmask), 0);
-      gstart[u] = (int32_t)i;
-    }
+    if (head[i]) gstart[u] = (int32_t)i;
     uid_of[pl] = u;
-    pcap[i] = (pl & 1u) ? 0 : (int64_t)cap[pl >> 1];
+    pcap[i] = pl < E ? (int64_t)cap[pl] : 0;
   }
 }
 
@@ -251,30 +278,40 @@ __global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, 
 // group; capacity of earlier parallel arcs of forward item i = pc[i] - pc of
 // its group's start (the sort is stable, so a group's arcs are in input
 // order).
-// A group holds the forward items of arcs u->v and the backward items of arcs
-// v->u, so its size counts every input arc joining the pair.
+// The group head writes its entry (column, merged capacity) and the initial
+// residual copy.  A sum above INT32_MAX is an overflow by itself; sums of at
+// least 2^30 are counted, since only such an entry can overflow together
+// with its mate (two sums below 2^30 add up to less than 2^31).
 __global__ void k_group_caps(const uint64_t *keys, int vb, bool inline_self, const uint32_t *vals, BuildStatus *st,
                              const int32_t *head, const int32_t *hx, const int32_t *gstart, const int64_t *pc,
-                             unsigned long long *capacc, int32_t *pbefore_arc, int64_t N) {
+                             int32_t vbase, int2 *ent, int32_t *cap0, int32_t *pbefore_arc, int64_t N) {
   const int64_t mraw = inline_self ? N : N - 2 * (int64_t)st->nself;
-  int gmax = 0;
+  const uint32_t E = (uint32_t)(N / 2);
+  const uint64_t cmask = (1ull << vb) - 1;
+  int big = 0, ovf = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mraw; i += (int64_t)gridDim.x * blockDim.x) {
-    if (inline_self && self_key(keys[i], vb)) continue;
+    const uint64_t key = keys[i];
+    if (inline_self && self_key(key, vb)) continue;
     const int32_t u = hx[i] + head[i] - 1;
     const int32_t gs = gstart[u];
     const int64_t g0 = pc[gs];
     if (head[i]) {
-      const int32_t ge = gstart[u + 1];
-      capacc[u] = (unsigned long long)(pc[ge] - g0);
-      gmax = max(gmax, ge - gs);
+      const int64_t c = pc[gstart[u + 1]] - g0;
+      big += c >= (1ll << 30);
+      ovf += c > 0x7fffffffll;
+      const int32_t c32 = c > 0x7fffffffll ? 0 : (int32_t)c;
+      ent[u] = make_int2(vbase + (int)(key & cmask), c32);
+      cap0[u] = c32;
     }
     const uint32_t pl = vals[i];
-    if (!(pl & 1u)) pbefore_arc[pl >> 1] = (int32_t)(pc[i] - g0);
+    if (pl < E) pbefore_arc[pl] = (int32_t)(pc[i] - g0);
   }
-#pragma unroll
-  for (int o = WB_WAVE / 2; o > 0; o >>= 1) gmax = max(gmax, __shfl_xor(gmax, o, WB_WAVE));
-  if (lane() == 0 && gmax > __hip_atomic_load(&st->maxgroup, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-    atomicMax(&st->maxgroup, gmax);
+  big = block_reduce_i32<false>(big);
+  ovf = block_reduce_i32<false>(ovf);
+  if (threadIdx.x == 0) {
+    if (big) atomicAdd(&st->big, big);
+    if (ovf) atomicAdd(&st->overflow, ovf);
+  }
 }
 
 // Step 3c.  Row pointers without atomics (rows such as s and t of a grid cut
@@ -304,39 +341,40 @@ __global__ void k_rowb(const int32_t *rptr, int32_t V, int32_t vbase, int32_t mb
 // rev and arc2ent point at this build's slices of the arena; the stored
 // indices are absolute (local + mbase).
 __global__ void k_arcs(int64_t E, const int32_t *uid_of, int32_t mbase, int32_t *rev, int32_t *arc2ent,
-                       int32_t *pbefore) {
+                       int32_t *pbefore, BuildStatus *st) {
+  const int32_t M = st->M;
+  int bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
     if (arc2ent[i] < 0) {
       pbefore[i] = 0;
       continue;
     }
-    const int32_t f = uid_of[2 * i], b = uid_of[2 * i + 1];
+    const int32_t f = uid_of[i], b = uid_of[E + i];
+    if (f < 0 || f >= M || b < 0 || b >= M) {  // cannot happen unless the build has a bug
+      bad++;
+      continue;
+    }
     rev[f] = mbase + b;
     rev[b] = mbase + f;
     arc2ent[i] = mbase + f;
   }
+  bad = block_reduce_i32<false>(bad);
+  if (threadIdx.x == 0 && bad) atomicAdd(&st->bad_input, bad);
 }
 
-__global__ void k_caps(const BuildStatus *st, const unsigned long long *capacc, const int32_t *rev, int32_t mbase,
-                       int2 *ent, int32_t *cap0, BuildStatus *stw) {
-  int64_t M = st->M;
-  // c(u->v) + c(v->u) is at most (arcs joining the pair) x (largest
-  // capacity); when that bound fits in int32 the mate's sum need not be read
-  const bool exact = (long long)st->cmax * (long long)st->maxgroup > 0x7fffffffll;
+// Step 4b.  Exact pairwise int32 check c(u,v) + c(v,u), needed only when
+// some entry holds at least 2^30; otherwise every workgroup leaves at once.
+__global__ void k_pair_check(const int32_t *rev, int32_t mbase, const int2 *ent, BuildStatus *st) {
+  if (st->big == 0) return;
+  const int64_t M = st->M;
   int ovf = 0;
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < M; j += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r = rev[j] - mbase;
-    if (r < 0 || r >= M) {  // every entry gets a mate; anything else is a bug
-      atomicAdd(&stw->bad_input, 1);
-      continue;
-    }
-    unsigned long long c = capacc[j];
-    if (exact && c + capacc[r] > 0x7fffffffull) { ovf++; c = 0; }
-    ent[j].y = (int)c;
-    cap0[j] = (int32_t)c;
+    if (r < 0 || r >= M) continue;  // k_arcs has reported it
+    ovf += (int64_t)ent[j].y + (int64_t)ent[r].y > 0x7fffffffll;
   }
-  ovf = wave_sum_i32(ovf);
-  if (lane() == 0 && ovf) atomicAdd(&stw->overflow, ovf);
+  ovf = block_reduce_i32<false>(ovf);
+  if (threadIdx.x == 0 && ovf) atomicAdd(&st->overflow, ovf);
 }
 
 hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, int32_t V, int64_t E,
@@ -361,8 +399,21 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
     return hipGetLastError();
   }
   const int vb = bits_for(V);
-  hipLaunchKernelGGL(k_emit_keys, dim3(grid_for(E)), dim3(BT), 0, st, row_ptr, col, cap, V, E, vb, s.k0, s.v0, arc2ent,
-                     acap, status_dev);
+  // The backward keys start where an odd number of radix passes on their
+  // row bits leaves them in k0 + E, beside the forward keys in k0, so the
+  // merge reads both from k0 and writes k1 with no copies in between.
+  const bool odd = radix_sort_passes(vb) & 1;
+  uint64_t *bk = odd ? s.k1 + E : s.k0 + E;
+  uint32_t *bv = odd ? s.v1 + E : s.v0 + E;
+  // row of every arc: marks at the row starts, then a prefix sum (head and
+  // hx are free until step 3)
+  e = hipMemsetAsync(s.head, 0, 4 * ((size_t)E + 1), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_marks, dim3(grid_for(V)), dim3(BT), 0, st, row_ptr, V, E, s.head);
+  e = excl_scan_i32(s.head, s.hx, E + 1, nullptr, s.stemp, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_emit_keys, dim3(grid_for(E)), dim3(BT), 0, st, row_ptr, s.hx + 1, col, cap, V, E, vb, s.k0,
+                     s.v0, bk, bv, arc2ent, acap, status_dev);
   // which path: the host needs the row-order check (and the self-loop count)
   BuildStatus hs;
   e = hipMemcpyAsync(&hs, status_dev, sizeof(hs), hipMemcpyDeviceToHost, st);
@@ -376,18 +427,25 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
     // order, so equal rows stay ordered by the arc's tail), then merge with
     // the forward keys, which are sorted already
     int alt = 0;
-    e = radix_sort_u64_u32(s.k0 + E, s.v0 + E, s.k1 + E, s.v1 + E, E, vb, s.hist, s.stemp, &alt, st, vb);
+    uint64_t *ok = odd ? s.k0 + E : s.k1 + E;
+    uint32_t *ov = odd ? s.v0 + E : s.v1 + E;
+    e = radix_sort_u64_u32(bk, bv, ok, ov, E, vb, s.hist, s.stemp, &alt, st, vb);
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(s.k1, s.k0, 8 * (size_t)E, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.v1, s.v0, 4 * (size_t)E, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess && !alt) e = hipMemcpyAsync(s.k1 + E, s.k0 + E, 8 * (size_t)E, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess && !alt) e = hipMemcpyAsync(s.v1 + E, s.v0 + E, 4 * (size_t)E, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge, dim3(grid_for((N + MERGE_TILE - 1) / MERGE_TILE, 1)), dim3(MERGE_THREADS), 0, st, s.k1,
-                       s.v1, s.k1 + E, s.v1 + E, E, s.k0, s.v0);
-    keys = s.k0;
-    vals = s.v0;
+    if ((alt ? ok : bk) != s.k0 + E) {  // pass count disagrees with radix_sort_passes
+      e = hipMemcpyAsync(s.k0 + E, alt ? ok : bk, 8 * (size_t)E, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(s.v0 + E, alt ? ov : bv, 4 * (size_t)E, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_merge, dim3(grid_for((N + MERGE_TILE - 1) / MERGE_TILE, 1)), dim3(MERGE_THREADS), 0, st, s.k0,
+                       s.v0, s.k0 + E, s.v0 + E, E, s.k1, s.v1);
+    keys = s.k1;
+    vals = s.v1;
   } else {
+    if (odd) {  // the full sort wants all keys contiguous in k0
+      e = hipMemcpyAsync(s.k0 + E, bk, 8 * (size_t)E, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(s.v0 + E, bv, 4 * (size_t)E, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return e;
+    }
     if (hs.nself > 0) hipLaunchKernelGGL(k_selfloops_last, dim3(grid_for(N)), dim3(BT), 0, st, s.k0, N, vb);
     int alt = 0;
     e = radix_sort_u64_u32(s.k0, s.v0, s.k1, s.v1, N, 2 * vb, s.hist, s.stemp, &alt, st);
@@ -399,18 +457,18 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
   e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_unique, dim3(grid_for(N + 1)), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev,
-                     s.head, s.hx, ent, pl.vbase, s.gstart, s.uid_of, s.pcap);
+                     s.head, s.hx, s.gstart, s.uid_of, s.pcap);
   e = excl_scan_i64(s.pcap, s.pcap, N + 1, nullptr, s.stemp64, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_group_caps, dim3(grid_for(N)), dim3(BT), 0, st, keys, vb, inline_self, vals, status_dev, s.head,
-                     s.hx, s.gstart, s.pcap, s.capacc, pbefore, N);
+                     s.hx, s.gstart, s.pcap, pl.vbase, ent, cap0, pbefore, N);
   hipLaunchKernelGGL(k_rowptr, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, N, vb, inline_self, V,
                      status_dev, s.hx, s.rptr);
   hipLaunchKernelGGL(k_rowb, dim3(grid_for(V)), dim3(BT), 0, st, s.rptr, V, pl.vbase, (int32_t)pl.mbase, A.rowb);
   hipLaunchKernelGGL(k_arcs, dim3(grid_for(E)), dim3(BT), 0, st, E, s.uid_of, (int32_t)pl.mbase, rev, arc2ent,
-                     pbefore);
-  hipLaunchKernelGGL(k_caps, dim3(grid_for(N)), dim3(BT), 0, st, status_dev, s.capacc, rev, (int32_t)pl.mbase, ent,
-                     cap0, status_dev);
+                     pbefore, status_dev);
+  hipLaunchKernelGGL(k_pair_check, dim3(grid_for(N, 64 * BT)), dim3(BT), 0, st, rev, (int32_t)pl.mbase, ent,
+                     status_dev);
   return hipGetLastError();
 }
 

@@ -273,6 +273,8 @@ int64_t radix_hist_elems(int64_t n) { return (int64_t)RS_BINS * ((n + RS_TILE - 
 // Sorts (k0,v0) stably on key bits [shift0, shift0 + bits); (k1,v1) is
 // scratch of the same size.  *result_in_alt is set when the sorted data ends
 // in (k1,v1).
+int radix_sort_passes(int bits) { return (bits + RS_BITS - 1) / RS_BITS; }
+
 hipError_t radix_sort_u64_u32(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int bits,
                               int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st, int shift0) {
   *result_in_alt = 0;

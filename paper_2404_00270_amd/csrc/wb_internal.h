@@ -12,6 +12,9 @@ int64_t scan_temp_elems(int64_t n);
 hipError_t excl_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, int32_t *temp, hipStream_t st);
 hipError_t excl_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, int64_t *temp, hipStream_t st);
 int64_t radix_hist_elems(int64_t n);
+// passes radix_sort_u64_u32 makes over `bits` key bits (for n > 1); an odd
+// count leaves the result in the alternate buffers
+int radix_sort_passes(int bits);
 hipError_t radix_sort_u64_u32(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int bits,
                               int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st, int shift0 = 0);
 
@@ -40,10 +43,10 @@ struct BuildStatus {
   int32_t overflow;   // merged pair capacity above INT32_MAX
   int32_t nself;      // self-loops
   int32_t M;          // merged entries
-  int32_t cmax;       // largest input capacity
-  int32_t maxgroup;   // most input arcs joining one vertex pair (both directions)
+  int32_t big;        // entries whose summed capacity is at least 2^30 (only
+                      // these can overflow int32 together with their mate)
   int32_t unsorted;   // rows whose columns are not non-decreasing
-  int32_t pad;
+  int32_t pad[2];
 };
 
 // Device scratch needed by build_residual for V vertices and E arcs.

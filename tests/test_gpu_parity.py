@@ -77,6 +77,26 @@ def test_random_graphs_ragged(solver, V, E, seed):
     check_against_oracle(g, solver.solve(g))
 
 
+def _reorder_rows(g, seed=None):
+    """Same graph with each row's arcs sorted by column (seed None) or shuffled."""
+    row = np.repeat(np.arange(g.V), np.diff(g.row_ptr))
+    minor = g.col if seed is None else np.random.default_rng(seed).random(g.E)
+    order = np.lexsort((minor, row))
+    tag = "-sorted" if seed is None else "-shuffled"
+    return W.Graph(g.V, g.row_ptr, g.col[order].copy(), g.cap[order].copy(), g.s, g.t, g.name + tag)
+
+
+# both builder paths (column-sorted rows: backward-key sort + merge; any
+# order: full sort), at 1, 2 and 3 radix passes over the row bits
+@pytest.mark.parametrize("V,E,seed", [(200, 1500, 5), (5000, 40000, 6), (70000, 300000, 7)])
+def test_sorted_and_unsorted_rows(solver, V, E, seed):
+    g0 = W.multigraph(V, E, cmax=25, seed=seed)
+    ref = oracle.reference(g0.V, g0.row_ptr, g0.col, g0.cap, g0.s, g0.t)
+    for g in (_reorder_rows(g0), _reorder_rows(g0, seed)):
+        say(f"[row-order] {g.name}")
+        check_against_oracle(g, solver.solve(g), ref)
+
+
 def test_degenerate_cases(solver):
     cases = [
         W.from_arcs(2, [], 0, 1, "no-arcs"),
@@ -205,6 +225,14 @@ def test_error_paths(solver):
     ovf = W.from_arcs(3, [(0, 1, 2**31 - 1), (1, 0, 5), (1, 2, 4)], 0, 2)
     rc = wbpr.wbpr_solve(ctx, ovf.V, ovf.row_ptr, ovf.col, ovf.cap, 0, 2, return_code=True)
     assert rc == wbpr.WBPR_EOVERFLOW
+    # parallel arcs whose sum alone leaves int32; a pair summing to 2^31
+    for arcs in ([(0, 1, 2**31 - 1), (0, 1, 1), (1, 2, 4)], [(0, 1, 2**30), (1, 0, 2**30), (1, 2, 4)]):
+        o = W.from_arcs(3, arcs, 0, 2)
+        rc = wbpr.wbpr_solve(ctx, o.V, o.row_ptr, o.col, o.cap, 0, 2, return_code=True)
+        assert rc == wbpr.WBPR_EOVERFLOW, arcs
+    # largest pair sum that fits: solves
+    fit = W.from_arcs(3, [(0, 1, 2**30), (1, 0, 2**30 - 1), (1, 2, 4), (0, 1, 0)], 0, 2)
+    check_against_oracle(fit, solver.solve(fit))
     # the context still works after errors
     check_against_oracle(g, solver.solve(g))
 
