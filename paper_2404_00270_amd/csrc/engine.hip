@@ -353,6 +353,8 @@ Engine::Engine(int device) : device_(device) {
 Engine::~Engine() {
   drop_graphs();
   for (auto &e : ev_) hipEventDestroy(e);
+  for (auto &e : fork_ev_) hipEventDestroy(e);
+  if (side_) hipStreamDestroy(side_);
   if (arena_) hipFree(arena_);
   if (scratch_) hipFree(scratch_);
   if (pin_) hipHostFree(pin_);
@@ -361,7 +363,7 @@ Engine::~Engine() {
 void Engine::set_config(const SolveConfig &cfg) {
   cfg_ = cfg;
   drop_graphs();
-  next_K_ = 64;
+  next_K_ = 12;
 }
 
 void Engine::drop_graphs() {
@@ -901,8 +903,29 @@ void Engine::dump_sweep_log(hipStream_t st) {
   hipMemsetAsync(&misc->log_n, 0, 4, st);
 }
 
+bool Engine::ensure_side() {
+  if (side_) return true;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
+  std::vector<hipEvent_t> ev(2 * 64, nullptr);
+  for (auto &e : ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      for (auto &x : ev)
+        if (x) hipEventDestroy(x);
+      hipStreamDestroy(s);
+      return false;
+    }
+  }
+  side_ = s;
+  fork_ev_ = std::move(ev);
+  return true;
+}
+
 // tiers: bit 0 launches the medium-row kernel, bit 1 the long-row chunk
-// kernels (the tile kernel and the control kernel always run).
+// kernels (the tile kernel and the control kernel always run).  With both,
+// the long-row chain runs on the side stream beside the medium-row kernel:
+// every queued vertex is in exactly one of the two lists, and the two touch
+// shared state only through atomics, as workgroups of one kernel do.
 void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
   MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
   Graph g{(int32_t)Vcap_, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_};
@@ -913,6 +936,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
   const int mode = cfg_.push_mode == 1 ? 0 : 1;
   const bool timed = cfg_.time_kernels;
   const bool fs = cfg_.full_scan;
+  const bool fork = !timed && (tiers & 3) == 3 && side_ != nullptr;
   for (int j = 0; j < K; j++) {
     SweepQ q;
     q.qin = fs ? q_[1] : q_[j & 1];
@@ -965,15 +989,27 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
       launch_avq_scan(sweep_blocks, st, g, &misc->span, q_[1], &misc->scan_cnt, (int32_t)Vcap_, misc->err,
                       &misc->halt[0]);
     launch_sweep_tile(P_, sweep_blocks, st, g, q);
-    if (timed) hipEventRecord(ev_[evb + 1], st);
-    if (tiers & 1) launch_sweep_tile(mid_lanes_, sweep_blocks, st, g, qw);
-    if (timed) hipEventRecord(ev_[evb + 2], st);
-    if (tiers & 2) {
-      launch_sweep_chunk(0, chunk_blocks, st, g, q);
-      launch_sweep_chunk(1, chunk_blocks, st, g, q);
-      launch_sweep_chunk(2, 64, st, g, q);
+    if (fork) {
+      hipEvent_t ef = fork_ev_[(2 * j) % fork_ev_.size()], ej = fork_ev_[(2 * j + 1) % fork_ev_.size()];
+      hipEventRecord(ef, st);
+      hipStreamWaitEvent(side_, ef, 0);
+      launch_sweep_chunk(0, chunk_blocks, side_, g, q);
+      launch_sweep_chunk(1, chunk_blocks, side_, g, q);
+      launch_sweep_chunk(2, 64, side_, g, q);
+      hipEventRecord(ej, side_);
+      launch_sweep_tile(mid_lanes_, sweep_blocks, st, g, qw);
+      hipStreamWaitEvent(st, ej, 0);
+    } else {
+      if (timed) hipEventRecord(ev_[evb + 1], st);
+      if (tiers & 1) launch_sweep_tile(mid_lanes_, sweep_blocks, st, g, qw);
+      if (timed) hipEventRecord(ev_[evb + 2], st);
+      if (tiers & 2) {
+        launch_sweep_chunk(0, chunk_blocks, st, g, q);
+        launch_sweep_chunk(1, chunk_blocks, st, g, q);
+        launch_sweep_chunk(2, 64, st, g, q);
+      }
+      if (timed) hipEventRecord(ev_[evb + 3], st);
     }
-    if (timed) hipEventRecord(ev_[evb + 3], st);
     SweepCtl ctl;
     ctl.qin_cnt = q.qin_cnt;
     ctl.mid_cnt = q.mid_cnt;
@@ -1211,41 +1247,63 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   launch_inst_kernel(IK_DECODE, fin2, st);
   for (int i : to2) inst_[i].phase = 2;
   for (int i : fin_done) inst_[i].phase = 3;
-  // sweeps for the instances still active
-  // sweeps that found work in the last batch: the next batch is sized to
-  // about twice that (a halted sweep slot costs a few microseconds of empty
-  // launches), doubling while batches run to their end; the device ends a
-  // batch early on an empty queue, the relabel budget or stagnation
+  // sweeps for the instances still active.  A round starts with a batch
+  // sized to the sweeps that found work in the last round (an empty sweep
+  // slot after the device halts still costs its launches); while a batch
+  // runs to its end without a halt the round goes on with one twice as long,
+  // up to 72 sweeps in the round (heights older than that cost more sweeps
+  // than a relabel on the grid cut), so no relabel is spent on a batch that
+  // was merely short.
+  // The device ends a batch early on an empty queue, the relabel budget or
+  // stagnation.  Batch lengths are multiples of 6: sweep j takes its queue
+  // count from slot j % 3 and its lists from slot j % 2, so such a batch
+  // leaves the rings where the next batch's first sweep starts.
   long long nonempty = 0;
   std::memcpy(&nonempty, rb + 64, 8);
   const long long ran = nonempty - last_nonempty_;
   last_nonempty_ = nonempty;
   if (last_K_ > 0) {
-    int k = ran >= last_K_ ? 2 * last_K_ : 16;
-    while (k < 2 * ran) k *= 2;
-    next_K_ = std::min(std::max(k, 16), 64);
+    int k = 6;
+    while (k < ran) k *= 2;
+    next_K_ = std::min(k, 48);
   }
   if (status[0] > 0) {
-    const int K = cfg_.gr_every_sweeps > 0 ? cfg_.gr_every_sweeps : next_K_;
+    const bool fixed = cfg_.gr_every_sweeps > 0;
+    int K = fixed ? cfg_.gr_every_sweeps : next_K_;
     last_K_ = K;
     // tiers that no resident row can reach are not launched
     int32_t rows = 0;
     for (int i = 0; i < ncap_; i++)
       if (inst_[i].used && inst_[i].phase < 3) rows = std::max(rows, inst_[i].maxdeg);
     const int tiers = (rows > t_mid_ ? 1 : 0) | (rows > t_big_ ? 2 : 0);
-    if (cfg_.use_graph && !cfg_.time_kernels) {
-      hipGraphExec_t exec = nullptr;
-      int rc = ensure_graph(st, K, tiers, &exec, err);
-      if (rc) return rc;
-      he = hipGraphLaunch(exec, st);
+    if ((tiers & 3) == 3) ensure_side();  // before any capture begins
+    int32_t *hhalt = reinterpret_cast<int32_t *>(rb + 96);
+    for (int total = 0;;) {
+      if (cfg_.use_graph && !cfg_.time_kernels) {
+        hipGraphExec_t exec = nullptr;
+        int rc = ensure_graph(st, K, tiers, &exec, err);
+        if (rc) return rc;
+        he = hipGraphLaunch(exec, st);
+        if (he != hipSuccess) {
+          *err = std::string("graph launch: ") + hipGetErrorString(he);
+          return WBPR_EDEVICE;
+        }
+      } else {
+        enqueue_sweeps(st, K, tiers);
+      }
+      acc_.sweeps += K;
+      total += K;
+      const int more = std::min(2 * K, 72 - total) / 6 * 6;
+      if (fixed || more <= 0) break;
+      he = hipMemcpyAsync(hhalt, &misc->halt[0], 4, hipMemcpyDeviceToHost, st);
+      if (he == hipSuccess) he = hipStreamSynchronize(st);
       if (he != hipSuccess) {
-        *err = std::string("graph launch: ") + hipGetErrorString(he);
+        *err = std::string("sweeps: ") + hipGetErrorString(he);
         return WBPR_EDEVICE;
       }
-    } else {
-      enqueue_sweeps(st, K, tiers);
+      if (*hhalt) break;
+      K = more;
     }
-    acc_.sweeps += K;
   }
   he = hipGetLastError();
   if (he != hipSuccess) {
@@ -1324,7 +1382,7 @@ void Engine::abandon(hipStream_t st) {
 
 void Engine::reset_stats() {
   acc_ = EngineStats();
-  next_K_ = 64;
+  next_K_ = 12;
   last_K_ = 0;
   ev_used_ = 0;
   ev_marks_.clear();

@@ -220,8 +220,13 @@ class Engine {
   int mid_lanes_ = 64;  // lanes per medium row (16 and 32 measured no faster on R-MAT)
   // captured sweep batches, one per (batch length, tiers); adaptive batch length
   std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs_;
-  int next_K_ = 64, last_K_ = 0;
+  int next_K_ = 12, last_K_ = 0;  // multiples of 6
   long long last_nonempty_ = 0;
+  // second stream for the long-row chain, which runs beside the medium-row
+  // kernel inside a sweep (fork/join events, reused cyclically)
+  hipStream_t side_ = nullptr;
+  std::vector<hipEvent_t> fork_ev_;
+  bool ensure_side();
   // timing
   std::vector<hipEvent_t> ev_;
   int ev_used_ = 0;
