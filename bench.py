@@ -298,6 +298,59 @@ def ablation(workloads, dev, steps=2):
     return out
 
 
+def wave_spread(tr):
+    """Per-wave execution times normalised by the mean of their launch, over
+    the waves that had work: (std-dev, p50, p90, p99, max, waves)."""
+    import numpy as np
+
+    busy = tr[tr[:, 4] > 0]
+    keys = busy[:, 0] * 4 + busy[:, 1]
+    order = np.argsort(keys, kind="stable")
+    keys, t = keys[order], busy[order, 2].astype(np.float64)
+    bounds = np.flatnonzero(np.diff(keys)) + 1
+    norm = [x / x.mean() for x in np.split(t, bounds) if len(x) > 1 and x.mean() > 0]
+    if not norm:
+        return None
+    v = np.concatenate(norm)
+    q = np.percentile(v, [50, 90, 99])
+    return dict(std=round(float(v.std()), 3), p50=round(float(q[0]), 3), p90=round(float(q[1]), 3),
+                p99=round(float(q[2]), 3), max=round(float(v.max()), 2), waves=int(len(v)))
+
+
+def wave_trace_study(workloads, dev):
+    """The paper's workload analysis (section 5): every wave's execution time,
+    normalised by its launch's mean, for the thread-centric and the
+    vertex-centric kernel (both with the full-scan queue of Algorithm 2, as
+    the paper's comparison), and for the default schedule."""
+    import torch
+
+    from paper_2404_00270_amd import workloads as W
+    from paper_2404_00270_amd import wbpr
+
+    variants = [("TC, full-scan queue", dict(lanes_per_vertex=1, avq_mode=1)),
+                ("VC, full-scan queue", dict(avq_mode=1)),
+                ("VC, default schedule", {})]
+    out = []
+    for name in workloads:
+        g = W.CONFIGS[name]()
+        rp = torch.from_numpy(g.row_ptr).to(dev)
+        col = torch.from_numpy(g.col).to(dev)
+        cap = torch.from_numpy(g.cap).to(dev)
+        value = torch.zeros(1, dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        row = {"workload": g.name}
+        for label, opts in variants:
+            with wbpr.Solver(0, max_wall_ms=60_000, wave_trace=1, **opts) as solver:
+                solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value)  # warm-up (graph capture)
+                st = solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value)
+                tr = solver.wave_trace()
+            row[label] = dict(spread=wave_spread(tr), records=int(len(tr)), ms=round(st["ms_total"], 2),
+                              value=int(value.item()))
+            log(f"[wave-trace] {g.name} {label}: {row[label]}")
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +373,8 @@ def main():
                     help="only run plain device copies of this many MiB (HBM counter calibration)")
     ap.add_argument("--ablation", default="", metavar="W1,W2",
                     help="only run the thread-centric / vertex-centric comparison on these workloads")
+    ap.add_argument("--wave-trace", default="", metavar="W1,W2",
+                    help="only run the per-wave workload analysis on these workloads")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -336,6 +391,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.ablation:
         print(json.dumps({"ablation": ablation(args.ablation.split(","), dev)}), flush=True)
+        return
+    if args.wave_trace:
+        print(json.dumps({"wave_trace": wave_trace_study(args.wave_trace.split(","), dev)}), flush=True)
         return
     if args.calibrate_copy > 0:
         # a plain copy reads and writes exactly n bytes each: the reference

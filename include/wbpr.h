@@ -89,7 +89,7 @@ typedef struct wbpr_options {
                                   mean row length */
     int32_t split_degree;      /* rows longer than this get one wave each */
     int32_t gr_every_sweeps;   /* fixed sweeps between global relabels
-                                  (0 = adaptive, at most 64) */
+                                  (0 = adaptive, at most 72) */
     int64_t max_sweeps;        /* watchdog on total sweeps (0 = none) */
     int32_t max_wall_ms;       /* watchdog on wall time (0 = none) */
     int32_t grid_blocks;       /* workgroups per sweep launch */
@@ -116,7 +116,10 @@ typedef struct wbpr_options {
                                   new smallest active queue (0 = from the mean
                                   row length: 32, 8 or 4 for <= 10, <= 20,
                                   longer) */
-    int32_t reserved[1];
+    int32_t wave_trace;        /* 1: every wave of every sweep launch records
+                                  its execution time and work (the per-warp
+                                  timing of the paper's workload analysis,
+                                  section 5); read with wbpr_wave_trace */
 } wbpr_options;
 
 /* Per-solve counters and timings (filled when a non-NULL pointer is given). */
@@ -252,6 +255,23 @@ void wbpr_graph_free(wbpr_graph *gr);
  * full-scan queue to the candidates. */
 int wbpr_autotune(wbpr_ctx *ctx, const wbpr_csr *g, int32_t s, int32_t t, int32_t max_trials,
                   int32_t include_full_scan, wbpr_options *best, double *best_ms);
+
+/* Per-wave trace of the last solve on ctx (section 5, workload analysis: the
+ * paper times every warp from its first thread; here the first lane of every
+ * wave of every sweep launch that ran records one entry).  Needs
+ * wave_trace = 1 in the options of that solve; else *count = 0.
+ * A record is four int32: [0] = sweep index since the solve started * 4 +
+ * kernel (0 short-row tiles, 1 medium rows, one wave each, 2 first chunks
+ * of long rows, 3 further chunks), [1] the wave's execution time in ticks of
+ * the 100 MHz device wall clock (from its first to its last instruction of
+ * the launch), [2] residual entries it scanned, [3] vertices (kernels 0-2) or
+ * chunk tasks (kernel 3) it processed.  Waves that found nothing to do are
+ * recorded too ([3] = 0).  A solve keeps at most 4,194,304 records (the rest
+ * are dropped).  Copies min(*count, cap) records into the HOST array
+ * records[4 * cap] (nullable when cap = 0); *count = records kept.  Records
+ * are in completion order.  WBPR_EINVAL: ctx or count NULL, cap < 0, or
+ * records NULL with cap > 0. */
+int wbpr_wave_trace(wbpr_ctx *ctx, int32_t *records, int64_t cap, int64_t *count);
 
 /* ------------------------------------------------------------------------
  * Continuous-batching server.

@@ -52,6 +52,7 @@ wb::SolveConfig to_config(const wbpr_options *o) {
   c.use_graph = o->no_graph == 0;
   c.full_scan = o->avq_mode == 1;
   c.gr_stagnation = o->gr_stagnation;
+  c.wave_trace = o->wave_trace != 0;
   return c;
 }
 
@@ -664,6 +665,18 @@ int wbpr_autotune(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int32_t 
   best->avq_mode = win.full_scan ? 1 : 0;
   best->gr_stagnation = win.gr_stagnation;
   if (best_ms) *best_ms = bms;
+  return WBPR_OK;
+}
+
+int wbpr_wave_trace(wbpr_ctx *c, int32_t *records, int64_t cap, int64_t *count) {
+  if (!c || !count) return fail(WBPR_EINVAL, "null argument");
+  if (cap < 0 || (cap > 0 && !records)) return fail(WBPR_EINVAL, "records must hold cap records");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  std::string err;
+  const int64_t n = c->engine->read_wave_trace(c->stream, records, cap, &err);
+  if (n < 0) return fail(WBPR_EDEVICE, "wave trace: " + err);
+  *count = n;
   return WBPR_OK;
 }
 

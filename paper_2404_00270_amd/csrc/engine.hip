@@ -272,6 +272,8 @@ struct MiscLayout {
   int32_t scan_cnt;  // full-scan queue count
   int32_t span;      // end of the highest resident vertex range
   int32_t stag[2];   // stagnation state of the sweeps
+  int32_t wtrace_n;  // per-wave trace records written this solve
+  int32_t sweep_no;  // sweeps that ran this solve (trace only)
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -355,6 +357,7 @@ Engine::~Engine() {
   for (auto &e : ev_) hipEventDestroy(e);
   for (auto &e : fork_ev_) hipEventDestroy(e);
   if (side_) hipStreamDestroy(side_);
+  if (wtrace_) hipFree(wtrace_);
   if (arena_) hipFree(arena_);
   if (scratch_) hipFree(scratch_);
   if (pin_) hipHostFree(pin_);
@@ -966,7 +969,13 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
     q.halt = &misc->halt[0];
     q.qcap = (int32_t)Vcap_;
     q.err = misc->err;
+    q.wtrace = cfg_.wave_trace ? wtrace_ : nullptr;
+    q.wtrace_n = &misc->wtrace_n;
+    q.wtrace_cap = kTraceCap;
+    q.sweep_no = &misc->sweep_no;
+    q.kind = 0;
     SweepQ qw = q;
+    qw.kind = 1;
     qw.qin = mid_;
     qw.qin_cnt = &misc->mid_cnt[j & 1];
     qw.zero_cnt = nullptr;
@@ -1026,6 +1035,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
     ctl.log = sweep_log_;
     ctl.log_n = &misc->log_n;
     ctl.log_cap = kSweepLogCap / 2;
+    ctl.sweep_no = q.wtrace ? &misc->sweep_no : nullptr;
     launch_sweep_control(st, ctl);
   }
 }
@@ -1277,6 +1287,11 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
       if (inst_[i].used && inst_[i].phase < 3) rows = std::max(rows, inst_[i].maxdeg);
     const int tiers = (rows > t_mid_ ? 1 : 0) | (rows > t_big_ ? 2 : 0);
     if ((tiers & 3) == 3) ensure_side();  // before any capture begins
+    if (cfg_.wave_trace && !wtrace_ && hipMalloc(&wtrace_, 16 * (size_t)kTraceCap) != hipSuccess) {
+      wtrace_ = nullptr;
+      *err = "out of device memory for the wave trace";
+      return WBPR_ENOMEM;
+    }
     int32_t *hhalt = reinterpret_cast<int32_t *>(rb + 96);
     for (int total = 0;;) {
       if (cfg_.use_graph && !cfg_.time_kernels) {
@@ -1390,7 +1405,32 @@ void Engine::reset_stats() {
   if (misc_) {
     MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
     hipMemset(misc->stats, 0, sizeof(misc->stats));
+    hipMemset(&misc->wtrace_n, 0, 2 * sizeof(int32_t));
   }
+}
+
+int64_t Engine::read_wave_trace(hipStream_t st, int32_t *host, int64_t cap, std::string *err) {
+  if (!wtrace_ || !misc_) return 0;
+  MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+  int32_t n = 0;
+  hipError_t e = hipMemcpyAsync(pin_ + 3072, &misc->wtrace_n, 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    *err = hipGetErrorString(e);
+    return -1;
+  }
+  std::memcpy(&n, pin_ + 3072, 4);
+  const int64_t kept = std::min<int64_t>(n, kTraceCap);
+  const int64_t k = std::min<int64_t>(kept, cap);
+  if (k > 0) {
+    e = hipMemcpyAsync(host, wtrace_, 16 * (size_t)k, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      *err = hipGetErrorString(e);
+      return -1;
+    }
+  }
+  return kept;
 }
 
 int Engine::collect_stats(hipStream_t st, EngineStats *out, std::string *err) {

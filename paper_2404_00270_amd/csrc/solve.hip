@@ -73,6 +73,23 @@ __device__ __forceinline__ void flush_stats(long long *stats, long long scans, i
   }
 }
 
+// Per-wave trace record, written by the first lane of every wave at the end
+// of a sweep launch when tracing is on (the paper's per-warp timing, section
+// 5).  All lanes of the wave call it, converged.
+__device__ __forceinline__ void trace_wave(const SweepQ &q, int kind, long long t0, long long scans,
+                                           long long items) {
+  scans = group_sum_i64<WB_WAVE>(scans);
+  items = group_sum_i64<WB_WAVE>(items);
+  if (lane() == 0) {
+    const long long dt = (long long)wall_clock64() - t0;
+    const int32_t slot = atomic_add_i32(q.wtrace_n, 1);
+    if (slot < q.wtrace_cap)
+      reinterpret_cast<int4 *>(q.wtrace)[slot] =
+          make_int4((*q.sweep_no << 2) | kind, (int)min(dt, 0x7fffffffll), (int)min(scans, 0x7fffffffll),
+                    (int)min(items, 0x7fffffffll));
+  }
+}
+
 // End of a sweep (one thread): stop the rest of this round's sweeps once the
 // queue is empty or the relabelling done since the last global relabel has
 // scanned more than `budget` entries (then fresh exact heights are worth a
@@ -110,6 +127,7 @@ __global__ void k_sweep_control(SweepCtl c) {
   }
   if (next == 0 || stagnant || *c.rwork - *c.rwork_at_gr > *c.budget) *c.halt = 1;
   if (c.scan_cnt) *c.scan_cnt = 0;
+  if (c.sweep_no) *c.sweep_no += 1;
 }
 
 // Full-scan queue (Algorithm 2's compaction): ballot over a wave, LDS
@@ -202,6 +220,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
   const WaveQ wmid{s_mbuf[wl], &s_qcnt[wl][1], q.mid_v, q.mid_cnt, q.qcap, q.err, DEFER_BUF};
   const WaveQ wbig{s_bbuf[wl], &s_qcnt[wl][2], q.big_v, q.big_cnt, q.qcap, q.err, DEFER_BUF};
   if (*q.halt) return;
+  const long long wt0 = q.wtrace ? (long long)wall_clock64() : 0;
   if (blockIdx.x == 0 && threadIdx.x == 0 && q.zero_cnt) {
     *q.zero_cnt = 0;
     *q.zero_a = 0;
@@ -373,6 +392,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
     waveq_flush(wbig);
   }
   flush_stats(q.stats, scans, pushes, relabels, queued, q.rwork, rwork);
+  if (q.wtrace) trace_wave(q, q.kind, wt0, scans, queued);
 }
 
 constexpr int BLK_WAVES = BLK / WB_WAVE;
@@ -474,6 +494,8 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
   __shared__ unsigned long long s_wmin[BLK_WAVES];
   __shared__ long long s_take;
   if (*q.halt) return;
+  const long long wt0 = q.wtrace ? (long long)wall_clock64() : 0;
+  long long tasks = 0;  // per wave, counted by its first lane
   const int32_t ntask = FIRST ? min(*q.big_cnt, q.qcap) : min(*q.task_cnt, q.tcap);
   const int w = threadIdx.x / WB_WAVE;
   if (lane() == 0) s_qcnt[w] = 0;
@@ -481,6 +503,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
   long long scans = 0, queued = 0, rwork = 0;
   int pushes = 0, relabels = 0;
   for (int32_t task = blockIdx.x; task < ntask; task += gridDim.x) {
+    if (lane() == 0) tasks++;
     const int32_t u = FIRST ? q.big_v[task] : q.task_u[task];
     const int32_t c = FIRST ? 0 : q.task_c[task];
     const int2 rb = g.rowb[u];
@@ -585,6 +608,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
   }
   waveq_flush(wq);
   flush_stats(q.stats + 8, scans, pushes, relabels, queued, q.rwork, rwork);
+  if (q.wtrace) trace_wave(q, FIRST ? 2 : 3, wt0, scans, tasks);
 }
 
 // Third pass: one thread finishes each long row whose chunks ran in the

@@ -31,6 +31,7 @@ struct SolveConfig {
   bool use_graph = true;      // replay the sweep batch as a captured hipGraph
   bool full_scan = false;     // rebuild the active queue by a full scan every sweep
   int gr_stagnation = 0;      // sweeps without a new smallest queue that end a round (0: by mean row length)
+  bool wave_trace = false;    // per-wave execution time and work of every sweep launch
 };
 
 // Counters of the engine since the last reset_stats().
@@ -140,6 +141,9 @@ class Engine {
   int64_t rounds_run() const { return acc_.global_relabels; }
 
   void reset_stats();
+  // Copies up to cap per-wave trace records of the solve since reset_stats()
+  // to host memory; returns the number of records kept (-1 on error).
+  int64_t read_wave_trace(hipStream_t st, int32_t *host, int64_t cap, std::string *err);
   int collect_stats(hipStream_t st, EngineStats *out, std::string *err);
 
  private:
@@ -227,6 +231,9 @@ class Engine {
   hipStream_t side_ = nullptr;
   std::vector<hipEvent_t> fork_ev_;
   bool ensure_side();
+  // per-wave trace (wave_trace option): int4 records, at most kTraceCap per solve
+  static constexpr int32_t kTraceCap = 1 << 22;
+  int32_t *wtrace_ = nullptr;
   // timing
   std::vector<hipEvent_t> ev_;
   int ev_used_ = 0;

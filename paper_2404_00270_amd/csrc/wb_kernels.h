@@ -62,6 +62,11 @@ struct SweepQ {
                      // 1: full discharge (push along every lower residual arc, then relabel)
   int32_t append;    // 1: append push targets and still-active vertices to qout (incremental
                      // queue); 0: the next sweep's full scan finds them
+  int32_t *wtrace;   // nullable: per-wave records (int4: sweep * 4 + kind, ticks, scans, items)
+  int32_t *wtrace_n; // records written so far (may exceed wtrace_cap: the excess is dropped)
+  int32_t wtrace_cap;
+  const int32_t *sweep_no;  // sweeps completed since the solve started (counted by the control step)
+  int32_t kind;      // 0 short-row tiles, 1 medium rows, 2 first chunks, 3 further chunks
 };
 
 // End-of-sweep control (one thread): halt decision and optional log.
@@ -75,6 +80,7 @@ struct SweepCtl {
   int32_t *log;      // nullable: [log_cap][6] per-sweep records
   int32_t *log_n;
   int32_t log_cap;
+  int32_t *sweep_no;  // nullable: incremented once per sweep that ran
 };
 
 struct GRArgs {

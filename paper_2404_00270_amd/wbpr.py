@@ -35,7 +35,7 @@ STATUS_NAMES = {
 EXPORTS = (
     "wbpr_version", "wbpr_last_error", "wbpr_device_arch", "wbpr_ctx_create", "wbpr_ctx_destroy",
     "wbpr_ctx_set_options", "wbpr_solve", "wbpr_solve_device", "wbpr_solve_batch", "wbpr_solve_batch_device",
-    "wbpr_graph_upload", "wbpr_graph_solve", "wbpr_graph_free", "wbpr_autotune",
+    "wbpr_graph_upload", "wbpr_graph_solve", "wbpr_graph_free", "wbpr_autotune", "wbpr_wave_trace",
     "wbpr_server_create", "wbpr_server_submit", "wbpr_server_poll", "wbpr_server_wait", "wbpr_result_free",
     "wbpr_server_get_stats", "wbpr_server_footprint", "wbpr_server_destroy",
 )
@@ -67,7 +67,7 @@ class wbpr_options(ctypes.Structure):
         ("no_graph", ctypes.c_int32),
         ("avq_mode", ctypes.c_int32),
         ("gr_stagnation", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("wave_trace", ctypes.c_int32),
     ]
 
 
@@ -222,6 +222,8 @@ def load_library(path: str = LIB_PATH):
     lib.wbpr_autotune.restype = ctypes.c_int
     lib.wbpr_autotune.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, i32, i32, i32, ctypes.POINTER(wbpr_options),
                                   ctypes.POINTER(ctypes.c_double)]
+    lib.wbpr_wave_trace.restype = ctypes.c_int
+    lib.wbpr_wave_trace.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.wbpr_server_create.restype = ctypes.c_int
     lib.wbpr_server_create.argtypes = [vp, ctypes.POINTER(wbpr_server_options), ctypes.POINTER(ctypes.c_void_p)]
     lib.wbpr_server_submit.restype = ctypes.c_int
@@ -410,7 +412,20 @@ class Solver:
         ms = ctypes.c_double()
         _check(lib.wbpr_autotune(self.ctx, ctypes.byref(csr), g.s, g.t, max_trials, int(include_full_scan),
                                  ctypes.byref(best), ctypes.byref(ms)))
-        return {name: getattr(best, name) for name, _ in best._fields_ if name != "reserved"}, ms.value
+        return {name: getattr(best, name) for name, _ in best._fields_}, ms.value
+
+    def wave_trace(self) -> np.ndarray:
+        """Per-wave records of the last solve (needs wave_trace=1): an int64
+        array of shape (n, 5) with columns sweep, kernel (0 short-row tiles,
+        1 medium rows, 2 first chunks, 3 further chunks), ticks of the 100 MHz
+        device clock, arc scans, items (vertices or chunk tasks)."""
+        lib = load_library()
+        n = ctypes.c_int64()
+        _check(lib.wbpr_wave_trace(self.ctx, None, 0, ctypes.byref(n)))
+        rec = np.zeros((max(n.value, 1), 4), np.int32)
+        _check(lib.wbpr_wave_trace(self.ctx, rec.ctypes.data, n.value, ctypes.byref(n)))
+        rec = rec[: n.value].astype(np.int64)
+        return np.stack([rec[:, 0] >> 2, rec[:, 0] & 3, rec[:, 1], rec[:, 2], rec[:, 3]], axis=1)
 
     def solve_batch(self, graphs, want_flow: bool = True, want_side: bool = True) -> BatchResult:
         return wbpr_solve_batch(self.ctx, graphs, want_flow, want_side)
