@@ -274,6 +274,48 @@ int wbpr_autotune(wbpr_ctx *ctx, const wbpr_csr *g, int32_t s, int32_t t, int32_
 int wbpr_wave_trace(wbpr_ctx *ctx, int32_t *records, int64_t cap, int64_t *count);
 
 /* ------------------------------------------------------------------------
+ * Multi-terminal front end: the paper's experimental protocol (section 4).
+ * Graphs without given terminals get source/sink pairs chosen by
+ * breadth-first search among the vertices farthest apart, and a
+ * super-source and a super-sink joined to all of them make the multi-source,
+ * multi-sink problem one s-t maximum flow.  BFS distances count arcs of
+ * positive capacity (the network at zero flow); self-loops never count.
+ * g is a HOST CSR (validated on the host: row pointers, columns in range).
+ * ---------------------------------------------------------------------- */
+
+/* Eccentricity of each from[i] (largest BFS distance to a vertex it reaches;
+ * 0 when it reaches nothing) into ecc[i], and the farthest vertex (smallest
+ * id among those at that distance; from[i] itself when it reaches nothing)
+ * into farthest[i].  HOST arrays [n].  Runs on the GPU as a bit-parallel
+ * BFS of up to 64 sources per pass (24 bytes per vertex of device memory
+ * for the call).  WBPR_ETIMEOUT when the context's max_wall_ms passes. */
+int wbpr_bfs_farthest(wbpr_ctx *ctx, const wbpr_csr *g, int32_t n, const int32_t *from, int32_t *ecc,
+                      int32_t *farthest);
+
+/* Up to k source/sink pairs by the paper's rule, read as: 4k candidate
+ * sources (distinct vertices with an arc of positive capacity to another
+ * vertex, drawn by SplitMix64 from `seed`, x -> x mod V in draw order), each
+ * paired with its farthest vertex; the pairs are taken by decreasing
+ * eccentricity (draw order on ties), skipping pairs with eccentricity 0 or
+ * a vertex already used, so the k kept (the top quarter of the candidates
+ * when enough are usable) use 2k distinct vertices.  HOST arrays
+ * sources[k], sinks[k]; *npairs = pairs written (may be below k). */
+int wbpr_pick_terminals(wbpr_ctx *ctx, const wbpr_csr *g, int32_t k, uint64_t seed, int32_t *sources,
+                        int32_t *sinks, int32_t *npairs);
+
+/* Maximum flow from the k sources to the k sinks (HOST arrays [k], 2k
+ * distinct vertices): a super-source S = V with an arc to every source of
+ * that source's outgoing capacity and a super-sink T = V + 1 with an arc
+ * from every sink of that sink's incoming capacity (neither can bind) are
+ * added, and the s-t path solves (S, T).  Outputs as wbpr_solve, for the
+ * original graph: *value, arc_flow[E] and cut_side[V] (HOST, nullable;
+ * cut_side[v] = 1 when v reaches T in the final residual graph).  Errors as
+ * wbpr_solve; WBPR_EINVAL for a terminal out of range or listed twice;
+ * WBPR_EOVERFLOW when a terminal's capacity sum exceeds INT32_MAX. */
+int wbpr_solve_multi(wbpr_ctx *ctx, const wbpr_csr *g, int32_t k, const int32_t *sources, const int32_t *sinks,
+                     int64_t *value, int32_t *arc_flow, uint8_t *cut_side, wbpr_stats *stats);
+
+/* ------------------------------------------------------------------------
  * Continuous-batching server.
  *
  * Requests (one instance each) arrive at any time from any thread.  A worker

@@ -215,7 +215,7 @@ bool same_schedule(const wb::SolveConfig &a, const wb::SolveConfig &b) {
          a.block_degree == b.block_degree &&
          a.gr_every_sweeps == b.gr_every_sweeps && a.grid_blocks == b.grid_blocks &&
          a.time_kernels == b.time_kernels && a.push_mode == b.push_mode && a.use_graph == b.use_graph &&
-         a.max_sweeps == b.max_sweeps && a.max_wall_ms == b.max_wall_ms;
+         a.max_sweeps == b.max_sweeps && a.max_wall_ms == b.max_wall_ms && a.wave_trace == b.wave_trace;
 }
 
 // Solves a group already packed on the device, from an empty engine.

@@ -36,6 +36,7 @@ EXPORTS = (
     "wbpr_version", "wbpr_last_error", "wbpr_device_arch", "wbpr_ctx_create", "wbpr_ctx_destroy",
     "wbpr_ctx_set_options", "wbpr_solve", "wbpr_solve_device", "wbpr_solve_batch", "wbpr_solve_batch_device",
     "wbpr_graph_upload", "wbpr_graph_solve", "wbpr_graph_free", "wbpr_autotune", "wbpr_wave_trace",
+    "wbpr_bfs_farthest", "wbpr_pick_terminals", "wbpr_solve_multi",
     "wbpr_server_create", "wbpr_server_submit", "wbpr_server_poll", "wbpr_server_wait", "wbpr_result_free",
     "wbpr_server_get_stats", "wbpr_server_footprint", "wbpr_server_destroy",
 )
@@ -222,6 +223,14 @@ def load_library(path: str = LIB_PATH):
     lib.wbpr_autotune.restype = ctypes.c_int
     lib.wbpr_autotune.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, i32, i32, i32, ctypes.POINTER(wbpr_options),
                                   ctypes.POINTER(ctypes.c_double)]
+    lib.wbpr_bfs_farthest.restype = ctypes.c_int
+    lib.wbpr_bfs_farthest.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, vp, vp, vp]
+    lib.wbpr_pick_terminals.restype = ctypes.c_int
+    lib.wbpr_pick_terminals.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, ctypes.c_uint64, vp, vp,
+                                        ctypes.POINTER(ctypes.c_int32)]
+    lib.wbpr_solve_multi.restype = ctypes.c_int
+    lib.wbpr_solve_multi.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, vp, vp, vp, vp, vp,
+                                     ctypes.POINTER(wbpr_stats)]
     lib.wbpr_wave_trace.restype = ctypes.c_int
     lib.wbpr_wave_trace.argtypes = [vp, vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.wbpr_server_create.restype = ctypes.c_int
@@ -320,6 +329,64 @@ def wbpr_solve(ctx: int, V: int, row_ptr, col, cap, s: int, t: int, want_flow: b
                   side[:V] if side is not None else None, st.as_dict())
 
 
+def _host_csr(g):
+    """(wbpr_csr, arrays to keep alive) for a host graph object."""
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(g.col, dtype=np.int32)
+    k = np.ascontiguousarray(g.cap, dtype=np.int32)
+    E = int(c.shape[0])
+    return wbpr_csr(g.V, E, rp.ctypes.data, c.ctypes.data if E else None, k.ctypes.data if E else None), (rp, c, k)
+
+
+def wbpr_bfs_farthest(ctx: int, g, sources):
+    """(eccentricity, farthest vertex) arrays for every vertex in sources."""
+    lib = load_library()
+    csr, keep = _host_csr(g)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    n = int(src.shape[0])
+    ecc = np.zeros(max(n, 1), np.int32)
+    far = np.zeros(max(n, 1), np.int32)
+    _check(lib.wbpr_bfs_farthest(ctx, ctypes.byref(csr), n, src.ctypes.data if n else None,
+                                 ecc.ctypes.data if n else None, far.ctypes.data if n else None))
+    return ecc[:n], far[:n]
+
+
+def wbpr_pick_terminals(ctx: int, g, k: int, seed: int):
+    """(sources, sinks) chosen by the paper's BFS rule (at most k pairs)."""
+    lib = load_library()
+    csr, keep = _host_csr(g)
+    src = np.zeros(max(k, 1), np.int32)
+    snk = np.zeros(max(k, 1), np.int32)
+    n = ctypes.c_int32(0)
+    _check(lib.wbpr_pick_terminals(ctx, ctypes.byref(csr), k, seed, src.ctypes.data, snk.ctypes.data, ctypes.byref(n)))
+    return src[: n.value], snk[: n.value]
+
+
+def wbpr_solve_multi(ctx: int, g, sources, sinks, want_flow: bool = True, want_side: bool = True,
+                     return_code: bool = False):
+    """Multi-source, multi-sink maximum flow through a super-source and super-sink."""
+    lib = load_library()
+    csr, keep = _host_csr(g)
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    snk = np.ascontiguousarray(sinks, dtype=np.int32)
+    if src.shape != snk.shape:
+        raise ValueError("sources and sinks must have the same length")
+    k = int(src.shape[0])
+    value = ctypes.c_int64(0)
+    flow = np.zeros(max(csr.E, 1), np.int32) if want_flow else None
+    side = np.zeros(max(g.V, 1), np.uint8) if want_side else None
+    st = wbpr_stats()
+    rc = lib.wbpr_solve_multi(ctx, ctypes.byref(csr), k, src.ctypes.data if k else None,
+                              snk.ctypes.data if k else None, ctypes.addressof(value),
+                              flow.ctypes.data if flow is not None else None,
+                              side.ctypes.data if side is not None else None, ctypes.byref(st))
+    if return_code:
+        return rc
+    _check(rc)
+    return Result(int(value.value), flow[: csr.E] if flow is not None else None,
+                  side[: g.V] if side is not None else None, st.as_dict())
+
+
 def wbpr_solve_device(ctx: int, V: int, E: int, row_ptr_ptr: int, col_ptr: int, cap_ptr: int, s: int, t: int,
                       stream: int, value_ptr: int, flow_ptr: int | None, side_ptr: int | None) -> dict:
     """Solve from device pointers (e.g. torch tensor data_ptr()); returns the stats dict."""
@@ -413,6 +480,15 @@ class Solver:
         _check(lib.wbpr_autotune(self.ctx, ctypes.byref(csr), g.s, g.t, max_trials, int(include_full_scan),
                                  ctypes.byref(best), ctypes.byref(ms)))
         return {name: getattr(best, name) for name, _ in best._fields_}, ms.value
+
+    def bfs_farthest(self, g, sources):
+        return wbpr_bfs_farthest(self.ctx, g, sources)
+
+    def pick_terminals(self, g, k: int, seed: int = 1):
+        return wbpr_pick_terminals(self.ctx, g, k, seed)
+
+    def solve_multi(self, g, sources, sinks, want_flow: bool = True, want_side: bool = True) -> Result:
+        return wbpr_solve_multi(self.ctx, g, sources, sinks, want_flow, want_side)
 
     def wave_trace(self) -> np.ndarray:
         """Per-wave records of the last solve (needs wave_trace=1): an int64
