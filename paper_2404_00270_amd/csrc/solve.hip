@@ -758,12 +758,19 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     a.task_cnt[1] = 0;
   }
   grid_barrier(a.bar, nblocks);
+  long long root_edges = 0;
   for (int64_t j = gtid; j < a.nroots; j += nthreads) {
     g.h[a.roots[j]] = a.root_h[j];
     a.vis[a.roots[j]] = dist_code(0);
     bm_set(bm_vis, a.roots[j]);
     bm_set(a.bm + a.bm_words, a.roots[j]);  // frontier of level 0
+    const int2 rb = g.rowb[a.roots[j]];
+    root_edges += rb.y - rb.x;
   }
+  // row lengths of the roots: a root whose row holds a large share of the
+  // entries (the grid cut's sink) is expanded bottom-up from level 0
+  root_edges = group_sum_i64<WB_WAVE>(root_edges);
+  if (lane() == 0 && root_edges) atomic_add_i64(&a.fedges[0], root_edges);
   for (int64_t j = gtid; j < a.nexcl; j += nthreads) {
     g.h[a.excl[j]] = g.hcap + 1;
     a.vis[a.excl[j]] = 3;
@@ -774,7 +781,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   long long bscans = 0, buscans = 0;  // entries examined top-down / bottom-up
   int32_t level = 0, bu_levels = 0;
   int32_t n = min(a.nroots, a.qcap);
-  long long nedges = 0;  // row-length sum of the current frontier (0: the root alone)
+  long long nedges = atomic_load_i64(&a.fedges[0]);  // row-length sum of the current frontier
   long long vedges = 0;  // row-length sum of every vertex labelled so far
   bool queue_valid = true;  // the frontier of this level is in fq[level & 1]
   for (;;) {
