@@ -92,7 +92,8 @@ typedef struct wbpr_options {
                                   (0 = adaptive, at most 72) */
     int64_t max_sweeps;        /* watchdog on total sweeps (0 = none) */
     int32_t max_wall_ms;       /* watchdog on wall time (0 = none) */
-    int32_t grid_blocks;       /* workgroups per sweep launch */
+    int32_t grid_blocks;       /* workgroups per tile-kernel launch of a sweep
+                                  (0 = 256, one per compute unit) */
     int32_t time_kernels;      /* 1: time every sweep and global-relabel
                                   launch with HIP events (kernel_ms) */
     int32_t push_mode;         /* 1: one push per visit to the minimum-height

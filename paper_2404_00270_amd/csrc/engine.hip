@@ -932,9 +932,13 @@ bool Engine::ensure_side() {
 void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
   MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
   Graph g{(int32_t)Vcap_, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_};
-  // 1024 workgroups (4 per CU): measured faster than 2048 on the grid cut
-  // (122 vs 144 ms) and R-MAT (66 vs 74 ms); most sweeps have small queues
-  const int sweep_blocks = cfg_.grid_blocks > 0 ? cfg_.grid_blocks : 1024;
+  // tile kernels: 256 workgroups, one per CU.  Measured on R-MAT / grid cut
+  // / bipartite: 1024 -> 34.3 / 94 / 6.35 ms, 512 -> 30.2 / 85 / 6.08,
+  // 256 -> 30.0 / 78 / 6.0, 192 and 128 slower again (31.2 and 34 ms on
+  // R-MAT); most sweeps have short queues, and each workgroup pays for its
+  // start, its queue flushes and its counter atomics.  The long-row chunk
+  // kernels keep 1024 (one workgroup per chunk task; 256 measured slower).
+  const int sweep_blocks = cfg_.grid_blocks > 0 ? cfg_.grid_blocks : 256;
   const int chunk_blocks = 1024;
   const int mode = cfg_.push_mode == 1 ? 0 : 1;
   const bool timed = cfg_.time_kernels;

@@ -25,7 +25,7 @@ struct SolveConfig {
   int gr_work_permille = 0;   // adaptive relabel budget in thousandths of V + M (0: 1000)
   int64_t max_sweeps = 0;
   int max_wall_ms = 0;
-  int grid_blocks = 0;        // workgroups per sweep launch (0: 1024)
+  int grid_blocks = 0;        // workgroups per tile-kernel launch (0: 256)
   bool time_kernels = false;  // bracket every sweep / relabel launch with events
   int push_mode = 0;          // 1: single push to the lowest neighbour; 0/2: full discharge
   bool use_graph = true;      // replay the sweep batch as a captured hipGraph
