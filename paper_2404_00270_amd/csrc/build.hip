@@ -14,8 +14,9 @@
 //      keys are sorted already and the backward keys need only a stable sort
 //      on their row (the head of the arc), then the two are merged; else a
 //      stable radix sort of all keys on (row, column), self-loops last
-//   3. group heads -> unique entry ids (scan), merged capacities (scan of
-//      the forward arcs' capacities, differenced at group bounds)
+//   3. group heads -> unique entry ids (scan); each head walks its group
+//      for the merged capacity and the parallel-arc prefixes (long groups:
+//      one workgroup each)
 //   4. row pointers, mates and arc->entry map, parallel-arc prefixes; the
 //      pairwise int32 overflow check runs only if some entry holds >= 2^30
 #include "wb_common.h"
@@ -35,8 +36,7 @@ namespace {
 struct Scratch {
   uint64_t *k0, *k1;
   uint32_t *v0, *v1;
-  int32_t *head, *hx, *uid_of, *gstart, *rowcnt, *rptr, *hist, *stemp;
-  int64_t *pcap, *stemp64;
+  int32_t *head, *hx, *uid_of, *gstart, *rowcnt, *rptr, *hist, *stemp;  // gstart: long-group list
 };
 
 size_t carve_scratch(int32_t V, int64_t E, void *mem, Scratch *s) {
@@ -57,8 +57,6 @@ size_t carve_scratch(int32_t V, int64_t E, void *mem, Scratch *s) {
   s->rptr = (int32_t *)take(4 * ((size_t)V + 1));
   s->hist = (int32_t *)take(4 * (size_t)hn);
   s->stemp = (int32_t *)take(4 * (size_t)st);
-  s->pcap = (int64_t *)take(8 * (N + 1));
-  s->stemp64 = (int64_t *)take(8 * (size_t)st);
   return (size_t)(p - base);
 }
 }  // namespace
@@ -245,69 +243,116 @@ __global__ void k_heads(const uint64_t *keys, int64_t N, int vb, bool inline_sel
   }
 }
 
-// Step 3b.  Unique id of item i = hx[i] + head[i] - 1.  Group heads write
-// the entry's column and start; every item records its unique id under its
-// payload (arc * 2 + direction) and its forward capacity for the scan.
-__global__ void k_unique(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, bool inline_self,
-                         const int32_t *cap, const BuildStatus *st, const int32_t *head, const int32_t *hx,
-                         int32_t *gstart, int32_t *uid_of, int64_t *pcap) {
-  const int64_t mraw = inline_self ? N : N - 2 * (int64_t)st->nself;
-  const int32_t M = st->M;
-  const uint32_t E = (uint32_t)(N / 2);  // payloads below E are forward arcs
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= N; i += (int64_t)gridDim.x * blockDim.x) {
-    if (i >= mraw) {
-      pcap[i] = 0;
-      if (i == mraw) gstart[M] = (int32_t)mraw;  // end of the last group
-      continue;
-    }
-    const uint64_t key = keys[i];
-    if (inline_self && self_key(key, vb)) {
-      pcap[i] = 0;
-      continue;
-    }
-    const uint32_t pl = vals[i];
-    const int32_t u = hx[i] + head[i] - 1;
-    if (head[i]) gstart[u] = (int32_t)i;
-    uid_of[pl] = u;
-    pcap[i] = pl < E ? (int64_t)cap[pl] : 0;
-  }
+// Step 3b.  A group (a run of equal keys: the forward items of every arc
+// u->v and the backward items of every arc v->u) becomes entry hx[head].
+// Its head walks it in sorted order (the sort is stable, so a group's arcs
+// are in input order), records the entry id of every item under its payload,
+// the capacity of earlier parallel arcs for each forward arc, and writes the
+// entry: column and summed forward capacity, plus the initial residual copy.
+// A sum above INT32_MAX is an overflow by itself; sums of at least 2^30 are
+// counted, since only such an entry can overflow together with its mate (two
+// sums below 2^30 add up to less than 2^31).  Groups longer than GROUP_WALK
+// items (many parallel arcs) are listed for k_long_groups instead, so no
+// thread walks far.
+constexpr int GROUP_WALK = 256;
+
+__device__ __forceinline__ void write_entry(int32_t u, uint64_t key, uint64_t cmask, int32_t vbase, long long c,
+                                            int2 *ent, int32_t *cap0, int *big, int *ovf) {
+  *big += c >= (1ll << 30);
+  *ovf += c > 0x7fffffffll;
+  const int32_t c32 = c > 0x7fffffffll ? 0 : (int32_t)c;
+  ent[u] = make_int2(vbase + (int)(key & cmask), c32);
+  cap0[u] = c32;
 }
 
-// Step 3b'.  After the scan of pcap (pc[i] = forward capacity of sorted
-// items before i): merged capacity of entry u = forward capacity of its
-// group; capacity of earlier parallel arcs of forward item i = pc[i] - pc of
-// its group's start (the sort is stable, so a group's arcs are in input
-// order).
-// The group head writes its entry (column, merged capacity) and the initial
-// residual copy.  A sum above INT32_MAX is an overflow by itself; sums of at
-// least 2^30 are counted, since only such an entry can overflow together
-// with its mate (two sums below 2^30 add up to less than 2^31).
-__global__ void k_group_caps(const uint64_t *keys, int vb, bool inline_self, const uint32_t *vals, BuildStatus *st,
-                             const int32_t *head, const int32_t *hx, const int32_t *gstart, const int64_t *pc,
-                             int32_t vbase, int2 *ent, int32_t *cap0, int32_t *pbefore_arc, int64_t N) {
+__global__ void k_groups(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, bool inline_self,
+                         const int32_t *cap, BuildStatus *st, const int32_t *head, const int32_t *hx, int32_t vbase,
+                         int2 *ent, int32_t *cap0, int32_t *uid_of, int32_t *pbefore_arc, int32_t *long_list) {
   const int64_t mraw = inline_self ? N : N - 2 * (int64_t)st->nself;
-  const uint32_t E = (uint32_t)(N / 2);
+  const uint32_t E = (uint32_t)(N / 2);  // payloads below E are forward arcs
   const uint64_t cmask = (1ull << vb) - 1;
   int big = 0, ovf = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < mraw; i += (int64_t)gridDim.x * blockDim.x) {
+    if (!head[i]) continue;  // also every self-loop key
     const uint64_t key = keys[i];
-    if (inline_self && self_key(key, vb)) continue;
-    const int32_t u = hx[i] + head[i] - 1;
-    const int32_t gs = gstart[u];
-    const int64_t g0 = pc[gs];
-    if (head[i]) {
-      const int64_t c = pc[gstart[u + 1]] - g0;
-      big += c >= (1ll << 30);
-      ovf += c > 0x7fffffffll;
-      const int32_t c32 = c > 0x7fffffffll ? 0 : (int32_t)c;
-      ent[u] = make_int2(vbase + (int)(key & cmask), c32);
-      cap0[u] = c32;
+    const int32_t u = hx[i];
+    long long acc = 0;
+    int64_t j = i;
+    for (; j < mraw && j - i < GROUP_WALK && keys[j] == key; j++) {
+      const uint32_t pl = vals[j];
+      uid_of[pl] = u;
+      if (pl < E) {
+        pbefore_arc[pl] = acc > 0x7fffffffll ? 0 : (int32_t)acc;
+        acc += cap[pl];
+      }
     }
-    const uint32_t pl = vals[i];
-    if (pl < E) pbefore_arc[pl] = (int32_t)(pc[i] - g0);
+    if (j - i == GROUP_WALK && j < mraw && keys[j] == key) {
+      long_list[atomicAdd(&st->nlong, 1)] = (int32_t)i;  // at most N / GROUP_WALK of them
+      continue;
+    }
+    write_entry(u, key, cmask, vbase, acc, ent, cap0, &big, &ovf);
   }
   big = block_reduce_i32<false>(big);
   ovf = block_reduce_i32<false>(ovf);
+  if (threadIdx.x == 0) {
+    if (big) atomicAdd(&st->big, big);
+    if (ovf) atomicAdd(&st->overflow, ovf);
+  }
+}
+
+// Exclusive prefix sum over the workgroup (BT threads); total in *total.
+__device__ long long block_excl_scan(long long x, long long *total) {
+  __shared__ long long s_w[BT / WB_WAVE];
+  long long incl = x;
+#pragma unroll
+  for (int o = 1; o < WB_WAVE; o <<= 1) {
+    const unsigned long long y = shfl_u64((unsigned long long)incl, lane() >= o ? lane() - o : lane());
+    if (lane() >= o) incl += (long long)y;
+  }
+  __syncthreads();  // s_w may still be read by a previous call
+  if (lane() == WB_WAVE - 1) s_w[threadIdx.x / WB_WAVE] = incl;
+  __syncthreads();
+  long long before = 0, all = 0;
+  for (int w = 0; w < BT / WB_WAVE; w++) {
+    if (w < (int)(threadIdx.x / WB_WAVE)) before += s_w[w];
+    all += s_w[w];
+  }
+  *total = all;
+  return before + incl - x;
+}
+
+// Step 3b'.  Long groups, one workgroup each: tiles of BT items, a block
+// prefix sum of the forward capacities, the running total carried over.
+__global__ void __launch_bounds__(BT) k_long_groups(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb,
+                                                    bool inline_self, const int32_t *cap, BuildStatus *st,
+                                                    const int32_t *hx, int32_t vbase, int2 *ent, int32_t *cap0,
+                                                    int32_t *uid_of, int32_t *pbefore_arc, const int32_t *long_list) {
+  const int64_t mraw = inline_self ? N : N - 2 * (int64_t)st->nself;
+  const int32_t nlong = st->nlong;
+  const uint32_t E = (uint32_t)(N / 2);
+  const uint64_t cmask = (1ull << vb) - 1;
+  int big = 0, ovf = 0;
+  for (int32_t gi = blockIdx.x; gi < nlong; gi += gridDim.x) {  // workgroup-uniform
+    const int64_t i0 = long_list[gi];
+    const uint64_t key = keys[i0];
+    const int32_t u = hx[i0];
+    long long carry = 0;
+    for (int64_t base = i0;; base += BT) {
+      const int64_t j = base + threadIdx.x;
+      const bool in = j < mraw && keys[j] == key;  // the group is one contiguous run
+      const uint32_t pl = in ? vals[j] : 0;
+      const bool fwd = in && pl < E;
+      long long tile = 0;
+      const long long pre = block_excl_scan(fwd ? (long long)cap[pl] : 0, &tile);
+      if (in) {
+        uid_of[pl] = u;
+        if (fwd) pbefore_arc[pl] = carry + pre > 0x7fffffffll ? 0 : (int32_t)(carry + pre);
+      }
+      carry += tile;
+      if (__syncthreads_or(!in)) break;
+    }
+    if (threadIdx.x == 0) write_entry(u, key, cmask, vbase, carry, ent, cap0, &big, &ovf);
+  }
   if (threadIdx.x == 0) {
     if (big) atomicAdd(&st->big, big);
     if (ovf) atomicAdd(&st->overflow, ovf);
@@ -456,12 +501,10 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
   hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(BT), 0, st, keys, N, vb, inline_self, status_dev, s.head);
   e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_unique, dim3(grid_for(N + 1)), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev,
-                     s.head, s.hx, s.gstart, s.uid_of, s.pcap);
-  e = excl_scan_i64(s.pcap, s.pcap, N + 1, nullptr, s.stemp64, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_group_caps, dim3(grid_for(N)), dim3(BT), 0, st, keys, vb, inline_self, vals, status_dev, s.head,
-                     s.hx, s.gstart, s.pcap, pl.vbase, ent, cap0, pbefore, N);
+  hipLaunchKernelGGL(k_groups, dim3(grid_for(N)), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev,
+                     s.head, s.hx, pl.vbase, ent, cap0, s.uid_of, pbefore, s.gstart);
+  hipLaunchKernelGGL(k_long_groups, dim3(256), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev, s.hx,
+                     pl.vbase, ent, cap0, s.uid_of, pbefore, s.gstart);
   hipLaunchKernelGGL(k_rowptr, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, N, vb, inline_self, V,
                      status_dev, s.hx, s.rptr);
   hipLaunchKernelGGL(k_rowb, dim3(grid_for(V)), dim3(BT), 0, st, s.rptr, V, pl.vbase, (int32_t)pl.mbase, A.rowb);

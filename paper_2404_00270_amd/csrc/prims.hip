@@ -130,9 +130,6 @@ static hipError_t scan_impl(const TI *in, TO *out, int64_t n, TO *total, TO *tem
 hipError_t excl_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, int32_t *temp, hipStream_t st) {
   return scan_impl<int32_t, int32_t>(in, out, n, total, temp, st);
 }
-hipError_t excl_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, int64_t *temp, hipStream_t st) {
-  return scan_impl<int64_t, int64_t>(in, out, n, total, temp, st);
-}
 
 // ------------------------------------------------------------- radix sort
 constexpr int RS_BITS = 8;

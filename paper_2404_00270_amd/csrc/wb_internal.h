@@ -10,7 +10,6 @@ namespace wb {
 // ---- primitives (prims.hip)
 int64_t scan_temp_elems(int64_t n);
 hipError_t excl_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *total, int32_t *temp, hipStream_t st);
-hipError_t excl_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, int64_t *temp, hipStream_t st);
 int64_t radix_hist_elems(int64_t n);
 // passes radix_sort_u64_u32 makes over `bits` key bits (for n > 1); an odd
 // count leaves the result in the alternate buffers
@@ -46,7 +45,8 @@ struct BuildStatus {
   int32_t big;        // entries whose summed capacity is at least 2^30 (only
                       // these can overflow int32 together with their mate)
   int32_t unsorted;   // rows whose columns are not non-decreasing
-  int32_t pad[2];
+  int32_t nlong;      // groups of equal keys too long for one thread to walk
+  int32_t pad;
 };
 
 // Device scratch needed by build_residual for V vertices and E arcs.

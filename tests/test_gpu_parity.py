@@ -97,6 +97,36 @@ def test_sorted_and_unsorted_rows(solver, V, E, seed):
         check_against_oracle(g, solver.solve(g), ref)
 
 
+@pytest.mark.parametrize("seed", [1, 2])
+def test_long_groups_of_parallel_arcs(solver, seed):
+    """Pairs joined by hundreds of parallel and antiparallel arcs (groups of
+    equal keys longer than one thread walks, up to several workgroup tiles)."""
+    rng = np.random.default_rng(seed)
+    V = 40
+    arcs = []
+    for (u, v), n in (((1, 2), 300), ((2, 1), 257), ((3, 4), 700), ((5, 6), 1500), ((6, 5), 40)):
+        arcs += [(u, v, int(c)) for c in rng.integers(0, 1000, n)]
+    for _ in range(400):
+        u, v = (int(x) for x in rng.integers(0, V, 2))
+        arcs.append((u, v, int(rng.integers(1, 5000))))
+    # route s -> the long pairs -> t so that their capacities matter
+    arcs += [(0, 1, 10**6), (0, 3, 10**6), (0, 5, 10**6), (2, V - 1, 10**6), (4, V - 1, 10**6), (6, V - 1, 10**6)]
+    order = rng.permutation(len(arcs))
+    g = W.from_arcs(V, [arcs[k] for k in order], 0, V - 1, f"long-groups-{seed}")
+    say(f"[long-groups] seed={seed} E={g.E}")
+    check_against_oracle(g, solver.solve(g))
+
+
+def test_long_group_overflow(solver):
+    from paper_2404_00270_amd import wbpr
+
+    # 600 parallel arcs of 2^22 sum past INT32_MAX; 500 of them do not
+    for n, code in ((600, wbpr.WBPR_EOVERFLOW), (500, wbpr.WBPR_OK)):
+        g = W.from_arcs(3, [(0, 1, 2**22)] * n + [(1, 2, 7)], 0, 2)
+        rc = wbpr.wbpr_solve(solver.ctx, g.V, g.row_ptr, g.col, g.cap, 0, 2, return_code=True)
+        assert rc == code, (n, rc)
+
+
 def test_degenerate_cases(solver):
     cases = [
         W.from_arcs(2, [], 0, 1, "no-arcs"),
