@@ -203,17 +203,30 @@ int wbpr_solve_device(wbpr_ctx *ctx, const wbpr_csr *dev_g, int32_t s, int32_t t
  * arrays [n] (local s, t).  Outputs are DEVICE arrays packed the same way:
  * dev_values int64[n] (required), dev_flows int32[sum E] and dev_sides
  * uint8[sum V] (nullable).  Limits: sum V < 2^30, 2 * sum E < 2^31.
- * Synchronous with respect to `stream` (NULL = the context's stream). */
+ * Synchronous with respect to `stream` (NULL = the context's stream).
+ *
+ * status (HOST int32[n], nullable): per-instance results.  NULL: any
+ * invalid instance fails the whole call with its code.  Non-NULL: an
+ * instance that fails its checks (WBPR_EINVAL: sizes, s/t, row pointers,
+ * columns, capacities; WBPR_EOVERFLOW: merged capacity over INT32_MAX) gets
+ * that code in status[i] and value 0, the others are solved and get
+ * WBPR_OK, and the call returns WBPR_OK unless the call itself failed (null
+ * arrays, negative sizes, which leave the packing undefined, or a device
+ * error).  When an instance fails a device check, the rest are solved one
+ * by one and `stats` is zeroed. */
 int wbpr_solve_batch_device(wbpr_ctx *ctx, int32_t n, const int32_t *V, const int64_t *E, const int32_t *s,
                             const int32_t *t, const int64_t *dev_row_ptr, const int32_t *dev_col,
                             const int32_t *dev_cap, void *stream, int64_t *dev_values, int32_t *dev_flows,
-                            uint8_t *dev_sides, wbpr_stats *stats);
+                            uint8_t *dev_sides, wbpr_stats *stats, int32_t *status);
 
 /* HOST variant: graphs[i] are host CSRs (copied before work starts),
  * s[i], t[i] local; values int64[n] (required); flows (nullable) holds n
- * pointers to int32[E_i]; sides (nullable) holds n pointers to uint8[V_i]. */
+ * pointers to int32[E_i]; sides (nullable) holds n pointers to uint8[V_i].
+ * status as above (an instance with null arrays is one more WBPR_EINVAL;
+ * the flows and sides of a failed instance are left untouched). */
 int wbpr_solve_batch(wbpr_ctx *ctx, int32_t n, const wbpr_csr *graphs, const int32_t *s, const int32_t *t,
-                     int64_t *values, int32_t *const *flows, uint8_t *const *sides, wbpr_stats *stats);
+                     int64_t *values, int32_t *const *flows, uint8_t *const *sides, wbpr_stats *stats,
+                     int32_t *status);
 
 /* ------------------------------------------------------------------------
  * Uploaded graphs: build the residual graph once, solve many (s, t) pairs.

@@ -334,83 +334,160 @@ int wbpr_solve(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int64_t *va
   return WBPR_OK;
 }
 
+namespace {
+
+// One instance of a packed device batch, solved alone (offsets into the
+// packed arrays).
+int solve_one_of(wbpr_ctx *c, int i, const int32_t *V, const int64_t *E, const int32_t *s, const int32_t *t,
+                 const int64_t *rp, const int32_t *col, const int32_t *cap, hipStream_t st, int64_t *values,
+                 int32_t *flows, uint8_t *sides, const std::vector<int64_t> &ro, const std::vector<int64_t> &eo,
+                 const std::vector<int64_t> &vo) {
+  wb::GroupInput in;
+  in.n = 1;
+  in.V = V + i;
+  in.E = E + i;
+  in.s = s + i;
+  in.t = t + i;
+  in.row_ptr = rp + ro[i];
+  in.col = col ? col + eo[i] : nullptr;
+  in.cap = cap ? cap + eo[i] : nullptr;
+  in.values = values + i;
+  in.flows = flows ? flows + eo[i] : nullptr;
+  in.sides = sides ? sides + vo[i] : nullptr;
+  return solve_group(c, in, st, nullptr);
+}
+
+}  // namespace
+
 int wbpr_solve_batch_device(wbpr_ctx *c, int32_t n, const int32_t *V, const int64_t *E, const int32_t *s,
                             const int32_t *t, const int64_t *dev_row_ptr, const int32_t *dev_col,
                             const int32_t *dev_cap, void *stream, int64_t *dev_values, int32_t *dev_flows,
-                            uint8_t *dev_sides, wbpr_stats *stats) {
+                            uint8_t *dev_sides, wbpr_stats *stats, int32_t *status) {
   if (!c) return fail(WBPR_EINVAL, "null context");
   if (n < 1) return fail(WBPR_EINVAL, "n must be at least 1");
   if (!V || !E || !s || !t || !dev_row_ptr || !dev_values) return fail(WBPR_EINVAL, "null argument");
   int64_t Et = 0;
+  bool all_ok = true;
+  for (int i = 0; i < n; i++)  // the packing itself needs every size
+    if (V[i] < 0 || E[i] < 0) return fail(WBPR_EINVAL, "instance " + std::to_string(i) + ": negative size");
   for (int i = 0; i < n; i++) {
     int rc = check_shape(V[i], E[i], s[i], t[i]);
     if (rc) {
-      g_err = "instance " + std::to_string(i) + ": " + g_err;
-      return rc;
+      if (!status) {
+        g_err = "instance " + std::to_string(i) + ": " + g_err;
+        return rc;
+      }
+      all_ok = false;
     }
+    if (status) status[i] = rc;
     Et += E[i];
   }
   if (Et > 0 && (!dev_col || !dev_cap)) return fail(WBPR_EINVAL, "null CSR array");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   hipStream_t st = stream ? (hipStream_t)stream : c->stream;
-  wb::GroupInput in;
-  in.n = n;
-  in.V = V;
-  in.E = E;
-  in.s = s;
-  in.t = t;
-  in.row_ptr = dev_row_ptr;
-  in.col = dev_col;
-  in.cap = dev_cap;
-  in.values = dev_values;
-  in.flows = dev_flows;
-  in.sides = dev_sides;
-  return solve_group(c, in, st, stats);
+  if (all_ok) {
+    wb::GroupInput in;
+    in.n = n;
+    in.V = V;
+    in.E = E;
+    in.s = s;
+    in.t = t;
+    in.row_ptr = dev_row_ptr;
+    in.col = dev_col;
+    in.cap = dev_cap;
+    in.values = dev_values;
+    in.flows = dev_flows;
+    in.sides = dev_sides;
+    const int rc = solve_group(c, in, st, stats);
+    if (!status || (rc != WBPR_EINVAL && rc != WBPR_EOVERFLOW)) return rc;
+    // an instance failed the device checks: find which by solving them alone
+  }
+  std::vector<int64_t> ro(n), eo(n), vo(n);
+  for (int i = 0, r = 0, x = 0, v = 0; i < n; i++) {
+    ro[i] = r;
+    eo[i] = x;
+    vo[i] = v;
+    r += V[i] + 1;
+    x += E[i];
+    v += V[i];
+  }
+  for (int i = 0; i < n; i++) {
+    if (status[i] == WBPR_OK) {
+      const int rc = solve_one_of(c, i, V, E, s, t, dev_row_ptr, dev_col, dev_cap, st, dev_values, dev_flows,
+                                  dev_sides, ro, eo, vo);
+      if (rc != WBPR_OK && rc != WBPR_EINVAL && rc != WBPR_EOVERFLOW) return rc;
+      status[i] = rc;
+    }
+    if (status[i] != WBPR_OK) {
+      e = hipMemsetAsync(dev_values + i, 0, 8, st);
+      if (e != hipSuccess) return hip_fail(e, "batch output");
+    }
+  }
+  if (stats) *stats = wbpr_stats{};
+  e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return hip_fail(e, "batch");
+  return WBPR_OK;
 }
 
 int wbpr_solve_batch(wbpr_ctx *c, int32_t n, const wbpr_csr *graphs, const int32_t *s, const int32_t *t,
-                     int64_t *values, int32_t *const *flows, uint8_t *const *sides, wbpr_stats *stats) {
+                     int64_t *values, int32_t *const *flows, uint8_t *const *sides, wbpr_stats *stats,
+                     int32_t *status) {
   if (!c) return fail(WBPR_EINVAL, "null context");
   if (n < 1 || !graphs || !s || !t || !values) return fail(WBPR_EINVAL, "null argument");
-  std::vector<int32_t> V(n);
-  std::vector<int64_t> E(n);
+  // instances that pass the host checks are packed and solved together;
+  // with a status array the others are reported there and skipped
+  std::vector<int32_t> V, S, T, idx;
+  std::vector<int64_t> E;
   int64_t Vt = 0, Et = 0;
   for (int i = 0; i < n; i++) {
     const wbpr_csr &g = graphs[i];
     int rc = check_shape(g.V, g.E, s[i], t[i]);
+    if (!rc && (!g.row_ptr || (g.E > 0 && (!g.col || !g.cap)))) rc = fail(WBPR_EINVAL, "null CSR array");
+    if (!rc && flows && !flows[i]) rc = fail(WBPR_EINVAL, "flows given but flows[i] is null");
+    if (!rc && sides && !sides[i]) rc = fail(WBPR_EINVAL, "sides given but sides[i] is null");
     if (rc) {
-      g_err = "instance " + std::to_string(i) + ": " + g_err;
-      return rc;
+      if (!status) {
+        g_err = "instance " + std::to_string(i) + ": " + g_err;
+        return rc;
+      }
+      status[i] = rc;
+      values[i] = 0;
+      continue;
     }
-    if (!g.row_ptr || (g.E > 0 && (!g.col || !g.cap))) return fail(WBPR_EINVAL, "null CSR array");
-    if (flows && !flows[i]) return fail(WBPR_EINVAL, "flows given but flows[i] is null");
-    if (sides && !sides[i]) return fail(WBPR_EINVAL, "sides given but sides[i] is null");
-    V[i] = g.V;
-    E[i] = g.E;
+    idx.push_back(i);
+    V.push_back(g.V);
+    E.push_back(g.E);
+    S.push_back(s[i]);
+    T.push_back(t[i]);
     Vt += g.V;
     Et += g.E;
   }
-  if (Vt + n >= (1ll << 30) || 2 * Et >= (1ll << 31) - 1) return fail(WBPR_ETOOBIG, "batch exceeds the index limits");
+  const int m = (int)idx.size();
+  if (m == 0) {
+    if (stats) *stats = wbpr_stats{};
+    return WBPR_OK;
+  }
+  if (Vt + m >= (1ll << 30) || 2 * Et >= (1ll << 31) - 1) return fail(WBPR_ETOOBIG, "batch exceeds the index limits");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   const size_t Ec = (size_t)(Et > 0 ? Et : 1);
-  e = c->input.ensure(al(8 * (size_t)(Vt + n)) + 2 * al(4 * Ec));
-  if (e == hipSuccess) e = c->output.ensure(al(8 * (size_t)n) + al(4 * Ec) + al((size_t)Vt));
+  e = c->input.ensure(al(8 * (size_t)(Vt + m)) + 2 * al(4 * Ec));
+  if (e == hipSuccess) e = c->output.ensure(al(8 * (size_t)m) + al(4 * Ec) + al((size_t)Vt));
   if (e != hipSuccess) return hip_fail(e, "device allocation (staging)");
   char *ip = (char *)c->input.p;
   int64_t *d_rp = (int64_t *)ip;
-  int32_t *d_col = (int32_t *)(ip + al(8 * (size_t)(Vt + n)));
-  int32_t *d_cap = (int32_t *)(ip + al(8 * (size_t)(Vt + n)) + al(4 * Ec));
+  int32_t *d_col = (int32_t *)(ip + al(8 * (size_t)(Vt + m)));
+  int32_t *d_cap = (int32_t *)(ip + al(8 * (size_t)(Vt + m)) + al(4 * Ec));
   char *op = (char *)c->output.p;
   int64_t *d_val = (int64_t *)op;
-  int32_t *d_flow = (int32_t *)(op + al(8 * (size_t)n));
-  uint8_t *d_side = (uint8_t *)(op + al(8 * (size_t)n) + al(4 * Ec));
+  int32_t *d_flow = (int32_t *)(op + al(8 * (size_t)m));
+  uint8_t *d_side = (uint8_t *)(op + al(8 * (size_t)m) + al(4 * Ec));
   hipStream_t st = c->stream;
   int64_t ro = 0, eo = 0;
-  for (int i = 0; i < n && e == hipSuccess; i++) {
-    const wbpr_csr &g = graphs[i];
+  for (int k = 0; k < m && e == hipSuccess; k++) {
+    const wbpr_csr &g = graphs[idx[k]];
     e = hipMemcpyAsync(d_rp + ro, g.row_ptr, 8 * ((size_t)g.V + 1), hipMemcpyHostToDevice, st);
     if (e == hipSuccess && g.E > 0) e = hipMemcpyAsync(d_col + eo, g.col, 4 * (size_t)g.E, hipMemcpyHostToDevice, st);
     if (e == hipSuccess && g.E > 0) e = hipMemcpyAsync(d_cap + eo, g.cap, 4 * (size_t)g.E, hipMemcpyHostToDevice, st);
@@ -418,23 +495,32 @@ int wbpr_solve_batch(wbpr_ctx *c, int32_t n, const wbpr_csr *graphs, const int32
     eo += g.E;
   }
   if (e != hipSuccess) return hip_fail(e, "host to device copy");
-  int rc = wbpr_solve_batch_device(c, n, V.data(), E.data(), s, t, d_rp, d_col, d_cap, st, d_val,
-                                   flows ? d_flow : nullptr, sides ? d_side : nullptr, stats);
+  std::vector<int32_t> sub(m, 0);
+  int rc = wbpr_solve_batch_device(c, m, V.data(), E.data(), S.data(), T.data(), d_rp, d_col, d_cap, st, d_val,
+                                   flows ? d_flow : nullptr, sides ? d_side : nullptr, stats,
+                                   status ? sub.data() : nullptr);
   if (rc) return rc;
-  e = hipMemcpyAsync(values, d_val, 8 * (size_t)n, hipMemcpyDeviceToHost, st);
+  std::vector<int64_t> hv(m);
+  e = hipMemcpyAsync(hv.data(), d_val, 8 * (size_t)m, hipMemcpyDeviceToHost, st);
   int64_t vo = 0;
   eo = 0;
-  for (int i = 0; i < n && e == hipSuccess; i++) {
-    if (flows && E[i] > 0) e = hipMemcpyAsync(flows[i], d_flow + eo, 4 * (size_t)E[i], hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess && sides) e = hipMemcpyAsync(sides[i], d_side + vo, (size_t)V[i], hipMemcpyDeviceToHost, st);
-    vo += V[i];
-    eo += E[i];
+  for (int k = 0; k < m && e == hipSuccess; k++) {
+    const int i = idx[k];
+    if (sub[k] == WBPR_OK) {
+      if (flows && E[k] > 0) e = hipMemcpyAsync(flows[i], d_flow + eo, 4 * (size_t)E[k], hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess && sides) e = hipMemcpyAsync(sides[i], d_side + vo, (size_t)V[k], hipMemcpyDeviceToHost, st);
+    }
+    vo += V[k];
+    eo += E[k];
   }
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return hip_fail(e, "device to host copy");
+  for (int k = 0; k < m; k++) {
+    values[idx[k]] = hv[k];
+    if (status) status[idx[k]] = sub[k];
+  }
   return WBPR_OK;
 }
-
 
 }  // extern "C"
 

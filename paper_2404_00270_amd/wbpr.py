@@ -210,10 +210,10 @@ def load_library(path: str = LIB_PATH):
                                       ctypes.POINTER(wbpr_stats)]
     lib.wbpr_solve_batch.restype = ctypes.c_int
     lib.wbpr_solve_batch.argtypes = [vp, i32, ctypes.POINTER(wbpr_csr), vp, vp, vp, vp, vp,
-                                     ctypes.POINTER(wbpr_stats)]
+                                     ctypes.POINTER(wbpr_stats), vp]
     lib.wbpr_solve_batch_device.restype = ctypes.c_int
     lib.wbpr_solve_batch_device.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp,
-                                            ctypes.POINTER(wbpr_stats)]
+                                            ctypes.POINTER(wbpr_stats), vp]
     lib.wbpr_graph_upload.restype = ctypes.c_int
     lib.wbpr_graph_upload.argtypes = [vp, ctypes.POINTER(wbpr_csr), ctypes.POINTER(ctypes.c_void_p)]
     lib.wbpr_graph_solve.restype = ctypes.c_int
@@ -404,11 +404,14 @@ class BatchResult:
     flows: list | None           # n arrays int32[E_i]
     sides: list | None           # n arrays uint8[V_i]
     stats: dict
+    status: np.ndarray | None = None  # int32[n] per-instance codes (per_instance=True)
 
 
 def wbpr_solve_batch(ctx: int, graphs, want_flow: bool = True, want_side: bool = True,
-                     return_code: bool = False):
-    """Batched solve from host graphs (objects with V, row_ptr, col, cap, s, t)."""
+                     return_code: bool = False, per_instance: bool = False):
+    """Batched solve from host graphs (objects with V, row_ptr, col, cap, s, t).
+    per_instance: invalid instances get their own status code (and value 0)
+    instead of failing the call."""
     lib = load_library()
     n = len(graphs)
     keep = []
@@ -428,20 +431,23 @@ def wbpr_solve_batch(ctx: int, graphs, want_flow: bool = True, want_side: bool =
     fp = (ctypes.c_void_p * n)(*[f.ctypes.data for f in flows]) if flows is not None else None
     sp = (ctypes.c_void_p * n)(*[x.ctypes.data for x in sides]) if sides is not None else None
     st = wbpr_stats()
+    status = np.zeros(n, np.int32) if per_instance else None
     rc = lib.wbpr_solve_batch(ctx, n, arr, s.ctypes.data, t.ctypes.data, values.ctypes.data,
                               ctypes.cast(fp, ctypes.c_void_p) if fp is not None else None,
-                              ctypes.cast(sp, ctypes.c_void_p) if sp is not None else None, ctypes.byref(st))
+                              ctypes.cast(sp, ctypes.c_void_p) if sp is not None else None, ctypes.byref(st),
+                              status.ctypes.data if status is not None else None)
     if return_code:
         return rc
     _check(rc)
     if flows is not None:
         flows = [f[: int(np.asarray(g.col).shape[0])] for f, g in zip(flows, graphs)]
-    return BatchResult(values, flows, sides, st.as_dict())
+    return BatchResult(values, flows, sides, st.as_dict(), status)
 
 
 def wbpr_solve_batch_device(ctx: int, V, E, s, t, row_ptr_ptr: int, col_ptr: int, cap_ptr: int, stream: int,
-                            values_ptr: int, flows_ptr: int | None, sides_ptr: int | None) -> dict:
-    """Batched solve from packed device arrays; V, E, s, t are host sequences."""
+                            values_ptr: int, flows_ptr: int | None, sides_ptr: int | None, status=None) -> dict:
+    """Batched solve from packed device arrays; V, E, s, t are host sequences.
+    status: optional host int32 numpy array [n] for per-instance codes."""
     lib = load_library()
     n = len(V)
     Va = np.ascontiguousarray(V, dtype=np.int32)
@@ -451,7 +457,8 @@ def wbpr_solve_batch_device(ctx: int, V, E, s, t, row_ptr_ptr: int, col_ptr: int
     st = wbpr_stats()
     _check(lib.wbpr_solve_batch_device(ctx, n, Va.ctypes.data, Ea.ctypes.data, sa.ctypes.data, ta.ctypes.data,
                                        row_ptr_ptr, col_ptr or None, cap_ptr or None, stream or None, values_ptr,
-                                       flows_ptr or None, sides_ptr or None, ctypes.byref(st)))
+                                       flows_ptr or None, sides_ptr or None, ctypes.byref(st),
+                                       status.ctypes.data if status is not None else None))
     return st.as_dict()
 
 
@@ -503,8 +510,9 @@ class Solver:
         rec = rec[: n.value].astype(np.int64)
         return np.stack([rec[:, 0] >> 2, rec[:, 0] & 3, rec[:, 1], rec[:, 2], rec[:, 3]], axis=1)
 
-    def solve_batch(self, graphs, want_flow: bool = True, want_side: bool = True) -> BatchResult:
-        return wbpr_solve_batch(self.ctx, graphs, want_flow, want_side)
+    def solve_batch(self, graphs, want_flow: bool = True, want_side: bool = True,
+                    per_instance: bool = False) -> BatchResult:
+        return wbpr_solve_batch(self.ctx, graphs, want_flow, want_side, per_instance=per_instance)
 
     def solve_tensors(self, V, row_ptr, col, cap, s, t, value, flow=None, side=None) -> dict:
         """Device-resident solve on torch tensors (torch supplies the memory).

@@ -159,6 +159,81 @@ def test_batch_bad_instance_rejected(solver):
     _check_batch(gs, solver.solve_batch(gs))
 
 
+def _faulty(gs):
+    """Copies of valid instances with one defect each, and the code each must get."""
+    from paper_2404_00270_amd import wbpr
+
+    b = gs[0] if gs[0].E else W.multigraph(10, 30, seed=5)
+    col = b.col.copy()
+    col[0] = b.V  # in range for the union of the batch, not for its own instance
+    cap = b.cap.copy()
+    cap[-1] = -3
+    return [
+        (W.Graph(b.V, b.row_ptr, col, b.cap, b.s, b.t, "bad-col"), wbpr.WBPR_EINVAL),
+        (W.Graph(b.V, b.row_ptr, b.col, b.cap, b.s, b.s, "s==t"), wbpr.WBPR_EINVAL),
+        (W.Graph(b.V, b.row_ptr, b.col, cap, b.s, b.t, "negative-cap"), wbpr.WBPR_EINVAL),
+        (W.from_arcs(3, [(0, 1, 2**31 - 1), (1, 0, 5), (1, 2, 4)], 0, 2, "overflow"), wbpr.WBPR_EOVERFLOW),
+    ]
+
+
+def test_batch_per_instance_status(solver):
+    good = _mixed_batch(43, n_small=4, n_stream=3)
+    bad = _faulty(good)
+    mixed = list(good)
+    for k, (g, _) in enumerate(bad):
+        mixed.insert(2 * k + 1, g)
+    codes = {id(g): c for g, c in bad}
+    say(f"[batch-status] n={len(mixed)}")
+    res = solver.solve_batch(mixed, per_instance=True)
+    for i, g in enumerate(mixed):
+        if id(g) in codes:
+            assert res.status[i] == codes[id(g)], (g.name, res.status[i])
+            assert res.values[i] == 0
+        else:
+            assert res.status[i] == 0, (g.name, res.status[i])
+            value, side, _ = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+            assert res.values[i] == value and np.array_equal(res.sides[i], side), g.name
+            c = oracle.check(g.V, g.row_ptr, g.col, g.cap, g.s, g.t, res.flows[i])
+            assert c.feasible and c.value == value
+    # all valid: one group, every status 0
+    res = solver.solve_batch(good, per_instance=True)
+    assert (res.status == 0).all()
+    _check_batch(good, res)
+
+
+def test_batch_device_per_instance_status(solver):
+    import torch
+
+    from paper_2404_00270_amd import wbpr
+
+    good = _mixed_batch(44, n_small=3, n_stream=2)
+    bad = _faulty(good)
+    gs = [good[0], bad[0][0], good[1], bad[3][0]] + good[2:]
+    want = [0, wbpr.WBPR_EINVAL, 0, wbpr.WBPR_EOVERFLOW] + [0] * (len(good) - 2)
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(np.concatenate([g.row_ptr for g in gs]).astype(np.int64)).to(dev)
+    col = torch.from_numpy(np.concatenate([g.col for g in gs]).astype(np.int32)).to(dev)
+    cap = torch.from_numpy(np.concatenate([g.cap for g in gs]).astype(np.int32)).to(dev)
+    n = len(gs)
+    values = torch.zeros(n, dtype=torch.int64, device=dev)
+    sides = torch.zeros(sum(g.V for g in gs), dtype=torch.uint8, device=dev)
+    status = np.full(n, -1, np.int32)
+    torch.cuda.synchronize()
+    wbpr.wbpr_solve_batch_device(solver.ctx, [g.V for g in gs], [g.E for g in gs], [g.s for g in gs],
+                                 [g.t for g in gs], rp.data_ptr(), col.data_ptr(), cap.data_ptr(), 0,
+                                 values.data_ptr(), 0, sides.data_ptr(), status=status)
+    torch.cuda.synchronize()
+    assert status.tolist() == want
+    hv, hs = values.cpu().numpy(), sides.cpu().numpy()
+    vo = np.cumsum([0] + [g.V for g in gs])
+    for i, g in enumerate(gs):
+        if want[i] == 0:
+            value, side, _ = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+            assert hv[i] == value and np.array_equal(hs[vo[i]:vo[i + 1]], side), g.name
+        else:
+            assert hv[i] == 0
+
+
 def test_batch_device_packed_torch(solver):
     import torch
 
