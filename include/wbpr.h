@@ -121,6 +121,12 @@ typedef struct wbpr_options {
                                   its execution time and work (the per-warp
                                   timing of the paper's workload analysis,
                                   section 5); read with wbpr_wave_trace */
+    int32_t lds_max_v;         /* instances of at most this many vertices
+                                  whose residual graph fits one workgroup's
+                                  LDS (8 bytes per entry + 20 per vertex,
+                                  up to 65,535 of each) are solved whole by
+                                  one workgroup at admission, without rounds
+                                  of launches (0 = 1024, negative = never) */
 } wbpr_options;
 
 /* Per-solve counters and timings (filled when a non-NULL pointer is given). */
@@ -152,6 +158,7 @@ typedef struct wbpr_stats {
     int64_t bfs_topdown_scans;     /* share of bfs_scans examined top-down */
     int32_t instances;             /* instances solved by the call */
     int32_t use_graph;             /* sweep batches replayed as a hipGraph */
+    int64_t lds_solved;            /* instances solved whole in LDS (lds_max_v) */
 } wbpr_stats;
 
 typedef struct wbpr_ctx wbpr_ctx;

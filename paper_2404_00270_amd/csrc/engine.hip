@@ -85,6 +85,7 @@ struct InstDev {
 
 enum InstKernel {
   IK_INIT = 0, IK_PREFLOW, IK_VALUE_ZERO, IK_VALUE, IK_SIDE, IK_PHASE2, IK_DECODE, IK_RELEASE, IK_PARK, IK_MAXDEG,
+  IK_SMALL,  // list slice of the LDS-resident solve (k_small_solve, not k_inst)
   IK_COUNT
 };
 
@@ -103,6 +104,185 @@ struct InstArgs {
   const int32_t *slot;  // [n] instance slot of list entry i (IK_INIT)
   int32_t *maxdeg;      // [n] longest row of list entry i, terminals excluded (IK_MAXDEG)
 };
+
+// Whole solve of one small instance by one workgroup, its residual graph in
+// LDS (the batched pattern for instances of up to about a thousand
+// vertices): starts from the preflow state in the arena, alternates a BFS
+// from the phase's target (exact heights, as the global relabel) with sweeps
+// of single pushes or relabels (Algorithms 1-2, one thread per active
+// vertex, LDS atomics), writes the value and the sink side when phase 1
+// ends, returns stranded excess to s when flows are wanted (phase 2), and
+// writes the final residuals back for the flow decode.  result[i]: 1 solved,
+// 0 not taken (does not fit the LDS budget), 2 gave up at the round cap.
+constexpr int SMALL_THREADS = 1024;
+
+struct SmallArgs {
+  const InstDev *L;
+  const int2 *rowb;
+  int2 *ent;
+  const int32_t *rev;
+  const int32_t *cap0;
+  long long *e;
+  int32_t *h;
+  int32_t *result;
+  int32_t lds_bytes;
+};
+
+__device__ __forceinline__ size_t small_al(size_t x) { return (x + 15) & ~(size_t)15; }
+
+__global__ void __launch_bounds__(SMALL_THREADS) k_small_solve(SmallArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  __shared__ int32_t s_cnt[2];
+  __shared__ long long s_part[SMALL_THREADS / WB_WAVE];
+  const InstDev d = a.L[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int32_t V = d.V;
+  const int64_t mb = a.rowb[d.vbase].x;
+  const int64_t M = (int64_t)a.rowb[d.vbase + V - 1].y - mb;
+  // LDS: row starts, excess, heights, two vertex lists, residuals, columns, mates
+  const size_t need = small_al(4 * ((size_t)V + 1)) + small_al(8 * (size_t)V) + small_al(4 * (size_t)V) +
+                      2 * small_al(2 * (size_t)V) + small_al(4 * (size_t)M) + 2 * small_al(2 * (size_t)M);
+  if (V > 65535 || M > 65535 || need > (size_t)a.lds_bytes) {  // uniform over the workgroup
+    if (tid == 0) a.result[blockIdx.x] = 0;
+    return;
+  }
+  unsigned char *p = lds;
+  int32_t *rp = (int32_t *)p;           p += small_al(4 * ((size_t)V + 1));
+  long long *ex = (long long *)p;       p += small_al(8 * (size_t)V);
+  int32_t *ht = (int32_t *)p;           p += small_al(4 * (size_t)V);
+  uint16_t *qa = (uint16_t *)p;         p += small_al(2 * (size_t)V);
+  uint16_t *qb = (uint16_t *)p;         p += small_al(2 * (size_t)V);
+  int32_t *res = (int32_t *)p;          p += small_al(4 * (size_t)M);
+  uint16_t *col = (uint16_t *)p;        p += small_al(2 * (size_t)M);
+  uint16_t *rv = (uint16_t *)p;
+  const int32_t ss = d.s - d.vbase, tt = d.t - d.vbase;
+  for (int32_t x = tid; x < V; x += SMALL_THREADS) {
+    rp[x] = (int32_t)(a.rowb[d.vbase + x].x - mb);
+    ex[x] = (x == ss || x == tt) ? 0 : a.e[d.vbase + x];
+  }
+  if (tid == 0) rp[V] = (int32_t)M;
+  for (int64_t k = tid; k < M; k += SMALL_THREADS) {
+    const int2 c = a.ent[mb + k];
+    col[k] = (uint16_t)(c.x - d.vbase);
+    res[k] = c.y;
+    rv[k] = (uint16_t)(a.rev[mb + k] - mb);
+  }
+  __syncthreads();
+  const bool two_phases = d.flow != nullptr;
+  const int32_t round_cap = 4 * V + 1024, sweep_cap = V + 16;
+  int phase = 1, rounds = 0;
+  bool ok = true;
+  for (;;) {  // every branch below is uniform over the workgroup
+    const int32_t target = phase == 1 ? tt : ss, other = phase == 1 ? ss : tt;
+    // exact heights: BFS from the target over arcs v -> w with residual > 0
+    for (int32_t x = tid; x < V; x += SMALL_THREADS) ht[x] = x == target ? 0 : (x == other ? V + 1 : V);
+    if (tid == 0) {
+      qa[0] = (uint16_t)target;
+      s_cnt[0] = 1;
+    }
+    __syncthreads();
+    uint16_t *fa = qa, *fb = qb;
+    int32_t nq = s_cnt[0];
+    for (int32_t lev = 1; nq > 0; lev++) {
+      __syncthreads();
+      if (tid == 0) s_cnt[0] = 0;
+      __syncthreads();
+      for (int32_t i = tid; i < nq; i += SMALL_THREADS) {
+        const int32_t w = fa[i];
+        for (int32_t k = rp[w]; k < rp[w + 1]; k++) {
+          const int32_t v = col[k];
+          if (ht[v] == V && res[rv[k]] > 0 && atomicCAS(&ht[v], V, lev) == V) fb[atomicAdd(&s_cnt[0], 1)] = (uint16_t)v;
+        }
+      }
+      __syncthreads();
+      nq = s_cnt[0];
+      uint16_t *tq = fa;
+      fa = fb;
+      fb = tq;
+    }
+    __syncthreads();
+    // active vertices: excess and a path to the target
+    if (tid == 0) s_cnt[1] = 0;
+    __syncthreads();
+    for (int32_t x = tid; x < V; x += SMALL_THREADS)
+      if (x != ss && x != tt && ex[x] > 0 && ht[x] < V) qa[atomicAdd(&s_cnt[1], 1)] = (uint16_t)x;
+    __syncthreads();
+    int32_t na = s_cnt[1];
+    if (na == 0) {
+      if (phase == 1) {
+        // maximum preflow: sink side = vertices that still reach t; value =
+        // flow into t = sum over t's row of (residual - initial capacity)
+        if (d.side)
+          for (int32_t x = tid; x < V; x += SMALL_THREADS) d.side[x] = ht[x] < V ? 1 : 0;
+        long long acc = 0;
+        for (int32_t k = rp[tt] + tid; k < rp[tt + 1]; k += SMALL_THREADS)
+          acc += (long long)res[k] - (long long)a.cap0[mb + k];
+        acc = group_sum_i64<WB_WAVE>(acc);
+        if (lane() == 0) s_part[tid / WB_WAVE] = acc;
+        __syncthreads();
+        if (tid == 0 && d.value) {
+          long long tot = 0;
+          for (int w = 0; w < SMALL_THREADS / WB_WAVE; w++) tot += s_part[w];
+          *d.value = tot;
+        }
+        if (!two_phases) break;
+        phase = 2;  // return stranded excess to s
+        continue;
+      }
+      break;
+    }
+    if (++rounds > round_cap) {
+      ok = false;
+      break;
+    }
+    // sweeps: one push to the lowest residual neighbour, else a relabel
+    for (int32_t sw = 0; sw < sweep_cap && na > 0; sw++) {
+      for (int32_t i = tid; i < na; i += SMALL_THREADS) {
+        const int32_t u = qa[i];
+        const long long eu = ex[u];
+        const int32_t hu = ht[u];
+        if (eu <= 0 || hu >= V) continue;
+        int32_t hmin = 0x7fffffff, kmin = -1;
+        for (int32_t k = rp[u]; k < rp[u + 1]; k++)
+          if (res[k] > 0) {
+            const int32_t hv = ht[col[k]];
+            if (hv < hmin) {
+              hmin = hv;
+              kmin = k;
+            }
+          }
+        if (kmin < 0) continue;
+        if (hu > hmin) {
+          const int32_t r = res[kmin];
+          const int32_t dd = (int32_t)(eu < (long long)r ? eu : (long long)r);
+          atomicSub(&res[kmin], dd);
+          atomicAdd(&res[rv[kmin]], dd);
+          atomicAdd((unsigned long long *)&ex[u], (unsigned long long)(-(long long)dd));
+          atomicAdd((unsigned long long *)&ex[col[kmin]], (unsigned long long)(long long)dd);
+        } else {
+          ht[u] = hmin + 1 < V ? hmin + 1 : V;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_cnt[1] = 0;
+      __syncthreads();
+      for (int32_t x = tid; x < V; x += SMALL_THREADS)
+        if (x != ss && x != tt && ex[x] > 0 && ht[x] < V) qa[atomicAdd(&s_cnt[1], 1)] = (uint16_t)x;
+      __syncthreads();
+      na = s_cnt[1];
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  if (ok) {
+    for (int64_t k = tid; k < M; k += SMALL_THREADS) a.ent[mb + k].y = res[k];
+    for (int32_t x = tid; x < V; x += SMALL_THREADS) {
+      a.e[d.vbase + x] = x == tt ? WB_EXCESS_BIAS : 0;
+      a.h[d.vbase + x] = HCAP;
+    }
+  }
+  if (tid == 0) a.result[blockIdx.x] = ok ? 1 : 2;
+}
 
 // blockIdx.y selects the instance of the list; blockIdx.x strides its range.
 __global__ void k_inst(InstArgs a, int which) {
@@ -579,6 +759,80 @@ void Engine::launch_inst_list(int which, const std::vector<InstDev> &list, const
   }
 }
 
+// Small instances of a freshly started group are solved whole, one
+// workgroup each with the residual graph in LDS; they are then retired by the
+// next round like any finished instance.  Those that do not fit stay with
+// the rounds, untouched.
+int Engine::solve_small(const std::vector<int> &slots, hipStream_t st, std::string *err) {
+  if (cfg_.lds_max_v < 0 || small_lds_ < 0) return 0;
+  const int vmax = cfg_.lds_max_v > 0 ? cfg_.lds_max_v : 1024;
+  std::vector<int> cand;
+  for (int sl : slots)
+    if (inst_[sl].V <= vmax) cand.push_back(sl);
+  if (cand.empty()) return 0;
+  if (small_lds_ == 0) {  // first use: the largest LDS a workgroup may have, less the static part
+    int dev_max = 0;
+    if (hipDeviceGetAttribute(&dev_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device_) != hipSuccess ||
+        dev_max - 2048 < 32768 ||
+        hipFuncSetAttribute((const void *)k_small_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            dev_max - 2048) != hipSuccess) {
+      hipGetLastError();
+      small_lds_ = -1;  // no LDS-resident path on this device
+      return 0;
+    }
+    small_lds_ = dev_max - 2048;
+  }
+  const int n = (int)cand.size();
+  InstDev *hl = reinterpret_cast<InstDev *>(pin_ + kPinnedHeader) + (size_t)IK_SMALL * ncap_;
+  InstDev *dl = reinterpret_cast<InstDev *>(inst_list_) + (size_t)IK_SMALL * ncap_;
+  for (int i = 0; i < n; i++) {
+    const Inst &I = inst_[cand[i]];
+    InstDev d;
+    d.vbase = I.vbase;
+    d.V = I.V;
+    d.s = I.s;
+    d.t = I.t;
+    d.abase = I.abase;
+    d.E = I.E;
+    d.value = (long long *)I.value;
+    d.flow = I.flow;
+    d.side = I.side;
+    hl[i] = d;
+  }
+  hipError_t e = hipMemcpyAsync(dl, hl, sizeof(InstDev) * n, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) {
+    *err = std::string("small solve: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  SmallArgs sa{dl, A_.rowb, A_.ent, A_.rev, A_.cap0, e_, h_, inst_stranded_, small_lds_};
+  hipLaunchKernelGGL(k_small_solve, dim3(n), dim3(SMALL_THREADS), small_lds_, st, sa);
+  int32_t *hres = reinterpret_cast<int32_t *>(pin_ + kPinnedHeader + sizeof(InstDev) * (size_t)ncap_ * kListKinds +
+                                              8 * (size_t)ncap_);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(hres, inst_stranded_, 4 * (size_t)n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    *err = std::string("small solve: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  std::vector<int> solved, decode;
+  for (int i = 0; i < n; i++) {
+    if (hres[i] == 2) {
+      *err = "LDS-resident solve of a small instance did not converge";
+      return WBPR_EINTERNAL;
+    }
+    if (hres[i] != 1) continue;
+    Inst &I = inst_[cand[i]];
+    solved.push_back(cand[i]);
+    if (I.flow) decode.push_back(cand[i]);
+    I.phase = 3;
+    I.pending_done = true;
+  }
+  launch_inst_kernel(IK_DECODE, decode, st);
+  acc_.small_solved += (int64_t)solved.size();
+  return 0;
+}
+
 int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
   if (in.n <= 0) return 0;
   if (in.keep && in.n != 1) {
@@ -757,6 +1011,8 @@ int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
   launch_inst_kernel(IK_INIT, slots, st);
   launch_inst_kernel(IK_PREFLOW, slots, st);
   int rc = measure_rows(slots, st, err);
+  if (rc) return rc;
+  rc = solve_small(slots, st, err);
   if (rc) return rc;
   e = hipGetLastError();
   if (e != hipSuccess) {
@@ -1329,6 +1585,12 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
     *err = std::string("launch: ") + hipGetErrorString(he);
     return WBPR_EDEVICE;
   }
+  // instances solved whole at admission retire with this round's
+  for (int i = 0; i < ncap_; i++)
+    if (inst_[i].used && inst_[i].pending_done) {
+      inst_[i].pending_done = false;
+      fin_done.push_back(i);
+    }
   // retire finished instances; release groups that have no instance left
   std::vector<int> empty_groups;
   std::vector<InstDev> parked;

@@ -32,6 +32,7 @@ struct SolveConfig {
   bool full_scan = false;     // rebuild the active queue by a full scan every sweep
   int gr_stagnation = 0;      // sweeps without a new smallest queue that end a round (0: by mean row length)
   bool wave_trace = false;    // per-wave execution time and work of every sweep launch
+  int lds_max_v = 0;          // instances up to this many vertices are solved in LDS (0: 1024, < 0: never)
 };
 
 // Counters of the engine since the last reset_stats().
@@ -40,6 +41,7 @@ struct EngineStats {
   int64_t sweeps = 0, phase2_sweeps = 0, global_relabels = 0, gr_levels = 0;
   int64_t arc_scans = 0, pushes = 0, relabels = 0, queued = 0, bfs_scans = 0, bfs_topdown_scans = 0;
   int64_t nonempty_sweeps = 0;
+  int64_t small_solved = 0;  // instances solved whole in LDS at admission
   // per kernel: 0 short-row tiles, 1 medium rows (one wave), 2 long rows (workgroup), 3 global relabel
   double k_ms[4] = {0, 0, 0, 0};
   int64_t k_launches[4] = {0, 0, 0, 0};
@@ -154,6 +156,7 @@ class Engine {
     int32_t vbase = 0, s = 0, t = 0;  // arena ids
     int64_t abase = 0;
     int phase = 0;  // 1: max preflow, 2: return excess to s, 3: done
+    bool pending_done = false;  // solved whole at admission, retired by the next round
     int32_t maxdeg = 0;  // longest row its sweeps can meet (terminals excluded)
     int group = -1;
     int32_t index = 0;
@@ -172,6 +175,8 @@ class Engine {
 
   int ensure_graph(hipStream_t st, int K, int tiers, hipGraphExec_t *exec, std::string *err);
   int measure_rows(const std::vector<int> &slots, hipStream_t st, std::string *err);
+  int solve_small(const std::vector<int> &slots, hipStream_t st, std::string *err);
+  int small_lds_ = 0;  // dynamic LDS bytes of the small-instance kernel (0: not yet set, -1: unavailable)
   void drop_graphs();
   void enqueue_sweeps(hipStream_t st, int K, int tiers);
   void launch_inst_kernel(int which, const std::vector<int> &slots, hipStream_t st);

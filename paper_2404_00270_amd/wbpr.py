@@ -69,6 +69,7 @@ class wbpr_options(ctypes.Structure):
         ("avq_mode", ctypes.c_int32),
         ("gr_stagnation", ctypes.c_int32),
         ("wave_trace", ctypes.c_int32),
+        ("lds_max_v", ctypes.c_int32),
     ]
 
 
@@ -108,6 +109,7 @@ class wbpr_stats(ctypes.Structure):
         ("bfs_topdown_scans", ctypes.c_int64),
         ("instances", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
+        ("lds_solved", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

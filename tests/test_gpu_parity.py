@@ -127,6 +127,46 @@ def test_long_group_overflow(solver):
         assert rc == code, (n, rc)
 
 
+@pytest.mark.parametrize("seed", range(0, 60, 4))
+def test_small_multigraphs_through_rounds(seed):
+    """The same small instances with the LDS-resident path off (rounds of launches)."""
+    from paper_2404_00270_amd import wbpr
+
+    rng = np.random.default_rng(seed)
+    V = int(rng.integers(2, 40))
+    E = int(rng.integers(0, 6 * V))
+    g = W.multigraph(V, E, cmax=int(rng.integers(0, 30)), seed=5000 + seed)
+    with wbpr.Solver(0, lds_max_v=-1, **WATCHDOG) as s:
+        r = s.solve(g)
+    assert r.stats["lds_solved"] == 0
+    check_against_oracle(g, r)
+
+
+def test_lds_resident_path(solver):
+    """Instances up to 1024 vertices that fit one workgroup's LDS are solved
+    whole by it; larger ones, or lds_max_v = -1, take the rounds."""
+    from paper_2404_00270_amd import wbpr
+
+    # the first fits even a 64 KiB budget; the others need the 160 KiB of a CU
+    for i, g in enumerate((W.random_graph(300, 2000, 1, 100, 76), W.random_graph(900, 7000, 1, 100, 77),
+                           W.config_plain(), W.grid(30, 30, seed=8), W.bipartite(300, 300, 3000, 2.1, 9))):
+        ref = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
+        r = solver.solve(g)
+        say(f"[lds] {g.name}: V={g.V} M={r.stats['M']} lds_solved={r.stats['lds_solved']} sweeps={r.stats['sweeps']}")
+        if i == 0:
+            assert r.stats["lds_solved"] == 1
+        check_against_oracle(g, r, ref)
+        v = solver.solve(g, want_flow=False)  # one phase only
+        assert v.value == ref[0] and np.array_equal(v.side, ref[1])
+    big = W.random_graph(5000, 40000, 1, 100, 78)
+    assert solver.solve(big).stats["lds_solved"] == 0
+    with wbpr.Solver(0, lds_max_v=100, **WATCHDOG) as s:
+        g = W.random_graph(500, 4000, 1, 100, 79)
+        r = s.solve(g)
+        assert r.stats["lds_solved"] == 0
+        check_against_oracle(g, r)
+
+
 def test_degenerate_cases(solver):
     cases = [
         W.from_arcs(2, [], 0, 1, "no-arcs"),
