@@ -70,6 +70,22 @@ def test_mixed_batch_matches_oracle(solver, seed):
     _check_batch(gs, res)
 
 
+def test_batch_of_small_instances_in_lds(solver):
+    """A batch of instances that all fit one workgroup's LDS, alone on the
+    device, is solved whole by one workgroup each (no rounds)."""
+    rng = np.random.default_rng(5)
+    gs = [W.multigraph(int(rng.integers(2, 60)), int(rng.integers(0, 300)), cmax=25, seed=600 + i) for i in range(20)]
+    gs += [W.batch_instance(100 + i, vmin=64, vmax=900) for i in range(12)]
+    say(f"[batch-lds] n={len(gs)}")
+    res = solver.solve_batch(gs)
+    assert res.stats["lds_solved"] == len(gs)
+    _check_batch(gs, res)
+    # with one larger instance the group takes the rounds
+    res = solver.solve_batch(gs + [W.batch_instance(7, vmin=2048, vmax=4096)])
+    assert res.stats["lds_solved"] == 0
+    _check_batch(gs + [W.batch_instance(7, vmin=2048, vmax=4096)], res)
+
+
 def test_batch_outputs_subsets(solver):
     gs = _mixed_batch(11)
     refs = [oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t) for g in gs]
