@@ -238,16 +238,38 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
   const int tbase = lane() & ~(P - 1);
   long long scans = 0, queued = 0, rwork = 0;
   int pushes = 0, relabels = 0;
-  for (int32_t base = wave * TPW; base < n; base += nwaves * TPW) {  // wave-uniform loop
+  // one row ahead: the tile's next queue entry is read while its current
+  // row is scanned, and the next row's bounds, height and excess before the
+  // current row's closing atomics (heights change only by the tile that
+  // visits the vertex; excess only grows until then, so the early read is a
+  // lower bound and the closing atomic returns the true remainder)
+  const int32_t stride = nwaves * TPW;
+  int32_t pu = 0, phu = 0;
+  int2 prb = make_int2(0, 0);
+  long long pe0 = 0;
+  {
+    const int32_t i0 = wave * TPW + sub;
+    if (i0 < n) {
+      pu = q.qin[i0];
+      prb = g.rowb[pu];
+      phu = g.h[pu];
+      if (tl == 0) pe0 = atomic_load_i64(&g.e[pu]);
+    }
+  }
+  for (int32_t base = wave * TPW; base < n; base += stride) {  // wave-uniform loop
     const int32_t i = base + sub;
     const bool valid = i < n;
-    int32_t u = 0, beg = 0, end = 0;
+    int32_t u = 0, beg = 0, end = 0, hpre = 0;
+    long long epre = 0;
     if (valid) {
-      u = q.qin[i];
-      const int2 rb = g.rowb[u];
-      beg = rb.x;
-      end = rb.y;
+      u = pu;
+      beg = prb.x;
+      end = prb.y;
+      hpre = phu;
+      epre = pe0;
     }
+    const int32_t ni = i + stride;
+    pu = ni < n ? q.qin[ni] : 0;
     const int32_t deg = end - beg;
     const bool split = valid && deg > q.t_mid;
     const bool scan = valid && !split;
@@ -275,6 +297,11 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
             }
           }
         }
+      }
+      if (ni < n) {
+        prb = g.rowb[pu];
+        phu = g.h[pu];
+        if (tl == 0) pe0 = atomic_load_i64(&g.e[pu]);
       }
       key = group_min<P>(key);
       bool app_v = false;
@@ -312,8 +339,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
       waveq_push(wq, q.append && app_v, v);
     } else {
       // full discharge; every lane of a scanning tile iterates the same count
-      const int32_t hu = scan ? g.h[u] : 0;
-      long long e0 = (scan && leader) ? atomic_load_i64(&g.e[u]) : 0;
+      const int32_t hu = scan ? hpre : 0;
+      long long e0 = (scan && leader) ? epre : 0;
       e0 = (long long)shfl_u64((unsigned long long)e0, tbase);
       long long erem = e0;
       unsigned long long key = WB_KEY_NONE;  // lowest residual entry not lower than u
@@ -360,6 +387,11 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
             erem -= tot;
           }
         }
+      }
+      if (ni < n) {
+        prb = g.rowb[pu];
+        phu = g.h[pu];
+        if (tl == 0) pe0 = atomic_load_i64(&g.e[pu]);
       }
       key = group_min<P>(key);
       if (leader && scan) {
