@@ -265,7 +265,7 @@ def ablation(workloads, dev, steps=2):
     ]
     out = []
     for name in workloads:
-        g = W.CONFIGS[name]()
+        g = W.WORKLOADS[name]()
         rp = torch.from_numpy(g.row_ptr).to(dev)
         col = torch.from_numpy(g.col).to(dev)
         cap = torch.from_numpy(g.cap).to(dev)
@@ -332,7 +332,7 @@ def wave_trace_study(workloads, dev):
                 ("VC, default schedule", {})]
     out = []
     for name in workloads:
-        g = W.CONFIGS[name]()
+        g = W.WORKLOADS[name]()
         rp = torch.from_numpy(g.row_ptr).to(dev)
         col = torch.from_numpy(g.col).to(dev)
         cap = torch.from_numpy(g.cap).to(dev)
@@ -360,7 +360,7 @@ def multi_terminal_study(workloads, pairs=20, seed=1, steps=2):
 
     out = []
     for name in workloads:
-        g = W.CONFIGS[name]()
+        g = W.WORKLOADS[name]()
         with wbpr.Solver(0, max_wall_ms=120_000) as solver:
             t0 = time.perf_counter()
             src, snk = solver.pick_terminals(g, pairs, seed)
@@ -441,7 +441,7 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": n, "copies": 3}), flush=True)
         return
     t0 = time.perf_counter()
-    g = W.CONFIGS[args.workload]()
+    g = W.WORKLOADS[args.workload]()
     log(f"[bench] generated {g.name}: V={g.V} E={g.E} in {time.perf_counter() - t0:.1f}s")
 
     rp = torch.from_numpy(g.row_ptr).to(dev)

@@ -189,7 +189,7 @@ def config_grid(seed: int = 4, W: int = 2048, H: int = 2048) -> Graph:
     return g
 
 
-CONFIGS = {
+WORKLOADS = {
     "plain": config_plain,
     "bipartite": config_bipartite,
     "rmat": config_rmat,

@@ -32,7 +32,7 @@ def main(names):
             data = json.load(f)
     for name in names:
         t0 = time.time()
-        g = W.CONFIGS[name]()
+        g = W.WORKLOADS[name]()
         value, side, cutcap = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
         data[name] = {
             "graph": g.name,

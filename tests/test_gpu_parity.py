@@ -338,7 +338,7 @@ def _golden():
 def test_full_size_workloads(solver, name):
     gold = _golden()[name]
     say(f"[full] generating {name}")
-    g = W.CONFIGS[name]()
+    g = W.WORKLOADS[name]()
     assert g.sha256() == gold["graph_sha256"], "workload generator drifted"
     say(f"[full] solving {name} V={g.V} E={g.E}")
     r = solver.solve(g)

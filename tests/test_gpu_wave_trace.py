@@ -72,7 +72,7 @@ def test_untraced_solve_reports_nothing():
 
 
 def test_vertex_centric_balances_waves_on_hubs():
-    g = W.CONFIGS["bipartite"]()
+    g = W.WORKLOADS["bipartite"]()
     ref = oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)[0]
     rv, tv = _solve_traced(g)
     rt, tt = _solve_traced(g, lanes_per_vertex=1)
