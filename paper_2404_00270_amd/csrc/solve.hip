@@ -56,20 +56,33 @@ __device__ __forceinline__ bool push_entry(const Graph &g, int32_t k, int32_t v,
   return oldv <= 0 && oldv + d > 0;
 }
 
+// Counters of a launch: summed per wave, then per workgroup in LDS, so each
+// workgroup makes at most one device atomic per counter (device atomics on
+// one address serialise).  Every thread of the workgroup calls it, at the end.
 __device__ __forceinline__ void flush_stats(long long *stats, long long scans, int pushes, int relabels, long long queued,
                                             long long *rwork_ctr, long long rwork) {
-  // one atomic per wave and counter
+  __shared__ unsigned long long s_acc[5];
   scans = (long long)group_sum_i64<WB_WAVE>(scans);
   long long p = group_sum_i64<WB_WAVE>((long long)pushes);
   long long r = group_sum_i64<WB_WAVE>((long long)relabels);
   queued = group_sum_i64<WB_WAVE>(queued);
   rwork = group_sum_i64<WB_WAVE>(rwork);
+  if (threadIdx.x < 5) s_acc[threadIdx.x] = 0;
+  __syncthreads();
   if (lane() == 0) {
-    if (scans) atomic_add_i64(&stats[0], scans);
-    if (p) atomic_add_i64(&stats[1], p);
-    if (r) atomic_add_i64(&stats[2], r);
-    if (queued) atomic_add_i64(&stats[3], queued);
-    if (rwork) atomic_add_i64(rwork_ctr, rwork);
+    if (scans) atomicAdd(&s_acc[0], (unsigned long long)scans);
+    if (p) atomicAdd(&s_acc[1], (unsigned long long)p);
+    if (r) atomicAdd(&s_acc[2], (unsigned long long)r);
+    if (queued) atomicAdd(&s_acc[3], (unsigned long long)queued);
+    if (rwork) atomicAdd(&s_acc[4], (unsigned long long)rwork);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_acc[0]) atomic_add_i64(&stats[0], (long long)s_acc[0]);
+    if (s_acc[1]) atomic_add_i64(&stats[1], (long long)s_acc[1]);
+    if (s_acc[2]) atomic_add_i64(&stats[2], (long long)s_acc[2]);
+    if (s_acc[3]) atomic_add_i64(&stats[3], (long long)s_acc[3]);
+    if (s_acc[4]) atomic_add_i64(rwork_ctr, (long long)s_acc[4]);
   }
 }
 
