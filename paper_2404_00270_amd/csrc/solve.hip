@@ -749,6 +749,29 @@ __device__ __forceinline__ void key_count_add(bool pred, int32_t key, KeyCount &
 // can only have residual arcs into distance-L vertices during step L (one at
 // distance L-2 would have made it distance L-1), so "code == code(L)" names
 // the frontier exactly.
+// Sums (x, y) over the workgroup in LDS; thread 0 adds the nonzero totals
+// to the device counters (one atomic per workgroup and counter instead of
+// one per wave).  Every thread of the workgroup calls it, converged.
+__device__ __forceinline__ void block_add2(int32_t x, long long y, int32_t *cx, long long *cy) {
+  __shared__ unsigned long long s2[2];
+  x = wave_sum_i32(x);
+  y = group_sum_i64<WB_WAVE>(y);
+  if (threadIdx.x == 0) {
+    s2[0] = 0;
+    s2[1] = 0;
+  }
+  __syncthreads();
+  if (lane() == 0) {
+    if (x) atomicAdd(&s2[0], (unsigned long long)x);
+    if (y) atomicAdd(&s2[1], (unsigned long long)y);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (cx && s2[0]) atomic_add_i32(cx, (int32_t)s2[0]);
+    if (s2[1]) atomic_add_i64(cy, (long long)s2[1]);
+  }
+}
+
 template <int P>
 __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   __shared__ int s_qbuf[GR_THREADS / WB_WAVE][WB_QBUF];
@@ -947,10 +970,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         }
       }
       // publish this phase's counts before the barrier
-      found_cnt = wave_sum_i32(found_cnt);
-      my_edges = group_sum_i64<WB_WAVE>(my_edges);
-      if (lane() == 0 && found_cnt) atomic_add_i32(&a.bucnt[(level + 1) % 3], found_cnt);
-      if (lane() == 0 && my_edges) atomic_add_i64(fe_out, my_edges);
+      block_add2(found_cnt, my_edges, &a.bucnt[(level + 1) % 3], fe_out);
       found_cnt = 0;
       my_edges = 0;
       grid_barrier(a.bar, nblocks);
@@ -988,10 +1008,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         }
       }
       if (nc > 0) {
-        found_cnt = wave_sum_i32(found_cnt);
-        my_edges = group_sum_i64<WB_WAVE>(my_edges);
-        if (lane() == 0 && found_cnt) atomic_add_i32(&a.bucnt[(level + 1) % 3], found_cnt);
-        if (lane() == 0 && my_edges) atomic_add_i64(fe_out, my_edges);
+        block_add2(found_cnt, my_edges, &a.bucnt[(level + 1) % 3], fe_out);
         grid_barrier(a.bar, nblocks);
       }
       n = min(atomic_load_i32(&a.bucnt[(level + 1) % 3]), a.qcap);
@@ -1058,8 +1075,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         }
       }
       waveq_flush(wq);
-      my_edges = group_sum_i64<WB_WAVE>(my_edges);
-      if (lane() == 0 && my_edges) atomic_add_i64(fe_out, my_edges);
+      block_add2(0, my_edges, nullptr, fe_out);
       my_edges = 0;
       grid_barrier(a.bar, nblocks);
       // phase B: one wave per chunk of a long row (skipped, with its barrier,
@@ -1088,8 +1104,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
       }
       if (nc > 0) {
         waveq_flush(wq);
-        my_edges = group_sum_i64<WB_WAVE>(my_edges);
-        if (lane() == 0 && my_edges) atomic_add_i64(fe_out, my_edges);
+        block_add2(0, my_edges, nullptr, fe_out);
         grid_barrier(a.bar, nblocks);
       }
       n = min(atomic_load_i32(fout_cnt), a.qcap);
