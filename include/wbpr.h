@@ -14,11 +14,14 @@
  * parallelism: each sweep compacts the active vertices (e(u) > 0,
  * h(u) < |V|) into an active-vertex queue, a group of lanes scans each queued
  * vertex's residual arcs in the bidirectional CSR (section 3.2) for the
- * minimum-height residual neighbour, and one lane pushes (atomic updates of
- * residuals and excesses) or relabels.  A global relabel (backward BFS from
- * the sink in the residual graph, section 2.2) resets heights periodically;
- * it runs on the GPU.  Everything is exact integer arithmetic: capacities
- * and residuals int32, excesses and flow values int64.
+ * minimum-height residual neighbour, and the vertex pushes (atomic updates of
+ * residuals and excesses: by default along every residual arc to a lower
+ * neighbour while excess is left, push_mode 1 is the paper's single push) or
+ * relabels.  A global relabel (backward BFS from the sink in the residual
+ * graph, section 2.2) resets heights periodically; it runs on the GPU.  Small
+ * instances alone on the device are solved whole by one workgroup with the
+ * residual graph in LDS (wbpr_options.lds_max_v).  Everything is exact integer
+ * arithmetic: capacities and residuals int32, excesses and flow values int64.
  *
  * Graph input (all entry points):
  *   row_ptr  int64[V+1], row_ptr[0] = 0, non-decreasing, row_ptr[V] = E
