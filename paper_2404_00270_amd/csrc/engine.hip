@@ -512,7 +512,7 @@ constexpr size_t kPinnedHeader = 4096;
 }  // namespace
 
 size_t Engine::arena_bytes(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap) {
-  const int64_t nch = chunk_capacity(Vcap, Mcap, 1024);
+  const int64_t nch = chunk_capacity(Vcap, Mcap, BFS_CHUNK);
   size_t b = 0;
   b += al(8 * (size_t)Vcap);                 // rowb
   b += al(8 * (size_t)Mcap);                 // ent

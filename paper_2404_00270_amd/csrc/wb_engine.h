@@ -225,7 +225,7 @@ class Engine {
   int64_t resident_V_ = 0, resident_M_ = 0;
   int64_t last_M_ = 0;
   // tiers and launch shapes (fixed per config)
-  int P_ = 8, t_mid_ = 32, t_big_ = 2048, bfs_split_ = 64, chunk_ = 1024, stag_window_ = 16;
+  int P_ = 8, t_mid_ = 32, t_big_ = 2048, bfs_split_ = 64, chunk_ = BFS_CHUNK, stag_window_ = 16;
   int mid_lanes_ = 64;  // lanes per medium row (16 and 32 measured no faster on R-MAT)
   // captured sweep batches, one per (batch length, tiers); adaptive batch length
   std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs_;

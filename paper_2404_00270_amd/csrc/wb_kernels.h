@@ -18,6 +18,9 @@ constexpr int GR_THREADS = 1024;
 constexpr int32_t HCAP = 1 << 30;
 // Long rows are cut into tasks of CHUNK entries, one workgroup each.
 constexpr int32_t CHUNK = 1024;
+// The relabel's bottom-up pass cuts rows longer than its split degree into
+// BFS_CHUNK-entry pieces, one wave each.
+constexpr int32_t BFS_CHUNK = 1024;
 
 struct Graph {
   int32_t V;             // arena vertices
