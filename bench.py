@@ -257,13 +257,14 @@ def ablation(workloads, dev, steps=2):
     from paper_2404_00270_amd import workloads as W
     from paper_2404_00270_amd import wbpr
 
-    # every variant runs the rounds of sweep launches (lds_max_v = -1): the
-    # comparison is between the sweep kernels, not the LDS-resident solve
+    # every variant runs the rounds of sweep launches (lds_max_v = -1) without
+    # the gap heuristic (gap = -1): the comparison is between the paper's
+    # sweep kernels, not the LDS-resident solve or the added heuristic
     variants = [
-        ("VC, incremental queue (default)", dict(lds_max_v=-1)),
-        ("VC, full-scan queue (Algorithm 2)", dict(avq_mode=1, lds_max_v=-1)),
-        ("TC, full-scan queue (paper baseline)", dict(lanes_per_vertex=1, avq_mode=1, lds_max_v=-1)),
-        ("TC, incremental queue", dict(lanes_per_vertex=1, lds_max_v=-1)),
+        ("VC, incremental queue (default)", dict(lds_max_v=-1, gap=-1)),
+        ("VC, full-scan queue (Algorithm 2)", dict(avq_mode=1, lds_max_v=-1, gap=-1)),
+        ("TC, full-scan queue (paper baseline)", dict(lanes_per_vertex=1, avq_mode=1, lds_max_v=-1, gap=-1)),
+        ("TC, incremental queue", dict(lanes_per_vertex=1, lds_max_v=-1, gap=-1)),
     ]
     out = []
     for name in workloads:

@@ -18,7 +18,9 @@
  * residuals and excesses: by default along every residual arc to a lower
  * neighbour while excess is left, push_mode 1 is the paper's single push) or
  * relabels.  A global relabel (backward BFS from the sink in the residual
- * graph, section 2.2) resets heights periodically; it runs on the GPU.  Small
+ * graph, section 2.2) resets heights periodically; it runs on the GPU.
+ * Between global relabels a gap heuristic (not in the paper's method; option
+ * gap) parks the vertices above an emptied height until the next one.  Small
  * instances alone on the device are solved whole by one workgroup with the
  * residual graph in LDS (wbpr_options.lds_max_v).  Everything is exact integer
  * arithmetic: capacities and residuals int32, excesses and flow values int64.
@@ -130,6 +132,15 @@ typedef struct wbpr_options {
                                   up to 65,535 of each) are solved whole by
                                   one workgroup at admission, without rounds
                                   of launches (0 = 1024, negative = never) */
+    int32_t gap;               /* gap heuristic between global relabels, an
+                                  addition to the paper's method (0 or 1 =
+                                  on, negative = off): while one instance
+                                  runs its phase, relabels keep a count of
+                                  vertices at each of the first 256 heights
+                                  above its root, and once one of them
+                                  empties, sweeps leave every vertex above
+                                  it to the next global relabel.  Results
+                                  are unchanged */
 } wbpr_options;
 
 /* Per-solve counters and timings (filled when a non-NULL pointer is given). */
@@ -162,6 +173,8 @@ typedef struct wbpr_stats {
     int32_t instances;             /* instances solved by the call */
     int32_t use_graph;             /* sweep batches replayed as a hipGraph */
     int64_t lds_solved;            /* instances solved whole in LDS (lds_max_v) */
+    int64_t gap_skipped;           /* queued vertices the gap heuristic left to the
+                                      next global relabel (option gap) */
 } wbpr_stats;
 
 typedef struct wbpr_ctx wbpr_ctx;

@@ -54,6 +54,7 @@ wb::SolveConfig to_config(const wbpr_options *o) {
   c.gr_stagnation = o->gr_stagnation;
   c.wave_trace = o->wave_trace != 0;
   c.lds_max_v = o->lds_max_v;
+  c.gap = o->gap >= 0;
   return c;
 }
 
@@ -108,6 +109,7 @@ void fill_stats(wbpr_stats *st, const wb::EngineStats &r, const wb::SolveConfig 
   st->instances = n;
   st->use_graph = cfg.use_graph && !cfg.time_kernels;
   st->lds_solved = r.small_solved;
+  st->gap_skipped = r.gap_skipped;
 }
 
 }  // namespace
@@ -218,7 +220,7 @@ bool same_schedule(const wb::SolveConfig &a, const wb::SolveConfig &b) {
          a.gr_every_sweeps == b.gr_every_sweeps && a.grid_blocks == b.grid_blocks &&
          a.time_kernels == b.time_kernels && a.push_mode == b.push_mode && a.use_graph == b.use_graph &&
          a.max_sweeps == b.max_sweeps && a.max_wall_ms == b.max_wall_ms && a.wave_trace == b.wave_trace &&
-         a.lds_max_v == b.lds_max_v;
+         a.lds_max_v == b.lds_max_v && a.gap == b.gap;
 }
 
 // Solves a group already packed on the device, from an empty engine.

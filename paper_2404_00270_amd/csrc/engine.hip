@@ -467,6 +467,7 @@ struct MiscLayout {
   int32_t stag[2];   // stagnation state of the sweeps
   int32_t wtrace_n;  // per-wave trace records written this solve
   int32_t sweep_no;  // sweeps that ran this solve (trace only)
+  int32_t gap[4];    // gap heuristic state (lowest empty height, root height, heights counted)
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -525,6 +526,7 @@ size_t Engine::arena_bytes(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t nca
   b += 2 * al(4 * (size_t)Vcap);             // long-row list, lr_cnt
   b += 2 * al(4 * (size_t)task_capacity(Vcap, Mcap));  // chunk tasks
   b += al((size_t)Vcap);                     // vis
+  b += al(4 * (size_t)GAP_BINS);             // gap heuristic: vertices per height
   b += al(8 * (size_t)nch);                  // BFS chunk descriptors (sweeps: lr_key)
   b += 5 * al(4 * (size_t)ncap);             // active, stranded, roots, root_h, excl
   b += al(sizeof(InstDev) * (size_t)ncap * kListKinds + 4 * (size_t)ncap);  // lists + slots
@@ -630,6 +632,7 @@ int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int6
     task_u_ = (int32_t *)take(4 * (size_t)tcap_);
     task_c_ = (int32_t *)take(4 * (size_t)tcap_);
     vis_ = (uint8_t *)take((size_t)Vcap);
+    gap_hist_ = (int32_t *)take(4 * (size_t)GAP_BINS);
     nchunk_ = chunk_capacity(Vcap, Mcap, chunk_);
     chunk_w_ = (int32_t *)take(8 * (size_t)nchunk_);
     chunk_b_ = chunk_w_ + nchunk_;
@@ -1207,7 +1210,7 @@ bool Engine::ensure_side() {
 // shared state only through atomics, as workgroups of one kernel do.
 void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
   MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
-  Graph g{(int32_t)Vcap_, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_};
+  Graph g{(int32_t)Vcap_, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_, gap_hist_, misc->gap};
   // tile kernels: 256 workgroups, one per CU.  Measured on R-MAT / grid cut
   // / bipartite: 1024 -> 34.3 / 94 / 6.35 ms, 512 -> 30.2 / 85 / 6.08,
   // 256 -> 30.0 / 78 / 6.0, 192 and 128 slower again (31.2 and 34 ms on
@@ -1245,6 +1248,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
     q.t_big = t_big_;
     q.mode = mode;
     q.stats = misc->stats;
+    q.gap_skips = &misc->stats[15];
     q.rwork = &misc->rwork;
     q.halt = &misc->halt[0];
     q.qcap = (int32_t)Vcap_;
@@ -1392,7 +1396,7 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   hipMemsetAsync(inst_active_, 0, 4 * (size_t)ncap_, st);
   hipMemsetAsync(inst_stranded_, 0, 4 * (size_t)ncap_, st);
 
-  Graph g{(int32_t)vhi, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_};
+  Graph g{(int32_t)vhi, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_, gap_hist_, misc->gap};
   GRArgs ga;
   ga.g = g;
   ga.roots = roots_;
@@ -1440,6 +1444,10 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   // second half of the sweep-log space (the sweep log keeps the first)
   ga.tlog = log_level() >= 3 ? reinterpret_cast<long long *>(sweep_log_dev_ + 3 * (size_t)kSweepLogCap) : nullptr;
   ga.tlog_cap = kSweepLogCap / 2;
+  // gap heuristic: exact per-height counts need one root (one instance in
+  // its phase); batches run without it
+  ga.gap_base = nr == 1 ? hrh[0] : 0;
+  ga.gap_n = cfg_.gap && nr == 1 ? std::min(HCAP - hrh[0], GAP_BINS) : 0;
   const int Pg = std::max(P_, 4);  // tile width of the relabel's top-down expansion
   int lg = 0;
   while ((1 << lg) < Pg) lg++;
@@ -1744,6 +1752,7 @@ int Engine::collect_stats(hipStream_t st, EngineStats *out, std::string *err) {
   r.bfs_scans = hs[12] + hs[14];
   r.bfs_topdown_scans = hs[12];
   r.nonempty_sweeps = hs[13];
+  r.gap_skipped = hs[15];
   for (const auto &mk : ev_marks_) {
     if (mk.first == 3) {
       float ms = 0;

@@ -86,6 +86,53 @@ __device__ __forceinline__ void flush_stats(long long *stats, long long scans, i
   }
 }
 
+// Gap heuristic (an addition to the paper's method, single-instance solves):
+// the global relabel leaves in gap_hist the number of vertices at each of
+// the first gap[2] heights above the root, and every relabel moves its
+// vertex from its old height's count to the new one's.  When a count drops
+// to zero, no vertex above that height can reach the root through a
+// residual path (heights drop by at most one along residual arcs), so the
+// lowest such height is kept in gap[0] and sweeps leave the vertices above
+// it, with their excess, to the next global relabel, which labels every
+// vertex afresh.  Counts race with concurrent relabels; a transient zero
+// only parks vertices until that relabel and never changes a result.
+//
+// Long-row relabels (few) update the counts directly.
+__device__ __forceinline__ void gap_move(const Graph &g, int32_t ho, int32_t hn) {
+  if (!g.gap) return;
+  const int32_t n = g.gap[2];
+  if (n <= 0) return;
+  const int32_t base = g.gap[1];
+  const int32_t dn = hn - base, dold = ho - base;
+  if (dn > 0 && dn < n) atomicAdd(&g.gap_hist[dn], 1);
+  if (dold > 0 && dold < n && atomicSub(&g.gap_hist[dold], 1) == 1) atomicMin(&g.gap[0], ho);
+}
+
+// The tile kernels gather their moves per workgroup in LDS (n = 0: off) ...
+__device__ __forceinline__ void gap_move_lds(int *s_gap, int32_t base, int32_t n, int32_t ho, int32_t hn) {
+  const int32_t dn = hn - base, dold = ho - base;
+  if (dn > 0 && dn < n) atomicAdd(&s_gap[dn], 1);
+  if (dold > 0 && dold < n) atomicSub(&s_gap[dold], 1);
+}
+
+// ... and add them to the counts once, at the end (every thread, converged).
+__device__ __forceinline__ void gap_flush_lds(const Graph &g, const int *s_gap, int32_t base, int32_t n) {
+  if (n <= 0) return;
+  __syncthreads();
+  for (int32_t d = 1 + threadIdx.x; d < n; d += blockDim.x) {
+    const int dlt = s_gap[d];
+    if (dlt != 0) {
+      const int old = atomicAdd(&g.gap_hist[d], dlt);
+      if (dlt < 0 && old + dlt <= 0) atomicMin(&g.gap[0], base + d);
+    }
+  }
+}
+
+// Lowest height found empty (heights above it are cut off), hcap if none.
+__device__ __forceinline__ int32_t gap_cut(const Graph &g) {
+  return g.gap && g.gap[2] > 0 ? atomic_load_i32(&g.gap[0]) : g.hcap;
+}
+
 // Per-wave trace record, written by the first lane of every wave at the end
 // of a sweep launch when tracing is on (the paper's per-warp timing, section
 // 5).  All lanes of the wave call it, converged.
@@ -155,10 +202,11 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_avq_scan(Graph g, const int32
   const WaveQ wq{s_qbuf[wl], &s_qcnt[wl], list, cnt, cap, err};
   const int64_t n = *span;
   const int64_t nth = (int64_t)gridDim.x * blockDim.x;
+  const int32_t hlim = min(gap_cut(g), g.hcap - 1);  // heights above a gap wait for the relabel
   for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane(); v0 < n; v0 += nth) {  // wave-uniform
     const int64_t v = v0 + lane();
     bool act = false;
-    if (v < n) act = g.e[v] > 0 && g.h[v] < g.hcap;
+    if (v < n) act = g.e[v] > 0 && g.h[v] <= hlim;
     waveq_push(wq, act, (int32_t)v);
   }
   waveq_flush(wq);
@@ -222,6 +270,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
   __shared__ int s_mbuf[SWEEP_THREADS / WB_WAVE][DEFER_BUF];
   __shared__ int s_bbuf[SWEEP_THREADS / WB_WAVE][DEFER_BUF];
   __shared__ int s_qcnt[SWEEP_THREADS / WB_WAVE][3];
+  __shared__ int s_gap[GAP_BINS];
   const int wl = threadIdx.x / WB_WAVE;
   if (lane() == 0) {
     s_qcnt[wl][0] = 0;
@@ -250,7 +299,15 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
   const int tl = lane() % P;
   const int tbase = lane() & ~(P - 1);
   long long scans = 0, queued = 0, rwork = 0;
-  int pushes = 0, relabels = 0;
+  int pushes = 0, relabels = 0, gskips = 0;
+  const int32_t gcut = gap_cut(g);
+  // gap heuristic on (workgroup-uniform): per-height moves gathered in LDS
+  const int32_t gn = g.gap ? min(g.gap[2], GAP_BINS) : 0;
+  const int32_t gbase = gn > 0 ? g.gap[1] : 0;
+  if (gn > 0) {
+    for (int32_t d = threadIdx.x; d < GAP_BINS; d += blockDim.x) s_gap[d] = 0;
+    __syncthreads();
+  }
   // one row ahead: the tile's next queue entry is read while its current
   // row is scanned, and the next row's bounds, height and excess before the
   // current row's closing atomics (heights change only by the tile that
@@ -271,7 +328,9 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
   }
   for (int32_t base = wave * TPW; base < n; base += stride) {  // wave-uniform loop
     const int32_t i = base + sub;
-    const bool valid = i < n;
+    const bool cut = i < n && phu > gcut && phu < g.hcap;  // above a gap: left to the relabel
+    const bool valid = i < n && !cut;
+    if (cut && tl == 0) gskips++;
     int32_t u = 0, beg = 0, end = 0, hpre = 0;
     long long epre = 0;
     if (valid) {
@@ -343,6 +402,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
             int32_t nh = hmin + 1;
             if (nh > g.hcap) nh = g.hcap;
             g.h[u] = nh;
+            gap_move_lds(s_gap, gbase, gn, hpre, nh);
             relabels++;
             rwork += deg;
             app_u = nh < g.hcap;
@@ -420,6 +480,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
             int32_t nh = (int32_t)(key >> 32) + 1;
             if (nh > g.hcap) nh = g.hcap;
             g.h[u] = nh;
+            gap_move_lds(s_gap, gbase, gn, hpre, nh);
             relabels++;
             rwork += deg;
             app_u = nh < g.hcap;
@@ -437,6 +498,11 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
     waveq_flush(wbig);
   }
   flush_stats(q.stats, scans, pushes, relabels, queued, q.rwork, rwork);
+  gap_flush_lds(g, s_gap, gbase, gn);
+  if (q.gap_skips) {
+    const int32_t gs = wave_sum_i32(gskips);
+    if (lane() == 0 && gs) atomic_add_i64(q.gap_skips, gs);
+  }
   if (q.wtrace) trace_wave(q, q.kind, wt0, scans, queued);
 }
 
@@ -480,6 +546,7 @@ __device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q,
         int32_t nh = (int32_t)(kmin >> 32) + 1;
         if (nh > g.hcap) nh = g.hcap;
         g.h[u] = nh;
+        gap_move(g, hu, nh);
         (*relabels)++;
         *rwork += deg;
         *app_u = nh < g.hcap;
@@ -507,6 +574,7 @@ __device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q,
       int32_t nh = hmin + 1;
       if (nh > g.hcap) nh = g.hcap;
       g.h[u] = nh;
+      gap_move(g, hu, nh);
       (*relabels)++;
       *rwork += deg;
       *app_u = nh < g.hcap;
@@ -798,6 +866,14 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
     g.h[v] = g.hcap;
     a.vis[v] = 0;
   }
+  // gap heuristic: counts per distance from the root, filled level by level
+  // below; no gap until a relabel empties one
+  for (int64_t j = gtid; j < a.gap_n; j += nthreads) g.gap_hist[j] = 0;  // gap_n <= GAP_BINS
+  if (gtid == 0 && g.gap) {
+    g.gap[0] = g.hcap;
+    g.gap[1] = a.gap_base;
+    g.gap[2] = a.gap_n;
+  }
   // frontier membership and visited flags as bitmaps (1/32 of a byte array:
   // they stay in L2 where the per-entry gathers of a level hit them)
   uint32_t *const bm_vis = a.bm;
@@ -854,6 +930,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   bool queue_valid = true;  // the frontier of this level is in fq[level & 1]
   for (;;) {
     if (n == 0) break;
+    if (gtid == 0 && level < a.gap_n) g.gap_hist[level] = n;  // the n vertices at distance `level`
     const uint8_t cur = dist_code(level), nxt = dist_code(level + 1);
     // frontier bitmaps rotate over three: this level reads bm_in, writes
     // bm_out (cleared during the previous level) and clears the third

@@ -33,6 +33,7 @@ struct SolveConfig {
   int gr_stagnation = 0;      // sweeps without a new smallest queue that end a round (0: by mean row length)
   bool wave_trace = false;    // per-wave execution time and work of every sweep launch
   int lds_max_v = 0;          // instances up to this many vertices are solved in LDS (0: 1024, < 0: never)
+  bool gap = true;            // gap heuristic between global relabels (one instance in its phase)
 };
 
 // Counters of the engine since the last reset_stats().
@@ -42,6 +43,7 @@ struct EngineStats {
   int64_t arc_scans = 0, pushes = 0, relabels = 0, queued = 0, bfs_scans = 0, bfs_topdown_scans = 0;
   int64_t nonempty_sweeps = 0;
   int64_t small_solved = 0;  // instances solved whole in LDS at admission
+  int64_t gap_skipped = 0;   // queue entries left to the next global relabel by the gap heuristic
   // per kernel: 0 short-row tiles, 1 medium rows (one wave), 2 long rows (workgroup), 3 global relabel
   double k_ms[4] = {0, 0, 0, 0};
   int64_t k_launches[4] = {0, 0, 0, 0};
@@ -205,6 +207,7 @@ class Engine {
   unsigned long long *lr_key_ = nullptr;
   int64_t tcap_ = 0;
   uint8_t *vis_ = nullptr;
+  int32_t *gap_hist_ = nullptr;  // gap heuristic: vertices per height above the root
   int64_t nchunk_ = 0;
   int32_t *inst_active_ = nullptr, *inst_stranded_ = nullptr;
   int32_t *roots_ = nullptr, *root_h_ = nullptr, *excl_ = nullptr;

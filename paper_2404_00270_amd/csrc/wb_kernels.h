@@ -18,6 +18,9 @@ constexpr int GR_THREADS = 1024;
 constexpr int32_t HCAP = 1 << 30;
 // Long rows are cut into tasks of CHUNK entries, one workgroup each.
 constexpr int32_t CHUNK = 1024;
+// Gap heuristic: heights counted above the root (a gap among them cuts off
+// every vertex above it, counted or not).
+constexpr int32_t GAP_BINS = 256;
 // The relabel's bottom-up pass cuts rows longer than its split degree into
 // BFS_CHUNK-entry pieces, one wave each.
 constexpr int32_t BFS_CHUNK = 1024;
@@ -32,6 +35,12 @@ struct Graph {
   int32_t *h;
   const int32_t *sink;   // target whose excess is never read, so pushes into
                          // it skip the excess atomic (-1: none skipped)
+  // Gap heuristic (nullable; written by the global relabel): gap[0] lowest
+  // height found empty since the relabel (hcap: none), gap[1] the root's
+  // height, gap[2] the heights counted (<= GAP_BINS; 0: heuristic off);
+  // gap_hist[d] the vertices at height gap[1] + d.
+  int32_t *gap_hist;
+  int32_t *gap;
 };
 
 struct SweepQ {
@@ -70,6 +79,7 @@ struct SweepQ {
   int32_t wtrace_cap;
   const int32_t *sweep_no;  // sweeps completed since the solve started (counted by the control step)
   int32_t kind;      // 0 short-row tiles, 1 medium rows, 2 first chunks, 3 further chunks
+  long long *gap_skips;  // queue entries left to the next global relabel by the gap heuristic
 };
 
 // End-of-sweep control (one thread): halt decision and optional log.
@@ -127,6 +137,8 @@ struct GRArgs {
   int32_t bm_words;       // words per bitmap (>= V / 32)
   long long *tlog;        // nullable (diagnostics): per level {wall clock, frontier, bottom-up}
   int32_t tlog_cap;
+  int32_t gap_base;       // gap heuristic (g.gap non-null): the one root's height ...
+  int32_t gap_n;          // ... and heights counted from it (<= GAP_BINS; 0: off this round)
 };
 
 // Sweep kernels: tiles of P lanes (P = 4..64), one workgroup per long-row chunk,

@@ -70,6 +70,7 @@ class wbpr_options(ctypes.Structure):
         ("gr_stagnation", ctypes.c_int32),
         ("wave_trace", ctypes.c_int32),
         ("lds_max_v", ctypes.c_int32),
+        ("gap", ctypes.c_int32),
     ]
 
 
@@ -110,6 +111,7 @@ class wbpr_stats(ctypes.Structure):
         ("instances", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("lds_solved", ctypes.c_int64),
+        ("gap_skipped", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
