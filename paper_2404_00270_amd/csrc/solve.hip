@@ -97,18 +97,21 @@ __device__ __forceinline__ void flush_stats(long long *stats, long long scans, i
 // vertex afresh.  Counts race with concurrent relabels; a transient zero
 // only parks vertices until that relabel and never changes a result.
 //
-// Long-row relabels (few) update the counts directly.
-__device__ __forceinline__ void gap_move(const Graph &g, int32_t ho, int32_t hn) {
-  if (!g.gap) return;
-  const int32_t n = g.gap[2];
-  if (n <= 0) return;
-  const int32_t base = g.gap[1];
-  const int32_t dn = hn - base, dold = ho - base;
-  if (dn > 0 && dn < n) atomicAdd(&g.gap_hist[dn], 1);
-  if (dold > 0 && dold < n && atomicSub(&g.gap_hist[dold], 1) == 1) atomicMin(&g.gap[0], ho);
+// A sweep kernel gathers its moves per workgroup in an LDS histogram (the
+// relabels of one launch pile onto a few heights: one device atomic each
+// would serialise on those counters).  gap_begin clears it (every thread,
+// converged) and returns the heights counted, 0 when the heuristic is off.
+__device__ __forceinline__ int32_t gap_begin(const Graph &g, int *s_gap, int32_t *gbase) {
+  const int32_t gn = g.gap ? min(g.gap[2], GAP_BINS) : 0;
+  *gbase = gn > 0 ? g.gap[1] : 0;
+  if (gn > 0) {
+    for (int32_t d = threadIdx.x; d < GAP_BINS; d += blockDim.x) s_gap[d] = 0;
+    __syncthreads();
+  }
+  return gn;
 }
 
-// The tile kernels gather their moves per workgroup in LDS (n = 0: off) ...
+// One relabel from height ho to hn (n = 0: off) ...
 __device__ __forceinline__ void gap_move_lds(int *s_gap, int32_t base, int32_t n, int32_t ho, int32_t hn) {
   const int32_t dn = hn - base, dold = ho - base;
   if (dn > 0 && dn < n) atomicAdd(&s_gap[dn], 1);
@@ -301,13 +304,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
   long long scans = 0, queued = 0, rwork = 0;
   int pushes = 0, relabels = 0, gskips = 0;
   const int32_t gcut = gap_cut(g);
-  // gap heuristic on (workgroup-uniform): per-height moves gathered in LDS
-  const int32_t gn = g.gap ? min(g.gap[2], GAP_BINS) : 0;
-  const int32_t gbase = gn > 0 ? g.gap[1] : 0;
-  if (gn > 0) {
-    for (int32_t d = threadIdx.x; d < GAP_BINS; d += blockDim.x) s_gap[d] = 0;
-    __syncthreads();
-  }
+  int32_t gbase;
+  const int32_t gn = gap_begin(g, s_gap, &gbase);
   // one row ahead: the tile's next queue entry is read while its current
   // row is scanned, and the next row's bounds, height and excess before the
   // current row's closing atomics (heights change only by the tile that
@@ -535,7 +533,8 @@ __device__ __forceinline__ long long block_excl_scan_i64(long long x, long long 
 // (Algorithm 1).  Sets *app_u / *app_v (and *v) for the caller's queue.
 __device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q, int32_t u, int2 rb, int32_t hu,
                                                 unsigned long long kmin, bool more, bool *app_u, bool *app_v,
-                                                int32_t *v, int *pushes, int *relabels, long long *rwork) {
+                                                int32_t *v, int *pushes, int *relabels, long long *rwork,
+                                                int *s_gap, int32_t gbase, int32_t gn) {
   const int32_t deg = rb.y - rb.x;
   if (q.mode == 1) {
     const long long left = atomic_add_i64(&g.e[u], -CHUNK_BIAS) - CHUNK_BIAS;
@@ -546,7 +545,7 @@ __device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q,
         int32_t nh = (int32_t)(kmin >> 32) + 1;
         if (nh > g.hcap) nh = g.hcap;
         g.h[u] = nh;
-        gap_move(g, hu, nh);
+        gap_move_lds(s_gap, gbase, gn, hu, nh);
         (*relabels)++;
         *rwork += deg;
         *app_u = nh < g.hcap;
@@ -574,7 +573,7 @@ __device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q,
       int32_t nh = hmin + 1;
       if (nh > g.hcap) nh = g.hcap;
       g.h[u] = nh;
-      gap_move(g, hu, nh);
+      gap_move_lds(s_gap, gbase, gn, hu, nh);
       (*relabels)++;
       *rwork += deg;
       *app_u = nh < g.hcap;
@@ -606,8 +605,11 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
   __shared__ long long s_wsum[BLK_WAVES];
   __shared__ unsigned long long s_wmin[BLK_WAVES];
   __shared__ long long s_take;
+  __shared__ int s_gap[GAP_BINS];
   if (*q.halt) return;
   const long long wt0 = q.wtrace ? (long long)wall_clock64() : 0;
+  int32_t gbase;
+  const int32_t gn = gap_begin(g, s_gap, &gbase);
   long long tasks = 0;  // per wave, counted by its first lane
   const int32_t ntask = FIRST ? min(*q.big_cnt, q.qcap) : min(*q.task_cnt, q.tcap);
   const int w = threadIdx.x / WB_WAVE;
@@ -696,7 +698,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
         // relabelled here (excess that arrived meanwhile waits a sweep)
         queued += 1;
         finish_long_row(g, q, u, rb, hu, key, short_claim || nch > 1, &app_u, &app_v, &v, &pushes, &relabels,
-                        &rwork);
+                        &rwork, s_gap, gbase, gn);
       } else {
         if (key != WB_KEY_NONE) atomic_min_u64(&q.lr_key[u], key);
         if (short_claim) atomic_or_i32(&q.lr_cnt[u], CHUNK_MORE);
@@ -721,6 +723,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
   }
   waveq_flush(wq);
   flush_stats(q.stats + 8, scans, pushes, relabels, queued, q.rwork, rwork);
+  gap_flush_lds(g, s_gap, gbase, gn);
   if (q.wtrace) trace_wave(q, FIRST ? 2 : 3, wt0, scans, tasks);
 }
 
@@ -729,7 +732,10 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
 __global__ void __launch_bounds__(BLK) k_sweep_chunk_finish(Graph g, SweepQ q) {
   __shared__ int s_qbuf[BLK_WAVES][WB_QBUF];
   __shared__ int s_qcnt[BLK_WAVES];
+  __shared__ int s_gap[GAP_BINS];
   if (*q.halt) return;
+  int32_t gbase;
+  const int32_t gn = gap_begin(g, s_gap, &gbase);
   const int32_t ntask = min(*q.task_cnt, q.tcap);
   const int w = threadIdx.x / WB_WAVE;
   if (lane() == 0) s_qcnt[w] = 0;
@@ -746,13 +752,14 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk_finish(Graph g, SweepQ q) {
       const int2 rb = g.rowb[u];
       queued += 1;
       finish_long_row(g, q, u, rb, g.h[u], atomic_load_u64(&q.lr_key[u]), (q.lr_cnt[u] & CHUNK_MORE) != 0, &app_u,
-                      &app_v, &v, &pushes, &relabels, &rwork);
+                      &app_v, &v, &pushes, &relabels, &rwork, s_gap, gbase, gn);
     }
     waveq_push(wq, q.append && app_v, v);
     waveq_push(wq, q.append && app_u, u);
   }
   waveq_flush(wq);
   flush_stats(q.stats + 8, 0, pushes, relabels, queued, q.rwork, rwork);
+  gap_flush_lds(g, s_gap, gbase, gn);
 }
 
 // ------------------------------------------------------ global relabel
