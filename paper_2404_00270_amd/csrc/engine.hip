@@ -367,6 +367,9 @@ __global__ void k_inst(InstArgs a, int which) {
         }
       break;
     case IK_MAXDEG: {  // longest row a sweep can meet: terminals are never queued
+      __shared__ int s_m;
+      if (threadIdx.x == 0) s_m = 0;
+      __syncthreads();
       int32_t m = 0;
       for (int64_t x = tid; x < d.V; x += nth) {
         const int32_t v = d.vbase + (int32_t)x;
@@ -376,7 +379,10 @@ __global__ void k_inst(InstArgs a, int which) {
       }
 #pragma unroll
       for (int o = WB_WAVE / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, WB_WAVE));
-      if (lane() == 0 && m > 0) atomicMax(&a.maxdeg[blockIdx.y], m);
+      // one device atomic per workgroup (same-address atomics serialise)
+      if (lane() == 0 && m > 0) atomicMax(&s_m, m);
+      __syncthreads();
+      if (threadIdx.x == 0 && s_m > 0) atomicMax(&a.maxdeg[blockIdx.y], s_m);
       break;
     }
     case IK_RELEASE:
@@ -763,7 +769,8 @@ void Engine::launch_inst_list(int which, const std::vector<InstDev> &list, const
   if (which == IK_INIT) hipMemcpyAsync(dslot, hslot, 4 * (size_t)n, hipMemcpyHostToDevice, st);
   InstArgs a{dl, A_.rowb, A_.ent, A_.rev, A_.cap0, A_.arc2ent, A_.pbefore, A_.acap, e_, h_, inst_of_, dslot,
              inst_stranded_};
-  unsigned bx = which == IK_VALUE_ZERO || which == IK_PHASE2 ? 1u : grid1d(maxlen, 256, 1024);
+  // the decode's per-arc chain of dependent gathers wants every wave slot
+  unsigned bx = which == IK_VALUE_ZERO || which == IK_PHASE2 ? 1u : grid1d(maxlen, 256, which == IK_DECODE ? 4096 : 1024);
   if (which == IK_PREFLOW || which == IK_VALUE) bx = 64;
   for (int off = 0; off < n; off += 65535) {
     const int cnt = std::min(65535, n - off);
