@@ -173,6 +173,8 @@ typedef struct wbpr_stats {
     int32_t instances;             /* instances solved by the call */
     int32_t use_graph;             /* sweep batches replayed as a hipGraph */
     int64_t lds_solved;            /* instances solved whole in LDS (lds_max_v) */
+    int64_t lds_fallbacks;         /* LDS-resident solves that reached their round cap
+                                      and were finished by the rounds of launches */
     int64_t gap_skipped;           /* queued vertices the gap heuristic left to the
                                       next global relabel (option gap) */
 } wbpr_stats;
@@ -208,9 +210,12 @@ int wbpr_solve(wbpr_ctx *ctx, const wbpr_csr *g, int32_t s, int32_t t, int64_t *
 /* Solve one instance whose CSR arrays are already in DEVICE memory (e.g.
  * torch tensors).  Outputs are DEVICE pointers: dev_value int64[1]
  * (required), dev_arc_flow int32[E] and dev_cut_side uint8[V] (nullable).
- * Work is ordered after prior work on `stream` (a hipStream_t; NULL = the
- * context's own stream) and the call returns once the results are written
- * (the solver reads small status words back to drive its loop). */
+ * `stream` is the caller's hipStream_t (NULL = the legacy default stream),
+ * for instance torch.cuda.current_stream().cuda_stream: the library runs on
+ * its context's own stream, ordered after the work already queued on
+ * `stream` (one event), and makes later work on `stream` wait for the
+ * results (one event).  The call returns once the results are written (the
+ * solver reads small status words back to drive its loop). */
 int wbpr_solve_device(wbpr_ctx *ctx, const wbpr_csr *dev_g, int32_t s, int32_t t, void *stream,
                       int64_t *dev_value, int32_t *dev_arc_flow, uint8_t *dev_cut_side,
                       wbpr_stats *stats);
@@ -226,7 +231,8 @@ int wbpr_solve_device(wbpr_ctx *ctx, const wbpr_csr *dev_g, int32_t s, int32_t t
  * arrays [n] (local s, t).  Outputs are DEVICE arrays packed the same way:
  * dev_values int64[n] (required), dev_flows int32[sum E] and dev_sides
  * uint8[sum V] (nullable).  Limits: sum V < 2^30, 2 * sum E < 2^31.
- * Synchronous with respect to `stream` (NULL = the context's stream).
+ * `stream` as for wbpr_solve_device (ordered after its queued work, and
+ * later work on it waits for the results); returns once they are written.
  *
  * status (HOST int32[n], nullable): per-instance results.  NULL: any
  * invalid instance fails the whole call with its code.  Non-NULL: an

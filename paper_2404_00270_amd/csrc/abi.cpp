@@ -110,6 +110,7 @@ void fill_stats(wbpr_stats *st, const wb::EngineStats &r, const wb::SolveConfig 
   st->use_graph = cfg.use_graph && !cfg.time_kernels;
   st->lds_solved = r.small_solved;
   st->gap_skipped = r.gap_skipped;
+  st->lds_fallbacks = r.small_fallbacks;
 }
 
 }  // namespace
@@ -145,6 +146,8 @@ int wbpr_ctx_create(int device, const wbpr_options *opt, wbpr_ctx **out) {
   c->device = device;
   c->cfg = to_config(opt);
   e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
   if (e != hipSuccess) {
     wbpr_ctx_destroy(c);
     return hip_fail(e, "stream");
@@ -166,6 +169,8 @@ void wbpr_ctx_destroy(wbpr_ctx *c) {
   c->engine.reset();
   c->input.release();
   c->output.release();
+  if (c->ev_in) hipEventDestroy(c->ev_in);
+  if (c->ev_out) hipEventDestroy(c->ev_out);
   if (c->stream) hipStreamDestroy(c->stream);
   delete c;
 }
@@ -267,6 +272,23 @@ int solve_group(wbpr_ctx *c, wb::GroupInput &in, hipStream_t st, wbpr_stats *sta
   return WBPR_OK;
 }
 
+// Runs fn on the context's stream, ordered after the work already queued on
+// the caller's stream (NULL: the legacy default stream) and with the
+// caller's stream made to wait for everything fn queued.  The library keeps
+// its own stream because it captures sweep batches into graphs there.
+template <class F>
+int on_caller_stream(wbpr_ctx *c, void *stream, F fn) {
+  hipStream_t caller = (hipStream_t)stream;
+  hipError_t e = hipEventRecord(c->ev_in, caller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_in, 0);
+  if (e != hipSuccess) return hip_fail(e, "ordering after the caller's stream");
+  const int rc = fn(c->stream);
+  e = hipEventRecord(c->ev_out, c->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(caller, c->ev_out, 0);
+  if (e != hipSuccess && rc == WBPR_OK) return hip_fail(e, "ordering the caller's stream after the solve");
+  return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -281,7 +303,6 @@ int wbpr_solve_device(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, void
   if (!dev_value) return fail(WBPR_EINVAL, "null value pointer");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  hipStream_t st = stream ? (hipStream_t)stream : c->stream;
   int32_t V = g->V;
   int64_t E = g->E;
   wb::GroupInput in;
@@ -296,7 +317,7 @@ int wbpr_solve_device(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, void
   in.values = dev_value;
   in.flows = dev_arc_flow;
   in.sides = dev_cut_side;
-  return solve_group(c, in, st, stats);
+  return on_caller_stream(c, stream, [&](hipStream_t st) { return solve_group(c, in, st, stats); });
 }
 
 int wbpr_solve(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int64_t *value, int32_t *arc_flow,
@@ -390,49 +411,50 @@ int wbpr_solve_batch_device(wbpr_ctx *c, int32_t n, const int32_t *V, const int6
   if (Et > 0 && (!dev_col || !dev_cap)) return fail(WBPR_EINVAL, "null CSR array");
   hipError_t e = hipSetDevice(c->device);
   if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-  hipStream_t st = stream ? (hipStream_t)stream : c->stream;
-  if (all_ok) {
-    wb::GroupInput in;
-    in.n = n;
-    in.V = V;
-    in.E = E;
-    in.s = s;
-    in.t = t;
-    in.row_ptr = dev_row_ptr;
-    in.col = dev_col;
-    in.cap = dev_cap;
-    in.values = dev_values;
-    in.flows = dev_flows;
-    in.sides = dev_sides;
-    const int rc = solve_group(c, in, st, stats);
-    if (!status || (rc != WBPR_EINVAL && rc != WBPR_EOVERFLOW)) return rc;
-    // an instance failed the device checks: find which by solving them alone
-  }
-  std::vector<int64_t> ro(n), eo(n), vo(n);
-  for (int i = 0, r = 0, x = 0, v = 0; i < n; i++) {
-    ro[i] = r;
-    eo[i] = x;
-    vo[i] = v;
-    r += V[i] + 1;
-    x += E[i];
-    v += V[i];
-  }
-  for (int i = 0; i < n; i++) {
-    if (status[i] == WBPR_OK) {
-      const int rc = solve_one_of(c, i, V, E, s, t, dev_row_ptr, dev_col, dev_cap, st, dev_values, dev_flows,
-                                  dev_sides, ro, eo, vo);
-      if (rc != WBPR_OK && rc != WBPR_EINVAL && rc != WBPR_EOVERFLOW) return rc;
-      status[i] = rc;
+  return on_caller_stream(c, stream, [&](hipStream_t st) -> int {
+    if (all_ok) {
+      wb::GroupInput in;
+      in.n = n;
+      in.V = V;
+      in.E = E;
+      in.s = s;
+      in.t = t;
+      in.row_ptr = dev_row_ptr;
+      in.col = dev_col;
+      in.cap = dev_cap;
+      in.values = dev_values;
+      in.flows = dev_flows;
+      in.sides = dev_sides;
+      const int rc = solve_group(c, in, st, stats);
+      if (!status || (rc != WBPR_EINVAL && rc != WBPR_EOVERFLOW)) return rc;
+      // an instance failed the device checks: find which by solving them alone
     }
-    if (status[i] != WBPR_OK) {
-      e = hipMemsetAsync(dev_values + i, 0, 8, st);
-      if (e != hipSuccess) return hip_fail(e, "batch output");
+    std::vector<int64_t> ro(n), eo(n), vo(n);
+    for (int i = 0, r = 0, x = 0, v = 0; i < n; i++) {
+      ro[i] = r;
+      eo[i] = x;
+      vo[i] = v;
+      r += V[i] + 1;
+      x += E[i];
+      v += V[i];
     }
-  }
-  if (stats) *stats = wbpr_stats{};
-  e = hipStreamSynchronize(st);
-  if (e != hipSuccess) return hip_fail(e, "batch");
-  return WBPR_OK;
+    for (int i = 0; i < n; i++) {
+      if (status[i] == WBPR_OK) {
+        const int rc = solve_one_of(c, i, V, E, s, t, dev_row_ptr, dev_col, dev_cap, st, dev_values, dev_flows,
+                                    dev_sides, ro, eo, vo);
+        if (rc != WBPR_OK && rc != WBPR_EINVAL && rc != WBPR_EOVERFLOW) return rc;
+        status[i] = rc;
+      }
+      if (status[i] != WBPR_OK) {
+        hipError_t e2 = hipMemsetAsync(dev_values + i, 0, 8, st);
+        if (e2 != hipSuccess) return hip_fail(e2, "batch output");
+      }
+    }
+    if (stats) *stats = wbpr_stats{};
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "batch");
+    return WBPR_OK;
+  });
 }
 
 int wbpr_solve_batch(wbpr_ctx *c, int32_t n, const wbpr_csr *graphs, const int32_t *s, const int32_t *t,

@@ -55,6 +55,9 @@ int check_shape(int32_t V, int64_t E, int32_t s, int32_t t);
 struct wbpr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  // order the context stream after a caller's stream (entry) and the
+  // caller's stream after the context stream (exit)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
   wb::SolveConfig cfg;
   std::unique_ptr<wb::Engine> engine;
   wb::DevBuf input, output;

@@ -43,6 +43,7 @@ struct EngineStats {
   int64_t arc_scans = 0, pushes = 0, relabels = 0, queued = 0, bfs_scans = 0, bfs_topdown_scans = 0;
   int64_t nonempty_sweeps = 0;
   int64_t small_solved = 0;  // instances solved whole in LDS at admission
+  int64_t small_fallbacks = 0;  // LDS-resident solves that reached their round cap (rounds finished them)
   int64_t gap_skipped = 0;   // queue entries left to the next global relabel by the gap heuristic
   // per kernel: 0 short-row tiles, 1 medium rows (one wave), 2 long rows (workgroup), 3 global relabel
   double k_ms[4] = {0, 0, 0, 0};

@@ -6,8 +6,10 @@ missing it raises instead of falling back to anything else.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -111,6 +113,7 @@ class wbpr_stats(ctypes.Structure):
         ("instances", ctypes.c_int32),
         ("use_graph", ctypes.c_int32),
         ("lds_solved", ctypes.c_int64),
+        ("lds_fallbacks", ctypes.c_int64),
         ("gap_skipped", ctypes.c_int64),
     ]
 
@@ -130,12 +133,36 @@ class WbprError(RuntimeError):
 
 _lib = None
 
+# Handles still open at interpreter exit are closed by an atexit hook, in
+# dependency order (servers and uploaded graphs before the contexts they were
+# made from), so no stream, arena, captured graph or worker thread of the
+# library outlives Python's own shutdown and meets the HIP runtime's static
+# teardown.
+_live_servers: "weakref.WeakSet" = weakref.WeakSet()
+_live_graphs: "weakref.WeakSet" = weakref.WeakSet()
+_live_solvers: "weakref.WeakSet" = weakref.WeakSet()
+
+
+def close_all() -> None:
+    """Close every library handle this process still holds (idempotent)."""
+    for live in (_live_servers, _live_graphs, _live_solvers):
+        for h in list(live):
+            try:
+                h.close()
+            except Exception:
+                pass
+
+
+atexit.register(close_all)
+
 
 def _init_torch_first():
-    """PyTorch-ROCm ships its own HIP runtime; libwbpr.so links the system one.
-    Both share the process's GPU address space (so device pointers pass
-    freely), but torch's runtime fails to start once the other one has
-    claimed the device first.  So when torch is present, start it first."""
+    """PyTorch-ROCm ships its own copy of the HIP runtime (libamdhip64.so,
+    soname libamdhip64.so.7, the soname libwbpr.so asks for).  Loading torch
+    first makes the dynamic loader resolve libwbpr.so's dependency to that
+    already loaded copy, so the process holds one HIP runtime and torch's
+    device pointers and streams are the library's too.  Loading libwbpr.so
+    first would bring in the system copy as well."""
     try:
         import torch
     except Exception:
@@ -471,6 +498,7 @@ class Solver:
 
     def __init__(self, device: int = 0, **options):
         self.ctx = wbpr_ctx_create(device, **options)
+        _live_solvers.add(self)
 
     def set_options(self, **options):
         wbpr_ctx_set_options(self.ctx, **options)
@@ -518,21 +546,21 @@ class Solver:
                     per_instance: bool = False) -> BatchResult:
         return wbpr_solve_batch(self.ctx, graphs, want_flow, want_side, per_instance=per_instance)
 
-    def solve_tensors(self, V, row_ptr, col, cap, s, t, value, flow=None, side=None) -> dict:
+    def solve_tensors(self, V, row_ptr, col, cap, s, t, value, flow=None, side=None, stream=None) -> dict:
         """Device-resident solve on torch tensors (torch supplies the memory).
 
-        torch's streams belong to torch's own HIP runtime, so they are not
-        passed down: torch's pending work is synchronised first, the library
-        runs on its context stream, and the call returns with the outputs
-        written."""
+        The solve is ordered after the work queued on ``stream`` (default:
+        torch's current stream on the tensors' device) and later work on that
+        stream sees the outputs; the call returns with them written."""
         import torch
 
         for x in (row_ptr, col, cap, value, flow, side):
             if x is not None and (not x.is_cuda or not x.is_contiguous()):
                 raise ValueError("tensors must be contiguous device tensors")
-        torch.cuda.synchronize(row_ptr.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(row_ptr.device)
         return wbpr_solve_device(self.ctx, V, int(col.shape[0]), row_ptr.data_ptr(), col.data_ptr(),
-                                 cap.data_ptr(), s, t, 0, value.data_ptr(),
+                                 cap.data_ptr(), s, t, int(stream.cuda_stream), value.data_ptr(),
                                  flow.data_ptr() if flow is not None else None,
                                  side.data_ptr() if side is not None else None)
 
@@ -588,6 +616,7 @@ class Server:
         _check(lib.wbpr_server_create(solver.ctx, ctypes.byref(o), ctypes.byref(h)))
         self.h = h.value
         self._solver = solver  # the context must outlive the server
+        _live_servers.add(self)
 
     def submit(self, g, return_code: bool = False):
         lib = load_library()
@@ -667,6 +696,7 @@ class UploadedGraph:
         _check(lib.wbpr_graph_upload(solver.ctx, ctypes.byref(csr), ctypes.byref(h)))
         self.h = h.value
         del self._rp, self._col, self._cap  # the library copied them
+        _live_graphs.add(self)
 
     def solve(self, s: int, t: int, want_flow: bool = True, want_side: bool = True, return_code: bool = False):
         lib = load_library()

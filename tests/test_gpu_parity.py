@@ -167,6 +167,25 @@ def test_lds_resident_path(solver):
         check_against_oracle(g, r)
 
 
+def test_lds_round_cap_hands_over_to_rounds(monkeypatch):
+    """An LDS-resident solve that reaches its round cap writes nothing back
+    and the rounds of launches finish the instance: forced from the host by
+    a round cap of 1 (results must still equal the oracle's)."""
+    from paper_2404_00270_amd import wbpr
+
+    monkeypatch.setenv("WBPR_LDS_ROUND_CAP", "1")
+    fallbacks = 0
+    with wbpr.Solver(0, **WATCHDOG) as s:
+        for seed in range(6):
+            g = W.random_graph(200 + 100 * seed, 8 * (200 + 100 * seed), 1, 100, 300 + seed)
+            r = s.solve(g)
+            say(f"[lds-cap] {g.name}: lds_solved={r.stats['lds_solved']} fallbacks={r.stats['lds_fallbacks']}")
+            assert r.stats["lds_solved"] + r.stats["lds_fallbacks"] == 1
+            fallbacks += r.stats["lds_fallbacks"]
+            check_against_oracle(g, r)
+    assert fallbacks > 0
+
+
 def test_degenerate_cases(solver):
     cases = [
         W.from_arcs(2, [], 0, 1, "no-arcs"),

@@ -16,6 +16,11 @@ against things other than itself:
 * invariants: feasibility, value == cut capacity, and the canonical sink side
   (vertices that reach t in the residual graph) being identical for two
   different maximum flows;
+* the canonical sink side against brute force: among all minimum s-t cuts,
+  the set of vertices that reach t in the residual graph of a maximum flow
+  is the smallest sink side, i.e. the intersection of the sink sides of
+  every minimum cut (Picard-Queyranne); enumerating all cuts of tiny graphs
+  gives that intersection without any flow;
 * planted mistakes, which the certificate must reject.
 """
 import itertools
@@ -43,8 +48,9 @@ def certify(g, res):
     return c
 
 
-def brute_force_min_cut(g):
-    """Minimum over all 2^(V-2) s-t cuts of the cut capacity (vectorised)."""
+def _all_cut_capacities(g):
+    """(S, capacities): every one of the 2^(V-2) s-t cuts as a boolean
+    source-side matrix S (one row per cut) and its capacity."""
     V, s, t = g.V, g.s, g.t
     others = [v for v in range(V) if v not in (s, t)]
     k = len(others)
@@ -54,7 +60,22 @@ def brute_force_min_cut(g):
     S[:, others] = masks
     src = W.arc_sources(g)
     cut = S[:, src] & ~S[:, g.col]
-    return int((cut.astype(np.int64) @ g.cap.astype(np.int64)).min()) if g.E else 0
+    caps = cut.astype(np.int64) @ g.cap.astype(np.int64) if g.E else np.zeros(S.shape[0], np.int64)
+    return S, caps
+
+
+def brute_force_min_cut(g):
+    """Minimum over all 2^(V-2) s-t cuts of the cut capacity (vectorised)."""
+    _, caps = _all_cut_capacities(g)
+    return int(caps.min())
+
+
+def brute_force_sink_side(g):
+    """Intersection of the sink sides of all minimum s-t cuts (uint8[V]): the
+    sink-nearest minimum cut, found by enumeration without any flow."""
+    S, caps = _all_cut_capacities(g)
+    T = ~S[caps == caps.min()]
+    return np.logical_and.reduce(T, axis=0).astype(np.uint8)
 
 
 @pytest.mark.parametrize("seed", range(120))
@@ -69,8 +90,46 @@ def test_bruteforce_multigraphs(seed):
     assert b.value == want
     ca, cb = certify(g, a), certify(g, b)
     # the sink side of a minimum cut read from the residual graph does not
-    # depend on which maximum flow produced it
+    # depend on which maximum flow produced it ...
     assert np.array_equal(ca.side, cb.side)
+    # ... and is the sink-nearest minimum cut: the intersection of the sink
+    # sides of every minimum cut, from enumeration alone
+    assert np.array_equal(ca.side, brute_force_sink_side(g))
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_canonical_side_is_sink_nearest_min_cut(seed):
+    """Graphs with many tied minimum cuts (small capacities from {0, 1, 2}),
+    so the source-nearest and sink-nearest minimum cuts usually differ and a
+    side read the wrong way round (the complement of what s reaches) fails."""
+    rng = np.random.default_rng(5000 + seed)
+    V = int(rng.integers(3, 11))
+    g = W.multigraph(V, int(rng.integers(V, 4 * V)), cmax=2, seed=9000 + seed)
+    want = brute_force_sink_side(g)
+    for r in solve_both(g):
+        c = certify(g, r)
+        assert np.array_equal(c.side, want)
+
+
+def test_canonical_side_hand_cases():
+    # path 0 -> 1 -> 2 with equal capacities: both arcs are minimum cuts;
+    # only t reaches t in the residual graph, so the side is [0, 0, 1]
+    g = W.from_arcs(3, [(0, 1, 5), (1, 2, 5)], 0, 2)
+    for r in solve_both(g):
+        assert certify(g, r).side.tolist() == [0, 0, 1]
+    assert brute_force_sink_side(g).tolist() == [0, 0, 1]
+    # a bottleneck in the middle of a longer path: 0 -5-> 1 -2-> 2 -5-> 3;
+    # vertices after the bottleneck still reach t, those before it do not
+    g = W.from_arcs(4, [(0, 1, 5), (1, 2, 2), (2, 3, 5)], 0, 3)
+    for r in solve_both(g):
+        assert certify(g, r).side.tolist() == [0, 0, 1, 1]
+    # two tied cuts around vertex 1 with a side branch 1 -> 2 -> 3(t): after
+    # the maximum flow of 3 on 0 -> 1 -> 3, vertex 2 still reaches t through
+    # its own arc, 1 does not (its arcs to 2 and 3 are saturated or absent)
+    g = W.from_arcs(4, [(0, 1, 3), (1, 3, 3), (2, 3, 4)], 0, 3)
+    for r in solve_both(g):
+        assert certify(g, r).side.tolist() == [0, 0, 1, 1]
+    assert brute_force_sink_side(g).tolist() == [0, 0, 1, 1]
 
 
 def _path(caps):
