@@ -13,17 +13,29 @@ stand-in for the paper's large social-network max-flow inputs.
 Prints ONE JSON line.  value = arc-scans per second over the whole timed
 solve (residual entries examined by the sweeps / wall time); ms_per_step is
 the solve time.  The timed steps run exactly as a caller would (sweep
-batches replayed as captured hipGraphs, no events).  "roofline" prices the
-kernel with the largest share of GPU time by its algorithmic bytes per
-launch over its average launch duration; durations come from HIP events
-recorded on the library's stream around every launch of extra instrumented
-solves of the same graph, run right after the timed region (events cannot
-sit between the kernels of a captured batch).  "cpu_baseline" times the
-CPU oracle (FIFO push-relabel) on a bounded sample: the same R-MAT recipe at
-scale 20.  "batched" solves a sample of the batched stream (instances with
-log-uniform V in [256, 65536], out-degree 8, capacities U[1,100]) once as a
-single batch and once as one-at-a-time solves of the same instances, checks
-the results are identical, and reports solves/s of both.
+batches replayed as captured hipGraphs, no events).
+
+"roofline" prices the push-relabel sweep, the path's hot loop: the three
+sweep kernels (short-row tiles, one wave per medium row, workgroup chunks
+of long rows) together, their algorithmic bytes over their device time.
+Durations come from HIP events recorded on the library's stream around
+every launch of an extra instrumented solve of the same graph, run right
+after the timed region (events cannot sit between the kernels of a captured
+batch).  "secondary" prices the global relabel and the residual-graph
+builder the same way, and "kernels" lists every kernel.
+
+"workloads" solves the other three configurations (plain 1k-vertex graph,
+50k+50k Zipf bipartite matching, 2048x2048 grid cut) and checks each value
+against the oracle's stored answer; "rcsr_ms" is the headline graph in the
+paper's other residual layout.  "stream" is the batched and served stream
+as configured: 4,096 instances (V log-uniform in [256, 65536], out-degree 8,
+capacities U[1,100]) solved one at a time, in device batches, through the
+continuous-batching server with all of them queued at once, and with
+Poisson arrivals at 0.25, 0.5, 1 and 2 times the one-at-a-time rate; every
+route's values and cut sides are checked against the one-at-a-time results
+and the values against the oracle's stored answers.  "cpu_baseline" times
+both CPU oracle solvers (FIFO push-relabel, Dinic; one thread each, run
+side by side beside the GPU legs) on the headline graph itself.
 """
 from __future__ import annotations
 
@@ -31,6 +43,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -38,20 +51,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic bytes per unit of work (bidirectional CSR, int32 residuals,
-# int64 excesses, int32 heights):
-#   sweep kernels  per arc-scan 12 B: entry {column, residual} 8 B + height of
-#                  the column 4 B; per queued vertex 24 B: queue slot 4 + row
-#                  bounds 8 + e(u) 8 + h(u) 4; per push 52 B: two residual
-#                  atomics (2 x 8 B read+write), two excess atomics (2 x 16 B
-#                  read+write), mate index 4 B; per relabel 4 B.
+# Algorithmic bytes per unit of work (int32 residuals, int64 excesses, int32
+# heights):
+#   sweep kernels  per arc-scan 12 B (BCSR, RCSR forward entry): entry
+#                  {column, residual} 8 B + height of the column 4 B (an RCSR
+#                  reverse entry adds its 4 B flow gather: 16 B, counted as
+#                  12 B here, so RCSR figures are a lower bound); per queued
+#                  vertex 24 B: queue slot 4 + row bounds 8 + e(u) 8 + h(u) 4;
+#                  per push 52 B: two residual atomics (2 x 8 B read+write),
+#                  two excess atomics (2 x 16 B read+write), mate index 4 B;
+#                  per relabel 4 B.
 #   global relabel per top-down entry 12 B (entry 8 + head height 4); per
 #                  bottom-up entry 9 B (entry 8 + visit code 1); per vertex
 #                  and launch 17 B (height reset 4 + visit reset 1 + queue
 #                  rebuild reads e 8 + h 4).
+#   builder (BCSR) reads row_ptr 8 B per vertex and column + capacity 8 B per
+#                  arc; writes row bounds 8 B per vertex, 16 B per merged
+#                  entry (entry 8, mate 4, merged capacity 4) and 12 B per arc
+#                  (entry index, earlier parallel capacity, capacity): the
+#                  input once and the output once, no sort traffic.
 B_SCAN, B_QUEUED, B_PUSH, B_RELABEL = 12, 24, 52, 4
 B_BFS_TD, B_BFS_BU, B_BFS_V = 12, 9, 17
 KERNELS = ["k_sweep_tile", "k_sweep_tile<64> (medium rows)", "k_sweep_chunk (long-row chunks)", "k_global_relabel"]
+SWEEP_FAMILY = "sweep kernels (k_sweep_tile<P>, k_sweep_tile<64>, k_sweep_chunk*)"
 
 
 def kernel_bytes(st, k):
@@ -63,27 +85,73 @@ def kernel_bytes(st, k):
     return B_BFS_TD * td + B_BFS_BU * bu + B_BFS_V * st["V"] * st["kernel_launches"][3]
 
 
+def builder_bytes(st):
+    return 16 * st["V"] + 20 * st["E"] + 16 * st["M"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(scale: int = 20):
-    import oracle
-    from paper_2404_00270_amd import workloads as W
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    g = W.rmat(scale, 16, 0.57, 0.19, 0.19, 1, 1000, 3)
-    t0 = time.perf_counter()
-    r = oracle.fifo_pr(g.V, g.row_ptr, g.col, g.cap, g.s, g.t)
-    dt = time.perf_counter() - t0
-    return {
-        "value": r.arc_scans / dt,
-        "unit": "arc-scans/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": f"oracle FIFO push-relabel (single thread) on the same R-MAT recipe at scale {scale} "
-                  f"(V={g.V}, E={g.E}): {dt:.2f} s, {r.arc_scans} arc-scans, value {r.value}",
-        "solve_s": dt,
-    }
+
+class CpuBaseline:
+    """Both CPU oracle solvers on one graph, one thread each, side by side in
+    the background (the oracle's C code releases the GIL); the faster one is
+    the reported baseline."""
+
+    def __init__(self, g):
+        self.g = g
+        self.res = {}
+        self.threads = []
+
+    def start(self):
+        import oracle
+
+        def run(name, fn):
+            t0 = time.perf_counter()
+            r = fn(self.g.V, self.g.row_ptr, self.g.col, self.g.cap, self.g.s, self.g.t)
+            self.res[name] = (time.perf_counter() - t0, r.value, r.arc_scans)
+
+        for name, fn in (("fifo_pr", oracle.fifo_pr), ("dinic", oracle.dinic)):
+            th = threading.Thread(target=run, args=(name, fn), daemon=True)
+            th.start()
+            self.threads.append(th)
+        return self
+
+    def result(self, gpu_ms, timeout_s=600):
+        t_end = time.perf_counter() + timeout_s
+        for th in self.threads:
+            th.join(max(0.0, t_end - time.perf_counter()))
+        if not self.res:
+            return None
+        name = min(self.res, key=lambda k: self.res[k][0])
+        dt, value, scans = self.res[name]
+        per = {k: {"solve_s": round(v[0], 2), "value": v[1], "arc_scans": v[2]} for k, v in self.res.items()}
+        g = self.g
+        return {
+            "value": round(dt * 1000.0, 1),
+            "unit": "ms per solve",
+            "cores": len(self.threads),
+            "kind": "oracle",
+            "solver": {"fifo_pr": "FIFO push-relabel", "dinic": "Dinic"}[name],
+            "sample": f"the headline graph itself ({g.name}, V={g.V}, E={g.E}): both oracle solvers, one "
+                      f"thread each, run side by side beside the GPU legs; the faster is reported",
+            "solvers": per,
+            "same_value_as_gpu": None,
+            "host_cpu": host_cpu_model(),
+            "host_nproc": os.cpu_count(),
+            "gpu_speedup": round(dt * 1000.0 / gpu_ms, 1) if gpu_ms else None,
+        }
 
 
 def kernel_table(stats):
@@ -95,12 +163,18 @@ def kernel_table(stats):
         kernels.append({"kernel": KERNELS[k], "ms": round(ms, 3), "launches": launches,
                         "algorithmic_GB": round(nbytes / 1e9, 4),
                         "GBps": round(nbytes / (ms / 1e3) / 1e9, 2) if ms > 0 else None})
+    ms = sum(st["kernel_build_ms"] for st in stats)
+    nbytes = sum(builder_bytes(st) for st in stats)
+    kernels.append({"kernel": "builder (all build kernels)", "ms": round(ms, 3), "launches": len(stats),
+                    "algorithmic_GB": round(nbytes / 1e9, 4),
+                    "GBps": round(nbytes / (ms / 1e3) / 1e9, 2) if ms > 0 else None})
     return kernels
 
 
 def measured_traffic(kernel: str, workload: str):
-    """Calibrated HBM bytes per launch from the committed rocprofv3 counter
-    runs, or None when the kernel sources changed since they were taken."""
+    """Calibrated HBM bytes per launch (per solve for the sweep family and the
+    builder) from the committed rocprofv3 counter runs, or None when the
+    kernel sources changed since they were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
@@ -111,19 +185,15 @@ def measured_traffic(kernel: str, workload: str):
     h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in rec["sources"])).hexdigest()
     if h != rec["sources_sha256"]:
         return None
-    return rec["bytes_per_launch"].get(kernel)
+    return rec.get("bytes", {}).get(kernel)
 
 
-def roofline_of(stats, kernels):
-    dom = max(range(4), key=lambda k: kernels[k]["ms"])
-    if kernels[dom]["launches"] == 0 or kernels[dom]["ms"] <= 0:
+def _priced(name, nbytes, ms, launches, unit_note):
+    if ms <= 0 or launches <= 0:
         return None
-    launches = kernels[dom]["launches"]
-    per_launch_bytes = sum(kernel_bytes(st, dom) for st in stats) / launches
-    avg_launch_s = kernels[dom]["ms"] / 1e3 / launches
-    achieved = per_launch_bytes / avg_launch_s / 1e9
+    achieved = nbytes / (ms / 1e3) / 1e9
     return {
-        "kernel": KERNELS[dom],
+        "kernel": name,
         "bound": "hbm",
         "achieved": round(achieved, 2),
         "peak": HBM_PEAK_GBS,
@@ -131,26 +201,133 @@ def roofline_of(stats, kernels):
         "frac": round(achieved / HBM_PEAK_GBS, 5),
         "traffic": None,
         "launches": launches,
-        "avg_launch_us": round(avg_launch_s * 1e6, 3),
-        "algorithmic_bytes_per_launch": round(per_launch_bytes, 1),
+        "avg_launch_us": round(ms * 1e3 / launches, 3),
+        "algorithmic_bytes_per_launch": round(nbytes / launches, 1),
+        "note": unit_note,
     }
 
 
-def batched_leg(solver, n, dev):
-    """One batch of n stream instances vs n one-at-a-time solves (same outputs)."""
+def roofline_of(stats, kernels):
+    """Headline: the sweep family; secondary: global relabel and builder."""
+    n = len(stats)
+    sw_bytes = sum(kernel_bytes(st, k) for st in stats for k in range(3))
+    sw_ms = sum(kernels[k]["ms"] for k in range(3))
+    sw_launches = sum(kernels[k]["launches"] for k in range(3))
+    head = _priced(SWEEP_FAMILY, sw_bytes, sw_ms, sw_launches,
+                   "achieved = algorithmic bytes of every sweep-kernel launch / their summed event-timed "
+                   "durations; traffic = counter bytes of the sweep kernels per solve")
+    if head is not None:
+        head["per_solve_bytes"] = round(sw_bytes / n, 1)
+        head["per_solve_ms"] = round(sw_ms / n, 3)
+        head["share_of_kernel_time"] = round(sw_ms / max(1e-9, sum(k["ms"] for k in kernels)), 3)
+    rel = _priced(KERNELS[3], sum(kernel_bytes(st, 3) for st in stats), kernels[3]["ms"], kernels[3]["launches"],
+                  "per cooperative launch")
+    bld = _priced("builder", sum(builder_bytes(st) for st in stats), kernels[4]["ms"], n,
+                  "per solve: input read once plus output written once over the builder's device time")
+    return head, [x for x in (rel, bld) if x is not None]
+
+
+def other_workloads(names, dev, steps=3):
+    """Solve times of the other configurations, each value checked against
+    the oracle's stored answer."""
+    import torch
+
+    from paper_2404_00270_amd import workloads as W
+    from paper_2404_00270_amd import wbpr
+
+    with open(os.path.join(ROOT, "tests", "golden", "workload_values.json")) as f:
+        gold = json.load(f)
+    out = {}
+    for name in names:
+        t0 = time.perf_counter()
+        g = W.WORKLOADS[name]()
+        gen_s = time.perf_counter() - t0
+        rp = torch.from_numpy(g.row_ptr).to(dev)
+        col = torch.from_numpy(g.col).to(dev)
+        cap = torch.from_numpy(g.cap).to(dev)
+        value = torch.zeros(1, dtype=torch.int64, device=dev)
+        flow = torch.zeros(max(g.E, 1), dtype=torch.int32, device=dev)
+        side = torch.zeros(g.V, dtype=torch.uint8, device=dev)
+        with wbpr.Solver(0, max_wall_ms=120_000) as solver:
+            solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)  # warm-up
+            ms, scans = [], 0
+            for _ in range(steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)
+                torch.cuda.synchronize()
+                ms.append((time.perf_counter() - t0) * 1000.0)
+                scans += st["arc_scans"]
+        ms.sort()
+        v = int(value.item())
+        out[name] = {"graph": g.name, "V": g.V, "E": g.E, "ms_per_solve": round(ms[len(ms) // 2], 3),
+                     "arc_scans_per_s": round(scans / (sum(ms) / 1e3), 1), "max_flow": v,
+                     "equals_oracle": v == gold[name]["value"], "lds_resident": bool(st["lds_solved"]),
+                     "generated_s": round(gen_s, 1)}
+        log(f"[bench] {name}: {out[name]}")
+        del rp, col, cap, flow, side
+    return out
+
+
+def layout_time(g, rp, col, cap, dev, layout, steps=3):
+    """Median solve time of the headline graph in another residual layout."""
+    import torch
+
+    from paper_2404_00270_amd import wbpr
+
+    value = torch.zeros(1, dtype=torch.int64, device=dev)
+    flow = torch.zeros(max(g.E, 1), dtype=torch.int32, device=dev)
+    side = torch.zeros(g.V, dtype=torch.uint8, device=dev)
+    with wbpr.Solver(0, max_wall_ms=120_000, layout=layout) as solver:
+        solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)
+        ms = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            solver.solve_tensors(g.V, rp, col, cap, g.s, g.t, value, flow, side)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1000.0)
+    ms.sort()
+    return ms[len(ms) // 2], int(value.item())
+
+
+def _stream_golden(n):
+    path = os.path.join(ROOT, "tests", "golden", "batch_stream_values.txt")
+    vals = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            for ln in f:
+                if ln.startswith("#") or not ln.strip():
+                    continue
+                parts = ln.split()
+                vals[int(parts[0])] = int(parts[3])
+    return [vals.get(i) for i in range(n)]
+
+
+def stream_leg(n, dev, rates, group=256, budget=1 << 30, slots=256, seed=5):
+    """The batched and served stream: n instances solved one at a time, in
+    device batches of `group`, through the server with all queued at once,
+    and through the server with Poisson arrivals at each rate multiple of
+    the one-at-a-time throughput."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
     import torch
 
     from paper_2404_00270_amd import workloads as W
     from paper_2404_00270_amd import wbpr
 
-    gs = [W.batch_instance(i) for i in range(n)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(16) as ex:  # the generator releases the GIL
+        gs = list(ex.map(W.batch_instance, range(n)))
+    gen_s = time.perf_counter() - t0
     Vs = [g.V for g in gs]
     Es = [g.E for g in gs]
+    Vt, Et = sum(Vs), sum(Es)
+    log(f"[bench] stream: {n} instances, V={Vt} E={Et}, generated in {gen_s:.1f}s")
     rp = torch.from_numpy(np.concatenate([g.row_ptr for g in gs]).astype(np.int64)).to(dev)
     col = torch.from_numpy(np.concatenate([g.col for g in gs]).astype(np.int32)).to(dev)
     cap = torch.from_numpy(np.concatenate([g.cap for g in gs]).astype(np.int32)).to(dev)
-    Vt, Et = sum(Vs), sum(Es)
     vals = [torch.zeros(n, dtype=torch.int64, device=dev) for _ in range(2)]
     flows = [torch.zeros(max(Et, 1), dtype=torch.int32, device=dev) for _ in range(2)]
     sides = [torch.zeros(Vt, dtype=torch.uint8, device=dev) for _ in range(2)]
@@ -158,58 +335,66 @@ def batched_leg(solver, n, dev):
     eo = np.concatenate([[0], np.cumsum(Es)])
     vo = np.concatenate([[0], np.cumsum(Vs)])
     torch.cuda.synchronize()
-
-    def one_at_a_time():
-        for i, g in enumerate(gs):
+    out = {"instances": n, "V_total": Vt, "E_total": Et,
+           "recipe": f"batch_instance(0..{n - 1}): V log-uniform [256, 65536], 8V distinct uniform arcs, caps "
+                     "U[1,100], s = 0, t = V - 1; every route writes values, flows and cut sides"}
+    with wbpr.Solver(0, max_wall_ms=300_000) as solver:
+        def solve_one(i, k=0):
+            g = gs[i]
             wbpr.wbpr_solve_device(solver.ctx, g.V, g.E, rp.data_ptr() + 8 * int(ro[i]),
                                    col.data_ptr() + 4 * int(eo[i]), cap.data_ptr() + 4 * int(eo[i]), g.s, g.t, 0,
-                                   vals[0].data_ptr() + 8 * i, flows[0].data_ptr() + 4 * int(eo[i]),
-                                   sides[0].data_ptr() + int(vo[i]))
+                                   vals[k].data_ptr() + 8 * i, flows[k].data_ptr() + 4 * int(eo[i]),
+                                   sides[k].data_ptr() + int(vo[i]))
 
-    def batch():
-        return wbpr.wbpr_solve_batch_device(solver.ctx, Vs, Es, [g.s for g in gs], [g.t for g in gs], rp.data_ptr(),
-                                            col.data_ptr(), cap.data_ptr(), 0, vals[1].data_ptr(),
-                                            flows[1].data_ptr(), sides[1].data_ptr())
+        def solve_group(a, b):
+            return wbpr.wbpr_solve_batch_device(
+                solver.ctx, Vs[a:b], Es[a:b], [g.s for g in gs[a:b]], [g.t for g in gs[a:b]],
+                rp.data_ptr() + 8 * int(ro[a]), col.data_ptr() + 4 * int(eo[a]), cap.data_ptr() + 4 * int(eo[a]), 0,
+                vals[1].data_ptr() + 8 * a, flows[1].data_ptr() + 4 * int(eo[a]), sides[1].data_ptr() + int(vo[a]))
 
-    batch()  # warm: arena sized for the batch
-    one_at_a_time()
-    t0 = time.perf_counter()
-    one_at_a_time()
-    t_single = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    st = batch()
-    t_batch = time.perf_counter() - t0
-    same = bool(torch.equal(vals[0], vals[1]) and torch.equal(sides[0], sides[1]))
-    served = served_leg(solver, gs, rate=2.0 * n / t_single, alone_values=vals[0].cpu().numpy(),
-                        alone_sides=sides[0].cpu().numpy(), vo=vo)
-    return {
-        "instances": n,
-        "V_total": Vt,
-        "E_total": Et,
-        "batched_solves_per_s": n / t_batch,
-        "single_solves_per_s": n / t_single,
-        "speedup": t_single / t_batch,
-        "batched_ms": t_batch * 1e3,
-        "single_ms": t_single * 1e3,
-        "identical_values_and_cuts": same,
-        "batched_rounds": st["global_relabels"],
-        "batched_sweeps": st["sweeps"],
-        "sample": f"batch_instance(0..{n - 1}): V log-uniform [256, 65536], out-degree 8, caps U[1,100]; "
-                  "flows, cut sides and values written by both legs",
-        "served": served,
-    }
+        # warm-up: the arena grows to the largest instance and the largest group once
+        solve_one(int(np.argmax(Es)))
+        big_group = max(range(0, n, group), key=lambda a: sum(Es[a:a + group]))
+        solve_group(big_group, min(n, big_group + group))
+        t0 = time.perf_counter()
+        for i in range(n):
+            solve_one(i)
+        t_single = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for a in range(0, n, group):
+            solve_group(a, min(n, a + group))
+        t_batch = time.perf_counter() - t0
+        same = bool(torch.equal(vals[0], vals[1]) and torch.equal(sides[0], sides[1]))
+        alone_v = vals[0].cpu().numpy()
+        alone_s = sides[0].cpu().numpy()
+        gold = _stream_golden(n)
+        out["one_at_a_time"] = {"solves_per_s": round(n / t_single, 1), "ms": round(t_single * 1e3, 1)}
+        out["batched_groups"] = {"solves_per_s": round(n / t_batch, 1), "ms": round(t_batch * 1e3, 1),
+                                 "group": group, "identical_to_one_at_a_time": same}
+        out["values_equal_oracle"] = all(gv is not None and int(alone_v[i]) == gv for i, gv in enumerate(gold))
+        log(f"[bench] stream one-at-a-time {out['one_at_a_time']} batched {out['batched_groups']}")
+        r1 = n / t_single
+        served = []
+        for mult in [None] + list(rates):
+            rate = None if mult is None else mult * r1
+            leg = served_leg(solver, gs, rate, alone_v, alone_s, vo, budget, slots, seed)
+            leg["rate_multiple_of_one_at_a_time"] = mult
+            served.append(leg)
+            log(f"[bench] served {'saturating' if mult is None else f'{mult}x'}: {leg}")
+        out["served"] = served
+    out["generated_s"] = round(gen_s, 1)
+    return out
 
 
 def served_leg(solver, gs, rate, alone_values, alone_sides, vo, budget=1 << 30, slots=256, seed=5):
-    """Poisson arrivals at `rate` requests/s into the continuous-batching server."""
-    import threading
-
+    """Requests into the continuous-batching server: Poisson arrivals at `rate`
+    per second, or all queued at once (rate None: the server's capacity)."""
     import numpy as np
 
     from paper_2404_00270_amd import wbpr
 
     rng = np.random.default_rng(seed)
-    gaps = rng.exponential(1.0 / rate, size=len(gs))
+    gaps = rng.exponential(1.0 / rate, size=len(gs)) if rate else np.zeros(len(gs))
     tickets = [None] * len(gs)
     with wbpr.Server(solver, hbm_budget_bytes=budget, max_slots=slots) as srv:
         def producer():
@@ -232,26 +417,25 @@ def served_leg(solver, gs, rate, alone_values, alone_sides, vo, budget=1 << 30, 
     same = ok and all(int(r.value) == int(alone_values[i]) and
                       np.array_equal(r.side, alone_sides[vo[i]:vo[i + 1]]) for i, r in enumerate(res))
     return {
-        "arrival_rate_per_s": rate,
-        "solves_per_s": st["solves_per_s"],
-        "wall_solves_per_s": len(gs) / wall,
-        "p50_ms": st["p50_ms"],
-        "p99_ms": st["p99_ms"],
-        "max_ms": st["max_ms"],
+        "arrival_rate_per_s": round(rate, 1) if rate else "all queued at once",
+        "solves_per_s": round(st["solves_per_s"], 1),
+        "wall_solves_per_s": round(len(gs) / wall, 1),
+        "p50_ms": round(st["p50_ms"], 2),
+        "p99_ms": round(st["p99_ms"], 2),
+        "max_ms": round(st["max_ms"], 2),
         "peak_resident": st["peak_resident"],
         "rounds": st["rounds"],
-        "admissions": st["admissions"],
         "hbm_budget_bytes": budget,
-        "arena_bytes": st["arena_bytes"],
         "identical_to_alone": bool(same),
     }
 
 
 def ablation(workloads, dev, steps=2):
-    """The paper's thread-centric / vertex-centric comparison (its Tables 1-2)
-    on the synthetic stand-ins, BCSR layout: one thread per active vertex
-    versus tiles of lanes, each with the paper's full-scan active-vertex queue
-    and with the incremental queue.  Every variant must give the same value."""
+    """The paper's comparison (its Tables 1-2) on the synthetic stand-ins:
+    thread-centric (one thread per active vertex) versus vertex-centric
+    (tiles of lanes) on both residual layouts, BCSR and RCSR, each with the
+    paper's full-scan active-vertex queue and with the incremental queue.
+    Every variant must give the same value."""
     import torch
 
     from paper_2404_00270_amd import workloads as W
@@ -260,12 +444,14 @@ def ablation(workloads, dev, steps=2):
     # every variant runs the rounds of sweep launches (lds_max_v = -1) without
     # the gap heuristic (gap = -1): the comparison is between the paper's
     # sweep kernels, not the LDS-resident solve or the added heuristic
-    variants = [
-        ("VC, incremental queue (default)", dict(lds_max_v=-1, gap=-1)),
-        ("VC, full-scan queue (Algorithm 2)", dict(avq_mode=1, lds_max_v=-1, gap=-1)),
-        ("TC, full-scan queue (paper baseline)", dict(lanes_per_vertex=1, avq_mode=1, lds_max_v=-1, gap=-1)),
-        ("TC, incremental queue", dict(lanes_per_vertex=1, lds_max_v=-1, gap=-1)),
-    ]
+    variants = []
+    for lay, ln in ((1, "BCSR"), (2, "RCSR")):
+        variants += [
+            (f"VC+{ln}, incremental queue", dict(layout=lay, lds_max_v=-1, gap=-1)),
+            (f"VC+{ln}, full-scan queue", dict(layout=lay, avq_mode=1, lds_max_v=-1, gap=-1)),
+            (f"TC+{ln}, full-scan queue", dict(layout=lay, lanes_per_vertex=1, avq_mode=1, lds_max_v=-1, gap=-1)),
+            (f"TC+{ln}, incremental queue", dict(layout=lay, lanes_per_vertex=1, lds_max_v=-1, gap=-1)),
+        ]
     out = []
     for name in workloads:
         g = W.WORKLOADS[name]()
@@ -294,9 +480,10 @@ def ablation(workloads, dev, steps=2):
                 solver.close()
             log(f"[ablation] {g.name} {label}: {row[label]}")
         row["same_value"] = len(values) == 1
-        tc, vc = row.get("TC, full-scan queue (paper baseline)"), row.get("VC, full-scan queue (Algorithm 2)")
-        if isinstance(tc, float) and isinstance(vc, float):
-            row["paper_speedup_vc_over_tc"] = round(tc / vc, 2)
+        for ln in ("BCSR", "RCSR"):  # the paper's speed-up column: TC time / VC time, same layout
+            tc, vc = row.get(f"TC+{ln}, full-scan queue"), row.get(f"VC+{ln}, full-scan queue")
+            if isinstance(tc, float) and isinstance(vc, float):
+                row[f"speedup_vc_over_tc_{ln}"] = round(tc / vc, 2)
         out.append(row)
     return out
 
@@ -390,8 +577,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--kernel-steps", type=int, default=1, help="instrumented solves for the per-kernel roofline")
     ap.add_argument("--workload", default="rmat", choices=["plain", "bipartite", "rmat", "grid"])
+    ap.add_argument("--layout", type=int, default=0, help="residual layout of the timed steps (1 BCSR, 2 RCSR)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
+    ap.add_argument("--stream", type=int, default=4096, help="instances of the batched/served stream (0: skip)")
+    ap.add_argument("--stream-rates", default="0.25,0.5,1,2",
+                    help="served arrival rates, multiples of the one-at-a-time throughput")
+    ap.add_argument("--no-other-workloads", action="store_true")
     ap.add_argument("--no-flows", action="store_true", help="value and cut only (skips the second phase)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--gr-every", type=int, default=0)
@@ -457,7 +648,7 @@ def main():
 
     opts = dict(lanes_per_vertex=args.lanes, gr_every_sweeps=args.gr_every, gr_work_permille=args.gr_permille,
                 split_degree=args.split, block_degree=args.block_degree, push_mode=args.push_mode,
-                grid_blocks=args.blocks, no_graph=int(args.no_graph), max_wall_ms=300_000)
+                grid_blocks=args.blocks, no_graph=int(args.no_graph), layout=args.layout, max_wall_ms=300_000)
     solver = wbpr.Solver(0, **opts)
 
     def step():
@@ -489,13 +680,24 @@ def main():
         solver.set_options(**opts, time_kernels=1)
         for i in range(args.kernel_steps):
             kstats.append(step())
-            log(f"[bench] instrumented {i}: total {kstats[-1]['ms_total']:.1f} ms kernel_ms={kstats[-1]['kernel_ms']}")
+            log(f"[bench] instrumented {i}: total {kstats[-1]['ms_total']:.1f} ms kernel_ms={kstats[-1]['kernel_ms']} "
+                f"build_ms={kstats[-1]['kernel_build_ms']:.2f}")
         solver.set_options(**opts)
         assert int(value.item()) == flow_value
     kernels = kernel_table(kstats) if kstats else None
-    roofline = roofline_of(kstats, kernels) if kstats else None
-    if roofline is not None and args.workload == "rmat":
-        roofline["traffic"] = measured_traffic(roofline["kernel"], "rmat_s22")
+    roofline, secondary = roofline_of(kstats, kernels) if kstats else (None, [])
+    if args.workload == "rmat" and args.layout in (0, 1):
+        if roofline is not None:
+            roofline["traffic"] = measured_traffic("sweep", "rmat_s22")
+        for sec in secondary:
+            sec["traffic"] = measured_traffic("relabel" if sec["kernel"] == KERNELS[3] else "builder", "rmat_s22")
+    solver.close()
+
+    # the CPU oracle on the headline graph, in the background from here on
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle (FIFO push-relabel and Dinic) started on the headline graph")
+        cpu = CpuBaseline(g).start()
 
     out = {
         "metric": "max-flow solve time & arc-scans/s (GB/s vs HBM peak); batched solves/s + p99",
@@ -508,7 +710,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": "int32/int64",
         "data": "synthetic",
         "config": {
             "workload": g.name,
@@ -519,6 +721,7 @@ def main():
             "t": g.t,
             "max_flow": flow_value,
             "flows": not args.no_flows,
+            "layout": "RCSR" if stats and stats[-1]["layout"] == 2 else "BCSR",
             "lanes_per_vertex": stats[-1]["lanes_per_vertex"] if stats else None,
             "split_degree": stats[-1]["split_degree"] if stats else None,
             "block_degree": stats[-1]["block_degree"] if stats else None,
@@ -530,18 +733,30 @@ def main():
             "hipgraph": bool(stats[-1]["use_graph"]) if stats else None,
         },
         "roofline": roofline,
+        "secondary": secondary,
         "kernels": kernels,
         "cpu_baseline": None,
-        "batched": None,
+        "workloads": None,
+        "stream": None,
     }
-    if args.batch > 0:
-        log(f"[bench] batched leg: {args.batch} stream instances")
-        out["batched"] = batched_leg(solver, args.batch, dev)
-        log(f"[bench] batched: {out['batched']}")
-    if not args.no_cpu_baseline and args.workload == "rmat":
-        log("[bench] timing the CPU oracle on the bounded sample")
-        out["cpu_baseline"] = cpu_baseline()
-    solver.close()
+    if args.layout in (0, 1):
+        rc_ms, rc_value = layout_time(g, rp, col, cap, dev, 2)
+        out["rcsr_ms"] = round(rc_ms, 3)
+        out["rcsr_same_value"] = rc_value == flow_value
+        log(f"[bench] RCSR layout: {rc_ms:.1f} ms value={rc_value}")
+    del rp, col, cap, flow, side
+    torch.cuda.empty_cache()
+    if not args.no_other_workloads:
+        out["workloads"] = other_workloads([w for w in ("plain", "bipartite", "grid") if w != args.workload], dev)
+    torch.cuda.empty_cache()
+    if args.stream > 0:
+        rates = [float(x) for x in args.stream_rates.split(",") if x]
+        out["stream"] = stream_leg(args.stream, dev, rates)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu.result(ms_per_step)
+        if out["cpu_baseline"] is not None:
+            out["cpu_baseline"]["same_value_as_gpu"] = all(v[1] == flow_value for v in cpu.res.values())
+        log(f"[bench] cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
 

@@ -78,7 +78,18 @@ typedef struct wbpr_csr {
     const int32_t *cap;
 } wbpr_csr;
 
-enum wbpr_layout { WBPR_LAYOUT_AUTO = 0, WBPR_LAYOUT_BCSR = 1 };
+/* Residual-graph layouts (paper, section 3.2; same results, different speed):
+ *   BCSR: bidirectional CSR, one entry per ordered vertex pair (parallel and
+ *     antiparallel arcs merged), columns sorted, the mate entry of every
+ *     entry precomputed; every residual read is coalesced.
+ *   RCSR: the input CSR (forward entries, residual c - f) beside a reversed
+ *     CSR of every vertex's in-arcs whose entries point at the arc's forward
+ *     entry; the residual of a reverse entry (the arc's flow) is read through
+ *     that index, one uncoalesced gather.  No merging: parallel arcs stay
+ *     separate entries.  Instances in this layout always take the rounds of
+ *     launches (no LDS-resident solve).
+ * AUTO is BCSR. */
+enum wbpr_layout { WBPR_LAYOUT_AUTO = 0, WBPR_LAYOUT_BCSR = 1, WBPR_LAYOUT_RCSR = 2 };
 
 /* Tuning knobs.  Zero means "choose automatically" for every field.  None of
  * them changes the results, only the speed. */
@@ -177,6 +188,10 @@ typedef struct wbpr_stats {
                                       and were finished by the rounds of launches */
     int64_t gap_skipped;           /* queued vertices the gap heuristic left to the
                                       next global relabel (option gap) */
+    double kernel_build_ms;        /* residual-graph builder, device time between
+                                      events around it (time_kernels only) */
+    int32_t layout;                /* enum wbpr_layout the solve used */
+    int32_t reserved0;
 } wbpr_stats;
 
 typedef struct wbpr_ctx wbpr_ctx;

@@ -55,6 +55,7 @@ wb::SolveConfig to_config(const wbpr_options *o) {
   c.wave_trace = o->wave_trace != 0;
   c.lds_max_v = o->lds_max_v;
   c.gap = o->gap >= 0;
+  c.rcsr = o->layout == WBPR_LAYOUT_RCSR;
   return c;
 }
 
@@ -68,7 +69,8 @@ int check_options(const wbpr_options *o) {
       o->gr_stagnation < 0 ||
       o->max_sweeps < 0 || o->max_wall_ms < 0 || o->grid_blocks < 0)
     return fail(WBPR_EINVAL, "negative option");
-  if (o->layout != WBPR_LAYOUT_AUTO && o->layout != WBPR_LAYOUT_BCSR) return fail(WBPR_EINVAL, "unknown layout");
+  if (o->layout != WBPR_LAYOUT_AUTO && o->layout != WBPR_LAYOUT_BCSR && o->layout != WBPR_LAYOUT_RCSR)
+    return fail(WBPR_EINVAL, "unknown layout");
   if (o->push_mode < 0 || o->push_mode > 2) return fail(WBPR_EINVAL, "push_mode must be 0, 1 or 2");
   return WBPR_OK;
 }
@@ -111,13 +113,15 @@ void fill_stats(wbpr_stats *st, const wb::EngineStats &r, const wb::SolveConfig 
   st->lds_solved = r.small_solved;
   st->gap_skipped = r.gap_skipped;
   st->lds_fallbacks = r.small_fallbacks;
+  st->kernel_build_ms = r.build_ms;
+  st->layout = cfg.rcsr ? WBPR_LAYOUT_RCSR : WBPR_LAYOUT_BCSR;
 }
 
 }  // namespace
 
 extern "C" {
 
-const char *wbpr_version(void) { return "wbpr-mi355x 0.2 (gfx950, BCSR vertex-centric push-relabel, batched engine)"; }
+const char *wbpr_version(void) { return "wbpr-mi355x 0.2 (gfx950, BCSR and RCSR vertex-centric push-relabel, batched engine)"; }
 
 const char *wbpr_last_error(void) { return g_err.c_str(); }
 
@@ -225,7 +229,7 @@ bool same_schedule(const wb::SolveConfig &a, const wb::SolveConfig &b) {
          a.gr_every_sweeps == b.gr_every_sweeps && a.grid_blocks == b.grid_blocks &&
          a.time_kernels == b.time_kernels && a.push_mode == b.push_mode && a.use_graph == b.use_graph &&
          a.max_sweeps == b.max_sweeps && a.max_wall_ms == b.max_wall_ms && a.wave_trace == b.wave_trace &&
-         a.lds_max_v == b.lds_max_v && a.gap == b.gap;
+         a.lds_max_v == b.lds_max_v && a.gap == b.gap && a.rcsr == b.rcsr;
 }
 
 // Solves a group already packed on the device, from an empty engine.

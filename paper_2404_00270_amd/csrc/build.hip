@@ -21,6 +21,7 @@
 //      pairwise int32 overflow check runs only if some entry holds >= 2^30
 #include "wb_common.h"
 #include "wb_internal.h"
+#include "wb_kernels.h"
 
 namespace wb {
 
@@ -420,6 +421,136 @@ __global__ void k_pair_check(const int32_t *rev, int32_t mbase, const int2 *ent,
   }
   ovf = block_reduce_i32<false>(ovf);
   if (threadIdx.x == 0 && ovf) atomicAdd(&st->overflow, ovf);
+}
+
+// ------------------------------------------------------------------ RCSR
+// The paper's other layout (section 3.2, its reversed CSR): no merging.  Row
+// x of the arena is x's out-arcs in input order (forward entries, the input
+// CSR's own row, shifted by the number of in-arcs of lower vertices), then
+// x's in-arcs ordered by tail (reverse entries).  One stable radix sort of
+// the arcs by head gives every reverse row and, by binary search over the
+// sorted heads, the in-degree prefix R[x]; then
+//   first(x) = row_ptr[x] + R[x],   forward entry of arc i = i + R[u],
+//   reverse entry of the j-th arc in head order = row_ptr[v + 1] + j.
+
+// Validates arcs and emits the head of every arc as its sort key.
+__global__ void k_rc_keys(const int64_t *rp, const int32_t *row_of, const int32_t *col, const int32_t *cap, int32_t V,
+                          int64_t E, uint64_t *keys, uint32_t *vals, BuildStatus *st) {
+  int bad = 0, nself = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = col[i];
+    const bool ok = v >= 0 && v < V;
+    if (!ok || cap[i] < 0) bad++;
+    if (ok && v == row_of[i]) nself++;
+    keys[i] = ok ? (uint64_t)v : 0;
+    vals[i] = (uint32_t)i;
+  }
+  bad = block_reduce_i32<false>(bad);
+  nself = block_reduce_i32<false>(nself);
+  if (threadIdx.x == 0) {
+    if (bad) atomicAdd(&st->bad_input, bad);
+    if (nself) atomicAdd(&st->nself, nself);
+  }
+}
+
+// R[x] = arcs whose head is below x, x in [0, V]: first sorted head >= x.
+__global__ void k_rc_inprefix(const uint64_t *keys, int64_t E, int32_t V, int32_t *R) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= V; x += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = E;
+    while (lo < hi) {
+      const int64_t mid = lo + (hi - lo) / 2;
+      if (keys[mid] < (uint64_t)x) lo = mid + 1; else hi = mid;
+    }
+    R[x] = (int32_t)lo;
+  }
+}
+
+// Forward entries (arc order: coalesced reads and writes).  A self-loop gets
+// residual 0 both ways, so it never carries flow.
+__global__ void k_rc_forward(const int32_t *row_of, const int32_t *col, const int32_t *cap, int64_t E, const int32_t *R,
+                             int32_t vbase, int32_t mbase, int2 *ent, int32_t *cap0, int32_t *flow, int32_t *arc2ent) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = row_of[i], v = col[i];
+    const int32_t c = u == v ? 0 : cap[i];
+    const int32_t k = (int32_t)i + R[u];
+    ent[k] = make_int2(vbase + v, c);
+    cap0[k] = c;
+    flow[k] = 0;
+    arc2ent[i] = mbase + k;
+  }
+}
+
+// Reverse entries (head order: sequential writes, gathered tails).
+__global__ void k_rc_reverse(const int64_t *rp, const uint64_t *keys, const uint32_t *vals, const int32_t *row_of,
+                             int64_t E, const int32_t *R, int32_t vbase, int32_t mbase, int2 *ent, int32_t *cap0,
+                             int32_t *flow) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < E; j += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = (int32_t)keys[j];
+    const int32_t i = (int32_t)vals[j];
+    const int32_t u = row_of[i];
+    const int64_t r1 = rp[v + 1];
+    if (r1 < 0 || r1 > E) continue;  // malformed row pointers: k_check_rowptr rejects the build
+    const int32_t k = (int32_t)(r1 + j);
+    ent[k] = make_int2((vbase + u) | RC_REV, mbase + i + R[u]);
+    cap0[k] = 0;
+    flow[k] = 0;  // unused: a reverse entry's flow lives at its forward entry
+  }
+}
+
+__global__ void k_rc_rowb(const int64_t *rp, const int32_t *R, int32_t V, int64_t E, int32_t vbase, int32_t mbase,
+                          int2 *rowb) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < V; x += (int64_t)gridDim.x * blockDim.x) {
+    // clamped: a malformed build is rejected, but its rows must stay in range until then
+    const int64_t lo = rp[x] < 0 ? 0 : (rp[x] > E ? E : rp[x]);
+    const int64_t hi = rp[x + 1] < lo ? lo : (rp[x + 1] > E ? E : rp[x + 1]);
+    rowb[vbase + x] = make_int2(mbase + (int32_t)(lo + R[x]), mbase + (int32_t)(hi + R[x + 1]));
+  }
+}
+
+__global__ void k_rc_count(int64_t E, BuildStatus *st) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->M = (int32_t)(2 * E);
+}
+
+hipError_t build_residual_rcsr(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, int32_t V, int64_t E,
+                               const Arena &A, const Place &pl, void *scratch, BuildStatus *status_dev,
+                               hipStream_t st) {
+  Scratch s;
+  carve_scratch(V, E, scratch, &s);
+  hipError_t e = hipMemsetAsync(status_dev, 0, sizeof(BuildStatus), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_check_rowptr, dim3(grid_for(V + 1)), dim3(BT), 0, st, row_ptr, V, E, status_dev, s.rowcnt);
+  if (E == 0) {
+    e = excl_scan_i32(s.rowcnt, s.rptr, (int64_t)V + 1, nullptr, s.stemp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_rowb, dim3(grid_for(V)), dim3(BT), 0, st, s.rptr, V, pl.vbase, (int32_t)pl.mbase, A.rowb);
+    return hipGetLastError();
+  }
+  const int vb = bits_for(V);
+  // row of every arc (marks at the row starts and a prefix sum), as BCSR
+  e = hipMemsetAsync(s.head, 0, 4 * ((size_t)E + 1), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_marks, dim3(grid_for(V)), dim3(BT), 0, st, row_ptr, V, E, s.head);
+  e = excl_scan_i32(s.head, s.hx, E + 1, nullptr, s.stemp, st);
+  if (e != hipSuccess) return e;
+  const int32_t *row_of = s.hx + 1;
+  hipLaunchKernelGGL(k_rc_keys, dim3(grid_for(E)), dim3(BT), 0, st, row_ptr, row_of, col, cap, V, E, s.k0, s.v0,
+                     status_dev);
+  int alt = 0;
+  e = radix_sort_u64_u32(s.k0, s.v0, s.k1, s.v1, E, vb, s.hist, s.stemp, &alt, st);
+  if (e != hipSuccess) return e;
+  const uint64_t *keys = alt ? s.k1 : s.k0;
+  const uint32_t *vals = alt ? s.v1 : s.v0;
+  int32_t *R = s.rptr;
+  int32_t *flow = A.rev + pl.mbase;
+  hipLaunchKernelGGL(k_rc_inprefix, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, E, V, R);
+  hipLaunchKernelGGL(k_rc_forward, dim3(grid_for(E)), dim3(BT), 0, st, row_of, col, cap, E, R, pl.vbase,
+                     (int32_t)pl.mbase, A.ent + pl.mbase, A.cap0 + pl.mbase, flow, A.arc2ent + pl.abase);
+  hipLaunchKernelGGL(k_rc_reverse, dim3(grid_for(E)), dim3(BT), 0, st, row_ptr, keys, vals, row_of, E, R, pl.vbase,
+                     (int32_t)pl.mbase, A.ent + pl.mbase, A.cap0 + pl.mbase, flow);
+  hipLaunchKernelGGL(k_rc_rowb, dim3(grid_for(V)), dim3(BT), 0, st, row_ptr, R, V, E, pl.vbase, (int32_t)pl.mbase,
+                     A.rowb);
+  hipLaunchKernelGGL(k_rc_count, dim3(1), dim3(1), 0, st, E, status_dev);
+  return hipGetLastError();
 }
 
 hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, int32_t V, int64_t E,

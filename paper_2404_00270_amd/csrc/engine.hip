@@ -93,7 +93,7 @@ struct InstArgs {
   const InstDev *L;
   int2 *rowb;
   int2 *ent;
-  const int32_t *rev;
+  int32_t *rev;         // BCSR: mates; RCSR: flows (at forward entries)
   const int32_t *cap0;
   const int32_t *arc2ent;
   const int32_t *pbefore;
@@ -103,7 +103,14 @@ struct InstArgs {
   int32_t *inst_of;
   const int32_t *slot;  // [n] instance slot of list entry i (IK_INIT)
   int32_t *maxdeg;      // [n] longest row of list entry i, terminals excluded (IK_MAXDEG)
+  int32_t rcsr;         // rows in the RCSR layout
 };
+
+// Residual of entry k whose words are cr, in either layout (one-off
+// per-instance kernels: a runtime branch).
+__device__ __forceinline__ int32_t inst_res(const InstArgs &a, int2 cr) {
+  return a.rcsr && cr.x < 0 ? a.rev[cr.y] : cr.y;
+}
 
 // Whole solve of one small instance by one workgroup, its residual graph in
 // LDS (the batched pattern for instances of up to about a thousand
@@ -319,9 +326,17 @@ __global__ void k_inst(InstArgs a, int which) {
       const int2 rb = a.rowb[d.s];
       for (int64_t k = rb.x + tid; k < rb.y; k += nth) {
         const int2 cr = a.ent[k];
-        if (cr.y > 0) {
+        if (!a.rcsr) {
+          if (cr.y > 0) {
+            a.ent[k].y = 0;
+            atomic_add_i32(&a.ent[a.rev[k]].y, cr.y);
+            atomic_add_i64(&a.e[cr.x], (long long)cr.y);
+          }
+        } else if (cr.x >= 0 && cr.y > 0) {
+          // RCSR: only forward entries of s have residual at the start (the
+          // flow on s's in-arcs, their reverse entries' residual, is 0)
           a.ent[k].y = 0;
-          atomic_add_i32(&a.ent[a.rev[k]].y, cr.y);
+          a.rev[k] = cr.y;
           atomic_add_i64(&a.e[cr.x], (long long)cr.y);
         }
       }
@@ -337,7 +352,7 @@ __global__ void k_inst(InstArgs a, int which) {
       __shared__ long long s_part[256 / WB_WAVE];
       const int2 rb = a.rowb[d.t];
       long long acc = 0;
-      for (int64_t k = rb.x + tid; k < rb.y; k += nth) acc += (long long)a.ent[k].y - (long long)a.cap0[k];
+      for (int64_t k = rb.x + tid; k < rb.y; k += nth) acc += (long long)inst_res(a, a.ent[k]) - (long long)a.cap0[k];
       acc = group_sum_i64<WB_WAVE>(acc);
       if (lane() == 0) s_part[threadIdx.x / WB_WAVE] = acc;
       __syncthreads();
@@ -358,7 +373,9 @@ __global__ void k_inst(InstArgs a, int which) {
     case IK_DECODE:
       // per-arc flow from the merged net flow of the ordered pair (u,v):
       // parallel arcs u->v are filled in input order up to their capacities
-      if (d.flow)
+      if (d.flow && a.rcsr) {  // RCSR: every arc has its own flow word
+        for (int64_t i = tid; i < d.E; i += nth) d.flow[i] = a.rev[a.arc2ent[d.abase + i]];
+      } else if (d.flow)
         for (int64_t i = tid; i < d.E; i += nth) {
           const int32_t j = a.arc2ent[d.abase + i];
           int32_t f = 0;
@@ -615,6 +632,41 @@ int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int6
       return e == hipErrorOutOfMemory ? WBPR_ENOMEM : WBPR_EDEVICE;
     }
     arena_n_ = bytes;
+    carve(Vcap, Mcap, Ecap, ncap);
+    // free arena: empty rows, inactive vertices, no instance
+    e = hipMemset(arena_, 0, bytes);
+    if (e == hipSuccess) e = hipMemset(inst_of_, 0xff, 4 * (size_t)Vcap);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      *err = std::string("arena init: ") + hipGetErrorString(e);
+      return WBPR_EDEVICE;
+    }
+    reset_books();
+    e = ensure_pinned(err);
+    if (e != hipSuccess) return WBPR_ENOMEM;
+  }
+  sV_ = std::max(sV_, sV);
+  sE_ = std::max(sE_, sE);
+  sn_ = std::max(sn_, sn);
+  const size_t sbytes = scratch_bytes(sV_, sE_, sn_);
+  if (sbytes > scratch_n_) {
+    if (resident_ > 0 && scratch_) hipDeviceSynchronize();
+    if (scratch_) hipFree(scratch_);
+    scratch_ = nullptr;
+    scratch_n_ = 0;
+    hipError_t e = hipMalloc(&scratch_, sbytes);
+    if (e != hipSuccess) {
+      *err = std::string("scratch allocation: ") + hipGetErrorString(e);
+      return e == hipErrorOutOfMemory ? WBPR_ENOMEM : WBPR_EDEVICE;
+    }
+    scratch_n_ = sbytes;
+  }
+  return 0;
+}
+
+// Points every arena array into arena_ (arena_bytes(...) long).
+void Engine::carve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap) {
+  {
     Vcap_ = Vcap;
     Mcap_ = Mcap;
     Ecap_ = Ecap;
@@ -661,53 +713,37 @@ int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int6
     MiscLayout *m = reinterpret_cast<MiscLayout *>(misc_);
     sink_ = &m->sink;
     budget_ = &m->budget;
-    // free arena: empty rows, inactive vertices, no instance
-    e = hipMemset(arena_, 0, bytes);
-    if (e == hipSuccess) e = hipMemset(inst_of_, 0xff, 4 * (size_t)Vcap);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) {
-      *err = std::string("arena init: ") + hipGetErrorString(e);
-      return WBPR_EDEVICE;
-    }
-    valloc_.reset(Vcap);
-    malloc_.reset(Mcap);
-    aalloc_.reset(Ecap);
-    slot_free_.clear();
-    for (int32_t i = ncap - 1; i >= 0; i--) slot_free_.push_back(i);
-    inst_.assign(ncap, Inst());
-    groups_.clear();
-    const size_t pin_need = kPinnedHeader + sizeof(InstDev) * (size_t)ncap * kListKinds + 24 * (size_t)ncap + 4096;
-    if (pin_n_ < pin_need) {
-      if (pin_) hipHostFree(pin_);
-      pin_ = nullptr;
-      pin_n_ = 0;
-      e = hipHostMalloc((void **)&pin_, pin_need, hipHostMallocDefault);
-      if (e != hipSuccess) {
-        *err = std::string("pinned staging: ") + hipGetErrorString(e);
-        return WBPR_ENOMEM;
-      }
-      pin_n_ = pin_need;
-    }
   }
-  sV_ = std::max(sV_, sV);
-  sE_ = std::max(sE_, sE);
-  sn_ = std::max(sn_, sn);
-  const size_t sbytes = scratch_bytes(sV_, sE_, sn_);
-  if (sbytes > scratch_n_) {
-    if (resident_ > 0 && scratch_) hipDeviceSynchronize();
-    if (scratch_) hipFree(scratch_);
-    scratch_ = nullptr;
-    scratch_n_ = 0;
-    hipError_t e = hipMalloc(&scratch_, sbytes);
-    if (e != hipSuccess) {
-      *err = std::string("scratch allocation: ") + hipGetErrorString(e);
-      return e == hipErrorOutOfMemory ? WBPR_ENOMEM : WBPR_EDEVICE;
-    }
-    scratch_n_ = sbytes;
+}
+
+// Host bookkeeping of an empty arena.
+void Engine::reset_books() {
+  valloc_.reset(Vcap_);
+  malloc_.reset(Mcap_);
+  aalloc_.reset(Ecap_);
+  slot_free_.clear();
+  for (int32_t i = ncap_ - 1; i >= 0; i--) slot_free_.push_back(i);
+  inst_.assign(ncap_, Inst());
+  groups_.clear();
+  resident_ = 0;
+  resident_V_ = 0;
+  resident_M_ = 0;
+}
+
+// Pinned host staging for the instance lists and read-backs.
+hipError_t Engine::ensure_pinned(std::string *err) {
+  const size_t pin_need = kPinnedHeader + sizeof(InstDev) * (size_t)ncap_ * kListKinds + 24 * (size_t)ncap_ + 4096;
+  if (pin_n_ >= pin_need) return hipSuccess;
+  if (pin_) hipHostFree(pin_);
+  pin_ = nullptr;
+  pin_n_ = 0;
+  hipError_t e = hipHostMalloc((void **)&pin_, pin_need, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    *err = std::string("pinned staging: ") + hipGetErrorString(e);
+    return e;
   }
-  // tiers from the configuration (defaults from the arena's mean row length
-  // are refined per admission)
-  return 0;
+  pin_n_ = pin_need;
+  return hipSuccess;
 }
 
 // Longest row each listed instance's sweeps can meet (terminals excluded),
@@ -772,7 +808,7 @@ void Engine::launch_inst_list(int which, const std::vector<InstDev> &list, const
   hipMemcpyAsync(dl, hl, sizeof(InstDev) * n, hipMemcpyHostToDevice, st);
   if (which == IK_INIT) hipMemcpyAsync(dslot, hslot, 4 * (size_t)n, hipMemcpyHostToDevice, st);
   InstArgs a{dl, A_.rowb, A_.ent, A_.rev, A_.cap0, A_.arc2ent, A_.pbefore, A_.acap, e_, h_, inst_of_, dslot,
-             inst_stranded_};
+             inst_stranded_, cfg_.rcsr ? 1 : 0};
   // the decode's per-arc chain of dependent gathers wants every wave slot
   unsigned bx = which == IK_VALUE_ZERO || which == IK_PHASE2 ? 1u : grid1d(maxlen, 256, which == IK_DECODE ? 4096 : 1024);
   if (which == IK_PREFLOW || which == IK_VALUE) bx = 64;
@@ -786,6 +822,22 @@ void Engine::launch_inst_list(int which, const std::vector<InstDev> &list, const
   }
 }
 
+// The largest LDS a workgroup of the small-instance kernel may have, less
+// the static part (once; -1 when the device cannot give enough).
+void Engine::prime_small_lds() {
+  if (small_lds_ != 0) return;
+  int dev_max = 0;
+  if (hipDeviceGetAttribute(&dev_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device_) != hipSuccess ||
+      dev_max - 2048 < 32768 ||
+      hipFuncSetAttribute((const void *)k_small_solve, hipFuncAttributeMaxDynamicSharedMemorySize, dev_max - 2048) !=
+          hipSuccess) {
+    hipGetLastError();
+    small_lds_ = -1;  // no LDS-resident path on this device
+    return;
+  }
+  small_lds_ = dev_max - 2048;
+}
+
 // A freshly started group of small instances, alone on the device, is
 // solved whole: one workgroup per instance with its residual graph in LDS;
 // the instances are then retired by the next round like any finished one
@@ -795,24 +847,15 @@ void Engine::launch_inst_list(int which, const std::vector<InstDev> &list, const
 // a solve at admission would hold up everything else (measured: batched
 // solves/s 15.6k -> 12.4k, served p50 6.3 -> 9.4 ms).
 int Engine::solve_small(const std::vector<int> &slots, hipStream_t st, std::string *err) {
-  if (cfg_.lds_max_v < 0 || small_lds_ < 0 || resident_ != (int)slots.size()) return 0;
+  // BCSR only: the LDS copy of a row keeps 16-bit mates
+  if (cfg_.rcsr || cfg_.lds_max_v < 0 || small_lds_ < 0 || resident_ != (int)slots.size()) return 0;
   const int vmax = cfg_.lds_max_v > 0 ? cfg_.lds_max_v : 1024;
   std::vector<int> cand;
   for (int sl : slots)
     if (inst_[sl].V <= vmax) cand.push_back(sl);
   if (cand.empty() || cand.size() != slots.size()) return 0;
-  if (small_lds_ == 0) {  // first use: the largest LDS a workgroup may have, less the static part
-    int dev_max = 0;
-    if (hipDeviceGetAttribute(&dev_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device_) != hipSuccess ||
-        dev_max - 2048 < 32768 ||
-        hipFuncSetAttribute((const void *)k_small_solve, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            dev_max - 2048) != hipSuccess) {
-      hipGetLastError();
-      small_lds_ = -1;  // no LDS-resident path on this device
-      return 0;
-    }
-    small_lds_ = dev_max - 2048;
-  }
+  prime_small_lds();
+  if (small_lds_ < 0) return 0;
   const int n = (int)cand.size();
   InstDev *hl = reinterpret_cast<InstDev *>(pin_ + kPinnedHeader) + (size_t)IK_SMALL * ncap_;
   InstDev *dl = reinterpret_cast<InstDev *>(inst_list_) + (size_t)IK_SMALL * ncap_;
@@ -951,7 +994,21 @@ int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
   pl.vbase = (int32_t)vb;
   pl.mbase = mb;
   pl.abase = ab;
-  hipError_t e = build_residual(rp, col, in.cap, (int32_t)Vt, Et, A_, pl, bscratch, bst, st);
+  int evb = -1;
+  if (cfg_.time_kernels) {  // the builder's device time (events on the stream)
+    if (ev_used_ + 2 > (int)ev_.size()) {
+      const size_t old = ev_.size();
+      ev_.resize(old + 1024);
+      for (size_t i = old; i < ev_.size(); i++) hipEventCreate(&ev_[i]);
+    }
+    evb = ev_used_;
+    ev_used_ += 2;
+    ev_marks_.push_back({5, evb});
+    hipEventRecord(ev_[evb], st);
+  }
+  hipError_t e = cfg_.rcsr ? build_residual_rcsr(rp, col, in.cap, (int32_t)Vt, Et, A_, pl, bscratch, bst, st)
+                           : build_residual(rp, col, in.cap, (int32_t)Vt, Et, A_, pl, bscratch, bst, st);
+  if (evb >= 0 && e == hipSuccess) e = hipEventRecord(ev_[evb + 1], st);
   BuildStatus hb;
   if (e == hipSuccess) e = hipMemcpyAsync(pin_, bst, sizeof(BuildStatus), hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -1057,9 +1114,17 @@ int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
   return 0;
 }
 
-__global__ void k_reset_entries(int2 *ent, const int32_t *cap0, int64_t M) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x)
-    ent[k].y = cap0[k];
+// Residuals back to the input capacities; RCSR also zeroes every arc's flow
+// (reverse entries hold an index, not a residual, and stay as they are).
+__global__ void k_reset_entries(int2 *ent, const int32_t *cap0, int32_t *flow, int rcsr, int64_t M) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < M; k += (int64_t)gridDim.x * blockDim.x) {
+    if (!rcsr) {
+      ent[k].y = cap0[k];
+    } else if (ent[k].x >= 0) {
+      ent[k].y = cap0[k];
+      flow[k] = 0;
+    }
+  }
 }
 
 bool Engine::has_kept_groups() const {
@@ -1089,7 +1154,7 @@ int Engine::start_instance(int gid, int32_t s, int32_t t, int64_t *value, int32_
   }
   // residual capacities back to the merged input capacities
   hipLaunchKernelGGL(k_reset_entries, dim3(grid1d(G.Mres, 256, 16384)), dim3(256), 0, st, A_.ent + G.mbase,
-                     A_.cap0 + G.mbase, G.Mres);
+                     A_.cap0 + G.mbase, A_.rev + G.mbase, cfg_.rcsr ? 1 : 0, G.Mres);
   const int sl = slot_free_.back();
   slot_free_.pop_back();
   Inst &I = inst_[sl];
@@ -1224,7 +1289,8 @@ bool Engine::ensure_side() {
 // shared state only through atomics, as workgroups of one kernel do.
 void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
   MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
-  Graph g{(int32_t)Vcap_, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_, gap_hist_, misc->gap};
+  const bool rc = cfg_.rcsr;
+  Graph g{(int32_t)Vcap_, HCAP, A_.rowb, A_.ent, A_.rev, rc ? A_.rev : nullptr, e_, h_, sink_, gap_hist_, misc->gap};
   // tile kernels: 256 workgroups, one per CU.  Measured on R-MAT / grid cut
   // / bipartite: 1024 -> 34.3 / 94 / 6.35 ms, 512 -> 30.2 / 85 / 6.08,
   // 256 -> 30.0 / 78 / 6.0, 192 and 128 slower again (31.2 and 34 ms on
@@ -1295,25 +1361,25 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
     if (fs)
       launch_avq_scan(sweep_blocks, st, g, &misc->span, q_[1], &misc->scan_cnt, (int32_t)Vcap_, misc->err,
                       &misc->halt[0]);
-    launch_sweep_tile(P_, sweep_blocks, st, g, q);
+    launch_sweep_tile(P_, rc, sweep_blocks, st, g, q);
     if (fork) {
       hipEvent_t ef = fork_ev_[(2 * j) % fork_ev_.size()], ej = fork_ev_[(2 * j + 1) % fork_ev_.size()];
       hipEventRecord(ef, st);
       hipStreamWaitEvent(side_, ef, 0);
-      launch_sweep_chunk(0, chunk_blocks, side_, g, q);
-      launch_sweep_chunk(1, chunk_blocks, side_, g, q);
-      launch_sweep_chunk(2, 64, side_, g, q);
+      launch_sweep_chunk(0, rc, chunk_blocks, side_, g, q);
+      launch_sweep_chunk(1, rc, chunk_blocks, side_, g, q);
+      launch_sweep_chunk(2, rc, 64, side_, g, q);
       hipEventRecord(ej, side_);
-      launch_sweep_tile(mid_lanes_, sweep_blocks, st, g, qw);
+      launch_sweep_tile(mid_lanes_, rc, sweep_blocks, st, g, qw);
       hipStreamWaitEvent(st, ej, 0);
     } else {
       if (timed) hipEventRecord(ev_[evb + 1], st);
-      if (tiers & 1) launch_sweep_tile(mid_lanes_, sweep_blocks, st, g, qw);
+      if (tiers & 1) launch_sweep_tile(mid_lanes_, rc, sweep_blocks, st, g, qw);
       if (timed) hipEventRecord(ev_[evb + 2], st);
       if (tiers & 2) {
-        launch_sweep_chunk(0, chunk_blocks, st, g, q);
-        launch_sweep_chunk(1, chunk_blocks, st, g, q);
-        launch_sweep_chunk(2, 64, st, g, q);
+        launch_sweep_chunk(0, rc, chunk_blocks, st, g, q);
+        launch_sweep_chunk(1, rc, chunk_blocks, st, g, q);
+        launch_sweep_chunk(2, rc, 64, st, g, q);
       }
       if (timed) hipEventRecord(ev_[evb + 3], st);
     }
@@ -1410,7 +1476,8 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   hipMemsetAsync(inst_active_, 0, 4 * (size_t)ncap_, st);
   hipMemsetAsync(inst_stranded_, 0, 4 * (size_t)ncap_, st);
 
-  Graph g{(int32_t)vhi, HCAP, A_.rowb, A_.ent, A_.rev, e_, h_, sink_, gap_hist_, misc->gap};
+  Graph g{(int32_t)vhi, HCAP, A_.rowb, A_.ent, A_.rev, cfg_.rcsr ? A_.rev : nullptr, e_, h_, sink_, gap_hist_,
+          misc->gap};
   GRArgs ga;
   ga.g = g;
   ga.roots = roots_;
@@ -1484,7 +1551,7 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
     ev_marks_.push_back({3, evb});
     hipEventRecord(ev_[evb], st);
   }
-  hipError_t he = launch_global_relabel(Pg, gr_blocks, st, ga);
+  hipError_t he = launch_global_relabel(Pg, cfg_.rcsr, gr_blocks, st, ga);
   if (he != hipSuccess) {
     *err = std::string("global relabel launch: ") + hipGetErrorString(he);
     return WBPR_EDEVICE;
@@ -1768,6 +1835,11 @@ int Engine::collect_stats(hipStream_t st, EngineStats *out, std::string *err) {
   r.nonempty_sweeps = hs[13];
   r.gap_skipped = hs[15];
   for (const auto &mk : ev_marks_) {
+    if (mk.first == 5) {  // residual-graph build
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, ev_[mk.second], ev_[mk.second + 1]) == hipSuccess) r.build_ms += ms;
+      continue;
+    }
     if (mk.first == 3) {
       float ms = 0;
       if (hipEventElapsedTime(&ms, ev_[mk.second], ev_[mk.second + 1]) == hipSuccess) r.k_ms[3] += ms;

@@ -44,13 +44,23 @@ namespace wb {
 
 
 
-// Pushes d along residual entry k of row u into v: the four atomic updates
-// of Algorithm 1 except the decrement of e(u), which the caller applies once
-// per visit.  Returns true when v's excess crossed from <= 0 to > 0 (v must
-// then be enqueued, if it is not above the cap).
-__device__ __forceinline__ bool push_entry(const Graph &g, int32_t k, int32_t v, long long d) {
-  atomic_add_i32(&g.ent[k].y, -(int32_t)d);
-  atomic_add_i32(&g.ent[g.rev[k]].y, (int32_t)d);
+// Pushes d along the residual entry with push handle hk (see handle_of) of
+// row u into v: the four atomic updates of Algorithm 1 except the decrement
+// of e(u), which the caller applies once per visit.  Returns true when v's
+// excess crossed from <= 0 to > 0 (v must then be enqueued, if it is not
+// above the cap).
+template <bool RC>
+__device__ __forceinline__ bool push_entry(const Graph &g, int32_t hk, int32_t v, long long d) {
+  if (!RC) {
+    atomic_add_i32(&g.ent[hk].y, -(int32_t)d);
+    atomic_add_i32(&g.ent[g.rev[hk]].y, (int32_t)d);
+  } else if (hk >= 0) {  // forward entry: residual down, flow up
+    atomic_add_i32(&g.ent[hk].y, -(int32_t)d);
+    atomic_add_i32(&g.flow[hk], (int32_t)d);
+  } else {  // reverse entry: the arc's flow down, its forward residual up
+    atomic_add_i32(&g.flow[~hk], -(int32_t)d);
+    atomic_add_i32(&g.ent[~hk].y, (int32_t)d);
+  }
   if (v == *g.sink) return false;
   long long oldv = atomic_add_i64(&g.e[v], d);
   return oldv <= 0 && oldv + d > 0;
@@ -239,6 +249,16 @@ __device__ __forceinline__ long long group_excl_scan_i64(long long x, long long 
 }
 
 
+// Entry k re-read just before a single push (paper mode): its column, push
+// handle and current residual (device-scope load).
+template <bool RC>
+__device__ __forceinline__ void entry_for_push(const Graph &g, int32_t k, int32_t *v, int32_t *hk, int32_t *r) {
+  const int2 ck = g.ent[k];
+  *v = col_of<RC>(ck);
+  *hk = handle_of<RC>(k, ck);
+  *r = RC && ck.x < 0 ? atomic_load_i32(&g.flow[ck.y]) : atomic_load_i32(&g.ent[k].y);
+}
+
 constexpr int32_t CHUNK_MORE = 1 << 30;  // lr_cnt flag: a chunk left admissible capacity unpushed
 // Bias added to e(u) while the chunks of long row u work on it (discharge
 // mode): pushes into u then never see e(u) <= 0, so only u's last chunk
@@ -265,7 +285,7 @@ __device__ __forceinline__ void defer_long_row(const SweepQ &q, const Graph &g, 
 // lower than u, handing out e(u) in row order with a prefix sum, stops once
 // e(u) is spent, and relabels to 1 + the lowest remaining residual neighbour
 // if excess is left.
-template <int P>
+template <int P, bool RC>
 __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q) {
   constexpr int UNROLL = 4;
   constexpr int DEFER_BUF = 128;
@@ -356,13 +376,16 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
       if (scan) {
         for (int32_t kb = beg + tl; kb < end; kb += UNROLL * P) {
           int2 cr[UNROLL];
+          int32_t rr[UNROLL];
 #pragma unroll
           for (int j = 0; j < UNROLL; j++) cr[j] = kb + j * P < end ? g.ent[kb + j * P] : make_int2(0, 0);
 #pragma unroll
+          for (int j = 0; j < UNROLL; j++) rr[j] = res_of<RC>(g.flow, cr[j]);
+#pragma unroll
           for (int j = 0; j < UNROLL; j++) {
-            if (cr[j].y > 0) {
+            if (rr[j] > 0) {
               const unsigned long long kk =
-                  ((unsigned long long)(unsigned)g.h[cr[j].x] << 32) | (unsigned)(kb + j * P - beg);
+                  ((unsigned long long)(unsigned)g.h[col_of<RC>(cr[j])] << 32) | (unsigned)(kb + j * P - beg);
               key = kk < key ? kk : key;
             }
           }
@@ -385,11 +408,12 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
           const int32_t hmin = (int32_t)(key >> 32);
           const int32_t k = beg + (int32_t)(key & 0xffffffffu);
           if (g.h[u] > hmin) {
-            v = g.ent[k].x;
+            int32_t hk, rk;
+            entry_for_push<RC>(g, k, &v, &hk, &rk);
             long long eu = atomic_load_i64(&g.e[u]);
-            long long d = eu < (long long)atomic_load_i32(&g.ent[k].y) ? eu : (long long)atomic_load_i32(&g.ent[k].y);
+            long long d = eu < (long long)rk ? eu : (long long)rk;
             if (d > 0) {
-              app_v = push_entry(g, k, v, d) && g.h[v] < g.hcap;
+              app_v = push_entry<RC>(g, hk, v, d) && g.h[v] < g.hcap;
               long long oldu = atomic_add_i64(&g.e[u], -d);
               app_u = oldu - d > 0;
               pushes++;
@@ -422,6 +446,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
         // row order
         for (int32_t kb = beg; kb < end && erem > 0; kb += UNROLL * P) {
           int2 cr[UNROLL];
+          int32_t rr[UNROLL];
           int32_t hv[UNROLL];
 #pragma unroll
           for (int j = 0; j < UNROLL; j++) {
@@ -429,16 +454,18 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
             cr[j] = k < end ? g.ent[k] : make_int2(0, 0);
           }
 #pragma unroll
-          for (int j = 0; j < UNROLL; j++) hv[j] = cr[j].y > 0 ? g.h[cr[j].x] : 0;
+          for (int j = 0; j < UNROLL; j++) rr[j] = res_of<RC>(g.flow, cr[j]);
+#pragma unroll
+          for (int j = 0; j < UNROLL; j++) hv[j] = rr[j] > 0 ? g.h[col_of<RC>(cr[j])] : 0;
 #pragma unroll
           for (int j = 0; j < UNROLL; j++) {
             const int32_t k = kb + j * P + tl;
             long long want = 0;
             int32_t v = 0;
-            if (cr[j].y > 0) {
+            if (rr[j] > 0) {
               if (hv[j] < hu) {
-                want = cr[j].y;
-                v = cr[j].x;
+                want = rr[j];
+                v = col_of<RC>(cr[j]);
               } else {
                 unsigned long long kk = ((unsigned long long)(unsigned)hv[j] << 32) | (unsigned)(k - beg);
                 key = kk < key ? kk : key;
@@ -450,7 +477,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
             take = take < 0 ? 0 : (take > want ? want : take);
             bool app_v = false;
             if (take > 0) {
-              app_v = push_entry(g, k, v, take) && g.h[v] < g.hcap;
+              app_v = push_entry<RC>(g, handle_of<RC>(k, cr[j]), v, take) && g.h[v] < g.hcap;
               pushes++;
             }
             waveq_push(wq, q.append && app_v, v);
@@ -531,6 +558,7 @@ __device__ __forceinline__ long long block_excl_scan_i64(long long x, long long 
 // it (1 + the minimum over the row) when no chunk left admissible capacity
 // unpushed; paper mode pushes to the minimum-key neighbour or relabels
 // (Algorithm 1).  Sets *app_u / *app_v (and *v) for the caller's queue.
+template <bool RC>
 __device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q, int32_t u, int2 rb, int32_t hu,
                                                 unsigned long long kmin, bool more, bool *app_u, bool *app_v,
                                                 int32_t *v, int *pushes, int *relabels, long long *rwork,
@@ -558,11 +586,11 @@ __device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q,
     const int32_t k = rb.x + (int32_t)(kmin & 0xffffffffu);
     if (hu > hmin) {
       const long long e0 = atomic_load_i64(&g.e[u]);
-      *v = g.ent[k].x;
-      const int32_t rk = atomic_load_i32(&g.ent[k].y);
+      int32_t hk, rk;
+      entry_for_push<RC>(g, k, v, &hk, &rk);
       const long long d = e0 < (long long)rk ? e0 : (long long)rk;
       if (d > 0) {
-        *app_v = push_entry(g, k, *v, d) && g.h[*v] < g.hcap;
+        *app_v = push_entry<RC>(g, hk, *v, d) && g.h[*v] < g.hcap;
         const long long oldu = atomic_add_i64(&g.e[u], -d);
         *app_u = oldu - d > 0;
         (*pushes)++;
@@ -597,7 +625,7 @@ __device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q,
 // capacity, with atomics whose results they do not wait for.  Paper mode:
 // the chunks fold the minimum (height, position) key over all residual
 // entries of the row; the finish pushes to that neighbour or relabels.
-template <bool FIRST>
+template <bool FIRST, bool RC>
 __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
   constexpr int PER = CHUNK / BLK;
   __shared__ int s_qbuf[BLK_WAVES][WB_QBUF];
@@ -631,24 +659,30 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
     unsigned long long key = WB_KEY_NONE;
     int32_t vv[PER];
     int32_t want[PER];
+    int32_t hk[PER];  // push handles (RCSR; BCSR pushes at k0 + j)
+    int2 cr[PER];
+    int32_t rr[PER];
     long long mine = 0;
+#pragma unroll
+    for (int j = 0; j < PER; j++) cr[j] = k0 + j < end ? g.ent[k0 + j] : make_int2(0, 0);
+#pragma unroll
+    for (int j = 0; j < PER; j++) rr[j] = res_of<RC>(g.flow, cr[j]);
 #pragma unroll
     for (int j = 0; j < PER; j++) {
       const int32_t k = k0 + j;
       vv[j] = 0;
       want[j] = 0;
-      if (k < end) {
-        const int2 cr = g.ent[k];
-        if (cr.y > 0) {
-          const int32_t hv = g.h[cr.x];
-          if (q.mode == 1 && hv < hu) {
-            want[j] = cr.y;
-            vv[j] = cr.x;
-            mine += cr.y;
-          } else {
-            const unsigned long long kk = ((unsigned long long)(unsigned)hv << 32) | (unsigned)(k - rb.x);
-            key = kk < key ? kk : key;
-          }
+      hk[j] = handle_of<RC>(k, cr[j]);
+      if (rr[j] > 0) {
+        const int32_t c = col_of<RC>(cr[j]);
+        const int32_t hv = g.h[c];
+        if (q.mode == 1 && hv < hu) {
+          want[j] = rr[j];
+          vv[j] = c;
+          mine += rr[j];
+        } else {
+          const unsigned long long kk = ((unsigned long long)(unsigned)hv << 32) | (unsigned)(k - rb.x);
+          key = kk < key ? kk : key;
         }
       }
     }
@@ -677,7 +711,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
         const long long d = rem < 0 ? 0 : (rem > want[j] ? want[j] : rem);
         bool app_v = false;
         if (d > 0) {
-          app_v = push_entry(g, k0 + j, vv[j], d) && g.h[vv[j]] < g.hcap;
+          app_v = push_entry<RC>(g, RC ? hk[j] : k0 + j, vv[j], d) && g.h[vv[j]] < g.hcap;
           pushes++;
         }
         waveq_push(wq, q.append && app_v, vv[j]);
@@ -697,8 +731,8 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
         // whole row only when the row is one chunk, so a longer row is not
         // relabelled here (excess that arrived meanwhile waits a sweep)
         queued += 1;
-        finish_long_row(g, q, u, rb, hu, key, short_claim || nch > 1, &app_u, &app_v, &v, &pushes, &relabels,
-                        &rwork, s_gap, gbase, gn);
+        finish_long_row<RC>(g, q, u, rb, hu, key, short_claim || nch > 1, &app_u, &app_v, &v, &pushes, &relabels,
+                            &rwork, s_gap, gbase, gn);
       } else {
         if (key != WB_KEY_NONE) atomic_min_u64(&q.lr_key[u], key);
         if (short_claim) atomic_or_i32(&q.lr_cnt[u], CHUNK_MORE);
@@ -729,6 +763,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
 
 // Third pass: one thread finishes each long row whose chunks ran in the
 // second pass (the row's task with chunk index 1 stands for it).
+template <bool RC>
 __global__ void __launch_bounds__(BLK) k_sweep_chunk_finish(Graph g, SweepQ q) {
   __shared__ int s_qbuf[BLK_WAVES][WB_QBUF];
   __shared__ int s_qcnt[BLK_WAVES];
@@ -751,8 +786,8 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk_finish(Graph g, SweepQ q) {
       u = q.task_u[i];
       const int2 rb = g.rowb[u];
       queued += 1;
-      finish_long_row(g, q, u, rb, g.h[u], atomic_load_u64(&q.lr_key[u]), (q.lr_cnt[u] & CHUNK_MORE) != 0, &app_u,
-                      &app_v, &v, &pushes, &relabels, &rwork, s_gap, gbase, gn);
+      finish_long_row<RC>(g, q, u, rb, g.h[u], atomic_load_u64(&q.lr_key[u]), (q.lr_cnt[u] & CHUNK_MORE) != 0,
+                          &app_u, &app_v, &v, &pushes, &relabels, &rwork, s_gap, gbase, gn);
     }
     waveq_push(wq, q.append && app_v, v);
     waveq_push(wq, q.append && app_u, u);
@@ -847,7 +882,7 @@ __device__ __forceinline__ void block_add2(int32_t x, long long y, int32_t *cx, 
   }
 }
 
-template <int P>
+template <int P, bool RC>
 __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   __shared__ int s_qbuf[GR_THREADS / WB_WAVE][WB_QBUF];
   __shared__ int s_qcnt[GR_THREADS / WB_WAVE];
@@ -1005,11 +1040,14 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
           int32_t k = beg;
           for (; k < end && hitw < 0; k += 4) {
             int2 cr[4];
+            int32_t rr[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) cr[j] = k + j < end ? g.ent[k + j] : make_int2(0, 0);
 #pragma unroll
+            for (int j = 0; j < 4; j++) rr[j] = res_of<RC>(g.flow, cr[j]);
+#pragma unroll
             for (int j = 0; j < 4; j++)
-              if (hitw < 0 && cr[j].y > 0 && bm_test(bm_in, cr[j].x)) hitw = cr[j].x;
+              if (hitw < 0 && rr[j] > 0 && bm_test(bm_in, col_of<RC>(cr[j]))) hitw = col_of<RC>(cr[j]);
           }
           buscans += (k < end ? k : end) - beg;
           if (hitw >= 0) {
@@ -1034,8 +1072,8 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
             int32_t w = 0;
             if (k < me) {
               const int2 cr = g.ent[k];
-              w = cr.x;
-              hit = cr.y > 0 && bm_test(bm_in, w);
+              w = col_of<RC>(cr);
+              hit = res_of<RC>(g.flow, cr) > 0 && bm_test(bm_in, w);
             }
             const unsigned long long m = __ballot(hit);
             if (lane() == 0) buscans += min(WB_WAVE, me - kb);
@@ -1073,8 +1111,8 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
           int32_t w = 0;
           if (k < ce) {
             const int2 cr = g.ent[k];
-            w = cr.x;
-            hit = cr.y > 0 && bm_test(bm_in, w);
+            w = col_of<RC>(cr);
+            hit = res_of<RC>(g.flow, cr) > 0 && bm_test(bm_in, w);
           }
           const unsigned long long m = __ballot(hit);
           if (m) {
@@ -1142,9 +1180,10 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
             const int32_t hw1 = g.h[w] + 1;
             if (tl == 0) bscans += deg;
             for (int32_t k = beg + tl; k < end; k += P) {
-              const int32_t v = g.ent[k].x;
+              const int2 cr = g.ent[k];
+              const int32_t v = col_of<RC>(cr);
               bool claimed = false;
-              if (!bm_test(bm_vis, v) && g.ent[g.rev[k]].y > 0) {
+              if (!bm_test(bm_vis, v) && mate_res<RC>(g.ent, g.rev, g.flow, k, cr) > 0) {
                 claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
                 if (claimed) {
                   a.vis[v] = nxt;
@@ -1172,9 +1211,10 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         const int32_t hw1 = g.h[w] + 1;
         if (lane() == 0) bscans += ce - cb;
         for (int32_t k = cb + lane(); k < ce; k += WB_WAVE) {
-          const int32_t v = g.ent[k].x;
+          const int2 cr = g.ent[k];
+          const int32_t v = col_of<RC>(cr);
           bool claimed = false;
-          if (!bm_test(bm_vis, v) && g.ent[g.rev[k]].y > 0) {
+          if (!bm_test(bm_vis, v) && mate_res<RC>(g.ent, g.rev, g.flow, k, cr) > 0) {
             claimed = atomicCAS(&g.h[v], g.hcap, hw1) == g.hcap;
             if (claimed) {
               a.vis[v] = nxt;
@@ -1253,37 +1293,45 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
 typedef void (*TileFn)(Graph, SweepQ);
 typedef void (*GRFn)(GRArgs);
 
-static TileFn tile_fn(int P) {
+template <bool RC>
+static TileFn tile_fn_rc(int P) {
   switch (P) {
-    case 1: return k_sweep_tile<1>;
-    case 4: return k_sweep_tile<4>;
-    case 8: return k_sweep_tile<8>;
-    case 16: return k_sweep_tile<16>;
-    case 32: return k_sweep_tile<32>;
-    default: return k_sweep_tile<64>;
+    case 1: return k_sweep_tile<1, RC>;
+    case 4: return k_sweep_tile<4, RC>;
+    case 8: return k_sweep_tile<8, RC>;
+    case 16: return k_sweep_tile<16, RC>;
+    case 32: return k_sweep_tile<32, RC>;
+    default: return k_sweep_tile<64, RC>;
   }
 }
-static GRFn gr_fn(int P) {
+template <bool RC>
+static GRFn gr_fn_rc(int P) {
   switch (P) {
-    case 4: return k_global_relabel<4>;
-    case 8: return k_global_relabel<8>;
-    case 16: return k_global_relabel<16>;
-    case 32: return k_global_relabel<32>;
-    default: return k_global_relabel<64>;
+    case 4: return k_global_relabel<4, RC>;
+    case 8: return k_global_relabel<8, RC>;
+    case 16: return k_global_relabel<16, RC>;
+    case 32: return k_global_relabel<32, RC>;
+    default: return k_global_relabel<64, RC>;
   }
 }
+static TileFn tile_fn(int P, bool rc) { return rc ? tile_fn_rc<true>(P) : tile_fn_rc<false>(P); }
+static GRFn gr_fn(int P, bool rc) { return rc ? gr_fn_rc<true>(P) : gr_fn_rc<false>(P); }
 
-void launch_sweep_tile(int P, int blocks, hipStream_t st, const Graph &g, const SweepQ &q) {
-  hipLaunchKernelGGL(tile_fn(P), dim3(blocks), dim3(SWEEP_THREADS), 0, st, g, q);
+void launch_sweep_tile(int P, bool rc, int blocks, hipStream_t st, const Graph &g, const SweepQ &q) {
+  hipLaunchKernelGGL(tile_fn(P, rc), dim3(blocks), dim3(SWEEP_THREADS), 0, st, g, q);
 }
 
-void launch_sweep_chunk(int pass, int blocks, hipStream_t st, const Graph &g, const SweepQ &q) {
-  if (pass == 0)
-    hipLaunchKernelGGL(k_sweep_chunk<true>, dim3(blocks), dim3(BLK), 0, st, g, q);
-  else if (pass == 1)
-    hipLaunchKernelGGL(k_sweep_chunk<false>, dim3(blocks), dim3(BLK), 0, st, g, q);
-  else
-    hipLaunchKernelGGL(k_sweep_chunk_finish, dim3(blocks), dim3(BLK), 0, st, g, q);
+void launch_sweep_chunk(int pass, bool rc, int blocks, hipStream_t st, const Graph &g, const SweepQ &q) {
+  if (pass == 0) {
+    if (rc) hipLaunchKernelGGL((k_sweep_chunk<true, true>), dim3(blocks), dim3(BLK), 0, st, g, q);
+    else hipLaunchKernelGGL((k_sweep_chunk<true, false>), dim3(blocks), dim3(BLK), 0, st, g, q);
+  } else if (pass == 1) {
+    if (rc) hipLaunchKernelGGL((k_sweep_chunk<false, true>), dim3(blocks), dim3(BLK), 0, st, g, q);
+    else hipLaunchKernelGGL((k_sweep_chunk<false, false>), dim3(blocks), dim3(BLK), 0, st, g, q);
+  } else {
+    if (rc) hipLaunchKernelGGL(k_sweep_chunk_finish<true>, dim3(blocks), dim3(BLK), 0, st, g, q);
+    else hipLaunchKernelGGL(k_sweep_chunk_finish<false>, dim3(blocks), dim3(BLK), 0, st, g, q);
+  }
 }
 
 void launch_avq_scan(int blocks, hipStream_t st, const Graph &g, const int32_t *span, int32_t *list, int32_t *cnt,
@@ -1295,17 +1343,21 @@ void launch_sweep_control(hipStream_t st, const SweepCtl &c) {
   hipLaunchKernelGGL(k_sweep_control, dim3(1), dim3(1), 0, st, c);
 }
 
-hipError_t launch_global_relabel(int P, int blocks, hipStream_t st, GRArgs &a) {
+hipError_t launch_global_relabel(int P, bool rc, int blocks, hipStream_t st, GRArgs &a) {
   void *args[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(gr_fn(P)), dim3(blocks), dim3(GR_THREADS), args, 0,
-                                    st);
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(gr_fn(P, rc)), dim3(blocks), dim3(GR_THREADS), args,
+                                    0, st);
 }
 
 int gr_max_blocks(int device, int P) {
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(gr_fn(P)), GR_THREADS,
-                                                    0) != hipSuccess)
-    return 0;
+  int per_cu = 1 << 30;
+  for (int rc = 0; rc < 2; rc++) {  // both layouts' kernels must fit
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(gr_fn(P, rc != 0)),
+                                                      GR_THREADS, 0) != hipSuccess)
+      return 0;
+    per_cu = std::min(per_cu, n);
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) return 0;
   // one workgroup per CU: barrier latency grows with the number of

@@ -34,6 +34,7 @@ struct SolveConfig {
   bool wave_trace = false;    // per-wave execution time and work of every sweep launch
   int lds_max_v = 0;          // instances up to this many vertices are solved in LDS (0: 1024, < 0: never)
   bool gap = true;            // gap heuristic between global relabels (one instance in its phase)
+  bool rcsr = false;          // RCSR residual layout (paper section 3.2); else BCSR
 };
 
 // Counters of the engine since the last reset_stats().
@@ -47,6 +48,7 @@ struct EngineStats {
   int64_t gap_skipped = 0;   // queue entries left to the next global relabel by the gap heuristic
   // per kernel: 0 short-row tiles, 1 medium rows (one wave), 2 long rows (workgroup), 3 global relabel
   double k_ms[4] = {0, 0, 0, 0};
+  double build_ms = 0;       // residual-graph builder (event-timed with time_kernels)
   int64_t k_launches[4] = {0, 0, 0, 0};
   int64_t k_scans[4] = {0, 0, 0, 0}, k_pushes[4] = {0, 0, 0, 0}, k_relabels[4] = {0, 0, 0, 0},
           k_queued[4] = {0, 0, 0, 0};
@@ -177,6 +179,10 @@ class Engine {
   };
 
   int ensure_graph(hipStream_t st, int K, int tiers, hipGraphExec_t *exec, std::string *err);
+  void carve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap);
+  void reset_books();
+  hipError_t ensure_pinned(std::string *err);
+  void prime_small_lds();
   int measure_rows(const std::vector<int> &slots, hipStream_t st, std::string *err);
   int solve_small(const std::vector<int> &slots, hipStream_t st, std::string *err);
   int small_lds_ = 0;  // dynamic LDS bytes of the small-instance kernel (0: not yet set, -1: unavailable)

@@ -22,7 +22,8 @@ hipError_t radix_sort_u64_u32(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t
 struct Arena {
   int2 *rowb = nullptr;        // [Vcap] row bounds {first entry, end entry}
   int2 *ent = nullptr;         // [Mcap] {neighbour column, residual capacity}
-  int32_t *rev = nullptr;      // [Mcap] index of the mate entry (v,u) of (u,v)
+  int32_t *rev = nullptr;      // [Mcap] BCSR: index of the mate entry (v,u) of (u,v);
+                               //        RCSR: flow of the arc at its forward entry
   int32_t *cap0 = nullptr;     // [Mcap] merged forward capacity, sum of c(u->v)
   int32_t *arc2ent = nullptr;  // [Ecap] entry of input arc i, -1 for self-loops
   int32_t *pbefore = nullptr;  // [Ecap] capacity of earlier parallel arcs (u,v)
@@ -58,5 +59,11 @@ size_t build_scratch_bytes(int32_t V, int64_t E);
 // from *status_dev afterwards.
 hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, int32_t V, int64_t E,
                           const Arena &A, const Place &pl, void *scratch, BuildStatus *status_dev, hipStream_t st);
+
+// CSR -> RCSR rows in the arena at `pl` (2E entries: forward then reverse
+// entries per row, see build.hip); rev[] of those entries holds the flows.
+hipError_t build_residual_rcsr(const int64_t *row_ptr, const int32_t *col, const int32_t *cap, int32_t V, int64_t E,
+                               const Arena &A, const Place &pl, void *scratch, BuildStatus *status_dev,
+                               hipStream_t st);
 
 }  // namespace wb

@@ -25,12 +25,54 @@ constexpr int32_t GAP_BINS = 256;
 // BFS_CHUNK-entry pieces, one wave each.
 constexpr int32_t BFS_CHUNK = 1024;
 
+// Residual layouts (paper, section 3.2), the template flag RC of every
+// kernel that reads rows:
+//   BCSR (RC false): one entry per ordered vertex pair, {column, residual},
+//     rows sorted by column; the mate (v,u) of entry (u,v) is rev[k].
+//   RCSR (RC true): row u lists the arcs leaving u as forward entries
+//     {column, residual} (read coalesced), then the arcs entering u as
+//     reverse entries {column | RC_REV, index of the arc's forward entry}.
+//     The residual of a reverse entry is the arc's flow, flow[index]: one
+//     gather per entry, the cost the paper weighs against BCSR's search for
+//     the mate.  A push along forward entry k moves d from ent[k].y to
+//     flow[k]; along a reverse entry with index j, from flow[j] to ent[j].y.
+// A push handle names the two words a push moves capacity between: the
+// entry position k (BCSR, RCSR forward) or ~j (RCSR reverse).
+constexpr int32_t RC_REV = (int32_t)0x80000000;
+
+template <bool RC>
+__device__ __forceinline__ int32_t col_of(int2 cr) {
+  return RC ? (cr.x & 0x7fffffff) : cr.x;
+}
+
+template <bool RC>
+__device__ __forceinline__ int32_t handle_of(int32_t k, int2 cr) {
+  return RC && cr.x < 0 ? ~cr.y : k;
+}
+
+// Residual capacity of an entry whose words are cr (plain loads: a stale
+// value only delays a push or relabel to a later visit).
+template <bool RC>
+__device__ __forceinline__ int32_t res_of(const int32_t *flow, int2 cr) {
+  return RC && cr.x < 0 ? flow[cr.y] : cr.y;
+}
+
+// Residual capacity of the mate of entry k: the arc from the entry's
+// column back into the row's vertex (the global relabel's top-down step).
+template <bool RC>
+__device__ __forceinline__ int32_t mate_res(const int2 *ent, const int32_t *rev, const int32_t *flow, int32_t k,
+                                            int2 cr) {
+  if (!RC) return ent[rev[k]].y;
+  return cr.x < 0 ? ent[cr.y].y : flow[k];
+}
+
 struct Graph {
   int32_t V;             // arena vertices
   int32_t hcap;          // height cap: h >= hcap is inactive
   const int2 *rowb;      // row bounds {first entry, end entry}
   int2 *ent;
-  const int32_t *rev;
+  const int32_t *rev;    // BCSR: mate of every entry
+  int32_t *flow;         // RCSR: flow of every arc, at its forward entry
   long long *e;
   int32_t *h;
   const int32_t *sink;   // target whose excess is never read, so pushes into
@@ -142,17 +184,17 @@ struct GRArgs {
 };
 
 // Sweep kernels: tiles of P lanes (P = 4..64), one workgroup per long-row chunk,
-// and the one-thread round control.
-void launch_sweep_tile(int P, int blocks, hipStream_t st, const Graph &g, const SweepQ &q);
+// and the one-thread round control.  rc: rows in the RCSR layout (else BCSR).
+void launch_sweep_tile(int P, bool rc, int blocks, hipStream_t st, const Graph &g, const SweepQ &q);
 // pass 0: first chunks of long rows, 1: their other chunks, 2: finish rows of pass 1
-void launch_sweep_chunk(int pass, int blocks, hipStream_t st, const Graph &g, const SweepQ &q);
+void launch_sweep_chunk(int pass, bool rc, int blocks, hipStream_t st, const Graph &g, const SweepQ &q);
 void launch_sweep_control(hipStream_t st, const SweepCtl &c);
 // Full-scan active-vertex queue (Algorithm 2): vertices v < *span with
 // e(v) > 0 and h(v) < hcap, appended to list / *cnt.
 void launch_avq_scan(int blocks, hipStream_t st, const Graph &g, const int32_t *span, int32_t *list, int32_t *cnt,
                      int32_t cap, int32_t *err, const int32_t *halt);
 // Cooperative global relabel (all workgroups co-resident).
-hipError_t launch_global_relabel(int P, int blocks, hipStream_t st, GRArgs &a);
+hipError_t launch_global_relabel(int P, bool rc, int blocks, hipStream_t st, GRArgs &a);
 // Co-resident workgroup limit of the global relabel for P lanes.
 int gr_max_blocks(int device, int P);
 

@@ -115,6 +115,9 @@ class wbpr_stats(ctypes.Structure):
         ("lds_solved", ctypes.c_int64),
         ("lds_fallbacks", ctypes.c_int64),
         ("gap_skipped", ctypes.c_int64),
+        ("kernel_build_ms", ctypes.c_double),
+        ("layout", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
