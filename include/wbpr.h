@@ -152,6 +152,20 @@ typedef struct wbpr_options {
                                   empties, sweeps leave every vertex above
                                   it to the next global relabel.  Results
                                   are unchanged */
+    int32_t batch_kernel;      /* groups of instances (batches, server
+                                  admissions): 0 = automatic (the persistent
+                                  kernel below for a group of at least 64
+                                  eligible instances alone on the device),
+                                  1 = rounds of shared launches only, 2 =
+                                  every eligible instance (up to 131,072
+                                  vertices and 1,048,576 arcs) by the
+                                  persistent kernel: one workgroup per
+                                  instance, instances claimed largest first
+                                  from a device work queue, each solved whole
+                                  (exact BFS heights, sweeps, both phases,
+                                  flow decode) with its own tile width and
+                                  relabel budget; an instance that reaches a
+                                  cap there is finished by the rounds */
 } wbpr_options;
 
 /* Per-solve counters and timings (filled when a non-NULL pointer is given). */
@@ -192,6 +206,10 @@ typedef struct wbpr_stats {
                                       events around it (time_kernels only) */
     int32_t layout;                /* enum wbpr_layout the solve used */
     int32_t reserved0;
+    int64_t wg_solved;             /* instances solved by the persistent
+                                      workgroup-per-instance kernel */
+    int64_t wg_fallbacks;          /* ... that reached a cap there and were
+                                      finished by the rounds of launches */
 } wbpr_stats;
 
 typedef struct wbpr_ctx wbpr_ctx;

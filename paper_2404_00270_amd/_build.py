@@ -12,7 +12,8 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libwbpr.so")
 ROOT = os.path.dirname(PKG)
 
-SOURCES = ["prims.hip", "build.hip", "solve.hip", "engine.hip", "abi.cpp", "server.cpp", "terminals.hip"]
+SOURCES = ["prims.hip", "build.hip", "solve.hip", "engine.hip", "abi.cpp", "server.cpp", "terminals.hip",
+           "wgsolve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -56,6 +56,7 @@ wb::SolveConfig to_config(const wbpr_options *o) {
   c.lds_max_v = o->lds_max_v;
   c.gap = o->gap >= 0;
   c.rcsr = o->layout == WBPR_LAYOUT_RCSR;
+  c.batch_kernel = o->batch_kernel;
   return c;
 }
 
@@ -72,6 +73,7 @@ int check_options(const wbpr_options *o) {
   if (o->layout != WBPR_LAYOUT_AUTO && o->layout != WBPR_LAYOUT_BCSR && o->layout != WBPR_LAYOUT_RCSR)
     return fail(WBPR_EINVAL, "unknown layout");
   if (o->push_mode < 0 || o->push_mode > 2) return fail(WBPR_EINVAL, "push_mode must be 0, 1 or 2");
+  if (o->batch_kernel < 0 || o->batch_kernel > 2) return fail(WBPR_EINVAL, "batch_kernel must be 0, 1 or 2");
   return WBPR_OK;
 }
 
@@ -115,6 +117,8 @@ void fill_stats(wbpr_stats *st, const wb::EngineStats &r, const wb::SolveConfig 
   st->lds_fallbacks = r.small_fallbacks;
   st->kernel_build_ms = r.build_ms;
   st->layout = cfg.rcsr ? WBPR_LAYOUT_RCSR : WBPR_LAYOUT_BCSR;
+  st->wg_solved = r.wg_solved;
+  st->wg_fallbacks = r.wg_fallbacks;
 }
 
 }  // namespace
@@ -229,7 +233,7 @@ bool same_schedule(const wb::SolveConfig &a, const wb::SolveConfig &b) {
          a.gr_every_sweeps == b.gr_every_sweeps && a.grid_blocks == b.grid_blocks &&
          a.time_kernels == b.time_kernels && a.push_mode == b.push_mode && a.use_graph == b.use_graph &&
          a.max_sweeps == b.max_sweeps && a.max_wall_ms == b.max_wall_ms && a.wave_trace == b.wave_trace &&
-         a.lds_max_v == b.lds_max_v && a.gap == b.gap && a.rcsr == b.rcsr;
+         a.lds_max_v == b.lds_max_v && a.gap == b.gap && a.rcsr == b.rcsr && a.batch_kernel == b.batch_kernel;
 }
 
 // Solves a group already packed on the device, from an empty engine.

@@ -81,11 +81,13 @@ struct InstDev {
   long long *value;
   int32_t *flow;
   uint8_t *side;
+  int64_t pad;  // every list slice also holds WgInst entries of the same size
 };
 
 enum InstKernel {
   IK_INIT = 0, IK_PREFLOW, IK_VALUE_ZERO, IK_VALUE, IK_SIDE, IK_PHASE2, IK_DECODE, IK_RELEASE, IK_PARK, IK_MAXDEG,
   IK_SMALL,  // list slice of the LDS-resident solve (k_small_solve, not k_inst)
+  IK_WG,     // list slice of the persistent workgroup-per-instance solve (k_wg_solve)
   IK_COUNT
 };
 
@@ -495,6 +497,10 @@ struct MiscLayout {
   int32_t wtrace_n;  // per-wave trace records written this solve
   int32_t sweep_no;  // sweeps that ran this solve (trace only)
   int32_t gap[4];    // gap heuristic state (lowest empty height, root height, heights counted)
+  int32_t wg_head[2];  // claim counter of the persistent per-instance kernel
+  int32_t pk_head;     // persistent mode (live admission): entries claimed ...
+  int32_t pk_tail;     // ... and published
+  long long wg_stats[6];  // its scans, pushes, relabels, sweeps, BFS rounds, BFS scans
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -557,6 +563,7 @@ size_t Engine::arena_bytes(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t nca
   b += al(8 * (size_t)nch);                  // BFS chunk descriptors (sweeps: lr_key)
   b += 5 * al(4 * (size_t)ncap);             // active, stranded, roots, root_h, excl
   b += al(sizeof(InstDev) * (size_t)ncap * kListKinds + 4 * (size_t)ncap);  // lists + slots
+  b += 2 * al(sizeof(WgInst) * (size_t)ncap) + al(4 * (size_t)ncap);  // persistent ring, staging, results
   b += al(sizeof(MiscLayout));
   b += al(6 * 4 * (size_t)kSweepLogCap);     // sweep log (diagnostics)
   return b;
@@ -580,6 +587,10 @@ Engine::~Engine() {
   for (auto &e : fork_ev_) hipEventDestroy(e);
   if (side_) hipStreamDestroy(side_);
   if (wtrace_) hipFree(wtrace_);
+  if (pk_ev_) {
+    if (pk_launched_) hipEventSynchronize(pk_ev_);
+    hipEventDestroy(pk_ev_);
+  }
   if (arena_) hipFree(arena_);
   if (scratch_) hipFree(scratch_);
   if (pin_) hipHostFree(pin_);
@@ -707,6 +718,9 @@ void Engine::carve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap) {
     root_h_ = (int32_t *)take(4 * (size_t)ncap);
     excl_ = (int32_t *)take(4 * (size_t)ncap);
     inst_list_ = take(sizeof(InstDev) * (size_t)ncap * kListKinds + 4 * (size_t)ncap);
+    pk_ring_ = (WgInst *)take(sizeof(WgInst) * (size_t)ncap);
+    pk_stage_ = (WgInst *)take(sizeof(WgInst) * (size_t)ncap);
+    pk_result_ = (int32_t *)take(4 * (size_t)ncap);
     misc_ = (long long *)take(sizeof(MiscLayout));
     sweep_log_dev_ = (int32_t *)take(6 * 4 * (size_t)kSweepLogCap);
     sweep_log_ = log_level() >= 2 ? sweep_log_dev_ : nullptr;
@@ -911,6 +925,111 @@ int Engine::solve_small(const std::vector<int> &slots, hipStream_t st, std::stri
   return 0;
 }
 
+// Instances eligible for the persistent workgroup-per-instance kernel: up
+// to WG_MAX_V vertices and WG_MAX_E arcs (one workgroup's share of the GPU
+// solves them in a few milliseconds at most).  Automatic mode takes a group
+// of at least WG_MIN_GROUP of them, alone on the device (a kernel at
+// admission would hold up instances already in the rounds).
+constexpr int32_t WG_MAX_V = 1 << 17;
+constexpr int64_t WG_MAX_E = 1 << 20;
+constexpr int WG_MIN_GROUP = 64;
+
+// Descriptor of instance I for the persistent kernel, with its schedule:
+// tile width by its row lengths (as the rounds choose it), relabel budget
+// from the options.
+void Engine::fill_wg(const Inst &I, WgInst *d) const {
+  d->vbase = I.vbase;
+  d->V = I.V;
+  d->s = I.s;
+  d->t = I.t;
+  d->abase = I.abase;
+  d->E = I.E;
+  d->value = (long long *)I.value;
+  d->flow = I.flow;
+  d->side = I.side;
+  const double mean_row = I.V > 0 ? 2.0 * (double)I.E / (double)I.V : 1.0;
+  d->lanes = cfg_.lanes_per_vertex > 0 ? cfg_.lanes_per_vertex
+             : I.maxdeg <= 16          ? 1
+             : mean_row <= 10.0        ? 4
+             : mean_row <= 20.0        ? 8
+                                       : 16;
+  d->budget_pm = cfg_.gr_work_permille;
+}
+
+int Engine::solve_wg(const std::vector<int> &slots, hipStream_t st, std::string *err) {
+  if (cfg_.batch_kernel == 1 || resident_ != (int)slots.size()) return 0;
+  std::vector<int> cand;
+  for (int sl : slots) {
+    const Inst &I = inst_[sl];
+    if (I.phase == 1 && !I.pending_done && I.V <= WG_MAX_V && I.E <= WG_MAX_E) cand.push_back(sl);
+  }
+  if (cand.empty() || (cfg_.batch_kernel == 0 && (int)cand.size() < WG_MIN_GROUP)) return 0;
+  // largest first: the longest solves start first, the rest fill in behind
+  std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return inst_[a].E > inst_[b].E; });
+  const int n = (int)cand.size();
+  WgInst *hl = reinterpret_cast<WgInst *>(reinterpret_cast<InstDev *>(pin_ + kPinnedHeader) + (size_t)IK_WG * ncap_);
+  WgInst *dl = reinterpret_cast<WgInst *>(reinterpret_cast<InstDev *>(inst_list_) + (size_t)IK_WG * ncap_);
+  static_assert(sizeof(WgInst) <= sizeof(InstDev), "WgInst must fit its list slice");
+  for (int i = 0; i < n; i++) fill_wg(inst_[cand[i]], &hl[i]);
+  MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+  hipError_t e = hipMemcpyAsync(dl, hl, sizeof(WgInst) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(misc->wg_head, 0, sizeof(misc->wg_head), st);
+  if (e == hipSuccess) e = hipMemsetAsync(inst_stranded_, 0, 4 * (size_t)n, st);
+  if (e != hipSuccess) {
+    *err = std::string("persistent batch: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  WgArgs a;
+  a.L = dl;
+  a.n = n;
+  a.head = misc->wg_head;
+  a.tail = nullptr;
+  a.close = nullptr;
+  a.idle_ticks = 0;
+  a.result = inst_stranded_;
+  a.rowb = A_.rowb;
+  a.ent = A_.ent;
+  a.rev = A_.rev;
+  a.cap0 = A_.cap0;
+  a.arc2ent = A_.arc2ent;
+  a.pbefore = A_.pbefore;
+  a.acap = A_.acap;
+  a.e = e_;
+  a.h = h_;
+  a.qa = q_[0];
+  a.qb = q_[1];
+  a.stats = misc->wg_stats;
+  // WBPR_WG_ROUND_CAP (tests only) lowers the round cap so that the
+  // hand-over of unfinished instances to the rounds can be exercised
+  const char *cap_env = std::getenv("WBPR_WG_ROUND_CAP");
+  a.round_cap = cap_env ? std::max(0, std::atoi(cap_env)) : 0;
+  launch_wg_solve(cfg_.rcsr, std::min(n, 2048), st, a);
+  int32_t *hres = reinterpret_cast<int32_t *>(pin_ + kPinnedHeader + sizeof(InstDev) * (size_t)ncap_ * kListKinds +
+                                              8 * (size_t)ncap_);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipMemcpyAsync(hres, inst_stranded_, 4 * (size_t)n, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    *err = std::string("persistent batch: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  for (int i = 0; i < n; i++) {
+    Inst &I = inst_[cand[i]];
+    if (hres[i] == 1) {  // solved, flows decoded
+      I.phase = 3;
+      I.pending_done = true;
+      acc_.wg_solved++;
+    } else if (hres[i] == 2 || hres[i] == 3) {  // stopped at a cap: the rounds finish it
+      if (hres[i] == 3) I.phase = 2;  // value and side written, s carries its phase-2 bias
+      acc_.wg_fallbacks++;
+    } else {
+      *err = "persistent batch: an instance was not processed";
+      return WBPR_EINTERNAL;
+    }
+  }
+  return 0;
+}
+
 int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
   if (in.n <= 0) return 0;
   if (in.keep && in.n != 1) {
@@ -1104,8 +1223,15 @@ int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
   launch_inst_kernel(IK_PREFLOW, slots, st);
   int rc = measure_rows(slots, st, err);
   if (rc) return rc;
-  rc = solve_small(slots, st, err);
-  if (rc) return rc;
+  if (in.persistent) {
+    rc = pk_publish(slots, st, err);
+    if (rc) return rc;
+  } else {
+    rc = solve_small(slots, st, err);
+    if (rc) return rc;
+    rc = solve_wg(slots, st, err);
+    if (rc) return rc;
+  }
   e = hipGetLastError();
   if (e != hipSuccess) {
     *err = std::string("instance init: ") + hipGetErrorString(e);
@@ -1180,6 +1306,8 @@ int Engine::start_instance(int gid, int32_t s, int32_t t, int64_t *value, int32_
   int rc = measure_rows(std::vector<int>{sl}, st, err);
   if (rc) return rc;
   rc = solve_small(std::vector<int>{sl}, st, err);
+  if (rc) return rc;
+  rc = solve_wg(std::vector<int>{sl}, st, err);
   if (rc) return rc;
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
@@ -1700,7 +1828,13 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
       inst_[i].pending_done = false;
       fin_done.push_back(i);
     }
-  // retire finished instances; release groups that have no instance left
+  retire(fin_done, done, st);
+  return 0;
+}
+
+// Hands out finished instances, frees their slots and releases groups that
+// have no instance left (parks kept ones).
+void Engine::retire(const std::vector<int> &fin_done, std::vector<Finished> *done, hipStream_t st) {
   std::vector<int> empty_groups;
   std::vector<InstDev> parked;
   for (int i : fin_done) {
@@ -1722,8 +1856,135 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   }
   release_groups(empty_groups, st);
   if (!parked.empty()) launch_inst_list(IK_PARK, parked, std::vector<int>(parked.size(), 0), st);
+}
+
+// ------------------------------------------------- persistent kernel, live
+
+constexpr double kPkIdleMs = 2.0;  // a workgroup exits after this long without an entry
+
+int Engine::pk_publish(const std::vector<int> &slots, hipStream_t st, std::string *err) {
+  std::vector<int> cand;
+  for (int sl : slots) {
+    Inst &I = inst_[sl];
+    if (I.phase == 1 && I.V <= WG_MAX_V && I.E <= WG_MAX_E) cand.push_back(sl);
+  }
+  if (cand.empty()) return 0;
+  std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return inst_[a].E > inst_[b].E; });
+  const int n = (int)cand.size();
+  if ((int64_t)pk_out_.size() + n > ncap_) {  // cannot happen: a ring slot per resident instance
+    *err = "persistent ring overflow";
+    return WBPR_EINTERNAL;
+  }
+  WgInst *hl = reinterpret_cast<WgInst *>(reinterpret_cast<InstDev *>(pin_ + kPinnedHeader) + (size_t)IK_WG * ncap_);
+  for (int i = 0; i < n; i++) fill_wg(inst_[cand[i]], &hl[i]);
+  MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+  hipError_t e = hipMemcpyAsync(pk_stage_, hl, sizeof(WgInst) * n, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) {
+    launch_pk_publish(st, pk_stage_, n, pk_ring_, ncap_, pk_result_, &misc->pk_tail);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // the pinned slice is reused by the next publish
+  if (e != hipSuccess) {
+    *err = std::string("persistent publish: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  for (int i = 0; i < n; i++) {
+    inst_[cand[i]].phase = 4;
+    pk_out_.push_back({pk_tail_ + i, cand[i]});
+  }
+  pk_tail_ += n;
   return 0;
 }
+
+bool Engine::pk_alive() {
+  if (!pk_launched_) return false;
+  if (hipEventQuery(pk_ev_) == hipSuccess) pk_launched_ = false;
+  return pk_launched_;
+}
+
+int Engine::pk_ensure_running(hipStream_t st_pk, std::string *err) {
+  if (pk_out_.empty() || pk_alive()) return 0;
+  if (!pk_ev_ && hipEventCreateWithFlags(&pk_ev_, hipEventDisableTiming) != hipSuccess) {
+    pk_ev_ = nullptr;
+    *err = "persistent kernel event";
+    return WBPR_EDEVICE;
+  }
+  MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+  WgArgs a;
+  a.L = pk_ring_;
+  a.n = 0;
+  a.head = &misc->pk_head;
+  a.tail = &misc->pk_tail;
+  a.close = nullptr;
+  a.idle_ticks = (long long)(kPkIdleMs * 1e5);  // 100 MHz device clock
+  a.ring = ncap_;
+  a.result = pk_result_;
+  a.rowb = A_.rowb;
+  a.ent = A_.ent;
+  a.rev = A_.rev;
+  a.cap0 = A_.cap0;
+  a.arc2ent = A_.arc2ent;
+  a.pbefore = A_.pbefore;
+  a.acap = A_.acap;
+  a.e = e_;
+  a.h = h_;
+  a.qa = q_[0];
+  a.qb = q_[1];
+  a.stats = misc->wg_stats;
+  a.round_cap = 0;
+  // two workgroups per CU: the other wave slots stay free for the
+  // admissions' builder kernels on the server stream
+  int ncu = 256;
+  hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device_);
+  launch_wg_solve(cfg_.rcsr, 2 * ncu, st_pk, a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipEventRecord(pk_ev_, st_pk);
+  if (e != hipSuccess) {
+    *err = std::string("persistent kernel launch: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  pk_launched_ = true;
+  return 0;
+}
+
+int Engine::pk_collect(hipStream_t st, std::vector<Finished> *done, std::string *err) {
+  if (pk_out_.empty()) return 0;
+  int32_t *hres = reinterpret_cast<int32_t *>(pin_ + kPinnedHeader + sizeof(InstDev) * (size_t)ncap_ * kListKinds +
+                                              8 * (size_t)ncap_);
+  hipError_t e = hipMemcpyAsync(hres, pk_result_, 4 * (size_t)ncap_, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    *err = std::string("persistent results: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  std::vector<int> fin;
+  std::vector<std::pair<int32_t, int>> keep;
+  for (const auto &it : pk_out_) {
+    const int32_t r = hres[it.first % ncap_];
+    Inst &I = inst_[it.second];
+    if (r == 1) {
+      I.phase = 3;
+      fin.push_back(it.second);
+      acc_.wg_solved++;
+    } else if (r == 2 || r == 3) {  // stopped at a cap: the rounds finish it
+      I.phase = r == 3 ? 2 : 1;
+      acc_.wg_fallbacks++;
+    } else {
+      keep.push_back(it);
+    }
+  }
+  pk_out_.swap(keep);
+  retire(fin, done, st);
+  return 0;
+}
+
+int32_t Engine::rounds_resident() const {
+  int32_t n = 0;
+  for (const Inst &I : inst_)
+    if (I.used && (I.phase == 1 || I.phase == 2)) n++;
+  return n;
+}
+
 
 int Engine::run_to_completion(hipStream_t st, std::vector<Finished> *done, std::string *err) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1752,6 +2013,13 @@ int Engine::run_to_completion(hipStream_t st, std::vector<Finished> *done, std::
 
 void Engine::abandon(hipStream_t st) {
   hipStreamSynchronize(st);
+  if (misc_ && !pk_out_.empty()) {
+    // the persistent kernel has exited (callers wait for it): entries still
+    // in its ring are skipped, so a later launch never claims them
+    MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+    hipMemcpyAsync(&misc->pk_head, &misc->pk_tail, sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+  }
+  pk_out_.clear();
   if (arena_) {
     hipMemsetAsync(A_.rowb, 0, 8 * (size_t)Vcap_, st);
     hipMemsetAsync(e_, 0, 8 * (size_t)Vcap_, st);
@@ -1781,6 +2049,7 @@ void Engine::reset_stats() {
     MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
     hipMemset(misc->stats, 0, sizeof(misc->stats));
     hipMemset(&misc->wtrace_n, 0, 2 * sizeof(int32_t));
+    hipMemset(misc->wg_stats, 0, sizeof(misc->wg_stats));
   }
 }
 
@@ -1834,6 +2103,23 @@ int Engine::collect_stats(hipStream_t st, EngineStats *out, std::string *err) {
   r.bfs_topdown_scans = hs[12];
   r.nonempty_sweeps = hs[13];
   r.gap_skipped = hs[15];
+  long long wg[6];
+  e = hipMemcpy(wg, misc->wg_stats, sizeof(wg), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    *err = hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  // the persistent kernel's sweeps count with the short-row tile kernel's,
+  // its BFS rounds with the global relabels
+  r.k_scans[0] += wg[0];
+  r.k_pushes[0] += wg[1];
+  r.k_relabels[0] += wg[2];
+  r.arc_scans += wg[0];
+  r.pushes += wg[1];
+  r.relabels += wg[2];
+  r.sweeps += wg[3];
+  r.global_relabels += wg[4];
+  r.bfs_scans += wg[5];
   for (const auto &mk : ev_marks_) {
     if (mk.first == 5) {  // residual-graph build
       float ms = 0;

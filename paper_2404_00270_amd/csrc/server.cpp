@@ -3,10 +3,21 @@
 // One worker thread per server owns an Engine with a fixed arena carved from
 // the HBM budget.  Its loop: admit a group of waiting requests that fits the
 // free ranges (host staging -> device staging -> residual build, preflow),
-// run one engine round over everything resident (multi-root global relabel,
-// per-instance phase steps, one batch of sweeps), then copy the outputs of
-// the instances that finished back to host buffers and hand them out.
-// Requests that arrive while others are solving join the next round.
+// then solve, and copy the outputs of the instances that finished back to
+// host buffers and hand them out.  Two ways to solve:
+//
+// * persistent (default): admitted instances are published to the device
+//   ring of a persistent kernel that keeps running while requests arrive:
+//   its workgroups claim instances one at a time (largest first within an
+//   admission) and solve each whole, so a request admitted while others are
+//   on the GPU starts as soon as a workgroup is free, without waiting for a
+//   round.  The worker polls the kernel's results ring, relaunches the
+//   kernel when it has exited (idle) and work waits, and gives instances too
+//   large for it, or stopped at one of its caps, to the rounds below, which
+//   run only while the kernel is not running;
+// * rounds (batch_kernel = 1): one engine round over everything resident
+//   (multi-root global relabel, per-instance phase steps, one batch of
+//   sweeps) per loop; requests that arrive meanwhile join the next round.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,6 +81,8 @@ struct GroupRec {
 struct wbpr_server {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t pk_stream = nullptr;  // the persistent kernel's own stream
+  bool pk = true;                   // persistent mode (see above)
   std::unique_ptr<wb::Engine> engine;
   bool want_flows = true, want_sides = true;
   int32_t max_admit = 0, max_slots = 256;
@@ -225,6 +238,7 @@ int admit_group(wbpr_server *S, std::vector<Req> &reqs, uint64_t *gid_out, std::
   in.col = (const int32_t *)(d + rp_b);
   in.cap = (const int32_t *)(d + rp_b + c_b);
   in.values = (int64_t *)ob;
+  in.persistent = S->pk;
   in.flows = S->want_flows ? (int32_t *)(ob + al(8 * (size_t)n)) : nullptr;
   in.sides = S->want_sides ? (uint8_t *)(ob + al(8 * (size_t)n) + al(4 * (size_t)std::max<int64_t>(G.Et, 1))) : nullptr;
   const uint64_t gid = S->next_group++;
@@ -321,64 +335,102 @@ void fail_resident(wbpr_server *S, int status) {
   S->resident = 0;
 }
 
+void admit_waiting(wbpr_server *S) {
+  std::string err;
+  std::vector<Req> g = pick_group(S);
+  if (g.empty()) return;
+  std::vector<std::vector<Req>> tries;
+  tries.push_back(std::move(g));
+  while (!tries.empty()) {
+    std::vector<Req> grp = std::move(tries.back());
+    tries.pop_back();
+    uint64_t gid = 0;
+    const int n = (int)grp.size();
+    const int rc = admit_group(S, grp, &gid, &err);
+    if (rc == 0) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->resident += n;
+      S->admissions++;
+      S->peak_resident = std::max<int32_t>(S->peak_resident, (int32_t)S->resident);
+    } else if (rc == WBPR_EAGAIN) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (auto it = grp.rbegin(); it != grp.rend(); ++it) S->pending.push_front(std::move(*it));
+    } else if (n > 1 && (rc == WBPR_EINVAL || rc == WBPR_EOVERFLOW)) {
+      // isolate the offending request: admit the others one by one
+      for (auto &r : grp) {
+        std::vector<Req> one;
+        one.push_back(std::move(r));
+        tries.push_back(std::move(one));
+      }
+    } else {
+      const auto now = Clock::now();
+      for (const Req &r : grp) finish_req(S, r, rc, 0, nullptr, nullptr, now, false);
+    }
+  }
+}
+
+// One engine round over the instances in the rounds; publishes what finished.
+int run_round(wbpr_server *S, std::string *err) {
+  std::vector<Finished> fin;
+  const int64_t sw0 = S->engine->sweeps_run();
+  int rc = S->engine->round(S->stream, &fin, err);
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->rounds++;
+    S->sweeps += S->engine->sweeps_run() - sw0;
+  }
+  if (rc == 0) rc = publish(S, fin, err);
+  return rc;
+}
+
 void worker_main(wbpr_server *S) {
   hipSetDevice(S->device);
+  Engine &E = *S->engine;
   auto tick = Clock::now();
+  bool was_busy = false;
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(S->mu);
-      const auto now = Clock::now();
-      if (S->resident > 0 || !S->pending.empty()) S->busy_ms += ms_between(tick, now);
+      auto now = Clock::now();
+      if (was_busy) S->busy_ms += ms_between(tick, now);
       tick = now;
-      S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty() || S->resident > 0; });
+      if (S->pk && S->resident > 0) {
+        // instances on the device: look at them again after a short wait
+        // (or at once when a request arrives)
+        S->cv_work.wait_for(lk, std::chrono::microseconds(100), [&] { return S->stop || !S->pending.empty(); });
+      } else {
+        S->cv_work.wait(lk, [&] { return S->stop || !S->pending.empty() || S->resident > 0; });
+        tick = Clock::now();  // idle until now
+      }
       if (S->stop) break;
-      tick = Clock::now();
+      was_busy = true;
     }
     std::string err;
-    // admission
-    std::vector<Req> g = pick_group(S);
-    if (!g.empty()) {
-      std::vector<std::vector<Req>> tries;
-      tries.push_back(std::move(g));
-      while (!tries.empty()) {
-        std::vector<Req> grp = std::move(tries.back());
-        tries.pop_back();
-        uint64_t gid = 0;
-        const int n = (int)grp.size();
-        const int rc = admit_group(S, grp, &gid, &err);
-        if (rc == 0) {
-          std::lock_guard<std::mutex> lk(S->mu);
-          S->resident += n;
-          S->admissions++;
-          S->peak_resident = std::max<int32_t>(S->peak_resident, (int32_t)S->resident);
-        } else if (rc == WBPR_EAGAIN) {
-          std::lock_guard<std::mutex> lk(S->mu);
-          for (auto it = grp.rbegin(); it != grp.rend(); ++it) S->pending.push_front(std::move(*it));
-        } else if (n > 1 && (rc == WBPR_EINVAL || rc == WBPR_EOVERFLOW)) {
-          // isolate the offending request: admit the others one by one
-          for (auto &r : grp) {
-            std::vector<Req> one;
-            one.push_back(std::move(r));
-            tries.push_back(std::move(one));
-          }
-        } else {
-          const auto now = Clock::now();
-          for (const Req &r : grp) finish_req(S, r, rc, 0, nullptr, nullptr, now, false);
-        }
+    int rc = 0;
+    if (!S->pk) {
+      admit_waiting(S);
+      if (!E.idle()) rc = run_round(S, &err);
+    } else {
+      // while instances wait for the rounds, admit nothing: the persistent
+      // kernel drains and exits, then the rounds run
+      if (E.rounds_resident() == 0) admit_waiting(S);
+      std::vector<Finished> fin;
+      rc = E.pk_collect(S->stream, &fin, &err);
+      if (rc == 0) rc = publish(S, fin, &err);
+      if (rc == 0 && E.rounds_resident() > 0) {
+        if (!E.pk_alive()) rc = run_round(S, &err);
+      } else if (rc == 0) {
+        rc = E.pk_ensure_running(S->pk_stream, &err);
       }
     }
-    if (S->engine->idle()) continue;
-    // one round over everything resident
-    std::vector<Finished> fin;
-    const int64_t sw0 = S->engine->sweeps_run();
-    int rc = S->engine->round(S->stream, &fin, &err);
+    if (rc) {
+      hipStreamSynchronize(S->pk_stream);  // the kernel drains (idle exit) before the arena is cleared
+      fail_resident(S, rc);
+    }
     {
       std::lock_guard<std::mutex> lk(S->mu);
-      S->rounds++;
-      S->sweeps += S->engine->sweeps_run() - sw0;
+      was_busy = S->resident > 0 || !S->pending.empty();
     }
-    if (rc == 0) rc = publish(S, fin, &err);
-    if (rc) fail_resident(S, rc);
   }
 }
 
@@ -441,7 +493,9 @@ int wbpr_server_create(wbpr_ctx *ctx, const wbpr_server_options *opt, wbpr_serve
   };
   hipError_t e = hipSetDevice(S->device);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->pk_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return cleanup(hip_fail(e, "server stream"), wb::g_err);
+  S->pk = ctx->cfg.batch_kernel != 1;
   S->engine.reset(new (std::nothrow) wb::Engine(S->device));
   if (!S->engine) return cleanup(WBPR_ENOMEM, "engine");
   wb::SolveConfig cfg = ctx->cfg;
@@ -596,12 +650,14 @@ void wbpr_server_destroy(wbpr_server *S) {
   S->cv_done.notify_all();
   if (S->worker.joinable()) S->worker.join();
   hipSetDevice(S->device);
+  if (S->pk_stream) hipStreamSynchronize(S->pk_stream);  // the persistent kernel exits when idle
   if (S->stream) hipStreamSynchronize(S->stream);
   S->engine.reset();
   if (S->d_in) hipFree(S->d_in);
   if (S->d_out) hipFree(S->d_out);
   if (S->h_in) hipHostFree(S->h_in);
   if (S->stream) hipStreamDestroy(S->stream);
+  if (S->pk_stream) hipStreamDestroy(S->pk_stream);
   delete S;
 }
 

@@ -35,6 +35,8 @@ struct SolveConfig {
   int lds_max_v = 0;          // instances up to this many vertices are solved in LDS (0: 1024, < 0: never)
   bool gap = true;            // gap heuristic between global relabels (one instance in its phase)
   bool rcsr = false;          // RCSR residual layout (paper section 3.2); else BCSR
+  int batch_kernel = 0;       // groups: 0 auto, 1 rounds of launches only, 2 persistent
+                              // workgroup-per-instance kernel for every eligible instance
 };
 
 // Counters of the engine since the last reset_stats().
@@ -45,6 +47,8 @@ struct EngineStats {
   int64_t nonempty_sweeps = 0;
   int64_t small_solved = 0;  // instances solved whole in LDS at admission
   int64_t small_fallbacks = 0;  // LDS-resident solves that reached their round cap (rounds finished them)
+  int64_t wg_solved = 0;        // instances solved by the persistent workgroup-per-instance kernel
+  int64_t wg_fallbacks = 0;     // ... that reached a cap there and were finished by the rounds
   int64_t gap_skipped = 0;   // queue entries left to the next global relabel by the gap heuristic
   // per kernel: 0 short-row tiles, 1 medium rows (one wave), 2 long rows (workgroup), 3 global relabel
   double k_ms[4] = {0, 0, 0, 0};
@@ -73,6 +77,8 @@ struct GroupInput {
   uint64_t tag = 0;                  // caller's id, reported back on completion
   bool keep = false;                 // keep the built group after its instances finish (n == 1)
   bool start = true;                 // false: build only, start instances later (start_instance)
+  bool persistent = false;           // eligible instances go to the persistent kernel's ring
+                                     // (pk_publish) instead of the rounds; nothing is solved here
   int32_t *group_out = nullptr;      // receives the group id (nullable)
 };
 
@@ -136,6 +142,22 @@ class Engine {
   // Drops every resident instance (after an error) and clears the arena.
   void abandon(hipStream_t st);
 
+  // Persistent kernel with live admission (the server): instances admitted
+  // with GroupInput.persistent are published to a device ring while the
+  // kernel runs, and its workgroups claim them; a workgroup exits after
+  // kPkIdleMs without an entry.  Never run round() while pk_alive(): the
+  // global relabel labels every resident vertex.
+  bool pk_alive();
+  // (Re)starts the kernel on st_pk when published entries wait and it has exited.
+  int pk_ensure_running(hipStream_t st_pk, std::string *err);
+  // Reads the results ring (on st, synchronised): finished instances are
+  // retired into *done; stopped ones (a cap) join the rounds.
+  int pk_collect(hipStream_t st, std::vector<Finished> *done, std::string *err);
+  int32_t pk_outstanding() const { return (int32_t)pk_out_.size(); }
+  // Instances that need the rounds of launches (too large for the
+  // persistent kernel, or stopped at one of its caps).
+  int32_t rounds_resident() const;
+
   bool idle() const { return resident_ == 0; }
   bool has_kept_groups() const;
   int32_t resident() const { return resident_; }
@@ -160,7 +182,7 @@ class Engine {
     int64_t E = 0;
     int32_t vbase = 0, s = 0, t = 0;  // arena ids
     int64_t abase = 0;
-    int phase = 0;  // 1: max preflow, 2: return excess to s, 3: done
+    int phase = 0;  // 1: max preflow, 2: return excess to s, 3: done, 4: in the persistent kernel
     bool pending_done = false;  // solved whole at admission, retired by the next round
     int32_t maxdeg = 0;  // longest row its sweeps can meet (terminals excluded)
     int group = -1;
@@ -185,6 +207,17 @@ class Engine {
   void prime_small_lds();
   int measure_rows(const std::vector<int> &slots, hipStream_t st, std::string *err);
   int solve_small(const std::vector<int> &slots, hipStream_t st, std::string *err);
+  int solve_wg(const std::vector<int> &slots, hipStream_t st, std::string *err);
+  int pk_publish(const std::vector<int> &slots, hipStream_t st, std::string *err);
+  void fill_wg(const struct Inst &I, WgInst *d) const;
+  void retire(const std::vector<int> &fin_done, std::vector<Finished> *done, hipStream_t st);
+  // persistent kernel state
+  WgInst *pk_ring_ = nullptr, *pk_stage_ = nullptr;
+  int32_t *pk_result_ = nullptr;
+  hipEvent_t pk_ev_ = nullptr;
+  bool pk_launched_ = false;
+  int32_t pk_tail_ = 0;                          // entries published (host copy)
+  std::vector<std::pair<int32_t, int>> pk_out_;  // (entry, instance slot) not yet collected
   int small_lds_ = 0;  // dynamic LDS bytes of the small-instance kernel (0: not yet set, -1: unavailable)
   void drop_graphs();
   void enqueue_sweeps(hipStream_t st, int K, int tiers);

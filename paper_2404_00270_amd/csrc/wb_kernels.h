@@ -183,6 +183,50 @@ struct GRArgs {
   int32_t gap_n;          // ... and heights counted from it (<= GAP_BINS; 0: off this round)
 };
 
+// Persistent batched solve (wgsolve.hip): one workgroup of WG_THREADS per
+// instance, instances claimed from a work queue in list order.
+constexpr int WG_THREADS = 256;
+
+struct WgInst {
+  int32_t vbase, V, s, t;  // arena ids of local vertex 0, s and t
+  int64_t abase, E;        // input-arc range (flow decode)
+  long long *value;        // outputs (device, nullable but value)
+  int32_t *flow;
+  uint8_t *side;
+  int32_t lanes;           // tile width of the sweeps: 1, 4, 8, 16, 32 or 64
+  int32_t budget_pm;       // relabel work between BFSs, thousandths of V + M (0: 1000)
+};
+
+struct WgArgs {
+  const WgInst *L;
+  int32_t n;               // list entries
+  int32_t *head;           // claim counter (0 at launch)
+  const int32_t *tail;     // nullable: entries published so far (persistent mode); else all n
+  const int32_t *close;    // nullable (persistent mode): nonzero once nothing more will be published
+  long long idle_ticks;    // persistent mode: a workgroup exits after this long without an entry
+  int32_t ring;            // persistent mode: entry i lives in slot i % ring of L and result (0: no ring)
+  int32_t *result;         // per entry: 1 solved, 2 stopped in phase 1, 3 stopped in phase 2
+  const int2 *rowb;
+  int2 *ent;
+  int32_t *rev;            // BCSR mates / RCSR flows
+  const int32_t *cap0;
+  const int32_t *arc2ent;
+  const int32_t *pbefore;
+  const int32_t *acap;
+  long long *e;
+  int32_t *h;
+  int32_t *qa, *qb;        // vertex lists: an instance uses its vertex range of each
+  long long *stats;        // nullable: scans, pushes, relabels, sweeps, BFS rounds, BFS scans
+  int32_t round_cap;       // BFS rounds per instance before it is handed back (0: 4V + 1024)
+};
+
+void launch_wg_solve(bool rc, int blocks, hipStream_t st, const WgArgs &a);
+// Copies n staged entries into ring slots (tail + i) % R, clears their
+// results, then publishes them with a release store of tail + n (one
+// workgroup; the only writer of tail).
+void launch_pk_publish(hipStream_t st, const WgInst *staged, int32_t n, WgInst *ring, int32_t R, int32_t *result,
+                       int32_t *tail);
+
 // Sweep kernels: tiles of P lanes (P = 4..64), one workgroup per long-row chunk,
 // and the one-thread round control.  rc: rows in the RCSR layout (else BCSR).
 void launch_sweep_tile(int P, bool rc, int blocks, hipStream_t st, const Graph &g, const SweepQ &q);

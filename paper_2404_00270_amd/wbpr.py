@@ -73,6 +73,7 @@ class wbpr_options(ctypes.Structure):
         ("wave_trace", ctypes.c_int32),
         ("lds_max_v", ctypes.c_int32),
         ("gap", ctypes.c_int32),
+        ("batch_kernel", ctypes.c_int32),
     ]
 
 
@@ -118,6 +119,8 @@ class wbpr_stats(ctypes.Structure):
         ("kernel_build_ms", ctypes.c_double),
         ("layout", ctypes.c_int32),
         ("reserved0", ctypes.c_int32),
+        ("wg_solved", ctypes.c_int64),
+        ("wg_fallbacks", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:

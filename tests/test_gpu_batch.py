@@ -325,3 +325,43 @@ def test_autotune_then_tuned_solves(solver):
         assert r.value == oracle.reference(g2.V, g2.row_ptr, g2.col, g2.cap, g2.s, g2.t)[0]
         r = s2.solve(g)
         assert r.value == ref[0] and np.array_equal(r.side, ref[1])
+
+
+@pytest.mark.parametrize("layout", [1, 2])
+def test_persistent_per_instance_kernel(layout):
+    """Every instance of a mixed batch solved by the persistent kernel (one
+    workgroup per instance, claimed largest first): results equal the
+    oracle's, flows certified, in both residual layouts."""
+    from paper_2404_00270_amd import wbpr
+
+    gs = _mixed_batch(31, n_small=10, n_stream=24, vmax=65536)
+    refs = [oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t) for g in gs]
+    with wbpr.Solver(0, batch_kernel=2, layout=layout, **WATCHDOG) as s:
+        say(f"[wg] layout={layout} n={len(gs)} V={sum(g.V for g in gs)} E={sum(g.E for g in gs)}")
+        res = s.solve_batch(gs)
+        say(f"[wg] wg_solved={res.stats['wg_solved']} fallbacks={res.stats['wg_fallbacks']} "
+            f"lds={res.stats['lds_solved']} sweeps={res.stats['sweeps']}")
+        assert res.stats["wg_solved"] + res.stats["wg_fallbacks"] + res.stats["lds_solved"] == len(gs)
+        assert res.stats["wg_solved"] > 0
+        _check_batch(gs, res, refs)
+        for wf, ws in ((False, True), (False, False)):  # value only, and value with sides
+            r2 = s.solve_batch(gs, want_flow=wf, want_side=ws)
+            _check_batch(gs, r2, refs)
+
+
+@pytest.mark.parametrize("cap", ["1", "2"])
+def test_persistent_kernel_hands_over_to_rounds(monkeypatch, cap):
+    """Instances stopped at the persistent kernel's round cap (forced low from
+    the host) are finished by the rounds of launches: same results."""
+    from paper_2404_00270_amd import wbpr
+
+    monkeypatch.setenv("WBPR_WG_ROUND_CAP", cap)
+    gs = [W.batch_instance(200 + i, vmin=256, vmax=8192) for i in range(12)]
+    refs = [oracle.reference(g.V, g.row_ptr, g.col, g.cap, g.s, g.t) for g in gs]
+    with wbpr.Solver(0, batch_kernel=2, **WATCHDOG) as s:
+        res = s.solve_batch(gs)
+        say(f"[wg-cap {cap}] wg_solved={res.stats['wg_solved']} fallbacks={res.stats['wg_fallbacks']}")
+        assert res.stats["wg_solved"] + res.stats["wg_fallbacks"] == len(gs)
+        if cap == "1":  # one BFS round is too few for any of them
+            assert res.stats["wg_fallbacks"] > 0
+        _check_batch(gs, res, refs)

@@ -169,3 +169,59 @@ def test_server_rejections_and_shutdown(solver):
     t0 = time.time()
     srv.close()
     assert time.time() - t0 < 60
+
+
+@pytest.mark.parametrize("batch_kernel", [1, 2])
+def test_server_modes_equal_alone(batch_kernel):
+    """Both ways the server solves: rounds of shared launches (batch_kernel 1)
+    and the persistent kernel with live admission (the default, 2 forces it
+    for every eligible request); requests from several threads, staggered."""
+    from paper_2404_00270_amd import wbpr
+
+    gs = _stream(32, 7, vmax=32768)
+    with wbpr.Solver(0, batch_kernel=batch_kernel, **WATCHDOG) as s:
+        alone = [s.solve(g) for g in gs]
+        with wbpr.Server(s, hbm_budget_bytes=256 << 20, max_slots=64) as srv:
+            tickets = [None] * len(gs)
+
+            def client(k):
+                for i in range(k, len(gs), 4):
+                    tickets[i] = srv.submit(gs[i])
+                    time.sleep(0.003 * (i % 4))
+
+            th = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+            for t in th:
+                t.start()
+            for t in th:
+                t.join()
+            res = [srv.wait(tk, 120_000) for tk in tickets]
+            st = srv.stats()
+    say(f"[server-mode {batch_kernel}] rounds={st['rounds']} solves/s={st['solves_per_s']:.0f} "
+        f"p50={st['p50_ms']:.2f} p99={st['p99_ms']:.2f} peak_resident={st['peak_resident']}")
+    for g, r, a in zip(gs, res, alone):
+        assert r is not None, g.name
+        _check(g, r, a)
+    if batch_kernel == 2:
+        assert st["rounds"] == 0  # every request was eligible: no round ran
+    else:
+        assert st["rounds"] > 0
+
+
+def test_server_persistent_and_rounds_together(solver):
+    """A request too large for the persistent kernel (more than 131,072
+    vertices) is solved by the rounds while the others go through the
+    kernel; every result equals the oracle's."""
+    from paper_2404_00270_amd import wbpr
+
+    big = W.random_graph(140_000, 700_000, 1, 100, 71)
+    gs = _stream(12, 8, vmax=8192)
+    gs.insert(5, big)
+    with wbpr.Server(solver, hbm_budget_bytes=512 << 20, max_slots=32) as srv:
+        tickets = [srv.submit(g) for g in gs]
+        res = [srv.wait(tk, 120_000) for tk in tickets]
+        st = srv.stats()
+    say(f"[server-mixed] rounds={st['rounds']} completed={st['completed']}")
+    for g, r in zip(gs, res):
+        assert r is not None, g.name
+        _check(g, r)
+    assert st["rounds"] > 0
