@@ -166,6 +166,24 @@ typedef struct wbpr_options {
                                   flow decode) with its own tile width and
                                   relabel budget; an instance that reaches a
                                   cap there is finished by the rounds */
+    int32_t debug_checks;      /* 1: before every global relabel (a state
+                                  with no sweep running), a check kernel
+                                  verifies the invariants of a preflow
+                                  (section 2.2) on every instance in the
+                                  rounds: no residual capacity is negative;
+                                  BCSR: an entry's and its mate's residuals
+                                  sum to the pair's capacities; RCSR: an
+                                  arc's residual plus its flow is its
+                                  capacity and the flow is not negative;
+                                  every vertex other than s and t holds
+                                  exactly its inflow minus its outflow,
+                                  which is not negative.  A violation fails
+                                  the call with WBPR_EINTERNAL and a
+                                  message with the counts.  Every instance
+                                  then takes the rounds of launches (no
+                                  LDS-resident or persistent-kernel solve),
+                                  so every round is checked; one pass over
+                                  the residual graph per round */
 } wbpr_options;
 
 /* Per-solve counters and timings (filled when a non-NULL pointer is given). */
@@ -210,6 +228,8 @@ typedef struct wbpr_stats {
                                       workgroup-per-instance kernel */
     int64_t wg_fallbacks;          /* ... that reached a cap there and were
                                       finished by the rounds of launches */
+    int64_t debug_checked;         /* rounds whose state passed the invariant
+                                      checks (option debug_checks) */
 } wbpr_stats;
 
 typedef struct wbpr_ctx wbpr_ctx;

@@ -57,6 +57,7 @@ wb::SolveConfig to_config(const wbpr_options *o) {
   c.gap = o->gap >= 0;
   c.rcsr = o->layout == WBPR_LAYOUT_RCSR;
   c.batch_kernel = o->batch_kernel;
+  c.debug_checks = o->debug_checks != 0;
   return c;
 }
 
@@ -119,6 +120,7 @@ void fill_stats(wbpr_stats *st, const wb::EngineStats &r, const wb::SolveConfig 
   st->layout = cfg.rcsr ? WBPR_LAYOUT_RCSR : WBPR_LAYOUT_BCSR;
   st->wg_solved = r.wg_solved;
   st->wg_fallbacks = r.wg_fallbacks;
+  st->debug_checked = r.debug_checked;
 }
 
 }  // namespace
@@ -233,7 +235,8 @@ bool same_schedule(const wb::SolveConfig &a, const wb::SolveConfig &b) {
          a.gr_every_sweeps == b.gr_every_sweeps && a.grid_blocks == b.grid_blocks &&
          a.time_kernels == b.time_kernels && a.push_mode == b.push_mode && a.use_graph == b.use_graph &&
          a.max_sweeps == b.max_sweeps && a.max_wall_ms == b.max_wall_ms && a.wave_trace == b.wave_trace &&
-         a.lds_max_v == b.lds_max_v && a.gap == b.gap && a.rcsr == b.rcsr && a.batch_kernel == b.batch_kernel;
+         a.lds_max_v == b.lds_max_v && a.gap == b.gap && a.rcsr == b.rcsr && a.batch_kernel == b.batch_kernel &&
+         a.debug_checks == b.debug_checks;
 }
 
 // Solves a group already packed on the device, from an empty engine.

@@ -501,6 +501,7 @@ struct MiscLayout {
   int32_t pk_head;     // persistent mode (live admission): entries claimed ...
   int32_t pk_tail;     // ... and published
   long long wg_stats[6];  // its scans, pushes, relabels, sweeps, BFS rounds, BFS scans
+  unsigned long long dbg[2];  // debug_checks: entries, vertices violating the preflow invariants
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -561,7 +562,7 @@ size_t Engine::arena_bytes(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t nca
   b += al((size_t)Vcap);                     // vis
   b += al(4 * (size_t)GAP_BINS);             // gap heuristic: vertices per height
   b += al(8 * (size_t)nch);                  // BFS chunk descriptors (sweeps: lr_key)
-  b += 5 * al(4 * (size_t)ncap);             // active, stranded, roots, root_h, excl
+  b += 5 * al(4 * (size_t)ncap) + al(8 * (size_t)ncap);  // active, stranded, roots, root_h, excl; debug terminals
   b += al(sizeof(InstDev) * (size_t)ncap * kListKinds + 4 * (size_t)ncap);  // lists + slots
   b += 2 * al(sizeof(WgInst) * (size_t)ncap) + al(4 * (size_t)ncap);  // persistent ring, staging, results
   b += al(sizeof(MiscLayout));
@@ -591,9 +592,23 @@ Engine::~Engine() {
     if (pk_launched_) hipEventSynchronize(pk_ev_);
     hipEventDestroy(pk_ev_);
   }
-  if (arena_) hipFree(arena_);
-  if (scratch_) hipFree(scratch_);
-  if (pin_) hipHostFree(pin_);
+  if (!external_) {
+    if (arena_) hipFree(arena_);
+    if (scratch_) hipFree(scratch_);
+    if (pin_) hipHostFree(pin_);
+  }
+}
+
+void Engine::set_external(void *base, size_t bytes) {
+  external_ = true;
+  ext_base_ = base;
+  ext_bytes_ = bytes;
+  arena_ = scratch_ = nullptr;
+  arena_n_ = scratch_n_ = 0;
+  Vcap_ = Mcap_ = Ecap_ = 0;
+  ncap_ = 0;
+  sV_ = sE_ = 0;
+  sn_ = 0;
 }
 
 void Engine::set_config(const SolveConfig &cfg) {
@@ -619,6 +634,46 @@ int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int6
   if (Vcap >= (1ll << 30) || Mcap >= (1ll << 31) - 1 || Ecap >= (1ll << 31) - 1) {
     *err = "arena capacity beyond the 32-bit index limits";
     return WBPR_ETOOBIG;
+  }
+  if (external_) {
+    if (resident_ > 0) {
+      *err = "arena cannot change while instances are resident";
+      return WBPR_EAGAIN;
+    }
+    // the memory may have been used by anyone since the last call: carve it
+    // for exactly these sizes and clear the arena
+    sV = std::max<int64_t>(sV, 2);
+    sE = std::max<int64_t>(sE, 1);
+    sn = std::max<int32_t>(sn, 1);
+    const size_t abytes = arena_bytes(Vcap, Mcap, Ecap, ncap), sbytes = scratch_bytes(sV, sE, sn);
+    if (abytes + sbytes > ext_bytes_) {
+      char buf[200];
+      std::snprintf(buf, sizeof(buf),
+                    "the graph needs %zu bytes of device memory (arena %zu + builder %zu), more than the %zu bytes "
+                    "of the allocation-free entry point",
+                    abytes + sbytes, abytes, sbytes, ext_bytes_);
+      *err = buf;
+      return WBPR_ETOOBIG;
+    }
+    drop_graphs();
+    arena_ = ext_base_;
+    arena_n_ = abytes;
+    scratch_ = (char *)ext_base_ + abytes;  // abytes is a multiple of 256
+    scratch_n_ = sbytes;
+    sV_ = sV;
+    sE_ = sE;
+    sn_ = sn;
+    carve(Vcap, Mcap, Ecap, ncap);
+    hipError_t e = hipMemset(arena_, 0, abytes);
+    if (e == hipSuccess) e = hipMemset(inst_of_, 0xff, 4 * (size_t)Vcap);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      *err = std::string("arena init: ") + hipGetErrorString(e);
+      return WBPR_EDEVICE;
+    }
+    reset_books();
+    e = ensure_pinned(err);
+    return e == hipSuccess ? 0 : WBPR_ENOMEM;
   }
   const bool grow_arena = Vcap > Vcap_ || Mcap > Mcap_ || Ecap > Ecap_ || ncap > ncap_;
   if (grow_arena && resident_ > 0) {
@@ -717,6 +772,7 @@ void Engine::carve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap) {
     roots_ = (int32_t *)take(4 * (size_t)ncap);
     root_h_ = (int32_t *)take(4 * (size_t)ncap);
     excl_ = (int32_t *)take(4 * (size_t)ncap);
+    dbg_term_ = (int2 *)take(8 * (size_t)ncap);
     inst_list_ = take(sizeof(InstDev) * (size_t)ncap * kListKinds + 4 * (size_t)ncap);
     pk_ring_ = (WgInst *)take(sizeof(WgInst) * (size_t)ncap);
     pk_stage_ = (WgInst *)take(sizeof(WgInst) * (size_t)ncap);
@@ -748,6 +804,12 @@ void Engine::reset_books() {
 hipError_t Engine::ensure_pinned(std::string *err) {
   const size_t pin_need = kPinnedHeader + sizeof(InstDev) * (size_t)ncap_ * kListKinds + 24 * (size_t)ncap_ + 4096;
   if (pin_n_ >= pin_need) return hipSuccess;
+  if (external_) {  // plain host memory: no HIP allocation
+    ext_host_.assign(pin_need, 0);
+    pin_ = ext_host_.data();
+    pin_n_ = pin_need;
+    return hipSuccess;
+  }
   if (pin_) hipHostFree(pin_);
   pin_ = nullptr;
   pin_n_ = 0;
@@ -862,7 +924,8 @@ void Engine::prime_small_lds() {
 // solves/s 15.6k -> 12.4k, served p50 6.3 -> 9.4 ms).
 int Engine::solve_small(const std::vector<int> &slots, hipStream_t st, std::string *err) {
   // BCSR only: the LDS copy of a row keeps 16-bit mates
-  if (cfg_.rcsr || cfg_.lds_max_v < 0 || small_lds_ < 0 || resident_ != (int)slots.size()) return 0;
+  if (cfg_.rcsr || cfg_.debug_checks || cfg_.lds_max_v < 0 || small_lds_ < 0 || resident_ != (int)slots.size())
+    return 0;
   const int vmax = cfg_.lds_max_v > 0 ? cfg_.lds_max_v : 1024;
   std::vector<int> cand;
   for (int sl : slots)
@@ -933,6 +996,10 @@ int Engine::solve_small(const std::vector<int> &slots, hipStream_t st, std::stri
 constexpr int32_t WG_MAX_V = 1 << 17;
 constexpr int64_t WG_MAX_E = 1 << 20;
 constexpr int WG_MIN_GROUP = 64;
+// An instance still unsolved after this long in the persistent kernel is
+// handed to the rounds (a safety limit: the largest eligible instances take
+// tens of milliseconds).
+constexpr double kWgMaxMs = 2000.0;
 
 // Descriptor of instance I for the persistent kernel, with its schedule:
 // tile width by its row lengths (as the rounds choose it), relabel budget
@@ -957,7 +1024,7 @@ void Engine::fill_wg(const Inst &I, WgInst *d) const {
 }
 
 int Engine::solve_wg(const std::vector<int> &slots, hipStream_t st, std::string *err) {
-  if (cfg_.batch_kernel == 1 || resident_ != (int)slots.size()) return 0;
+  if (cfg_.batch_kernel == 1 || cfg_.debug_checks || resident_ != (int)slots.size()) return 0;
   std::vector<int> cand;
   for (int sl : slots) {
     const Inst &I = inst_[sl];
@@ -979,7 +1046,7 @@ int Engine::solve_wg(const std::vector<int> &slots, hipStream_t st, std::string 
     *err = std::string("persistent batch: ") + hipGetErrorString(e);
     return WBPR_EDEVICE;
   }
-  WgArgs a;
+  WgArgs a{};
   a.L = dl;
   a.n = n;
   a.head = misc->wg_head;
@@ -1003,6 +1070,7 @@ int Engine::solve_wg(const std::vector<int> &slots, hipStream_t st, std::string 
   // hand-over of unfinished instances to the rounds can be exercised
   const char *cap_env = std::getenv("WBPR_WG_ROUND_CAP");
   a.round_cap = cap_env ? std::max(0, std::atoi(cap_env)) : 0;
+  a.max_ticks = (long long)(kWgMaxMs * 1e5);  // 100 MHz device clock
   launch_wg_solve(cfg_.rcsr, std::min(n, 2048), st, a);
   int32_t *hres = reinterpret_cast<int32_t *>(pin_ + kPinnedHeader + sizeof(InstDev) * (size_t)ncap_ * kListKinds +
                                               8 * (size_t)ncap_);
@@ -1240,6 +1308,103 @@ int Engine::admit(const GroupInput &in, hipStream_t st, std::string *err) {
   return 0;
 }
 
+// Invariants of a preflow (section 2.2) on a state with no sweep running,
+// for the vertices of the instances whose slot has terminals term[slot] =
+// {s, t} (x = -1: not checked; option debug_checks): no residual is
+// negative; BCSR: an entry's and its mate's residuals sum to the pair's
+// merged capacities; RCSR: a forward entry's residual plus its arc's flow is
+// the arc's capacity, the flow not negative; every vertex other than s and t
+// holds exactly its inflow minus its outflow over its row, and not less than
+// 0.  One wave per vertex; bad[0] counts entries, bad[1] vertices.
+__global__ void __launch_bounds__(256) k_debug_check(const int2 *rowb, const int2 *ent, const int32_t *rev,
+                                                     const int32_t *cap0, const long long *e, const int32_t *inst_of,
+                                                     const int2 *term, int32_t nv, int rcsr,
+                                                     unsigned long long *bad) {
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WB_WAVE;
+  long long bad_ent = 0, bad_vtx = 0;
+  for (int64_t v = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WB_WAVE; v < nv; v += nw) {  // wave-uniform
+    const int32_t sl = inst_of[v];
+    if (sl < 0) continue;
+    const int2 st = term[sl];
+    if (st.x < 0) continue;
+    const int2 rb = rowb[v];
+    long long inflow = 0;  // inflow minus outflow
+    for (int32_t k = rb.x + lane(); k < rb.y; k += WB_WAVE) {
+      const int2 cr = ent[k];
+      if (!rcsr) {
+        const int32_t m = rev[k];
+        if (cr.y < 0 || (long long)cr.y + ent[m].y != (long long)cap0[k] + cap0[m]) bad_ent++;
+        inflow += (long long)cr.y - cap0[k];
+      } else if (cr.x >= 0) {
+        const int32_t f = rev[k];
+        if (cr.y < 0 || f < 0 || (long long)cr.y + f != (long long)cap0[k]) bad_ent++;
+        inflow -= f;
+      } else {
+        inflow += rev[cr.y];
+      }
+    }
+    inflow = group_sum_i64<WB_WAVE>(inflow);
+    const long long ev = e[v];
+    if (lane() == 0 && v != st.x && v != st.y && (ev < 0 || ev != inflow)) bad_vtx++;
+  }
+  bad_ent = group_sum_i64<WB_WAVE>(bad_ent);
+  bad_vtx = group_sum_i64<WB_WAVE>(bad_vtx);
+  if (lane() == 0 && bad_ent) atomicAdd(&bad[0], (unsigned long long)bad_ent);
+  if (lane() == 0 && bad_vtx) atomicAdd(&bad[1], (unsigned long long)bad_vtx);
+}
+
+int Engine::debug_check(hipStream_t st, int32_t vhi, std::string *err) {
+  std::vector<int2> term(ncap_, make_int2(-1, -1));
+  for (int i = 0; i < ncap_; i++)
+    if (inst_[i].used && (inst_[i].phase == 1 || inst_[i].phase == 2)) term[i] = make_int2(inst_[i].s, inst_[i].t);
+  MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
+  unsigned long long hb[2] = {0, 0};
+  hipError_t e = hipSuccess;
+  // WBPR_DEBUG_PLANT (tests only): before the first check, the host adds one
+  // unit of excess to a vertex other than s and t, a conservation violation
+  // the check must report
+  if (acc_.debug_checked == 0 && std::getenv("WBPR_DEBUG_PLANT")) {
+    for (int i = 0; i < ncap_; i++) {
+      const Inst &I = inst_[i];
+      if (term[i].x < 0 || I.V < 3) continue;
+      int32_t v = I.vbase;
+      while (v == I.s || v == I.t) v++;
+      long long x = 0;
+      e = hipMemcpyAsync(&x, e_ + v, 8, hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      x += 1;
+      if (e == hipSuccess) e = hipMemcpyAsync(e_ + v, &x, 8, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      break;
+    }
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(dbg_term_, term.data(), 8 * (size_t)ncap_, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemsetAsync(misc->dbg, 0, sizeof(misc->dbg), st);
+  if (e == hipSuccess) {
+    const int64_t waves = std::max<int64_t>(vhi, 1);
+    hipLaunchKernelGGL(k_debug_check, dim3(grid1d(waves * WB_WAVE, 256, 16384)), dim3(256), 0, st, A_.rowb, A_.ent,
+                       A_.rev, A_.cap0, e_, inst_of_, dbg_term_, vhi, cfg_.rcsr ? 1 : 0, misc->dbg);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(hb, misc->dbg, sizeof(hb), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    *err = std::string("debug check: ") + hipGetErrorString(e);
+    return WBPR_EDEVICE;
+  }
+  if (hb[0] || hb[1]) {
+    char buf[160];
+    std::snprintf(buf, sizeof(buf),
+                  "debug check before global relabel %lld: %llu entries and %llu vertices violate the preflow "
+                  "invariants",
+                  (long long)acc_.global_relabels + 1, hb[0], hb[1]);
+    *err = buf;
+    return WBPR_EINTERNAL;
+  }
+  acc_.debug_checked++;
+  return 0;
+}
+
 // Residuals back to the input capacities; RCSR also zeroes every arc's flow
 // (reverse entries hold an index, not a residual, and stay as they are).
 __global__ void k_reset_entries(int2 *ent, const int32_t *cap0, int32_t *flow, int rcsr, int64_t M) {
@@ -1394,6 +1559,7 @@ void Engine::dump_sweep_log(hipStream_t st) {
 
 bool Engine::ensure_side() {
   if (side_) return true;
+  if (external_) return false;  // creates nothing: the long-row chain stays on the solve stream
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
   std::vector<hipEvent_t> ev(2 * 64, nullptr);
@@ -1432,7 +1598,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
   const bool fs = cfg_.full_scan;
   const bool fork = !timed && (tiers & 3) == 3 && side_ != nullptr;
   for (int j = 0; j < K; j++) {
-    SweepQ q;
+    SweepQ q{};
     q.qin = fs ? q_[1] : q_[j & 1];
     q.qin_cnt = fs ? &misc->scan_cnt : &misc->qcnt[j % 3];
     q.qout = fs ? q_[0] : q_[(j + 1) & 1];
@@ -1511,7 +1677,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
       }
       if (timed) hipEventRecord(ev_[evb + 3], st);
     }
-    SweepCtl ctl;
+    SweepCtl ctl{};
     ctl.qin_cnt = q.qin_cnt;
     ctl.mid_cnt = q.mid_cnt;
     ctl.big_cnt = q.big_cnt;
@@ -1591,6 +1757,10 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   int64_t vhi = 0;
   for (const Group &G : groups_)
     if (G.used) vhi = std::max<int64_t>(vhi, (int64_t)G.vbase + G.V);
+  if (cfg_.debug_checks) {
+    const int rc = debug_check(st, (int32_t)vhi, err);
+    if (rc) return rc;
+  }
   hmisc[0] = sink;
   hmisc[2] = vhi;
   hmisc[1] = cfg_.gr_every_sweeps > 0 ? (1LL << 62) : (long long)(beta * (double)(resident_V_ + resident_M_));
@@ -1606,7 +1776,7 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
 
   Graph g{(int32_t)vhi, HCAP, A_.rowb, A_.ent, A_.rev, cfg_.rcsr ? A_.rev : nullptr, e_, h_, sink_, gap_hist_,
           misc->gap};
-  GRArgs ga;
+  GRArgs ga{};
   ga.g = g;
   ga.roots = roots_;
   ga.root_h = root_h_;
@@ -1910,7 +2080,7 @@ int Engine::pk_ensure_running(hipStream_t st_pk, std::string *err) {
     return WBPR_EDEVICE;
   }
   MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
-  WgArgs a;
+  WgArgs a{};
   a.L = pk_ring_;
   a.n = 0;
   a.head = &misc->pk_head;
@@ -1932,6 +2102,7 @@ int Engine::pk_ensure_running(hipStream_t st_pk, std::string *err) {
   a.qb = q_[1];
   a.stats = misc->wg_stats;
   a.round_cap = 0;
+  a.max_ticks = (long long)(kWgMaxMs * 1e5);
   // two workgroups per CU: the other wave slots stay free for the
   // admissions' builder kernels on the server stream
   int ncu = 256;

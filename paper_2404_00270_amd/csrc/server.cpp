@@ -495,7 +495,7 @@ int wbpr_server_create(wbpr_ctx *ctx, const wbpr_server_options *opt, wbpr_serve
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->pk_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return cleanup(hip_fail(e, "server stream"), wb::g_err);
-  S->pk = ctx->cfg.batch_kernel != 1;
+  S->pk = ctx->cfg.batch_kernel != 1 && !ctx->cfg.debug_checks;
   S->engine.reset(new (std::nothrow) wb::Engine(S->device));
   if (!S->engine) return cleanup(WBPR_ENOMEM, "engine");
   wb::SolveConfig cfg = ctx->cfg;

@@ -37,6 +37,7 @@ struct SolveConfig {
   bool rcsr = false;          // RCSR residual layout (paper section 3.2); else BCSR
   int batch_kernel = 0;       // groups: 0 auto, 1 rounds of launches only, 2 persistent
                               // workgroup-per-instance kernel for every eligible instance
+  bool debug_checks = false;  // preflow invariants checked before every global relabel (rounds only)
 };
 
 // Counters of the engine since the last reset_stats().
@@ -49,6 +50,7 @@ struct EngineStats {
   int64_t small_fallbacks = 0;  // LDS-resident solves that reached their round cap (rounds finished them)
   int64_t wg_solved = 0;        // instances solved by the persistent workgroup-per-instance kernel
   int64_t wg_fallbacks = 0;     // ... that reached a cap there and were finished by the rounds
+  int64_t debug_checked = 0;    // rounds whose state passed the invariant checks (debug_checks)
   int64_t gap_skipped = 0;   // queue entries left to the next global relabel by the gap heuristic
   // per kernel: 0 short-row tiles, 1 medium rows (one wave), 2 long rows (workgroup), 3 global relabel
   double k_ms[4] = {0, 0, 0, 0};
@@ -119,6 +121,14 @@ class Engine {
   // Device bytes of the per-admission scratch (builder, union CSR staging).
   static size_t scratch_bytes(int64_t V, int64_t E, int32_t n);
 
+  // External memory (the allocation-free entry point): the arena and the
+  // builder scratch are carved from [base, base + bytes), which the caller
+  // owns and which other users may overwrite between calls, so every
+  // reserve() re-carves it for the requested sizes and clears it; host
+  // staging is ordinary host memory.  Nothing is allocated on the device and
+  // no stream, event or graph is created (sweeps are launched one by one).
+  void set_external(void *base, size_t bytes);
+  bool external() const { return external_; }
   // Makes room for at least these capacities; only while nothing is
   // resident.  Returns 0 or a wbpr status.
   int reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int64_t scratch_V, int64_t scratch_E,
@@ -208,6 +218,7 @@ class Engine {
   int measure_rows(const std::vector<int> &slots, hipStream_t st, std::string *err);
   int solve_small(const std::vector<int> &slots, hipStream_t st, std::string *err);
   int solve_wg(const std::vector<int> &slots, hipStream_t st, std::string *err);
+  int debug_check(hipStream_t st, int32_t vhi, std::string *err);
   int pk_publish(const std::vector<int> &slots, hipStream_t st, std::string *err);
   void fill_wg(const struct Inst &I, WgInst *d) const;
   void retire(const std::vector<int> &fin_done, std::vector<Finished> *done, hipStream_t st);
@@ -251,14 +262,20 @@ class Engine {
   int64_t nchunk_ = 0;
   int32_t *inst_active_ = nullptr, *inst_stranded_ = nullptr;
   int32_t *roots_ = nullptr, *root_h_ = nullptr, *excl_ = nullptr;
+  int2 *dbg_term_ = nullptr;  // debug_checks: {s, t} per instance slot whose vertices are checked ({-1, -1}: none)
   void *inst_list_ = nullptr;  // per-instance kernel descriptors [ncap]
   long long *misc_ = nullptr;
   int32_t *sweep_log_dev_ = nullptr, *sweep_log_ = nullptr;  // log pointer passed to kernels (null: off)
   int32_t *sink_ = nullptr;
   long long *budget_ = nullptr;
-  // pinned host staging
+  // pinned host staging (external mode: plain host memory)
   char *pin_ = nullptr;
   size_t pin_n_ = 0;
+  // external device memory (set_external)
+  bool external_ = false;
+  void *ext_base_ = nullptr;
+  size_t ext_bytes_ = 0;
+  std::vector<char> ext_host_;
   // host bookkeeping
   RangeAlloc valloc_, malloc_, aalloc_;
   std::vector<int> slot_free_;

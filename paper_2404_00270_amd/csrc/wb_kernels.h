@@ -218,6 +218,7 @@ struct WgArgs {
   int32_t *qa, *qb;        // vertex lists: an instance uses its vertex range of each
   long long *stats;        // nullable: scans, pushes, relabels, sweeps, BFS rounds, BFS scans
   int32_t round_cap;       // BFS rounds per instance before it is handed back (0: 4V + 1024)
+  long long max_ticks;     // device-clock ticks (100 MHz) per instance before it is handed back (0: none)
 };
 
 void launch_wg_solve(bool rc, int blocks, hipStream_t st, const WgArgs &a);

@@ -22,9 +22,10 @@
 // One kernel runs for many milliseconds, so the CU's L1 keeps lines across
 // sweeps: every read of state that atomics change (residuals, heights,
 // excesses) is a device-scope atomic load, served by L2, never a stale L1
-// line.  Loops are bounded (rounds 4V + 1024, sweeps per round V + 16); an
-// instance that reaches a cap stops in a consistent preflow state and is
-// reported for the rounds of launches to finish.
+// line.  Loops are bounded (rounds 4V + 1024, sweeps per round V + 16, and a
+// time limit per instance checked after every sweep); an instance that
+// reaches a cap stops in a consistent preflow state and is reported for the
+// rounds of launches to finish.
 #include "wb_common.h"
 #include "wb_kernels.h"
 
@@ -127,6 +128,7 @@ struct WgSolve {
 struct WgShared {
   int32_t cnt[2];
   int32_t bad;
+  int32_t stop;              // the instance ran past its time limit
   int32_t item;
   unsigned long long work;   // relabel work (entries) since the BFS
   long long red[WG_THREADS / WB_WAVE];
@@ -329,6 +331,7 @@ __device__ int32_t wg_solve_one(const WgArgs &a, const WgInst &d, WgShared &sh, 
       (unsigned long long)((double)(d.budget_pm > 0 ? d.budget_pm : 1000) / 1000.0 * (double)(d.V + M)) + 1;
   const int32_t round_cap = a.round_cap > 0 ? a.round_cap : 4 * d.V + 1024, sweep_cap = d.V + 16;
   const int P = d.lanes;
+  const long long t_start = tid == 0 ? (long long)wall_clock64() : 0;  // read by thread 0 only
   int phase = 1, rounds = 0;
   for (;;) {  // every branch is uniform over the workgroup
     c.target = phase == 1 ? d.t : d.s;
@@ -378,13 +381,18 @@ __device__ int32_t wg_solve_one(const WgArgs &a, const WgInst &d, WgShared &sh, 
       if (tid == 0) sh.cnt[1 - cin] = 0;
       __syncthreads();
       wg_sweep_p<RC>(P, c, qin, na, qout, 1 - cin, sh, &st[0], &st[1], &st[2]);
-      if (tid == 0) st[3]++;
+      if (tid == 0) {
+        st[3]++;
+        sh.stop = a.max_ticks > 0 && (long long)wall_clock64() - t_start > a.max_ticks;
+      }
       __syncthreads();
       na = sh.cnt[1 - cin];
-      const bool over = sh.work > budget;
+      const bool over = sh.work > budget, stop = sh.stop != 0;
       __syncthreads();
       cin = 1 - cin;
-      if (sh.bad) return phase == 1 ? 2 : 3;
+      // a list overflow (cannot happen) or the time limit: the state after a
+      // whole sweep is a valid preflow, which the rounds finish
+      if (sh.bad || stop) return phase == 1 ? 2 : 3;
       if (over) break;
     }
   }

@@ -74,6 +74,7 @@ class wbpr_options(ctypes.Structure):
         ("lds_max_v", ctypes.c_int32),
         ("gap", ctypes.c_int32),
         ("batch_kernel", ctypes.c_int32),
+        ("debug_checks", ctypes.c_int32),
     ]
 
 
@@ -121,6 +122,7 @@ class wbpr_stats(ctypes.Structure):
         ("reserved0", ctypes.c_int32),
         ("wg_solved", ctypes.c_int64),
         ("wg_fallbacks", ctypes.c_int64),
+        ("debug_checked", ctypes.c_int64),
     ]
 
     def as_dict(self) -> dict:
