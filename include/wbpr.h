@@ -153,19 +153,23 @@ typedef struct wbpr_options {
                                   it to the next global relabel.  Results
                                   are unchanged */
     int32_t batch_kernel;      /* groups of instances (batches, server
-                                  admissions): 0 = automatic (the persistent
-                                  kernel below for a group of at least 64
-                                  eligible instances alone on the device),
-                                  1 = rounds of shared launches only, 2 =
-                                  every eligible instance (up to 131,072
-                                  vertices and 1,048,576 arcs) by the
-                                  persistent kernel: one workgroup per
-                                  instance, instances claimed largest first
-                                  from a device work queue, each solved whole
-                                  (exact BFS heights, sweeps, both phases,
-                                  flow decode) with its own tile width and
-                                  relabel budget; an instance that reaches a
-                                  cap there is finished by the rounds */
+                                  admissions): 0 or 1 = rounds of shared
+                                  launches over the disjoint union (a lone
+                                  group of small instances is solved in LDS,
+                                  see lds_max_v); 2 = every eligible
+                                  instance (up to 131,072 vertices and
+                                  1,048,576 arcs) by the persistent kernel:
+                                  one workgroup per instance, instances
+                                  claimed largest first from a device work
+                                  queue, each solved whole (exact BFS
+                                  heights, sweeps, both phases, flow decode)
+                                  with its own tile width and relabel
+                                  budget; an instance that reaches a cap
+                                  there is finished by the rounds.  The
+                                  server with 2 publishes admitted instances
+                                  into the running kernel.  The shared
+                                  rounds are faster for every size above
+                                  the LDS limit, hence the default */
     int32_t debug_checks;      /* 1: before every global relabel (a state
                                   with no sweep running), a check kernel
                                   verifies the invariants of a preflow

@@ -988,17 +988,15 @@ int Engine::solve_small(const std::vector<int> &slots, hipStream_t st, std::stri
   return 0;
 }
 
-// Instances eligible for the persistent workgroup-per-instance kernel: up
-// to WG_MAX_V vertices and WG_MAX_E arcs (one workgroup's share of the GPU
-// solves them in a few milliseconds at most).  Automatic mode takes a group
-// of at least WG_MIN_GROUP of them, alone on the device (a kernel at
-// admission would hold up instances already in the rounds).
+// Instances eligible for the persistent workgroup-per-instance kernel
+// (batch_kernel = 2): up to WG_MAX_V vertices and WG_MAX_E arcs, in a group
+// alone on the device (a kernel at admission would hold up instances
+// already in the rounds).
 constexpr int32_t WG_MAX_V = 1 << 17;
 constexpr int64_t WG_MAX_E = 1 << 20;
-constexpr int WG_MIN_GROUP = 64;
 // An instance still unsolved after this long in the persistent kernel is
 // handed to the rounds (a safety limit: the largest eligible instances take
-// tens of milliseconds).
+// a few hundred milliseconds in one workgroup).
 constexpr double kWgMaxMs = 2000.0;
 
 // Descriptor of instance I for the persistent kernel, with its schedule:
@@ -1024,13 +1022,17 @@ void Engine::fill_wg(const Inst &I, WgInst *d) const {
 }
 
 int Engine::solve_wg(const std::vector<int> &slots, hipStream_t st, std::string *err) {
-  if (cfg_.batch_kernel == 1 || cfg_.debug_checks || resident_ != (int)slots.size()) return 0;
+  // only on request (batch_kernel = 2): one workgroup per instance measured
+  // slower than the shared rounds for every size the LDS-resident solve
+  // does not take (instances above 1,024 vertices) and 3.6 times slower on
+  // the batched stream's mix of sizes
+  if (cfg_.batch_kernel != 2 || cfg_.debug_checks || resident_ != (int)slots.size()) return 0;
   std::vector<int> cand;
   for (int sl : slots) {
     const Inst &I = inst_[sl];
     if (I.phase == 1 && !I.pending_done && I.V <= WG_MAX_V && I.E <= WG_MAX_E) cand.push_back(sl);
   }
-  if (cand.empty() || (cfg_.batch_kernel == 0 && (int)cand.size() < WG_MIN_GROUP)) return 0;
+  if (cand.empty()) return 0;
   // largest first: the longest solves start first, the rest fill in behind
   std::stable_sort(cand.begin(), cand.end(), [&](int a, int b) { return inst_[a].E > inst_[b].E; });
   const int n = (int)cand.size();

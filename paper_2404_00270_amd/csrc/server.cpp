@@ -6,7 +6,7 @@
 // then solve, and copy the outputs of the instances that finished back to
 // host buffers and hand them out.  Two ways to solve:
 //
-// * persistent (default): admitted instances are published to the device
+// * persistent (batch_kernel = 2): admitted instances are published to the device
 //   ring of a persistent kernel that keeps running while requests arrive:
 //   its workgroups claim instances one at a time (largest first within an
 //   admission) and solve each whole, so a request admitted while others are
@@ -15,7 +15,7 @@
 //   kernel when it has exited (idle) and work waits, and gives instances too
 //   large for it, or stopped at one of its caps, to the rounds below, which
 //   run only while the kernel is not running;
-// * rounds (batch_kernel = 1): one engine round over everything resident
+// * rounds (the default): one engine round over everything resident
 //   (multi-root global relabel, per-instance phase steps, one batch of
 //   sweeps) per loop; requests that arrive meanwhile join the next round.
 #include <hip/hip_runtime.h>
@@ -495,7 +495,7 @@ int wbpr_server_create(wbpr_ctx *ctx, const wbpr_server_options *opt, wbpr_serve
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->pk_stream, hipStreamNonBlocking);
   if (e != hipSuccess) return cleanup(hip_fail(e, "server stream"), wb::g_err);
-  S->pk = ctx->cfg.batch_kernel != 1 && !ctx->cfg.debug_checks;
+  S->pk = ctx->cfg.batch_kernel == 2 && !ctx->cfg.debug_checks;
   S->engine.reset(new (std::nothrow) wb::Engine(S->device));
   if (!S->engine) return cleanup(WBPR_ENOMEM, "engine");
   wb::SolveConfig cfg = ctx->cfg;

@@ -173,9 +173,9 @@ def test_server_rejections_and_shutdown(solver):
 
 @pytest.mark.parametrize("batch_kernel", [1, 2])
 def test_server_modes_equal_alone(batch_kernel):
-    """Both ways the server solves: rounds of shared launches (batch_kernel 1)
-    and the persistent kernel with live admission (the default, 2 forces it
-    for every eligible request); requests from several threads, staggered."""
+    """Both ways the server solves: rounds of shared launches (the default)
+    and the persistent kernel with live admission (batch_kernel 2, for every
+    eligible request); requests from several threads, staggered."""
     from paper_2404_00270_amd import wbpr
 
     gs = _stream(32, 7, vmax=32768)
@@ -207,7 +207,7 @@ def test_server_modes_equal_alone(batch_kernel):
         assert st["rounds"] > 0
 
 
-def test_server_persistent_and_rounds_together(solver):
+def test_server_persistent_and_rounds_together():
     """A request too large for the persistent kernel (more than 131,072
     vertices) is solved by the rounds while the others go through the
     kernel; every result equals the oracle's."""
@@ -216,7 +216,8 @@ def test_server_persistent_and_rounds_together(solver):
     big = W.random_graph(140_000, 700_000, 1, 100, 71)
     gs = _stream(12, 8, vmax=8192)
     gs.insert(5, big)
-    with wbpr.Server(solver, hbm_budget_bytes=512 << 20, max_slots=32) as srv:
+    with wbpr.Solver(0, batch_kernel=2, **WATCHDOG) as solver, \
+            wbpr.Server(solver, hbm_budget_bytes=512 << 20, max_slots=32) as srv:
         tickets = [srv.submit(g) for g in gs]
         res = [srv.wait(tk, 120_000) for tk in tickets]
         st = srv.stats()
