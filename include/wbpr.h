@@ -277,6 +277,26 @@ int wbpr_solve_device(wbpr_ctx *ctx, const wbpr_csr *dev_g, int32_t s, int32_t t
                       int64_t *dev_value, int32_t *dev_arc_flow, uint8_t *dev_cut_side,
                       wbpr_stats *stats);
 
+/* Allocation-free variant of wbpr_solve_device, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, outputs, stream
+ * ordering and errors as wbpr_solve_device; `ctx` must have been created
+ * beforehand.  Every byte of device memory the solve needs (the arena and
+ * the builder's scratch) is carved from one static array of
+ * WBPR_NOALLOC_SCRATCH_BYTES (256 MiB) per device, which each device that
+ * runs the library holds from its first use until the process ends.  The
+ * call allocates no device or pinned memory and creates no stream, event or
+ * graph: sweeps are launched one by one, and there is no per-kernel timing
+ * or wave trace.  A graph whose arena and builder scratch exceed the array
+ * is rejected with WBPR_ETOOBIG (roughly 69 V + 124 E bytes: V = 100k,
+ * E = 1.5M fit).  Every call on a device shares that device's array (from
+ * any context or thread) and clears it first, so calls that overlap on one
+ * device race: the caller serialises them. */
+#define WBPR_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int wbpr_solve_device_noalloc(wbpr_ctx *ctx, const wbpr_csr *dev_g, int32_t s, int32_t t, void *stream,
+                              int64_t *dev_value, int32_t *dev_arc_flow, uint8_t *dev_cut_side,
+                              wbpr_stats *stats);
+
 /* Batched solve: n independent instances of uneven size, resident together
  * in one device arena and solved as a disjoint union, so one sweep and one
  * global relabel serve all of them (the sweep batch is replayed as a captured

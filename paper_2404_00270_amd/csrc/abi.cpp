@@ -6,7 +6,9 @@
 #include <chrono>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -177,6 +179,7 @@ void wbpr_ctx_destroy(wbpr_ctx *c) {
   hipSetDevice(c->device);
   if (c->stream) hipStreamSynchronize(c->stream);
   c->engine.reset();
+  c->engine_na.reset();
   c->input.release();
   c->output.release();
   if (c->ev_in) hipEventDestroy(c->ev_in);
@@ -240,7 +243,7 @@ bool same_schedule(const wb::SolveConfig &a, const wb::SolveConfig &b) {
 }
 
 // Solves a group already packed on the device, from an empty engine.
-int solve_group(wbpr_ctx *c, wb::GroupInput &in, hipStream_t st, wbpr_stats *stats) {
+int solve_group(wbpr_ctx *c, wb::GroupInput &in, hipStream_t st, wbpr_stats *stats, wb::Engine *engine = nullptr) {
   auto t0 = std::chrono::steady_clock::now();
   int64_t Vt = 0, Et = 0;
   for (int i = 0; i < in.n; i++) {
@@ -248,9 +251,14 @@ int solve_group(wbpr_ctx *c, wb::GroupInput &in, hipStream_t st, wbpr_stats *sta
     Et += in.E[i];
   }
   if (Vt >= (1ll << 30) || 2 * Et >= (1ll << 31) - 1) return fail(WBPR_ETOOBIG, "batch exceeds the 32-bit index limits");
-  wb::Engine &eng = *c->engine;
+  wb::Engine &eng = engine ? *engine : *c->engine;
   if (!eng.idle()) return fail(WBPR_EAGAIN, "context busy");
-  const wb::SolveConfig cfg = effective_config(c, Vt, Et);
+  wb::SolveConfig cfg = effective_config(c, Vt, Et);
+  if (eng.external()) {  // nothing that creates graphs, events or trace buffers
+    cfg.use_graph = false;
+    cfg.time_kernels = false;
+    cfg.wave_trace = false;
+  }
   if (!same_schedule(cfg, eng.config())) eng.set_config(cfg);
   std::string err;
   int rc = eng.reserve(Vt, 2 * Et, Et, in.n, Vt, Et, in.n, &err);
@@ -329,6 +337,79 @@ int wbpr_solve_device(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, void
   in.flows = dev_arc_flow;
   in.sides = dev_cut_side;
   return on_caller_stream(c, stream, [&](hipStream_t st) { return solve_group(c, in, st, stats); });
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- allocation-free
+// Device memory of the allocation-free entry point: one static array, of
+// which every device that loads this library's code holds its own copy until
+// the process ends.  In host code the name `scratch` is a host-side stand-in,
+// never a device address: host code only uses the address that
+// hipGetSymbolAddress returns for the current device, kept per device.
+static __device__ __align__(256) unsigned char scratch[WBPR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, void *> g_scratch_ptr;  // device -> its copy of scratch
+
+// Device address of scratch on `device`, which must be current; looked up
+// once per device.
+int scratch_on(int device, void **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return WBPR_OK;
+  }
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return hip_fail(e, "address of the static scratch array");
+  if (!p) return fail(WBPR_EDEVICE, "address of the static scratch array: null");
+  g_scratch_ptr[device] = p;
+  *out = p;
+  return WBPR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int wbpr_solve_device_noalloc(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, void *stream,
+                              int64_t *dev_value, int32_t *dev_arc_flow, uint8_t *dev_cut_side, wbpr_stats *stats) {
+  if (!c) return fail(WBPR_EINVAL, "null context");
+  if (!g) return fail(WBPR_EINVAL, "null graph");
+  int rc = check_shape(g->V, g->E, s, t);
+  if (rc) return rc;
+  if (!g->row_ptr || (g->E > 0 && (!g->col || !g->cap))) return fail(WBPR_EINVAL, "null CSR array");
+  if (!dev_value) return fail(WBPR_EINVAL, "null value pointer");
+  hipError_t e = hipSetDevice(c->device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+  void *base = nullptr;
+  rc = scratch_on(c->device, &base);
+  if (rc) return rc;
+  if (!c->engine_na) {  // host object only: it carves the static array, allocates nothing
+    c->engine_na.reset(new (std::nothrow) wb::Engine(c->device));
+    if (!c->engine_na) return fail(WBPR_ENOMEM, "engine");
+    c->engine_na->set_external(base, WBPR_NOALLOC_SCRATCH_BYTES);
+  }
+  int32_t V = g->V;
+  int64_t E = g->E;
+  wb::GroupInput in;
+  in.n = 1;
+  in.V = &V;
+  in.E = &E;
+  in.s = &s;
+  in.t = &t;
+  in.row_ptr = g->row_ptr;
+  in.col = g->col;
+  in.cap = g->cap;
+  in.values = dev_value;
+  in.flows = dev_arc_flow;
+  in.sides = dev_cut_side;
+  return on_caller_stream(c, stream,
+                          [&](hipStream_t st) { return solve_group(c, in, st, stats, c->engine_na.get()); });
 }
 
 int wbpr_solve(wbpr_ctx *c, const wbpr_csr *g, int32_t s, int32_t t, int64_t *value, int32_t *arc_flow,

@@ -60,6 +60,8 @@ struct wbpr_ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   wb::SolveConfig cfg;
   std::unique_ptr<wb::Engine> engine;
+  // engine of the allocation-free entry point (carves the static scratch array)
+  std::unique_ptr<wb::Engine> engine_na;
   wb::DevBuf input, output;
   // autotuned schedules by shape class (log2 V, log2 mean row length)
   std::map<std::pair<int, int>, wb::SolveConfig> tuned;

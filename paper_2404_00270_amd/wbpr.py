@@ -40,7 +40,7 @@ EXPORTS = (
     "wbpr_graph_upload", "wbpr_graph_solve", "wbpr_graph_free", "wbpr_autotune", "wbpr_wave_trace",
     "wbpr_bfs_farthest", "wbpr_pick_terminals", "wbpr_solve_multi",
     "wbpr_server_create", "wbpr_server_submit", "wbpr_server_poll", "wbpr_server_wait", "wbpr_result_free",
-    "wbpr_server_get_stats", "wbpr_server_footprint", "wbpr_server_destroy",
+    "wbpr_server_get_stats", "wbpr_server_footprint", "wbpr_server_destroy", "wbpr_solve_device_noalloc",
 )
 
 
@@ -247,6 +247,9 @@ def load_library(path: str = LIB_PATH):
     lib.wbpr_solve_device.restype = ctypes.c_int
     lib.wbpr_solve_device.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, i32, vp, vp, vp, vp,
                                       ctypes.POINTER(wbpr_stats)]
+    lib.wbpr_solve_device_noalloc.restype = ctypes.c_int
+    lib.wbpr_solve_device_noalloc.argtypes = [vp, ctypes.POINTER(wbpr_csr), i32, i32, vp, vp, vp, vp,
+                                              ctypes.POINTER(wbpr_stats)]
     lib.wbpr_solve_batch.restype = ctypes.c_int
     lib.wbpr_solve_batch.argtypes = [vp, i32, ctypes.POINTER(wbpr_csr), vp, vp, vp, vp, vp,
                                      ctypes.POINTER(wbpr_stats), vp]
@@ -434,6 +437,19 @@ def wbpr_solve_device(ctx: int, V: int, E: int, row_ptr_ptr: int, col_ptr: int, 
     st = wbpr_stats()
     _check(lib.wbpr_solve_device(ctx, ctypes.byref(g), s, t, stream or None, value_ptr, flow_ptr or None,
                                  side_ptr or None, ctypes.byref(st)))
+    return st.as_dict()
+
+
+def wbpr_solve_device_noalloc(ctx: int, V: int, E: int, row_ptr_ptr: int, col_ptr: int, cap_ptr: int, s: int,
+                              t: int, stream: int, value_ptr: int, flow_ptr: int | None,
+                              side_ptr: int | None) -> dict:
+    """wbpr_solve_device that allocates no device memory (the library's static
+    scratch array); returns the stats dict."""
+    lib = load_library()
+    g = wbpr_csr(V, E, row_ptr_ptr, col_ptr, cap_ptr)
+    st = wbpr_stats()
+    _check(lib.wbpr_solve_device_noalloc(ctx, ctypes.byref(g), s, t, stream or None, value_ptr, flow_ptr or None,
+                                         side_ptr or None, ctypes.byref(st)))
     return st.as_dict()
 
 
