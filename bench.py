@@ -172,9 +172,11 @@ def kernel_table(stats):
 
 
 def measured_traffic(kernel: str, workload: str):
-    """Calibrated HBM bytes per launch (per solve for the sweep family and the
-    builder) from the committed rocprofv3 counter runs, or None when the
-    kernel sources changed since they were taken."""
+    """Calibrated HBM bytes (FETCH_SIZE and WRITE_SIZE counters, scaled by
+    what they read for a plain device copy) from the committed rocprofv3
+    counter runs: per solve for the sweep family and the builder, per launch
+    for the global relabel; None when the kernel sources changed since the
+    counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
@@ -583,6 +585,7 @@ def main():
     ap.add_argument("--stream-rates", default="0.25,0.5,1,2",
                     help="served arrival rates, multiples of the one-at-a-time throughput")
     ap.add_argument("--no-other-workloads", action="store_true")
+    ap.add_argument("--no-rcsr", action="store_true", help="skip the headline graph in the RCSR layout")
     ap.add_argument("--no-flows", action="store_true", help="value and cut only (skips the second phase)")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--gr-every", type=int, default=0)
@@ -687,10 +690,15 @@ def main():
     kernels = kernel_table(kstats) if kstats else None
     roofline, secondary = roofline_of(kstats, kernels) if kstats else (None, [])
     if args.workload == "rmat" and args.layout in (0, 1):
+        # counter bytes per launch, as `achieved`: the family's and the
+        # builder's per-solve counts spread over their launches per solve
         if roofline is not None:
-            roofline["traffic"] = measured_traffic("sweep", "rmat_s22")
+            tr = measured_traffic("sweep", "rmat_s22")
+            per_solve_launches = roofline["launches"] / len(kstats)
+            roofline["traffic"] = round(tr / per_solve_launches, 1) if tr else None
         for sec in secondary:
-            sec["traffic"] = measured_traffic("relabel" if sec["kernel"] == KERNELS[3] else "builder", "rmat_s22")
+            tr = measured_traffic("relabel" if sec["kernel"] == KERNELS[3] else "builder", "rmat_s22")
+            sec["traffic"] = round(tr, 1) if tr else None
     solver.close()
 
     # the CPU oracle on the headline graph, in the background from here on
@@ -739,7 +747,7 @@ def main():
         "workloads": None,
         "stream": None,
     }
-    if args.layout in (0, 1):
+    if args.layout in (0, 1) and not args.no_rcsr:
         rc_ms, rc_value = layout_time(g, rp, col, cap, dev, 2)
         out["rcsr_ms"] = round(rc_ms, 3)
         out["rcsr_same_value"] = rc_value == flow_value

@@ -1594,7 +1594,10 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
   // start, its queue flushes and its counter atomics.  The long-row chunk
   // kernels keep 1024 (one workgroup per chunk task; 256 measured slower).
   const int sweep_blocks = cfg_.grid_blocks > 0 ? cfg_.grid_blocks : 256;
-  const int chunk_blocks = 1024;
+  static const int mid_env = std::getenv("WBPR_MID_BLOCKS") ? std::atoi(std::getenv("WBPR_MID_BLOCKS")) : 0;
+  static const int chunk_env = std::getenv("WBPR_CHUNK_BLOCKS") ? std::atoi(std::getenv("WBPR_CHUNK_BLOCKS")) : 0;
+  const int mid_blocks = mid_env > 0 ? mid_env : sweep_blocks;
+  const int chunk_blocks = chunk_env > 0 ? chunk_env : 1024;
   const int mode = cfg_.push_mode == 1 ? 0 : 1;
   const bool timed = cfg_.time_kernels;
   const bool fs = cfg_.full_scan;
@@ -1666,11 +1669,11 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
       launch_sweep_chunk(1, rc, chunk_blocks, side_, g, q);
       launch_sweep_chunk(2, rc, 64, side_, g, q);
       hipEventRecord(ej, side_);
-      launch_sweep_tile(mid_lanes_, rc, sweep_blocks, st, g, qw);
+      launch_sweep_tile(mid_lanes_, rc, mid_blocks, st, g, qw);
       hipStreamWaitEvent(st, ej, 0);
     } else {
       if (timed) hipEventRecord(ev_[evb + 1], st);
-      if (tiers & 1) launch_sweep_tile(mid_lanes_, rc, sweep_blocks, st, g, qw);
+      if (tiers & 1) launch_sweep_tile(mid_lanes_, rc, mid_blocks, st, g, qw);
       if (timed) hipEventRecord(ev_[evb + 2], st);
       if (tiers & 2) {
         launch_sweep_chunk(0, rc, chunk_blocks, st, g, q);
