@@ -185,8 +185,17 @@ __device__ __forceinline__ int64_t merge_split(const K *a, int64_t na, const K *
   return lo;
 }
 
+// Self-loop items: after the full sort they are the last 2 nself items
+// (dropped by mraw); on the sorted-rows path they stay inline with key (u,u)
+// and every step skips them.
+__device__ __forceinline__ bool self_key(uint64_t k, int vb) { return (k >> vb) == (k & ((1ull << vb) - 1)); }
+
+// The merge also marks where each group of equal keys starts (head[o] = 1
+// unless the key is a self-loop's): the output before the tile's first one
+// is the larger of the two inputs' predecessors.
 __global__ void __launch_bounds__(MERGE_THREADS) k_merge(const uint64_t *ka, const uint32_t *va, const uint64_t *kb,
-                                                         const uint32_t *vb, int64_t n, uint64_t *ko, uint32_t *vo) {
+                                                         const uint32_t *vb, int64_t n, uint64_t *ko, uint32_t *vo,
+                                                         int32_t *head, int kbits) {
   __shared__ uint64_t s_k[MERGE_TILE];
   __shared__ uint32_t s_v[MERGE_TILE];
   __shared__ uint16_t s_src[MERGE_TILE];
@@ -223,17 +232,23 @@ __global__ void __launch_bounds__(MERGE_THREADS) k_merge(const uint64_t *ka, con
     __syncthreads();
     for (int x = threadIdx.x; x < na + nb; x += MERGE_THREADS) {
       const int src = s_src[x];
-      ko[d0 + x] = s_k[src];
+      const uint64_t k = s_k[src];
+      ko[d0 + x] = k;
       vo[d0 + x] = s_v[src];
+      bool first;
+      if (x > 0) {
+        first = s_k[s_src[x - 1]] != k;
+      } else if (d0 == 0) {
+        first = true;
+      } else {
+        const uint64_t pa = i0 > 0 ? ka[i0 - 1] : 0, pb = j0 > 0 ? kb[j0 - 1] : 0;
+        first = (pa > pb ? pa : pb) != k;
+      }
+      head[d0 + x] = first && !self_key(k, kbits) ? 1 : 0;
     }
     __syncthreads();  // LDS is reused by the next tile
   }
 }
-
-// Self-loop items: after the full sort they are the last 2 nself items
-// (dropped by mraw); on the sorted-rows path they stay inline with key (u,u)
-// and every step skips them.
-__device__ __forceinline__ bool self_key(uint64_t k, int vb) { return (k >> vb) == (k & ((1ull << vb) - 1)); }
 
 // Step 3a.  head[i] = 1 where a new (row, column) group starts.
 __global__ void k_heads(const uint64_t *keys, int64_t N, int vb, bool inline_self, const BuildStatus *st,
@@ -612,8 +627,10 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
       if (e == hipSuccess) e = hipMemcpyAsync(s.v0 + E, alt ? ov : bv, 4 * (size_t)E, hipMemcpyDeviceToDevice, st);
       if (e != hipSuccess) return e;
     }
+    // the merge marks the group heads as it writes (row_of in hx is no
+    // longer needed)
     hipLaunchKernelGGL(k_merge, dim3(grid_for((N + MERGE_TILE - 1) / MERGE_TILE, 1)), dim3(MERGE_THREADS), 0, st, s.k0,
-                       s.v0, s.k0 + E, s.v0 + E, E, s.k1, s.v1);
+                       s.v0, s.k0 + E, s.v0 + E, E, s.k1, s.v1, s.head, vb);
     keys = s.k1;
     vals = s.v1;
   } else {
@@ -628,8 +645,8 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
     if (e != hipSuccess) return e;
     keys = alt ? s.k1 : s.k0;
     vals = alt ? s.v1 : s.v0;
+    hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(BT), 0, st, keys, N, vb, inline_self, status_dev, s.head);
   }
-  hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(BT), 0, st, keys, N, vb, inline_self, status_dev, s.head);
   e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_groups, dim3(grid_for(N)), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev,
