@@ -109,7 +109,7 @@ typedef struct wbpr_options {
     int64_t max_sweeps;        /* watchdog on total sweeps (0 = none) */
     int32_t max_wall_ms;       /* watchdog on wall time (0 = none) */
     int32_t grid_blocks;       /* workgroups per tile-kernel launch of a sweep
-                                  (0 = 256, one per compute unit) */
+                                  (0 = 512, two per compute unit) */
     int32_t time_kernels;      /* 1: time every sweep and global-relabel
                                   launch with HIP events (kernel_ms) */
     int32_t push_mode;         /* 1: one push per visit to the minimum-height

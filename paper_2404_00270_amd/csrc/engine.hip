@@ -1587,13 +1587,15 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
   MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
   const bool rc = cfg_.rcsr;
   Graph g{(int32_t)Vcap_, HCAP, A_.rowb, A_.ent, A_.rev, rc ? A_.rev : nullptr, e_, h_, sink_, gap_hist_, misc->gap};
-  // tile kernels: 256 workgroups, one per CU.  Measured on R-MAT / grid cut
-  // / bipartite: 1024 -> 34.3 / 94 / 6.35 ms, 512 -> 30.2 / 85 / 6.08,
-  // 256 -> 30.0 / 78 / 6.0, 192 and 128 slower again (31.2 and 34 ms on
-  // R-MAT); most sweeps have short queues, and each workgroup pays for its
-  // start, its queue flushes and its counter atomics.  The long-row chunk
-  // kernels keep 1024 (one workgroup per chunk task; 256 measured slower).
-  const int sweep_blocks = cfg_.grid_blocks > 0 ? cfg_.grid_blocks : 256;
+  // tile kernels: 512 workgroups, two per CU.  Measured on R-MAT / grid cut
+  // / bipartite (means of three interleaved runs of nine solves): 256 ->
+  // 26.0 / 70.9 / 4.55 ms, 512 -> 25.4 / 68.0 / 4.56, 1024 -> 26.1 / 72.0 /
+  // 4.65; most sweeps have short queues, and each workgroup pays for its
+  // start, its queue flushes and its counter atomics, while the big sweeps
+  // after a global relabel want more waves in flight.  The long-row chunk
+  // kernels keep 1024 (one workgroup per chunk task; 512 and 2048 measured
+  // slower).
+  const int sweep_blocks = cfg_.grid_blocks > 0 ? cfg_.grid_blocks : 512;
   static const int mid_env = std::getenv("WBPR_MID_BLOCKS") ? std::atoi(std::getenv("WBPR_MID_BLOCKS")) : 0;
   static const int chunk_env = std::getenv("WBPR_CHUNK_BLOCKS") ? std::atoi(std::getenv("WBPR_CHUNK_BLOCKS")) : 0;
   const int mid_blocks = mid_env > 0 ? mid_env : sweep_blocks;

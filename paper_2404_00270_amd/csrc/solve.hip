@@ -457,6 +457,13 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
           for (int j = 0; j < UNROLL; j++) rr[j] = res_of<RC>(g.flow, cr[j]);
 #pragma unroll
           for (int j = 0; j < UNROLL; j++) hv[j] = rr[j] > 0 ? g.h[col_of<RC>(cr[j])] : 0;
+          // the pushes of all UNROLL slices are issued before any of their
+          // returned excesses is needed (queue appends after the loop), so
+          // their atomics overlap.  A head whose excess was <= 0 before the
+          // push is not being visited with excess this sweep, so its height
+          // is still the gathered one, below u's and so below the cap.
+          bool apv[UNROLL];
+          int32_t vj[UNROLL];
 #pragma unroll
           for (int j = 0; j < UNROLL; j++) {
             const int32_t k = kb + j * P + tl;
@@ -475,15 +482,17 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
             const long long before = group_excl_scan_i64<P>(want, &tot);
             long long take = erem - before;
             take = take < 0 ? 0 : (take > want ? want : take);
-            bool app_v = false;
+            apv[j] = false;
+            vj[j] = v;
             if (take > 0) {
-              app_v = push_entry<RC>(g, handle_of<RC>(k, cr[j]), v, take) && g.h[v] < g.hcap;
+              apv[j] = push_entry<RC>(g, handle_of<RC>(k, cr[j]), v, take);
               pushes++;
             }
-            waveq_push(wq, q.append && app_v, v);
             if (erem > 0 && kb + j * P < end) nscan += P;
             erem -= tot;
           }
+#pragma unroll
+          for (int j = 0; j < UNROLL; j++) waveq_push(wq, q.append && apv[j], vj[j]);
         }
       }
       if (ni < n) {
@@ -706,17 +715,22 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
       }
       __syncthreads();
       long long rem = s_take - before;  // claim left for this thread's entries, in row order
+      // every push is issued before the returned excesses are needed (as in
+      // the tile kernel; a head with excess <= 0 before the push keeps the
+      // gathered height, below u's)
+      bool apv[PER];
 #pragma unroll
       for (int j = 0; j < PER; j++) {
         const long long d = rem < 0 ? 0 : (rem > want[j] ? want[j] : rem);
-        bool app_v = false;
+        apv[j] = false;
         if (d > 0) {
-          app_v = push_entry<RC>(g, RC ? hk[j] : k0 + j, vv[j], d) && g.h[vv[j]] < g.hcap;
+          apv[j] = push_entry<RC>(g, RC ? hk[j] : k0 + j, vv[j], d);
           pushes++;
         }
-        waveq_push(wq, q.append && app_v, vv[j]);
         rem -= want[j];
       }
+#pragma unroll
+      for (int j = 0; j < PER; j++) waveq_push(wq, q.append && apv[j], vv[j]);
     }
     key = group_min<WB_WAVE>(key);
     if (lane() == 0) s_wmin[w] = key;
