@@ -1025,14 +1025,30 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
       constexpr int32_t BU_SHORT = 32;
       int found_cnt = 0;
       int32_t *ccnt = &a.chunk_cnt[level & 1];
-      for (int64_t vb = (int64_t)wave * WB_WAVE; vb < g.V; vb += (int64_t)nwaves * WB_WAVE) {  // wave-uniform
+      // the visit code and row bounds of the wave's next 64 vertices are
+      // loaded while the current ones are scanned (only this wave labels
+      // them during this pass, and row bounds never change)
+      const int64_t bstride = (int64_t)nwaves * WB_WAVE;
+      uint8_t nvis = 1;
+      int2 nrb = make_int2(0, 0);
+      {
+        const int64_t v = (int64_t)wave * WB_WAVE + lane();
+        if (v < g.V) {
+          nvis = a.vis[v];
+          nrb = g.rowb[v];
+        }
+      }
+      for (int64_t vb = (int64_t)wave * WB_WAVE; vb < g.V; vb += bstride) {  // wave-uniform
         const int64_t v = vb + lane();
-        bool mine = v < g.V && a.vis[v] == 0;
+        bool mine = v < g.V && nvis == 0;
         int32_t beg = 0, end = 0;
         if (mine) {
-          const int2 rb = g.rowb[v];
-          beg = rb.x;
-          end = rb.y;
+          beg = nrb.x;
+          end = nrb.y;
+        }
+        if (v + bstride < g.V) {
+          nvis = a.vis[v + bstride];
+          nrb = g.rowb[v + bstride];
         }
         const int32_t deg = end - beg;
         if (mine && deg > a.split_deg) {
@@ -1262,21 +1278,29 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   {
     WaveQ wq{s_qbuf[wl], &s_qcnt[wl], a.qout, &a.qcnt[0], a.qcap, a.err};
     KeyCount kc_act, kc_str;
-    for (int64_t v0 = gtid - lane(); v0 < g.V; v0 += nthreads) {  // wave-uniform
-      const int64_t v = v0 + lane();
-      bool act = false, str = false;
-      int32_t ins = -1;
-      if (v < g.V) {
-        const long long ev = g.e[v];
-        const int32_t hv = g.h[v];
-        act = ev > 0 && hv < g.hcap;
-        str = ev > 0 && hv == g.hcap;
-        if (act || str) ins = a.inst_of[v];
+    // a wave takes 4 x 64 consecutive vertices at a time: their excess and
+    // height loads are all in flight before the first is used
+    constexpr int RB = 4;
+    for (int64_t v0 = (gtid - lane()) * RB; v0 < g.V; v0 += nthreads * RB) {  // wave-uniform
+      long long ev[RB];
+      int32_t hv[RB];
+#pragma unroll
+      for (int j = 0; j < RB; j++) {
+        const int64_t v = v0 + j * WB_WAVE + lane();
+        ev[j] = v < g.V ? g.e[v] : 0;
+        hv[j] = v < g.V ? g.h[v] : 0;
       }
-      stranded += str ? 1 : 0;
-      key_count_add(act && ins >= 0, ins, kc_act, a.inst_active);
-      key_count_add(str && ins >= 0, ins, kc_str, a.inst_stranded);
-      waveq_push(wq, act, (int32_t)v);
+#pragma unroll
+      for (int j = 0; j < RB; j++) {
+        const int64_t v = v0 + j * WB_WAVE + lane();
+        const bool act = ev[j] > 0 && hv[j] < g.hcap;
+        const bool str = ev[j] > 0 && hv[j] == g.hcap;
+        const int32_t ins = act || str ? a.inst_of[v] : -1;
+        stranded += str ? 1 : 0;
+        key_count_add(act && ins >= 0, ins, kc_act, a.inst_active);
+        key_count_add(str && ins >= 0, ins, kc_str, a.inst_stranded);
+        waveq_push(wq, act, (int32_t)v);
+      }
     }
     key_count_flush(kc_act, a.inst_active);
     key_count_flush(kc_str, a.inst_stranded);
