@@ -248,11 +248,44 @@ __device__ __forceinline__ void wg_sweep_p(int P, const WgSolve &c, const int32_
   }
 }
 
+// One level of the backward BFS: a tile of P lanes per frontier vertex w
+// walks w's row and claims every unlabelled v with residual capacity
+// toward w (the mate of entry (w, v)).
+template <int P, bool RC>
+__device__ void wg_bfs_level(const WgSolve &c, const int32_t *fin, int32_t n, int32_t *fout, int nc, int32_t lev,
+                             WgShared &sh, long long *bscans) {
+  constexpr int TPW = WB_WAVE / P;
+  const int wave = threadIdx.x / WB_WAVE, sub = lane() / P, tl = lane() % P;
+  for (int32_t b0 = wave * TPW; b0 < n; b0 += (WG_THREADS / WB_WAVE) * TPW) {  // wave-uniform
+    const int32_t i = b0 + sub;
+    int32_t beg = 0, end = 0;
+    if (i < n) {
+      const int2 rb = c.rowb[fin[i]];
+      beg = rb.x;
+      end = rb.y;
+      if (tl == 0) *bscans += end - beg;
+    }
+    for (int32_t kb = beg; kb < end; kb += P) {  // tile-uniform
+      const int32_t k = kb + tl;
+      bool claimed = false;
+      int32_t v = 0;
+      if (k < end) {
+        const int2 cr = ld_ent(&c.ent[k]);
+        v = col_of<RC>(cr);
+        if (ld_i32(&c.h[v]) == c.V && wg_mate_res<RC>(c.ent, c.rev, k, cr) > 0)
+          claimed = atomicCAS(&c.h[v], c.V, lev) == c.V;
+      }
+      wg_append(claimed, v, fout, &sh.cnt[nc], c.V, &sh.bad);
+    }
+  }
+}
+
 // Exact heights: backward BFS from c.target over arcs v -> w with residual
 // capacity; unreached vertices stay at V (inactive), the excluded terminal
-// at V + 1.  Frontiers alternate between fa and fb.  Returns the levels.
+// at V + 1.  Frontiers alternate between fa and fb; tiles of P lanes (the
+// instance's tile width, at least 4) expand them.  Returns the levels.
 template <bool RC>
-__device__ int32_t wg_bfs(const WgSolve &c, int32_t *fa, int32_t *fb, WgShared &sh, long long *bscans) {
+__device__ int32_t wg_bfs(const WgSolve &c, int lanes, int32_t *fa, int32_t *fb, WgShared &sh, long long *bscans) {
   const int tid = threadIdx.x;
   for (int32_t x = tid; x < c.V; x += WG_THREADS) {
     const int32_t v = c.vb + x;
@@ -272,23 +305,12 @@ __device__ int32_t wg_bfs(const WgSolve &c, int32_t *fa, int32_t *fb, WgShared &
     const int32_t *fin = cur == 0 ? fa : fb;
     int32_t *fout = cur == 0 ? fb : fa;
     const int nc = 1 - cur;
-    // one wave per frontier vertex, lanes over its row
-    for (int32_t i = tid / WB_WAVE; i < n; i += WG_THREADS / WB_WAVE) {  // wave-uniform
-      const int32_t w = fin[i];
-      const int2 rb = c.rowb[w];
-      if (lane() == 0) *bscans += rb.y - rb.x;
-      for (int32_t kb = rb.x; kb < rb.y; kb += WB_WAVE) {
-        const int32_t k = kb + lane();
-        bool claimed = false;
-        int32_t v = 0;
-        if (k < rb.y) {
-          const int2 cr = ld_ent(&c.ent[k]);
-          v = col_of<RC>(cr);
-          if (ld_i32(&c.h[v]) == c.V && wg_mate_res<RC>(c.ent, c.rev, k, cr) > 0)
-            claimed = atomicCAS(&c.h[v], c.V, lev) == c.V;
-        }
-        wg_append(claimed, v, fout, &sh.cnt[nc], c.V, &sh.bad);
-      }
+    switch (lanes) {
+      case 1:
+      case 4: wg_bfs_level<4, RC>(c, fin, n, fout, nc, lev, sh, bscans); break;
+      case 8: wg_bfs_level<8, RC>(c, fin, n, fout, nc, lev, sh, bscans); break;
+      case 16: wg_bfs_level<16, RC>(c, fin, n, fout, nc, lev, sh, bscans); break;
+      default: wg_bfs_level<64, RC>(c, fin, n, fout, nc, lev, sh, bscans); break;
     }
     __syncthreads();
     n = sh.cnt[nc];
@@ -337,7 +359,7 @@ __device__ int32_t wg_solve_one(const WgArgs &a, const WgInst &d, WgShared &sh, 
     c.target = phase == 1 ? d.t : d.s;
     c.other = phase == 1 ? d.s : d.t;
     if (tid == 0) sh.bad = 0;
-    wg_bfs<RC>(c, qa, qb, sh, &st[5]);
+    wg_bfs<RC>(c, d.lanes, qa, qb, sh, &st[5]);
     if (tid == 0) st[4]++;
     // active vertices: excess and a path to the target
     if (tid == 0) sh.cnt[0] = 0;
