@@ -16,7 +16,9 @@
 //      stable radix sort of all keys on (row, column), self-loops last
 //   3. group heads -> unique entry ids (scan); each head walks its group
 //      for the merged capacity and the parallel-arc prefixes (long groups:
-//      one workgroup each)
+//      one workgroup each).  On the sorted path, when no row repeats a
+//      column more than MT_RUN times, steps 2 (the merge) and 3 are one
+//      kernel with a decoupled look-back over tiles (k_merge_entries)
 //   4. row pointers, mates and arc->entry map, parallel-arc prefixes; the
 //      pairwise int32 overflow check runs only if some entry holds >= 2^30
 #include "wb_common.h"
@@ -115,16 +117,21 @@ __global__ void k_row_marks(const int64_t *rp, int32_t V, int64_t E, int32_t *cn
   }
 }
 
+// Longest run of equal columns in a sorted row that the fused merge below
+// accepts; a group of equal keys then holds at most 2 * MT_RUN items.
+constexpr int MT_RUN = 256;
+
 // Step 1b.  Forward key (u,v) goes to fkeys[i], backward key (v,u) to
 // bkeys[i], with u = row_of[i]; a self-loop (or an out-of-range column,
 // dropped as one) gets (u,u) in both, which keeps a column-sorted row
 // sorted; the full-sort path turns them into the largest key.  Also checks
-// that every row's columns are non-decreasing.  Counters are reduced per
-// workgroup, one atomic per workgroup and status word.
+// that every row's columns are non-decreasing and whether a row repeats a
+// column more than MT_RUN times.  Counters are reduced per workgroup, one
+// atomic per workgroup and status word.
 __global__ void k_emit_keys(const int64_t *rp, const int32_t *row_of, const int32_t *col, const int32_t *cap,
                             int32_t V, int64_t E, int vb, uint64_t *fkeys, uint32_t *fvals, uint64_t *bkeys,
                             uint32_t *bvals, int32_t *arc2ent, int32_t *acap, BuildStatus *st) {
-  int nself = 0, bad = 0, unsorted = 0;
+  int nself = 0, bad = 0, unsorted = 0, longrun = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r = row_of[i];
     const uint64_t u = (uint64_t)r;
@@ -132,7 +139,9 @@ __global__ void k_emit_keys(const int64_t *rp, const int32_t *row_of, const int3
     const int32_t c = cap[i];
     const bool ok = vv >= 0 && vv < V;
     if (!ok || c < 0) bad++;
-    if (i > rp[r] && col[i - 1] > vv) unsorted++;
+    const int64_t r0 = rp[r];
+    if (i > r0 && col[i - 1] > vv) unsorted++;
+    if (i - MT_RUN >= r0 && i >= MT_RUN && col[i - MT_RUN] == vv) longrun++;
     const uint64_t v = ok ? (uint64_t)vv : u;
     if (u == v) nself++;
     fkeys[i] = (u << vb) | v;
@@ -145,10 +154,12 @@ __global__ void k_emit_keys(const int64_t *rp, const int32_t *row_of, const int3
   nself = block_reduce_i32<false>(nself);
   bad = block_reduce_i32<false>(bad);
   unsorted = block_reduce_i32<false>(unsorted);
+  longrun = block_reduce_i32<false>(longrun);
   if (threadIdx.x == 0) {
     if (nself) atomicAdd(&st->nself, nself);
     if (bad) atomicAdd(&st->bad_input, bad);
     if (unsorted) atomicAdd(&st->unsorted, unsorted);
+    if (longrun) atomicAdd(&st->longrun, longrun);
   }
 }
 
@@ -279,6 +290,348 @@ __device__ __forceinline__ void write_entry(int32_t u, uint64_t key, uint64_t cm
   const int32_t c32 = c > 0x7fffffffll ? 0 : (int32_t)c;
   ent[u] = make_int2(vbase + (int)(key & cmask), c32);
   cap0[u] = c32;
+}
+
+// Sorted-rows path, fused (no row repeats a column more than MT_RUN times):
+// the merged keys, the head flags and their prefix sum never go through
+// memory.  The merge is cut into tiles of about MT_TILE outputs whose bounds
+// are moved forward past the group of equal keys that straddles them (a
+// group holds at most MT_SLACK items, so a tile holds fewer than MT_CAP),
+// which puts every group inside one tile.  Three passes: the tile bounds
+// (k_merge_splits), the number of entries (group heads) of every tile
+// (k_merge_count) and their prefix sum, then the entries (k_merge_entries):
+// each workgroup merges its tile in LDS, every item records its entry id
+// under its payload, every forward item the capacity of the earlier
+// parallel arcs of its group (a segmented prefix sum over the workgroup),
+// and the group ends write the entries (column, summed capacity, row).
+// (A single pass with a decoupled look-back between tiles was slower: its
+// waits held back the scattered writes.)
+constexpr int MT_THREADS = 256;
+constexpr int MT_TILE = 2048;
+constexpr int MT_SLACK = 2 * MT_RUN;
+constexpr int MT_CAP = MT_TILE + MT_SLACK;
+constexpr int MT_ITEMS = MT_CAP / MT_THREADS;
+constexpr int MT_WAVES = MT_THREADS / WB_WAVE;
+static_assert(MT_CAP % MT_THREADS == 0, "tile capacity is a whole number of items per thread");
+static_assert(MT_CAP <= 65536, "LDS source index is 16-bit");
+
+// First index in [lo, min(lo + MT_SLACK, n)) whose key exceeds k, else that bound.
+__device__ __forceinline__ int64_t run_end(const uint64_t *x, int64_t lo, int64_t n, uint64_t k) {
+  int64_t hi = lo + MT_SLACK < n ? lo + MT_SLACK : n;
+  while (lo < hi) {
+    const int64_t m = (lo + hi) >> 1;
+    if (x[m] <= k) lo = m + 1; else hi = m;
+  }
+  return lo;
+}
+
+// Merge-path split of a and b (n keys each) at output d, moved forward past
+// the group of equal keys that straddles d.  *bad is set if that group is
+// longer than MT_SLACK (the long-run check rules this out).
+__device__ void mt_split(const uint64_t *a, const uint64_t *b, int64_t n, int64_t d, int64_t *ia, int64_t *jb,
+                         int *bad) {
+  int64_t i = merge_split(a, n, b, n, d), j = d - i;
+  if (d > 0 && d < 2 * n) {
+    const uint64_t pa = i > 0 ? a[i - 1] : 0, pb = j > 0 ? b[j - 1] : 0;
+    const uint64_t pk = pa > pb ? pa : pb;  // last output before d
+    const uint64_t nk = (i < n && (j >= n || a[i] <= b[j])) ? a[i] : b[j];  // output d
+    if (nk == pk) {
+      const int64_t i2 = run_end(a, i, n, pk), j2 = run_end(b, j, n, pk);
+      if ((i2 - i) + (j2 - j) >= MT_SLACK) *bad = 1;
+      i = i2;
+      j = j2;
+    }
+  }
+  *ia = i;
+  *jb = j;
+}
+
+// Tile bounds, one thread per bound: split[2x], split[2x+1] = positions in
+// a and b where tile x starts.
+__global__ void k_merge_splits(const uint64_t *a, const uint64_t *b, int64_t n, int64_t ntiles, int64_t *split,
+                               BuildStatus *st) {
+  int bad = 0;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= ntiles; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = x * MT_TILE < 2 * n ? x * MT_TILE : 2 * n;
+    int64_t i, j;
+    mt_split(a, b, n, d, &i, &j, &bad);
+    split[2 * x] = i;
+    split[2 * x + 1] = j;
+  }
+  if (bad) atomicAdd(&st->bad_input, 1);
+}
+
+// Tile t's item counts (na, nb) from its bounds; false (and counts 0) for a
+// tile whose bounds a bad split left out of shape, which k_merge_splits has
+// reported.
+__device__ __forceinline__ bool mt_tile(const int64_t *split, int64_t t, int64_t *i0, int64_t *j0, int *na, int *nb) {
+  *i0 = split[2 * t];
+  *j0 = split[2 * t + 1];
+  const int64_t a = split[2 * t + 2] - *i0, b = split[2 * t + 3] - *j0;
+  const bool ok = a >= 0 && b >= 0 && a + b <= MT_CAP;
+  *na = ok ? (int)a : 0;
+  *nb = ok ? (int)b : 0;
+  return ok;
+}
+
+// Entries of every tile: its distinct keys that are not self-loops.  A key
+// of the tile's a-range counts at its first occurrence; one of the b-range
+// at its first occurrence unless the a-range holds it too (binary search in
+// LDS).  Groups do not straddle tiles, so these are the tile's group heads.
+__global__ void __launch_bounds__(MT_THREADS) k_merge_count(const uint64_t *ka, const uint64_t *kb, int kbits,
+                                                            int64_t ntiles, const int64_t *split, int32_t *heads) {
+  __shared__ uint64_t s_k[MT_CAP];
+  __shared__ int s_w[MT_WAVES];
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {  // workgroup-uniform
+    int64_t i0, j0;
+    int na, nb;
+    mt_tile(split, t, &i0, &j0, &na, &nb);
+    const int cnt = na + nb;
+    for (int x = threadIdx.x; x < cnt; x += MT_THREADS) s_k[x] = x < na ? ka[i0 + x] : kb[j0 + x - na];
+    __syncthreads();
+    int h = 0;
+    for (int x = threadIdx.x; x < cnt; x += MT_THREADS) {
+      const uint64_t k = s_k[x];
+      if (self_key(k, kbits)) continue;
+      if (x < na) {
+        h += x == 0 || s_k[x - 1] != k;
+      } else if (x == na || s_k[x - 1] != k) {
+        int lo = 0, hi = na;  // first a-item >= k
+        while (lo < hi) {
+          const int m = (lo + hi) >> 1;
+          if (s_k[m] < k) lo = m + 1; else hi = m;
+        }
+        h += lo == na || s_k[lo] != k;
+      }
+    }
+    h = wave_sum_i32(h);
+    if (lane() == 0) s_w[threadIdx.x / WB_WAVE] = h;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < MT_WAVES; w++) tot += s_w[w];
+      heads[t] = tot;
+    }
+    __syncthreads();  // LDS is reused by the next tile
+  }
+}
+
+__global__ void __launch_bounds__(MT_THREADS)
+    k_merge_entries(const uint64_t *ka, const uint64_t *kb, const uint32_t *vb, int64_t n, int kbits,
+                    const int32_t *cap, int32_t vbase, int64_t ntiles, const int64_t *split, const int32_t *hpre,
+                    BuildStatus *st, int2 *ent, int32_t *cap0, int32_t *erow, int32_t *uid_of, int32_t *pbefore_arc) {
+  // a-items (forward arcs, payload = their index) keep their capacity in
+  // s_v, b-items (backward) their payload; both arrays are reused to stage
+  // the outputs so that they leave in coalesced runs
+  __shared__ uint64_t s_k[MT_CAP];
+  __shared__ uint32_t s_v[MT_CAP];
+  __shared__ uint16_t s_src[MT_CAP];
+  __shared__ int s_wh[MT_WAVES];
+  __shared__ int s_wf[MT_WAVES];
+  __shared__ long long s_ws[MT_WAVES];
+  const uint64_t cmask = (1ull << kbits) - 1;
+  const int64_t total = 2 * n;
+  const int w = threadIdx.x / WB_WAVE;
+  int big = 0, ovf = 0;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {  // workgroup-uniform
+    int64_t i0, j0;
+    int na, nb;
+    mt_tile(split, t, &i0, &j0, &na, &nb);
+    const int cnt = na + nb;
+    const long long P = hpre[t];  // entries of the earlier tiles
+    for (int x = threadIdx.x; x < cnt; x += MT_THREADS) {
+      if (x < na) {
+        s_k[x] = ka[i0 + x];
+        s_v[x] = (uint32_t)cap[i0 + x];
+      } else {
+        s_k[x] = kb[j0 + x - na];
+        s_v[x] = vb[j0 + x - na];
+      }
+    }
+    __syncthreads();
+    const int x0 = threadIdx.x * MT_ITEMS;
+    if (x0 < cnt) {
+      const uint64_t *A = s_k, *B = s_k + na;
+      int i = (int)merge_split(A, na, B, nb, x0), j = x0 - i;
+      const int end = x0 + MT_ITEMS < cnt ? x0 + MT_ITEMS : cnt;
+      for (int o = x0; o < end; o++) {
+        const bool take_a = j >= nb || (i < na && A[i] <= B[j]);
+        s_src[o] = (uint16_t)(take_a ? i++ : na + j++);
+      }
+    }
+    __syncthreads();
+    // this thread's MT_ITEMS consecutive outputs: keys, payloads, forward
+    // capacities; group starts (seg), self-loop items, group ends
+    uint64_t kk[MT_ITEMS];
+    uint32_t pv[MT_ITEMS];
+    int32_t cv[MT_ITEMS];
+    unsigned segm = 0, selfm = 0, endm = 0;
+    uint64_t prev = x0 > 0 && x0 <= cnt ? s_k[s_src[x0 - 1]] : 0;
+    // key after this thread's last output (ends the thread's last group or not)
+    const uint64_t after = x0 + MT_ITEMS < cnt ? s_k[s_src[x0 + MT_ITEMS]] : 0;
+#pragma unroll
+    for (int q = 0; q < MT_ITEMS; q++) {
+      const int x = x0 + q;
+      kk[q] = 0;
+      pv[q] = 0;
+      cv[q] = 0;
+      if (x < cnt) {
+        const int src = s_src[x];
+        kk[q] = s_k[src];
+        const bool sf = self_key(kk[q], kbits);
+        if (src < na) {
+          pv[q] = (uint32_t)(i0 + src);
+          cv[q] = sf ? 0 : (int32_t)s_v[src];
+        } else {
+          pv[q] = s_v[src];
+        }
+        if (x == 0 || kk[q] != prev) segm |= 1u << q;
+        if (sf) selfm |= 1u << q;
+        prev = kk[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < MT_ITEMS; q++) {
+      const int x = x0 + q;
+      const bool nseg = q + 1 < MT_ITEMS ? ((segm >> (q + 1)) & 1) != 0 : after != kk[q];
+      if (x < cnt && (x + 1 >= cnt || nseg)) endm |= 1u << q;
+    }
+    int nh = 0;
+    long long tail = 0;
+#pragma unroll
+    for (int q = 0; q < MT_ITEMS; q++) {
+      const bool seg = (segm >> q) & 1;
+      nh += seg && !((selfm >> q) & 1);
+      if (seg) tail = 0;
+      tail += cv[q];
+    }
+    const int fl = segm != 0;
+    // workgroup scans: heads (sum) and the group sums carried into each
+    // thread (segmented: a thread with a group start resets the carry)
+    int hin = nh, fin = fl;
+    long long sin = tail;
+#pragma unroll
+    for (int d = 1; d < WB_WAVE; d <<= 1) {
+      const int hy = __shfl_up(hin, d, WB_WAVE);
+      const int fy = __shfl_up(fin, d, WB_WAVE);
+      const long long sy = (long long)shfl_up_u64((unsigned long long)sin, d);
+      if (lane() >= d) {
+        hin += hy;
+        sin = fin ? sin : sy + sin;
+        fin |= fy;
+      }
+    }
+    if (lane() == WB_WAVE - 1) {
+      s_wh[w] = hin;
+      s_wf[w] = fin;
+      s_ws[w] = sin;
+    }
+    __syncthreads();
+    int hoff = 0, H = 0;  // heads before this thread in the tile, in the tile
+    long long cs = 0;     // carry from the earlier waves
+#pragma unroll
+    for (int ww = 0; ww < MT_WAVES; ww++) {
+      if (ww < w) {
+        hoff += s_wh[ww];
+        cs = s_wf[ww] ? s_ws[ww] : cs + s_ws[ww];
+      }
+      H += s_wh[ww];
+    }
+    {
+      // exclusive within the wave: the inclusive value of the lane before
+      const int hx = __shfl_up(hin, 1, WB_WAVE);
+      const int fx = __shfl_up(fin, 1, WB_WAVE);
+      const long long sx = (long long)shfl_up_u64((unsigned long long)sin, 1);
+      if (lane() > 0) {
+        hoff += hx;
+        cs = fx ? sx : cs + sx;
+      }
+    }
+    __syncthreads();  // the items are in registers: LDS is free
+    // entry ids and earlier-parallel-arc capacities, staged by output
+    // position: s_k[x] = uid << 32 | payload (uid ~0: self-loop), s_v[x] =
+    // capacity before the item in its group; group totals stay in registers
+    long long run = cs;
+    int32_t hid = (int32_t)(P + hoff);  // entries before this thread's first output
+    int32_t gtot[MT_ITEMS];  // group total (clipped as stored), -1: not a group end
+    int32_t gent[MT_ITEMS];
+#pragma unroll
+    for (int q = 0; q < MT_ITEMS; q++) {
+      const int x = x0 + q;
+      gtot[q] = -1;
+      gent[q] = 0;
+      if (x < cnt) {
+        const bool seg = (segm >> q) & 1, self = (selfm >> q) & 1;
+        if (seg) run = 0;
+        const long long before = run;
+        run += cv[q];
+        if (seg && !self) hid++;
+        const uint32_t u = self ? 0xffffffffu : (uint32_t)(hid - 1);
+        s_k[x] = ((unsigned long long)u << 32) | pv[q];
+        s_v[x] = (uint32_t)(before > 0x7fffffffll ? 0 : before);
+        if (!self && ((endm >> q) & 1)) {
+          big += run >= (1ll << 30);
+          ovf += run > 0x7fffffffll;
+          gtot[q] = run > 0x7fffffffll ? 0 : (int32_t)run;
+          gent[q] = hid - 1;
+        }
+      }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < cnt; x += MT_THREADS) {
+      const unsigned long long r = s_k[x];
+      const uint32_t u = (uint32_t)(r >> 32), pl = (uint32_t)r;
+      if (u != 0xffffffffu && u < (uint64_t)total) {  // always in range; guards the writes
+        uid_of[pl] = (int32_t)u;
+        if (pl < (uint64_t)n) pbefore_arc[pl] = (int32_t)s_v[x];
+      }
+    }
+    __syncthreads();
+    // entries P .. P + H - 1 belong to this tile's group ends, in order:
+    // stage key and total by entry, then write the entries out
+#pragma unroll
+    for (int q = 0; q < MT_ITEMS; q++) {
+      if (gtot[q] >= 0) {
+        const long long h = (long long)gent[q] - P;
+        if (h >= 0 && h < MT_CAP) {  // always
+          s_k[h] = kk[q];
+          s_v[h] = (uint32_t)gtot[q];
+        }
+      }
+    }
+    __syncthreads();
+    for (int h = threadIdx.x; h < H && h < MT_CAP; h += MT_THREADS) {
+      const int64_t u = P + h;
+      if (u < total) {
+        const uint64_t key = s_k[h];
+        const int32_t c32 = (int32_t)s_v[h];
+        ent[u] = make_int2(vbase + (int)(key & cmask), c32);
+        cap0[u] = c32;
+        erow[u] = (int32_t)(key >> kbits);
+      }
+    }
+    __syncthreads();  // LDS is reused by the next tile
+  }
+  big = block_reduce_i32<false>(big);
+  ovf = block_reduce_i32<false>(ovf);
+  if (threadIdx.x == 0) {
+    if (big) atomicAdd(&st->big, big);
+    if (ovf) atomicAdd(&st->overflow, ovf);
+  }
+}
+
+// Row pointers of the fused path: rptr[x] = first entry whose row is >= x
+// (entries are in row order and erow[] holds each one's row).
+__global__ void k_rowptr_rows(const int32_t *erow, int32_t V, const BuildStatus *st, int32_t *rptr) {
+  const int32_t M = st->M;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= V; x += (int64_t)gridDim.x * blockDim.x) {
+    int32_t lo = 0, hi = M;
+    while (lo < hi) {
+      const int32_t mid = lo + (hi - lo) / 2;
+      if (erow[mid] < x) lo = mid + 1; else hi = mid;
+    }
+    rptr[x] = lo;
+  }
 }
 
 __global__ void k_groups(const uint64_t *keys, const uint32_t *vals, int64_t N, int vb, bool inline_self,
@@ -611,8 +964,11 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return e;
   const bool inline_self = hs.unsorted == 0;
-  uint64_t *keys;
-  uint32_t *vals;
+  // the fused merge needs short runs of equal columns; a malformed input
+  // (rejected after the build) takes the general steps
+  const bool fused = inline_self && hs.longrun == 0 && hs.bad_input == 0;
+  uint64_t *keys = nullptr;
+  uint32_t *vals = nullptr;
   if (inline_self) {
     // backward keys: stable sort on their row bits only (emitted in arc
     // order, so equal rows stay ordered by the arc's tail), then merge with
@@ -627,12 +983,32 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
       if (e == hipSuccess) e = hipMemcpyAsync(s.v0 + E, alt ? ov : bv, 4 * (size_t)E, hipMemcpyDeviceToDevice, st);
       if (e != hipSuccess) return e;
     }
-    // the merge marks the group heads as it writes (row_of in hx is no
-    // longer needed)
-    hipLaunchKernelGGL(k_merge, dim3(grid_for((N + MERGE_TILE - 1) / MERGE_TILE, 1)), dim3(MERGE_THREADS), 0, st, s.k0,
-                       s.v0, s.k0 + E, s.v0 + E, E, s.k1, s.v1, s.head, vb);
-    keys = s.k1;
-    vals = s.v1;
+    if (fused) {
+      // tile bounds, per-tile entry counts and their prefix sums in the
+      // radix histogram's space (free after the sort; its 1,024 bytes per
+      // 4,096 keys hold the 24 ntiles + 16 bytes); each entry's row in head[]
+      const int64_t ntiles = (N + MT_TILE - 1) / MT_TILE;
+      int64_t *split = (int64_t *)s.hist;
+      int32_t *heads = (int32_t *)(split + 2 * (ntiles + 1));
+      int32_t *hpre = heads + ntiles;
+      const unsigned tgrid = (unsigned)(ntiles < 65535 ? ntiles : 65535);
+      hipLaunchKernelGGL(k_merge_splits, dim3(grid_for(ntiles + 1)), dim3(BT), 0, st, s.k0, s.k0 + E, E, ntiles, split,
+                         status_dev);
+      hipLaunchKernelGGL(k_merge_count, dim3(tgrid), dim3(MT_THREADS), 0, st, s.k0, s.k0 + E, vb, ntiles, split, heads);
+      e = excl_scan_i32(heads, hpre, ntiles, &status_dev->M, s.stemp, st);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k_merge_entries, dim3(tgrid), dim3(MT_THREADS), 0, st, s.k0, s.k0 + E, s.v0 + E, E, vb, cap,
+                         pl.vbase, ntiles, split, hpre, status_dev, ent, cap0, s.head, s.uid_of, pbefore);
+      hipLaunchKernelGGL(k_rowptr_rows, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, s.head, V, status_dev,
+                         s.rptr);
+    } else {
+      // the merge marks the group heads as it writes (row_of in hx is no
+      // longer needed)
+      hipLaunchKernelGGL(k_merge, dim3(grid_for((N + MERGE_TILE - 1) / MERGE_TILE, 1)), dim3(MERGE_THREADS), 0, st,
+                         s.k0, s.v0, s.k0 + E, s.v0 + E, E, s.k1, s.v1, s.head, vb);
+      keys = s.k1;
+      vals = s.v1;
+    }
   } else {
     if (odd) {  // the full sort wants all keys contiguous in k0
       e = hipMemcpyAsync(s.k0 + E, bk, 8 * (size_t)E, hipMemcpyDeviceToDevice, st);
@@ -647,14 +1023,16 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
     vals = alt ? s.v1 : s.v0;
     hipLaunchKernelGGL(k_heads, dim3(grid_for(N)), dim3(BT), 0, st, keys, N, vb, inline_self, status_dev, s.head);
   }
-  e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_groups, dim3(grid_for(N)), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev,
-                     s.head, s.hx, pl.vbase, ent, cap0, s.uid_of, pbefore, s.gstart);
-  hipLaunchKernelGGL(k_long_groups, dim3(256), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev, s.hx,
-                     pl.vbase, ent, cap0, s.uid_of, pbefore, s.gstart);
-  hipLaunchKernelGGL(k_rowptr, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, N, vb, inline_self, V,
-                     status_dev, s.hx, s.rptr);
+  if (!fused) {
+    e = excl_scan_i32(s.head, s.hx, N, &status_dev->M, s.stemp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_groups, dim3(grid_for(N)), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev,
+                       s.head, s.hx, pl.vbase, ent, cap0, s.uid_of, pbefore, s.gstart);
+    hipLaunchKernelGGL(k_long_groups, dim3(256), dim3(BT), 0, st, keys, vals, N, vb, inline_self, cap, status_dev,
+                       s.hx, pl.vbase, ent, cap0, s.uid_of, pbefore, s.gstart);
+    hipLaunchKernelGGL(k_rowptr, dim3(grid_for((int64_t)V + 1)), dim3(BT), 0, st, keys, N, vb, inline_self, V,
+                       status_dev, s.hx, s.rptr);
+  }
   hipLaunchKernelGGL(k_rowb, dim3(grid_for(V)), dim3(BT), 0, st, s.rptr, V, pl.vbase, (int32_t)pl.mbase, A.rowb);
   hipLaunchKernelGGL(k_arcs, dim3(grid_for(E)), dim3(BT), 0, st, E, s.uid_of, (int32_t)pl.mbase, rev, arc2ent,
                      pbefore, status_dev);

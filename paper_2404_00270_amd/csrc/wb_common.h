@@ -39,6 +39,13 @@ __device__ __forceinline__ unsigned long long shfl_u64(unsigned long long v, int
 
 // Minimum over aligned groups of P lanes (P a power of two <= 64).  Every
 // lane of the wave must execute this (converged control flow).
+__device__ __forceinline__ unsigned long long shfl_up_u64(unsigned long long v, int d) {
+  unsigned lo = (unsigned)v, hi = (unsigned)(v >> 32);
+  lo = (unsigned)__shfl_up((int)lo, d, WB_WAVE);
+  hi = (unsigned)__shfl_up((int)hi, d, WB_WAVE);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 template <int P>
 __device__ __forceinline__ unsigned long long group_min(unsigned long long k) {
 #pragma unroll

@@ -47,7 +47,7 @@ struct BuildStatus {
                       // these can overflow int32 together with their mate)
   int32_t unsorted;   // rows whose columns are not non-decreasing
   int32_t nlong;      // groups of equal keys too long for one thread to walk
-  int32_t pad;
+  int32_t longrun;    // sorted rows holding a run of more than 256 equal columns
 };
 
 // Device scratch needed by build_residual for V vertices and E arcs.

@@ -117,6 +117,59 @@ def test_long_groups_of_parallel_arcs(solver, seed):
     check_against_oracle(g, solver.solve(g))
 
 
+def _longest_column_run(g):
+    """Longest run of one column inside a row (rows sorted by column)."""
+    row = np.repeat(np.arange(g.V), np.diff(g.row_ptr))
+    same = (row[1:] == row[:-1]) & (g.col[1:] == g.col[:-1])
+    best = run = 1 if g.E else 0
+    for x in same:
+        run = run + 1 if x else 1
+        best = max(best, run)
+    return best
+
+
+@pytest.mark.parametrize("run", [256, 257])
+def test_sorted_rows_with_runs_of_parallel_arcs(solver, run):
+    """Column-sorted rows repeating columns up to `run` times, in both
+    directions and as self-loops, among ~60k short groups (about 70 merge
+    tiles of 2,048 keys): with runs of at most 256 the builder merges and
+    finishes the entries in one kernel, moving each tile bound past a group
+    of up to 512 equal keys; one run of 257 sends it through the general
+    sorted path.  Both against the oracle."""
+    rng = np.random.default_rng(run)
+    V = 2000
+    arcs, pairs = [], set()
+    for k in range(24):
+        while True:
+            u, v = (int(x) for x in rng.integers(1, 200, 2))
+            if u != v and (u, v) not in pairs and (v, u) not in pairs:
+                break
+        pairs.add((u, v))
+        n1 = run if k % 4 == 0 else int(rng.integers(1, run + 1))
+        n2 = run if k % 8 == 0 else int(rng.integers(0, run + 1))
+        arcs += [(u, v, int(c)) for c in rng.integers(0, 1000, n1)]
+        arcs += [(v, u, int(c)) for c in rng.integers(0, 1000, n2)]
+    loops = set()
+    for k in range(6):
+        u = int(rng.integers(200, 300))
+        if u not in loops:
+            loops.add(u)
+            arcs += [(u, u, int(c)) for c in rng.integers(0, 50, run if k == 0 else int(rng.integers(1, run + 1)))]
+    taken = pairs | {(v, u) for u, v in pairs}
+    for _ in range(60000):
+        u, v = (int(x) for x in rng.integers(0, V, 2))
+        if (u, v) in taken or (u == v and u in loops):
+            continue
+        arcs.append((u, v, int(rng.integers(1, 5000))))
+    # s feeds the long pairs' tails and their heads drain to t
+    for u, v in sorted(pairs):
+        arcs += [(0, u, 10**6), (v, V - 1, 10**6), (0, v, 10**5), (u, V - 1, 10**5)]
+    g = _reorder_rows(W.from_arcs(V, arcs, 0, V - 1, f"runs-{run}"))
+    assert _longest_column_run(g) == run
+    say(f"[runs] run={run} E={g.E}")
+    check_against_oracle(g, solver.solve(g))
+
+
 def test_long_group_overflow(solver):
     from paper_2404_00270_amd import wbpr
 
