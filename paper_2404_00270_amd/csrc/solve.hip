@@ -1051,35 +1051,26 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
           nrb = g.rowb[v + bstride];
         }
         const int32_t deg = end - beg;
-        if (mine && deg > a.split_deg) {
-          mine = false;
-          const int32_t nch = (deg + a.chunk - 1) / a.chunk;
-          const int32_t c0 = atomic_add_i32(ccnt, nch);
-          if (c0 + nch <= a.chunk_cap) {
-            for (int32_t j = 0; j < nch; j++) {
-              a.chunk_w[c0 + j] = (int32_t)v;
-              a.chunk_b[c0 + j] = beg + j * a.chunk;
-            }
-          } else {
-            atomic_add_i32(a.err, 1);
-          }
-        }
-        if (mine && deg <= BU_SHORT) {
-          // four entries per step: their loads and bitmap probes overlap
-          int32_t hitw = -1;
+        // every row first gets its first BU_SHORT entries examined by its
+        // own lane, four per step (their loads and bitmap probes overlap),
+        // up to the first residual arc into the frontier: next to a large
+        // frontier most vertices are settled here, whatever their row length
+        int32_t hitw = -1;
+        if (mine) {
+          const int32_t pend = end < beg + BU_SHORT ? end : beg + BU_SHORT;
           int32_t k = beg;
-          for (; k < end && hitw < 0; k += 4) {
+          for (; k < pend && hitw < 0; k += 4) {
             int2 cr[4];
             int32_t rr[4];
 #pragma unroll
-            for (int j = 0; j < 4; j++) cr[j] = k + j < end ? g.ent[k + j] : make_int2(0, 0);
+            for (int j = 0; j < 4; j++) cr[j] = k + j < pend ? g.ent[k + j] : make_int2(0, 0);
 #pragma unroll
             for (int j = 0; j < 4; j++) rr[j] = res_of<RC>(g.flow, cr[j]);
 #pragma unroll
             for (int j = 0; j < 4; j++)
               if (hitw < 0 && rr[j] > 0 && bm_test(bm_in, col_of<RC>(cr[j]))) hitw = col_of<RC>(cr[j]);
           }
-          buscans += (k < end ? k : end) - beg;
+          buscans += (k < pend ? k : pend) - beg;
           if (hitw >= 0) {
             g.h[v] = g.h[hitw] + 1;
             a.vis[v] = nxt;
@@ -1089,13 +1080,30 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
             my_edges += deg;
           }
         }
-        // medium rows of this wave, one after the other with all lanes
-        unsigned long long med = __ballot(mine && deg > BU_SHORT);
+        // the rest of a longer row without a hit: up to split_deg entries by
+        // the whole wave (below), more as chunks of one wave each (next phase)
+        const int32_t rbeg = beg + BU_SHORT;
+        const bool rest = mine && hitw < 0 && end > rbeg;
+        if (rest && end - rbeg > a.split_deg) {
+          const int32_t nch = (end - rbeg + a.chunk - 1) / a.chunk;
+          const int32_t c0 = atomic_add_i32(ccnt, nch);
+          if (c0 + nch <= a.chunk_cap) {
+            for (int32_t j = 0; j < nch; j++) {
+              a.chunk_w[c0 + j] = (int32_t)v;
+              a.chunk_b[c0 + j] = rbeg + j * a.chunk;
+            }
+          } else {
+            atomic_add_i32(a.err, 1);
+          }
+        }
+        // medium rests of this wave, one after the other with all lanes
+        unsigned long long med = __ballot(rest && end - rbeg <= a.split_deg);
         while (med) {
           const int src = __ffsll((long long)med) - 1;
           med &= med - 1;
           const int32_t mv = (int32_t)(vb + src);
-          const int32_t mb = __shfl(beg, src, WB_WAVE), me = __shfl(end, src, WB_WAVE);
+          const int32_t mb = __shfl(rbeg, src, WB_WAVE), me = __shfl(end, src, WB_WAVE);
+          const int32_t mdeg = __shfl(deg, src, WB_WAVE);
           for (int32_t kb = mb; kb < me; kb += WB_WAVE) {  // wave-uniform
             const int32_t k = kb + lane();
             bool hit = false;
@@ -1114,7 +1122,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
                 bm_set(bm_vis, mv);
                 bm_set(bm_out, mv);
                 found_cnt++;
-                my_edges += me - mb;
+                my_edges += mdeg;
               }
               break;
             }
@@ -1129,22 +1137,42 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
       // long unvisited rows: one wave per chunk; a hit claims v by CAS.
       // nc is read after the barrier, so every workgroup agrees on it and on
       // whether the second barrier below is needed.
+      // four wave widths per step: their entry loads and bitmap probes are
+      // in flight together (rows that reach this phase mostly hold no
+      // residual arc into the frontier and are read to their end); a chunk
+      // whose vertex an earlier chunk has labelled is skipped
       const int32_t nc = min(atomic_load_i32(ccnt), a.chunk_cap);
       for (int32_t c = wave; c < nc; c += nwaves) {
         const int32_t v = a.chunk_w[c];
         const int32_t cb = a.chunk_b[c];
-        const int32_t ce = min(cb + a.chunk, g.rowb[v].y);
-        if (lane() == 0) buscans += ce - cb;
-        for (int32_t kb = cb; kb < ce; kb += WB_WAVE) {
-          const int32_t k = kb + lane();
-          bool hit = false;
-          int32_t w = 0;
-          if (k < ce) {
-            const int2 cr = g.ent[k];
-            w = col_of<RC>(cr);
-            hit = res_of<RC>(g.flow, cr) > 0 && bm_test(bm_in, w);
+        const int2 vrb = g.rowb[v];
+        const int32_t ce = min(cb + a.chunk, vrb.y);
+        if (bm_test(bm_vis, v)) continue;  // wave-uniform
+        constexpr int BU_UNROLL = 4;
+        for (int32_t kb = cb; kb < ce; kb += BU_UNROLL * WB_WAVE) {  // wave-uniform
+          int2 cr[BU_UNROLL];
+#pragma unroll
+          for (int j = 0; j < BU_UNROLL; j++) {
+            const int32_t k = kb + j * WB_WAVE + lane();
+            cr[j] = k < ce ? g.ent[k] : make_int2(0, 0);
           }
-          const unsigned long long m = __ballot(hit);
+          bool hit[BU_UNROLL];
+#pragma unroll
+          for (int j = 0; j < BU_UNROLL; j++) {
+            const int32_t k = kb + j * WB_WAVE + lane();
+            hit[j] = k < ce && res_of<RC>(g.flow, cr[j]) > 0 && bm_test(bm_in, col_of<RC>(cr[j]));
+          }
+          unsigned long long m = 0;
+          int32_t w = 0;
+#pragma unroll
+          for (int j = 0; j < BU_UNROLL; j++) {  // the first hit in row order
+            const unsigned long long mj = __ballot(hit[j]);
+            if (m == 0 && mj != 0) {
+              m = mj;
+              w = col_of<RC>(cr[j]);
+            }
+          }
+          if (lane() == 0) buscans += min(BU_UNROLL * WB_WAVE, ce - kb);
           if (m) {
             if (lane() == __ffsll((long long)m) - 1) {
               if (atomicCAS(&g.h[v], g.hcap, g.h[w] + 1) == g.hcap) {
@@ -1152,7 +1180,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
                 bm_set(bm_vis, v);
                 bm_set(bm_out, v);
                 found_cnt++;
-                my_edges += (g.rowb[v].y - g.rowb[v].x);
+                my_edges += vrb.y - vrb.x;
               }
             }
             break;
@@ -1231,15 +1259,19 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
       block_add2(0, my_edges, nullptr, fe_out);
       my_edges = 0;
       grid_barrier(a.bar, nblocks);
-      // phase B: one wave per chunk of a long row (skipped, with its barrier,
-      // when the level met no long row: nc is read after the barrier)
+      // phase B: the chunks of long rows, cut into pieces of one wave's
+      // width that all waves take at once (a hub's row is spread over the
+      // whole grid; skipped, with its barrier, when the level met no long
+      // row: nc is read after the barrier)
       const int32_t nc = min(atomic_load_i32(ccnt), a.chunk_cap);
-      for (int32_t c = wave; c < nc; c += nwaves) {
+      const int32_t pieces = (a.chunk + WB_WAVE - 1) / WB_WAVE;
+      for (int64_t pc = wave; pc < (int64_t)nc * pieces; pc += nwaves) {
+        const int32_t c = (int32_t)(pc / pieces);
         const int32_t w = a.chunk_w[c];
-        const int32_t cb = a.chunk_b[c];
-        const int32_t ce = min(cb + a.chunk, g.rowb[w].y);
+        const int32_t cb = a.chunk_b[c] + (int32_t)(pc % pieces) * WB_WAVE;
+        const int32_t ce = min(min(cb + WB_WAVE, a.chunk_b[c] + a.chunk), g.rowb[w].y);
         const int32_t hw1 = g.h[w] + 1;
-        if (lane() == 0) bscans += ce - cb;
+        if (lane() == 0 && ce > cb) bscans += ce - cb;
         for (int32_t k = cb + lane(); k < ce; k += WB_WAVE) {
           const int2 cr = g.ent[k];
           const int32_t v = col_of<RC>(cr);
