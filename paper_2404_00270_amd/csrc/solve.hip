@@ -1074,12 +1074,13 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
           if (hitw >= 0) {
             g.h[v] = g.h[hitw] + 1;
             a.vis[v] = nxt;
-            bm_set(bm_vis, (int32_t)v);
-            bm_set(bm_out, (int32_t)v);
             found_cnt++;
             my_edges += deg;
           }
         }
+        // the wave's 64 vertices fill two bitmap words: their bits are set
+        // with one atomic per word at the end of the batch, not one per lane
+        unsigned long long newbits = __ballot(hitw >= 0);
         // the rest of a longer row without a hit: up to split_deg entries by
         // the whole wave (below), more as chunks of one wave each (next phase)
         const int32_t rbeg = beg + BU_SHORT;
@@ -1119,13 +1120,20 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
               if (lane() == __ffsll((long long)m) - 1) {
                 g.h[mv] = g.h[w] + 1;
                 a.vis[mv] = nxt;
-                bm_set(bm_vis, mv);
-                bm_set(bm_out, mv);
                 found_cnt++;
                 my_edges += mdeg;
               }
+              newbits |= 1ull << src;
               break;
             }
+          }
+        }
+        if (newbits && lane() < 2) {  // vb is a multiple of 64
+          const unsigned word = (unsigned)(newbits >> (32 * lane()));
+          if (word) {
+            const int64_t wi = (vb >> 5) + lane();
+            __hip_atomic_fetch_or(&bm_vis[wi], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_or(&bm_out[wi], word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           }
         }
       }
