@@ -1059,16 +1059,33 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         if (mine) {
           const int32_t pend = end < beg + BU_SHORT ? end : beg + BU_SHORT;
           int32_t k = beg;
-          for (; k < pend && hitw < 0; k += 4) {
+          // entries are read in 16-byte pairs from an even index: lanes read
+          // different rows, so every load instruction touches 64 cache lines,
+          // and pairs halve those requests (a pair's first entry may belong to
+          // the row before, which is in bounds and masked out)
+          while (k < pend && hitw < 0) {
+            const int32_t p0 = k & ~1;
             int2 cr[4];
-            int32_t rr[4];
 #pragma unroll
-            for (int j = 0; j < 4; j++) cr[j] = k + j < pend ? g.ent[k + j] : make_int2(0, 0);
+            for (int h2 = 0; h2 < 2; h2++) {
+              const int32_t p = p0 + 2 * h2;
+              int4 pr = make_int4(0, 0, 0, 0);
+              if (p + 1 < end) {
+                pr = *reinterpret_cast<const int4 *>(g.ent + p);
+              } else if (p < end) {
+                const int2 e1 = g.ent[p];
+                pr = make_int4(e1.x, e1.y, 0, 0);
+              }
+              cr[2 * h2] = make_int2(pr.x, pr.y);
+              cr[2 * h2 + 1] = make_int2(pr.z, pr.w);
+            }
 #pragma unroll
-            for (int j = 0; j < 4; j++) rr[j] = res_of<RC>(g.flow, cr[j]);
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-              if (hitw < 0 && rr[j] > 0 && bm_test(bm_in, col_of<RC>(cr[j]))) hitw = col_of<RC>(cr[j]);
+            for (int j = 0; j < 4; j++) {
+              const bool in = p0 + j >= k && p0 + j < pend;
+              if (hitw < 0 && in && res_of<RC>(g.flow, cr[j]) > 0 && bm_test(bm_in, col_of<RC>(cr[j])))
+                hitw = col_of<RC>(cr[j]);
+            }
+            k = p0 + 4;
           }
           buscans += (k < pend ? k : pend) - beg;
           if (hitw >= 0) {
@@ -1342,17 +1359,74 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         waveq_push(wq, act, (int32_t)v);
       }
     }
-    key_count_flush(kc_act, a.inst_active);
-    key_count_flush(kc_str, a.inst_stranded);
-    waveq_flush(wq);
+    // per-instance counts and the queue tail of every wave, combined over
+    // the workgroup before their atomics (the active count of a single
+    // instance and the queue counter are one address each)
+    __shared__ int32_t s_kk[GR_THREADS / WB_WAVE][4];
+    if (lane() == 0) {
+      s_kk[wl][0] = kc_act.cnt ? kc_act.key : -1;
+      s_kk[wl][1] = kc_act.cnt;
+      s_kk[wl][2] = kc_str.cnt ? kc_str.key : -1;
+      s_kk[wl][3] = kc_str.cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {  // thread 0: active counts, thread 1: stranded counts
+      int32_t *ctr = threadIdx.x == 0 ? a.inst_active : a.inst_stranded;
+      int32_t key = -1, cnt = 0;
+      for (int w = 0; w < GR_THREADS / WB_WAVE; w++) {
+        const int32_t k = s_kk[w][2 * threadIdx.x], c = s_kk[w][2 * threadIdx.x + 1];
+        if (k < 0) continue;
+        if (k != key) {
+          if (cnt) atomic_add_i32(&ctr[key], cnt);
+          key = k;
+          cnt = 0;
+        }
+        cnt += c;
+      }
+      if (cnt) atomic_add_i32(&ctr[key], cnt);
+    }
+    // queue tails: one atomic for the workgroup, then each wave copies its
+    // LDS slice to its share
+    __shared__ int32_t s_qoff[GR_THREADS / WB_WAVE + 1];
+    if (threadIdx.x == 0) {
+      int32_t tot = 0;
+      for (int w = 0; w < GR_THREADS / WB_WAVE; w++) {
+        s_qoff[w] = tot;
+        tot += s_qcnt[w];
+      }
+      s_qoff[GR_THREADS / WB_WAVE] = tot ? atomic_add_i32(&a.qcnt[0], tot) : 0;
+    }
+    __syncthreads();
+    {
+      const int32_t c = s_qcnt[wl];
+      const int32_t base = s_qoff[GR_THREADS / WB_WAVE] + s_qoff[wl];
+      for (int32_t j = lane(); j < c; j += WB_WAVE) {
+        const int32_t idx = base + j;
+        if (idx < a.qcap) a.qout[idx] = s_qbuf[wl][j];
+        else atomic_add_i32(a.err, 1);
+      }
+    }
   }
-  stranded = wave_sum_i32(stranded);
-  const long long bs = group_sum_i64<WB_WAVE>(bscans);
-  const long long bus = group_sum_i64<WB_WAVE>(buscans);
-  if (lane() == 0) {
-    if (stranded) atomic_add_i64(&a.status[1], stranded);
-    if (bs) atomic_add_i64(&a.stats[12], bs);
-    if (bus) atomic_add_i64(&a.stats[14], bus);
+  // counters summed over the workgroup first: one atomic per workgroup and
+  // counter (one per wave would serialise thousands on each address)
+  {
+    __shared__ long long s_cnt[3];
+    const long long st = wave_sum_i32(stranded);
+    const long long bs = group_sum_i64<WB_WAVE>(bscans);
+    const long long bus = group_sum_i64<WB_WAVE>(buscans);
+    if (threadIdx.x < 3) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    if (lane() == 0) {
+      if (st) atomicAdd((unsigned long long *)&s_cnt[0], (unsigned long long)st);
+      if (bs) atomicAdd((unsigned long long *)&s_cnt[1], (unsigned long long)bs);
+      if (bus) atomicAdd((unsigned long long *)&s_cnt[2], (unsigned long long)bus);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (s_cnt[0]) atomic_add_i64(&a.status[1], s_cnt[0]);
+      if (s_cnt[1]) atomic_add_i64(&a.stats[12], s_cnt[1]);
+      if (s_cnt[2]) atomic_add_i64(&a.stats[14], s_cnt[2]);
+    }
   }
   grid_barrier(a.bar, nblocks);
   if (gtid == 0) {
