@@ -222,7 +222,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_avq_scan(Graph g, const int32
     if (v < n) act = g.e[v] > 0 && g.h[v] <= hlim;
     waveq_push(wq, act, (int32_t)v);
   }
-  waveq_flush(wq);
+  __shared__ int s_off[SWEEP_THREADS / WB_WAVE + 1];
+  block_flush<SWEEP_THREADS / WB_WAVE>(wq, s_off);
 }
 
 template <int P>
@@ -526,10 +527,13 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
     }
     waveq_push(wq, q.append && app_u, u);
   }
-  waveq_flush(wq);
-  if (defers) {
-    waveq_flush(wmid);
-    waveq_flush(wbig);
+  {
+    __shared__ int s_off[SWEEP_THREADS / WB_WAVE + 1];
+    block_flush<SWEEP_THREADS / WB_WAVE>(wq, s_off);
+    if (defers) {
+      block_flush<SWEEP_THREADS / WB_WAVE>(wmid, s_off);
+      block_flush<SWEEP_THREADS / WB_WAVE>(wbig, s_off);
+    }
   }
   flush_stats(q.stats, scans, pushes, relabels, queued, q.rwork, rwork);
   gap_flush_lds(g, s_gap, gbase, gn);
@@ -769,7 +773,10 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
     }
     __syncthreads();  // s_take, s_wmin and s_wsum are reused by the next task
   }
-  waveq_flush(wq);
+  {
+    __shared__ int s_off[BLK_WAVES + 1];
+    block_flush<BLK_WAVES>(wq, s_off);
+  }
   flush_stats(q.stats + 8, scans, pushes, relabels, queued, q.rwork, rwork);
   gap_flush_lds(g, s_gap, gbase, gn);
   if (q.wtrace) trace_wave(q, FIRST ? 2 : 3, wt0, scans, tasks);
@@ -806,7 +813,10 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk_finish(Graph g, SweepQ q) {
     waveq_push(wq, q.append && app_v, v);
     waveq_push(wq, q.append && app_u, u);
   }
-  waveq_flush(wq);
+  {
+    __shared__ int s_off[BLK_WAVES + 1];
+    block_flush<BLK_WAVES>(wq, s_off);
+  }
   flush_stats(q.stats + 8, 0, pushes, relabels, queued, q.rwork, rwork);
   gap_flush_lds(g, s_gap, gbase, gn);
 }
@@ -900,6 +910,7 @@ template <int P, bool RC>
 __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   __shared__ int s_qbuf[GR_THREADS / WB_WAVE][WB_QBUF];
   __shared__ int s_qcnt[GR_THREADS / WB_WAVE];
+  __shared__ int s_goff[GR_THREADS / WB_WAVE + 1];
   const Graph &g = a.g;
   const unsigned nblocks = gridDim.x;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1232,7 +1243,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
           const int64_t v = v0 + lane();
           waveq_push(wq, v < g.V && bm_test(bm_in, (int32_t)v), (int32_t)v);
         }
-        waveq_flush(wq);
+        block_flush<GR_THREADS / WB_WAVE>(wq, s_goff);
         grid_barrier(a.bar, nblocks);
         n = min(atomic_load_i32(&a.fcnt[level % 3]), a.qcap);
       }
@@ -1280,7 +1291,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
           }
         }
       }
-      waveq_flush(wq);
+      block_flush<GR_THREADS / WB_WAVE>(wq, s_goff);
       block_add2(0, my_edges, nullptr, fe_out);
       my_edges = 0;
       grid_barrier(a.bar, nblocks);
@@ -1314,7 +1325,7 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
         }
       }
       if (nc > 0) {
-        waveq_flush(wq);
+        block_flush<GR_THREADS / WB_WAVE>(wq, s_goff);
         block_add2(0, my_edges, nullptr, fe_out);
         grid_barrier(a.bar, nblocks);
       }

@@ -177,6 +177,40 @@ __device__ __forceinline__ void waveq_push(const WaveQ &q, bool pred, int val) {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Final flush of the WaveQ of every wave of a workgroup (WAVES waves), with
+// one atomic on the global counter for the whole workgroup: atomics on one
+// address serialise, and one per wave costs thousands per launch.  Every
+// thread of the workgroup calls it, converged; s_off is LDS scratch of
+// WAVES + 1 ints, free again when it returns.
+template <int WAVES>
+__device__ __forceinline__ void block_flush(const WaveQ &q, int *s_off) {
+  const int w = threadIdx.x / WB_WAVE;
+  __builtin_amdgcn_wave_barrier();
+  const int c = *(volatile int *)q.cnt;
+  if (lane() == 0) s_off[w] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int tot = 0;
+    for (int i = 0; i < WAVES; i++) {
+      const int x = s_off[i];
+      s_off[i] = tot;
+      tot += x;
+    }
+    s_off[WAVES] = tot ? atomic_add_i32(q.gcnt, tot) : 0;
+  }
+  __syncthreads();
+  const int base = s_off[WAVES] + s_off[w];
+  for (int j = lane(); j < c; j += WB_WAVE) {
+    const int idx = base + j;
+    const int v = ((volatile int *)q.buf)[j];
+    if (idx < q.gcap) q.gq[idx] = v;
+    else atomic_add_i32(q.err, 1);
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane() == 0) *(volatile int *)q.cnt = 0;
+  __syncthreads();  // s_off may be reused at once
+}
+
 // Grid-wide barrier for cooperative launches (all workgroups co-resident).
 // Two levels: workgroups count on the cache line of their group
 // (blockIdx % WB_BAR_GROUPS, which follows the round-robin placement of
