@@ -502,6 +502,7 @@ struct MiscLayout {
   int32_t pk_tail;     // ... and published
   long long wg_stats[6];  // its scans, pushes, relabels, sweeps, BFS rounds, BFS scans
   unsigned long long dbg[2];  // debug_checks: entries, vertices violating the preflow invariants
+  alignas(128) long long part[PART_SLOTS * PART_WORDS];  // sweep kernels' per-workgroup counters
 };
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -1631,6 +1632,8 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
     q.stats = misc->stats;
     q.gap_skips = &misc->stats[15];
     q.rwork = &misc->rwork;
+    q.part = misc->part;
+    q.sofs = 0;
     q.halt = &misc->halt[0];
     q.qcap = (int32_t)Vcap_;
     q.err = misc->err;
@@ -1646,7 +1649,7 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
     qw.zero_cnt = nullptr;
     qw.t_mid = 0x7fffffff;
     qw.t_big = 0x7fffffff;
-    qw.stats = misc->stats + 4;
+    qw.sofs = 4;
     int evb = -1;
     if (timed) {
       if (ev_used_ + 4 > (int)ev_.size()) {
@@ -1701,6 +1704,9 @@ void Engine::enqueue_sweeps(hipStream_t st, int K, int tiers) {
     ctl.log_n = &misc->log_n;
     ctl.log_cap = kSweepLogCap / 2;
     ctl.sweep_no = q.wtrace ? &misc->sweep_no : nullptr;
+    ctl.part = misc->part;
+    ctl.stats = misc->stats;
+    ctl.rwork_acc = &misc->rwork;
     launch_sweep_control(st, ctl);
   }
 }
@@ -2226,6 +2232,7 @@ void Engine::reset_stats() {
   if (misc_) {
     MiscLayout *misc = reinterpret_cast<MiscLayout *>(misc_);
     hipMemset(misc->stats, 0, sizeof(misc->stats));
+    hipMemset(misc->part, 0, sizeof(misc->part));
     hipMemset(&misc->wtrace_n, 0, 2 * sizeof(int32_t));
     hipMemset(misc->wg_stats, 0, sizeof(misc->wg_stats));
   }

@@ -66,11 +66,21 @@ __device__ __forceinline__ bool push_entry(const Graph &g, int32_t hk, int32_t v
   return oldv <= 0 && oldv + d > 0;
 }
 
-// Counters of a launch: summed per wave, then per workgroup in LDS, so each
-// workgroup makes at most one device atomic per counter (device atomics on
-// one address serialise).  Every thread of the workgroup calls it, at the end.
-__device__ __forceinline__ void flush_stats(long long *stats, long long scans, int pushes, int relabels, long long queued,
-                                            long long *rwork_ctr, long long rwork) {
+// Counters of a launch: summed per wave, then per workgroup in LDS, then
+// added to the workgroup's partial-counter slot (its own cache line: device
+// atomics on one address serialise, and every workgroup of every sweep
+// launch adding to the same five counters cost thousands of serialised
+// atomics per launch), which the control step folds; without slots, to the
+// counters themselves.  Every thread of the workgroup calls it, at the end.
+__device__ __forceinline__ void flush_stats(const SweepQ &q, int kofs, long long scans, int pushes, int relabels,
+                                            long long queued, long long rwork) {
+  long long *stats = q.stats + q.sofs + kofs;
+  long long *rwork_ctr = q.rwork;
+  if (q.part) {
+    long long *slot = q.part + (int64_t)(blockIdx.x % PART_SLOTS) * PART_WORDS;
+    stats = slot + q.sofs + kofs;
+    rwork_ctr = slot + 12;
+  }
   __shared__ unsigned long long s_acc[5];
   scans = (long long)group_sum_i64<WB_WAVE>(scans);
   long long p = group_sum_i64<WB_WAVE>((long long)pushes);
@@ -171,8 +181,36 @@ __device__ __forceinline__ void trace_wave(const SweepQ &q, int kind, long long 
 // With a sweep log (diagnostics), every sweep that ran appends one record:
 // queue in, medium rows, long rows, second-pass chunk tasks, queue out,
 // relabel work since the last global relabel (saturated to int32).
-__global__ void k_sweep_control(SweepCtl c) {
+__global__ void __launch_bounds__(PART_SLOTS) k_sweep_control(SweepCtl c) {
   if (*c.halt) return;
+  if (c.part) {
+    // fold the sweep kernels' per-workgroup partial counters: thread i takes
+    // slot i, then one sum per counter over the workgroup
+    __shared__ long long s_sum[PART_SLOTS / WB_WAVE][13];
+    long long *slot = c.part + (int64_t)threadIdx.x * PART_WORDS;
+    long long x[13];
+#pragma unroll
+    for (int k = 0; k < 13; k++) {
+      x[k] = slot[k];
+      slot[k] = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < 13; k++) x[k] = group_sum_i64<WB_WAVE>(x[k]);
+    if (lane() == 0)
+#pragma unroll
+      for (int k = 0; k < 13; k++) s_sum[threadIdx.x / WB_WAVE][k] = x[k];
+    __syncthreads();
+    if (threadIdx.x < 13) {
+      long long t = 0;
+      for (int w = 0; w < PART_SLOTS / WB_WAVE; w++) t += s_sum[w][threadIdx.x];
+      if (t) {
+        if (threadIdx.x < 12) c.stats[threadIdx.x] += t;
+        else *c.rwork_acc += t;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
   const int32_t next = c.scan_cnt ? *c.qin_cnt : *c.qout_cnt;  // full scan: this sweep's queue
   if (c.log) {
     const int32_t i = *c.log_n;
@@ -535,7 +573,7 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
       block_flush<SWEEP_THREADS / WB_WAVE>(wbig, s_off);
     }
   }
-  flush_stats(q.stats, scans, pushes, relabels, queued, q.rwork, rwork);
+  flush_stats(q, 0, scans, pushes, relabels, queued, rwork);
   gap_flush_lds(g, s_gap, gbase, gn);
   if (q.gap_skips) {
     const int32_t gs = wave_sum_i32(gskips);
@@ -777,7 +815,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
     __shared__ int s_off[BLK_WAVES + 1];
     block_flush<BLK_WAVES>(wq, s_off);
   }
-  flush_stats(q.stats + 8, scans, pushes, relabels, queued, q.rwork, rwork);
+  flush_stats(q, 8, scans, pushes, relabels, queued, rwork);
   gap_flush_lds(g, s_gap, gbase, gn);
   if (q.wtrace) trace_wave(q, FIRST ? 2 : 3, wt0, scans, tasks);
 }
@@ -817,7 +855,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk_finish(Graph g, SweepQ q) {
     __shared__ int s_off[BLK_WAVES + 1];
     block_flush<BLK_WAVES>(wq, s_off);
   }
-  flush_stats(q.stats + 8, 0, pushes, relabels, queued, q.rwork, rwork);
+  flush_stats(q, 8, 0, pushes, relabels, queued, rwork);
   gap_flush_lds(g, s_gap, gbase, gn);
 }
 
@@ -1503,7 +1541,7 @@ void launch_avq_scan(int blocks, hipStream_t st, const Graph &g, const int32_t *
 }
 
 void launch_sweep_control(hipStream_t st, const SweepCtl &c) {
-  hipLaunchKernelGGL(k_sweep_control, dim3(1), dim3(1), 0, st, c);
+  hipLaunchKernelGGL(k_sweep_control, dim3(1), dim3(c.part ? PART_SLOTS : 1), 0, st, c);
 }
 
 hipError_t launch_global_relabel(int P, bool rc, int blocks, hipStream_t st, GRArgs &a) {

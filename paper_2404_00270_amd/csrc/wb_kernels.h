@@ -109,6 +109,12 @@ struct SweepQ {
   long long *stats;     // per kernel k (0 tile, 1 wave, 2 workgroup): [4k] arc scans, [4k+1] pushes,
                         // [4k+2] relabels, [4k+3] queued; [12] bfs scans; [13] nonempty sweeps
   long long *rwork;     // running sum of row lengths scanned by relabels
+  // nullable: per-workgroup partial counters, PART_SLOTS slots of PART_WORDS
+  // (one cache line each: [0..11] as stats[0..11], [12] relabel work), which
+  // the control step folds into stats and rwork; without it the kernels add
+  // to stats and rwork directly
+  long long *part;
+  int32_t sofs;         // this launch's offset into stats ([4k] of its kernel k above)
   const int32_t *halt;  // set by k_sweep_control: the rest of this round's sweeps do nothing
   int32_t qcap;      // capacity of every queue and of the medium-row list (V)
   int32_t *err;      // overflow counter (must stay 0)
@@ -124,7 +130,10 @@ struct SweepQ {
   long long *gap_skips;  // queue entries left to the next global relabel by the gap heuristic
 };
 
-// End-of-sweep control (one thread): halt decision and optional log.
+constexpr int PART_SLOTS = 256;  // = the control step's threads
+constexpr int PART_WORDS = 16;
+
+// End-of-sweep control (one thread after the fold): halt decision and optional log.
 struct SweepCtl {
   const int32_t *qin_cnt, *mid_cnt, *big_cnt, *task_cnt, *qout_cnt;
   const long long *rwork, *rwork_at_gr, *budget;
@@ -136,6 +145,9 @@ struct SweepCtl {
   int32_t *log_n;
   int32_t log_cap;
   int32_t *sweep_no;  // nullable: incremented once per sweep that ran
+  long long *part;    // nullable: per-workgroup partial counters to fold ...
+  long long *stats;   // ... into these counters [0..11] ...
+  long long *rwork_acc;  // ... and into the relabel work (the rwork above)
 };
 
 struct GRArgs {
