@@ -183,32 +183,25 @@ __device__ __forceinline__ void trace_wave(const SweepQ &q, int kind, long long 
 // relabel work since the last global relabel (saturated to int32).
 __global__ void __launch_bounds__(PART_SLOTS) k_sweep_control(SweepCtl c) {
   if (*c.halt) return;
+  static_assert(PART_SLOTS == WB_WAVE, "one lane per partial-counter slot");
   if (c.part) {
-    // fold the sweep kernels' per-workgroup partial counters: thread i takes
-    // slot i, then one sum per counter over the workgroup
-    __shared__ long long s_sum[PART_SLOTS / WB_WAVE][13];
+    // fold the sweep kernels' per-workgroup partial counters: lane i takes
+    // slot i, then one sum per counter over the wave
     long long *slot = c.part + (int64_t)threadIdx.x * PART_WORDS;
     long long x[13];
 #pragma unroll
+    for (int k = 0; k < 13; k++) x[k] = slot[k];
+#pragma unroll
+    for (int k = 0; k < 13; k++) slot[k] = 0;
+#pragma unroll
     for (int k = 0; k < 13; k++) {
-      x[k] = slot[k];
-      slot[k] = 0;
-    }
-#pragma unroll
-    for (int k = 0; k < 13; k++) x[k] = group_sum_i64<WB_WAVE>(x[k]);
-    if (lane() == 0)
-#pragma unroll
-      for (int k = 0; k < 13; k++) s_sum[threadIdx.x / WB_WAVE][k] = x[k];
-    __syncthreads();
-    if (threadIdx.x < 13) {
-      long long t = 0;
-      for (int w = 0; w < PART_SLOTS / WB_WAVE; w++) t += s_sum[w][threadIdx.x];
-      if (t) {
-        if (threadIdx.x < 12) c.stats[threadIdx.x] += t;
+      if (__ballot(x[k] != 0) == 0) continue;  // wave-uniform
+      const long long t = group_sum_i64<WB_WAVE>(x[k]);
+      if (threadIdx.x == 0) {
+        if (k < 12) c.stats[k] += t;
         else *c.rwork_acc += t;
       }
     }
-    __syncthreads();
   }
   if (threadIdx.x != 0) return;
   const int32_t next = c.scan_cnt ? *c.qin_cnt : *c.qout_cnt;  // full scan: this sweep's queue

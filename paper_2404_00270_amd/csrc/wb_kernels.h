@@ -130,7 +130,7 @@ struct SweepQ {
   long long *gap_skips;  // queue entries left to the next global relabel by the gap heuristic
 };
 
-constexpr int PART_SLOTS = 256;  // = the control step's threads
+constexpr int PART_SLOTS = 64;  // = the control step's threads (one wave)
 constexpr int PART_WORDS = 16;
 
 // End-of-sweep control (one thread after the fold): halt decision and optional log.
