@@ -733,6 +733,7 @@ int Engine::reserve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap, int6
 
 // Points every arena array into arena_ (arena_bytes(...) long).
 void Engine::carve(int64_t Vcap, int64_t Mcap, int64_t Ecap, int32_t ncap) {
+  gr_uploaded_.clear();
   {
     Vcap_ = Vcap;
     Mcap_ = Mcap;
@@ -1777,15 +1778,29 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   hmisc[0] = sink;
   hmisc[2] = vhi;
   hmisc[1] = cfg_.gr_every_sweeps > 0 ? (1LL << 62) : (long long)(beta * (double)(resident_V_ + resident_M_));
-  hipMemcpyAsync(roots_, hroots, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
-  hipMemcpyAsync(root_h_, hrh, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
-  hipMemcpyAsync(excl_, hex, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
-  hipMemcpyAsync(sink_, &hmisc[0], 4, hipMemcpyHostToDevice, st);
-  hipMemcpyAsync(budget_, &hmisc[1], 8, hipMemcpyHostToDevice, st);
-  hipMemcpyAsync(&misc->span, &hmisc[2], 4, hipMemcpyHostToDevice, st);
-  hipMemsetAsync(misc->status, 0, sizeof(misc->status), st);
-  hipMemsetAsync(inst_active_, 0, 4 * (size_t)ncap_, st);
-  hipMemsetAsync(inst_stranded_, 0, 4 * (size_t)ncap_, st);
+  // the same arguments as the last round's (one instance: every round of a
+  // phase) are already on the device: each copy costs a blit on the stream
+  std::vector<int64_t> up;
+  up.reserve(3 * (size_t)nr + 4);
+  up.push_back(nr);
+  for (int i = 0; i < nr; i++) {
+    up.push_back(hroots[i]);
+    up.push_back(hrh[i]);
+    up.push_back(hex[i]);
+  }
+  up.push_back(hmisc[0]);
+  up.push_back(hmisc[1]);
+  up.push_back(hmisc[2]);
+  if (up != gr_uploaded_) {
+    hipMemcpyAsync(roots_, hroots, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(root_h_, hrh, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(excl_, hex, 4 * (size_t)nr, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(sink_, &hmisc[0], 4, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(budget_, &hmisc[1], 8, hipMemcpyHostToDevice, st);
+    hipMemcpyAsync(&misc->span, &hmisc[2], 4, hipMemcpyHostToDevice, st);
+    gr_uploaded_ = std::move(up);
+  }
+  // status and the per-instance counts are cleared by the relabel itself
 
   Graph g{(int32_t)vhi, HCAP, A_.rowb, A_.ent, A_.rev, cfg_.rcsr ? A_.rev : nullptr, e_, h_, sink_, gap_hist_,
           misc->gap};
@@ -1798,6 +1813,7 @@ int Engine::round(hipStream_t st, std::vector<Finished> *done, std::string *err)
   ga.nexcl = nr;
   ga.inst_of = inst_of_;
   ga.inst_active = inst_active_;
+  ga.ninst = ncap_;
   ga.inst_stranded = inst_stranded_;
   ga.fq[0] = fq_[0];
   ga.fq[1] = fq_[1];

@@ -977,7 +977,15 @@ __global__ void __launch_bounds__(GR_THREADS) k_global_relabel(GRArgs a) {
   uint32_t *const bm_vis = a.bm;
   for (int64_t j = gtid; j < 4 * (int64_t)a.bm_words; j += nthreads) a.bm[j] = 0;
   for (int64_t j = gtid; j < a.nroots; j += nthreads) a.fq[0][j] = a.roots[j];
+  for (int64_t j = gtid; j < a.ninst; j += nthreads) {
+    a.inst_active[j] = 0;
+    a.inst_stranded[j] = 0;
+  }
   if (gtid == 0) {
+    a.status[0] = 0;
+    a.status[1] = 0;
+    a.status[2] = 0;
+    a.status[3] = 0;
     a.fcnt[0] = a.nroots;
     a.fcnt[1] = 0;
     a.fcnt[2] = 0;

@@ -284,6 +284,10 @@ class Engine {
   int32_t resident_ = 0;
   int64_t resident_V_ = 0, resident_M_ = 0;
   int64_t last_M_ = 0;
+  // what the last round uploaded (roots, their heights, excluded terminals,
+  // sink, budget, span): a round that would upload the same skips the copies;
+  // emptied when the arena is carved (its memory cleared)
+  std::vector<int64_t> gr_uploaded_;
   // tiers and launch shapes (fixed per config)
   int P_ = 8, t_mid_ = 32, t_big_ = 2048, bfs_split_ = 64, chunk_ = BFS_CHUNK, stag_window_ = 16;
   int mid_lanes_ = 64;  // lanes per medium row (16 and 32 measured no faster on R-MAT)

@@ -160,6 +160,7 @@ struct GRArgs {
   const int32_t *inst_of;  // [V] instance slot of every arena vertex (-1: free)
   int32_t *inst_active;    // per instance: active vertices after this relabel
   int32_t *inst_stranded;  // per instance: excess vertices that cannot reach the root
+  int32_t ninst;           // instance slots (inst_active and inst_stranded are cleared first)
   int32_t *fq[2];
   int32_t *fcnt;      // [3] rotating frontier counters
   uint8_t *vis;       // [V] 0 unvisited, 1/2 labelled at even/odd distance, 3 excluded
