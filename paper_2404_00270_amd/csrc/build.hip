@@ -8,7 +8,8 @@
 //
 // Pipeline, entirely on the GPU:
 //   1. validate + emit two keys per arc: (u,v) forward and (v,u) backward,
-//      payload = arc index (forward) or E + arc index (backward)
+//      payload = arc index (forward) or E + arc index (backward); each
+//      arc's row from its tile's row starts staged in LDS
 //   2. sorted (row, column) sequence of all keys: when every input row lists
 //      its columns in non-decreasing order (the common case), the forward
 //      keys are sorted already and the backward keys need only a stable sort
@@ -105,7 +106,7 @@ __device__ int block_reduce_i32(int x) {
   return x;
 }
 
-// Step 1a.  Row of every arc without a per-arc search: cnt[rp[u]] += 1 for
+// Step 1a (RCSR).  Row of every arc without a per-arc search: cnt[rp[u]] += 1 for
 // each row u >= 1 that starts inside [0, E); the inclusive prefix sum of cnt
 // at arc i then counts the rows u >= 1 that start at or before i, which is
 // the row of i (empty rows share a start and are counted, so the last of
@@ -121,35 +122,85 @@ __global__ void k_row_marks(const int64_t *rp, int32_t V, int64_t E, int32_t *cn
 // accepts; a group of equal keys then holds at most 2 * MT_RUN items.
 constexpr int MT_RUN = 256;
 
-// Step 1b.  Forward key (u,v) goes to fkeys[i], backward key (v,u) to
-// bkeys[i], with u = row_of[i]; a self-loop (or an out-of-range column,
-// dropped as one) gets (u,u) in both, which keeps a column-sorted row
-// sorted; the full-sort path turns them into the largest key.  Also checks
-// that every row's columns are non-decreasing and whether a row repeats a
-// column more than MT_RUN times.  Counters are reduced per workgroup, one
-// atomic per workgroup and status word.
-__global__ void k_emit_keys(const int64_t *rp, const int32_t *row_of, const int32_t *col, const int32_t *cap,
-                            int32_t V, int64_t E, int vb, uint64_t *fkeys, uint32_t *fvals, uint64_t *bkeys,
-                            uint32_t *bvals, int32_t *arc2ent, int32_t *acap, BuildStatus *st) {
+// Step 1 (BCSR).  Forward key (u,v) goes to fkeys[i], backward key (v,u)
+// to bkeys[i], with u the row of arc i; a self-loop (or an out-of-range
+// column, dropped as one) gets (u,u) in both, which keeps a column-sorted
+// row sorted; the full-sort path turns them into the largest key.  Also
+// checks that every row's columns are non-decreasing and whether a row
+// repeats a column more than MT_RUN times.  Counters are reduced per
+// workgroup, one atomic per workgroup and status word.  The rows come
+// without a per-arc array: arcs are taken in tiles of EK_TILE, k_tile_rows
+// gives each tile the rows of its first and last arcs (one binary search
+// over row_ptr per tile bound), the tile loads those rows' starts into LDS,
+// and each arc finds its row there by a short binary search (marks at the
+// row starts and a prefix sum over all arcs, as the RCSR builder does, cost
+// a fill, three scan passes and the array).
+constexpr int EK_TILE = 2048;
+constexpr int EK_ROWS = 2048;  // row starts a tile keeps in LDS; more: searched in row_ptr
+
+// Largest row r in [lo, hi] with rp[r] <= i (rp non-decreasing; clamped).
+__device__ __forceinline__ int32_t row_search(const int64_t *rp, int32_t lo, int32_t hi, int64_t i) {
+  while (lo < hi) {
+    const int32_t m = lo + (hi - lo + 1) / 2;
+    if (rp[m] <= i) lo = m; else hi = m - 1;
+  }
+  return lo;
+}
+
+__global__ void k_tile_rows(const int64_t *rp, int32_t V, int64_t E, int64_t ntiles, int32_t *trow) {
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x <= ntiles; x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = x < ntiles ? x * EK_TILE : E - 1;  // tile starts, then the last arc
+    trow[x] = row_search(rp, 0, V - 1, i);
+  }
+}
+
+__global__ void __launch_bounds__(BT) k_emit_keys_tiled(const int64_t *rp, const int32_t *trow, int64_t ntiles,
+                                                        const int32_t *col, const int32_t *cap, int32_t V, int64_t E,
+                                                        int vb, uint64_t *fkeys, uint32_t *fvals, uint64_t *bkeys,
+                                                        uint32_t *bvals, int32_t *arc2ent, int32_t *acap,
+                                                        BuildStatus *st) {
+  __shared__ int64_t s_rp[EK_ROWS];
   int nself = 0, bad = 0, unsorted = 0, longrun = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < E; i += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t r = row_of[i];
-    const uint64_t u = (uint64_t)r;
-    const int32_t vv = col[i];
-    const int32_t c = cap[i];
-    const bool ok = vv >= 0 && vv < V;
-    if (!ok || c < 0) bad++;
-    const int64_t r0 = rp[r];
-    if (i > r0 && col[i - 1] > vv) unsorted++;
-    if (i - MT_RUN >= r0 && i >= MT_RUN && col[i - MT_RUN] == vv) longrun++;
-    const uint64_t v = ok ? (uint64_t)vv : u;
-    if (u == v) nself++;
-    fkeys[i] = (u << vb) | v;
-    bkeys[i] = (v << vb) | u;
-    arc2ent[i] = u == v ? -1 : 0;
-    fvals[i] = (uint32_t)i;
-    bvals[i] = (uint32_t)(E + i);
-    acap[i] = c;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {  // workgroup-uniform
+    const int64_t a0 = t * EK_TILE;
+    const int64_t a1 = a0 + EK_TILE < E ? a0 + EK_TILE : E;
+    const int32_t r0 = trow[t];
+    const int32_t r1 = t + 1 < ntiles ? trow[t + 1] : trow[ntiles];  // row of a1 (or of the last arc)
+    const int32_t lo = r0 < r1 ? r0 : r1, hi = r0 < r1 ? r1 : r0;  // ordered even for a malformed row_ptr
+    const bool in_lds = hi - lo + 1 <= EK_ROWS;
+    __syncthreads();  // s_rp of the previous tile is read
+    if (in_lds)
+      for (int32_t r = lo + threadIdx.x; r <= hi; r += BT) s_rp[r - lo] = rp[r];
+    __syncthreads();
+    for (int64_t i = a0 + threadIdx.x; i < a1; i += BT) {
+      int32_t r;
+      if (in_lds) {
+        int32_t l = 0, h = hi - lo;  // largest index with s_rp <= i
+        while (l < h) {
+          const int32_t m = l + (h - l + 1) / 2;
+          if (s_rp[m] <= i) l = m; else h = m - 1;
+        }
+        r = lo + l;
+      } else {
+        r = row_search(rp, lo, hi, i);
+      }
+      const uint64_t u = (uint64_t)r;
+      const int32_t vv = col[i];
+      const int32_t c = cap[i];
+      const bool ok = vv >= 0 && vv < V;
+      if (!ok || c < 0) bad++;
+      const int64_t rs = in_lds ? s_rp[r - lo] : rp[r];
+      if (i > rs && col[i - 1] > vv) unsorted++;
+      if (i - MT_RUN >= rs && i >= MT_RUN && col[i - MT_RUN] == vv) longrun++;
+      const uint64_t v = ok ? (uint64_t)vv : u;
+      if (u == v) nself++;
+      fkeys[i] = (u << vb) | v;
+      bkeys[i] = (v << vb) | u;
+      arc2ent[i] = u == v ? -1 : 0;
+      fvals[i] = (uint32_t)i;
+      bvals[i] = (uint32_t)(E + i);
+      acap[i] = c;
+    }
   }
   nself = block_reduce_i32<false>(nself);
   bad = block_reduce_i32<false>(bad);
@@ -894,7 +945,7 @@ hipError_t build_residual_rcsr(const int64_t *row_ptr, const int32_t *col, const
     return hipGetLastError();
   }
   const int vb = bits_for(V);
-  // row of every arc (marks at the row starts and a prefix sum), as BCSR
+  // row of every arc (marks at the row starts and a prefix sum)
   e = hipMemsetAsync(s.head, 0, 4 * ((size_t)E + 1), st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_row_marks, dim3(grid_for(V)), dim3(BT), 0, st, row_ptr, V, E, s.head);
@@ -949,15 +1000,14 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
   const bool odd = radix_sort_passes(vb) & 1;
   uint64_t *bk = odd ? s.k1 + E : s.k0 + E;
   uint32_t *bv = odd ? s.v1 + E : s.v0 + E;
-  // row of every arc: marks at the row starts, then a prefix sum (head and
-  // hx are free until step 3)
-  e = hipMemsetAsync(s.head, 0, 4 * ((size_t)E + 1), st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_row_marks, dim3(grid_for(V)), dim3(BT), 0, st, row_ptr, V, E, s.head);
-  e = excl_scan_i32(s.head, s.hx, E + 1, nullptr, s.stemp, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_emit_keys, dim3(grid_for(E)), dim3(BT), 0, st, row_ptr, s.hx + 1, col, cap, V, E, vb, s.k0,
-                     s.v0, bk, bv, arc2ent, acap, status_dev);
+  // keys, with each arc's row found in its tile's row starts (the tile
+  // bounds' rows in hx, which is free until step 3)
+  {
+    const int64_t ntiles = (E + EK_TILE - 1) / EK_TILE;
+    hipLaunchKernelGGL(k_tile_rows, dim3(grid_for(ntiles + 1)), dim3(BT), 0, st, row_ptr, V, E, ntiles, s.hx);
+    hipLaunchKernelGGL(k_emit_keys_tiled, dim3((unsigned)(ntiles < 65535 ? ntiles : 65535)), dim3(BT), 0, st, row_ptr,
+                       s.hx, ntiles, col, cap, V, E, vb, s.k0, s.v0, bk, bv, arc2ent, acap, status_dev);
+  }
   // which path: the host needs the row-order check (and the self-loop count)
   BuildStatus hs;
   e = hipMemcpyAsync(&hs, status_dev, sizeof(hs), hipMemcpyDeviceToHost, st);
