@@ -154,9 +154,16 @@ __global__ void k_tile_rows(const int64_t *rp, int32_t V, int64_t E, int64_t nti
   }
 }
 
+// Payloads of the forward keys (their arc indices), for the paths that
+// carry them through a merge or sort; the fused merge knows them by position.
+__global__ void k_iota(uint32_t *v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    v[i] = (uint32_t)i;
+}
+
 __global__ void __launch_bounds__(BT) k_emit_keys_tiled(const int64_t *rp, const int32_t *trow, int64_t ntiles,
                                                         const int32_t *col, const int32_t *cap, int32_t V, int64_t E,
-                                                        int vb, uint64_t *fkeys, uint32_t *fvals, uint64_t *bkeys,
+                                                        int vb, uint64_t *fkeys, uint64_t *bkeys,
                                                         uint32_t *bvals, int32_t *arc2ent, int32_t *acap,
                                                         BuildStatus *st) {
   __shared__ int64_t s_rp[EK_ROWS];
@@ -197,7 +204,6 @@ __global__ void __launch_bounds__(BT) k_emit_keys_tiled(const int64_t *rp, const
       fkeys[i] = (u << vb) | v;
       bkeys[i] = (v << vb) | u;
       arc2ent[i] = u == v ? -1 : 0;
-      fvals[i] = (uint32_t)i;
       bvals[i] = (uint32_t)(E + i);
       acap[i] = c;
     }
@@ -1006,7 +1012,7 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
     const int64_t ntiles = (E + EK_TILE - 1) / EK_TILE;
     hipLaunchKernelGGL(k_tile_rows, dim3(grid_for(ntiles + 1)), dim3(BT), 0, st, row_ptr, V, E, ntiles, s.hx);
     hipLaunchKernelGGL(k_emit_keys_tiled, dim3((unsigned)(ntiles < 65535 ? ntiles : 65535)), dim3(BT), 0, st, row_ptr,
-                       s.hx, ntiles, col, cap, V, E, vb, s.k0, s.v0, bk, bv, arc2ent, acap, status_dev);
+                       s.hx, ntiles, col, cap, V, E, vb, s.k0, bk, bv, arc2ent, acap, status_dev);
   }
   // which path: the host needs the row-order check (and the self-loop count)
   BuildStatus hs;
@@ -1054,6 +1060,7 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
     } else {
       // the merge marks the group heads as it writes (row_of in hx is no
       // longer needed)
+      hipLaunchKernelGGL(k_iota, dim3(grid_for(E)), dim3(BT), 0, st, s.v0, E);
       hipLaunchKernelGGL(k_merge, dim3(grid_for((N + MERGE_TILE - 1) / MERGE_TILE, 1)), dim3(MERGE_THREADS), 0, st,
                          s.k0, s.v0, s.k0 + E, s.v0 + E, E, s.k1, s.v1, s.head, vb);
       keys = s.k1;
@@ -1065,6 +1072,7 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
       if (e == hipSuccess) e = hipMemcpyAsync(s.v0 + E, bv, 4 * (size_t)E, hipMemcpyDeviceToDevice, st);
       if (e != hipSuccess) return e;
     }
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(E)), dim3(BT), 0, st, s.v0, E);
     if (hs.nself > 0) hipLaunchKernelGGL(k_selfloops_last, dim3(grid_for(N)), dim3(BT), 0, st, s.k0, N, vb);
     int alt = 0;
     e = radix_sort_u64_u32(s.k0, s.v0, s.k1, s.v1, N, 2 * vb, s.hist, s.stemp, &alt, st);
