@@ -77,6 +77,23 @@ def test_random_graphs_ragged(solver, V, E, seed):
     check_against_oracle(g, solver.solve(g))
 
 
+@pytest.mark.parametrize("V,E,seed", [(50_000, 3_000, 11), (300_000, 40_000, 12)])
+def test_sparse_rows_spanning_many_empty_rows(solver, V, E, seed):
+    """Most rows empty: the builder's tiles of 2,048 arcs span more rows than
+    it keeps in LDS (2,048 row starts), so arcs find their rows by a search
+    over the whole row_ptr, and empty rows sit at both ends."""
+    rng = np.random.default_rng(seed)
+    hi = V - V // 10
+    u = rng.integers(V // 10, hi, E)
+    v = rng.integers(V // 10, hi, E)
+    arcs = [(int(a), int(b), int(c)) for a, b, c in zip(u, v, rng.integers(1, 100, E))]
+    s, t = int(u[0]), int(v[-1])
+    arcs += [(s, int(x), 1000) for x in u[1:50]] + [(int(x), t, 1000) for x in v[1:50]]
+    g = _reorder_rows(W.from_arcs(V, arcs, s, t, f"sparse-{V}-{E}"))
+    say(f"[sparse] V={V} E={g.E}")
+    check_against_oracle(g, solver.solve(g))
+
+
 def _reorder_rows(g, seed=None):
     """Same graph with each row's arcs sorted by column (seed None) or shuffled."""
     row = np.repeat(np.arange(g.V), np.diff(g.row_ptr))
