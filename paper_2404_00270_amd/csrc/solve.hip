@@ -347,6 +347,9 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
   }
   const int32_t n = min(*q.qin_cnt, q.qcap);
   constexpr int TPW = WB_WAVE / P;  // tiles per wave
+  // a workgroup whose first tile is past the queue has nothing to visit
+  // (short queues leave most of the grid idle; traced runs keep every wave)
+  if ((int64_t)blockIdx.x * (SWEEP_THREADS / WB_WAVE) * TPW >= n && !q.wtrace) return;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int32_t wave = (int32_t)(gtid / WB_WAVE);
   const int32_t nwaves = (int32_t)((int64_t)gridDim.x * blockDim.x / WB_WAVE);
@@ -679,11 +682,12 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
   __shared__ long long s_take;
   __shared__ int s_gap[GAP_BINS];
   if (*q.halt) return;
+  const int32_t ntask = FIRST ? min(*q.big_cnt, q.qcap) : min(*q.task_cnt, q.tcap);
+  if ((int32_t)blockIdx.x >= ntask && !q.wtrace) return;  // no task for this workgroup
   const long long wt0 = q.wtrace ? (long long)wall_clock64() : 0;
   int32_t gbase;
   const int32_t gn = gap_begin(g, s_gap, &gbase);
   long long tasks = 0;  // per wave, counted by its first lane
-  const int32_t ntask = FIRST ? min(*q.big_cnt, q.qcap) : min(*q.task_cnt, q.tcap);
   const int w = threadIdx.x / WB_WAVE;
   if (lane() == 0) s_qcnt[w] = 0;
   const WaveQ wq{s_qbuf[w], &s_qcnt[w], q.qout, q.qout_cnt, q.qcap, q.err};
@@ -821,9 +825,10 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk_finish(Graph g, SweepQ q) {
   __shared__ int s_qcnt[BLK_WAVES];
   __shared__ int s_gap[GAP_BINS];
   if (*q.halt) return;
+  const int32_t ntask = min(*q.task_cnt, q.tcap);
+  if ((int64_t)blockIdx.x * blockDim.x >= ntask) return;  // no task for this workgroup
   int32_t gbase;
   const int32_t gn = gap_begin(g, s_gap, &gbase);
-  const int32_t ntask = min(*q.task_cnt, q.tcap);
   const int w = threadIdx.x / WB_WAVE;
   if (lane() == 0) s_qcnt[w] = 0;
   const WaveQ wq{s_qbuf[w], &s_qcnt[w], q.qout, q.qout_cnt, q.qcap, q.err};
