@@ -672,9 +672,34 @@ __device__ __forceinline__ void finish_long_row(const Graph &g, const SweepQ &q,
 // capacity, with atomics whose results they do not wait for.  Paper mode:
 // the chunks fold the minimum (height, position) key over all residual
 // entries of the row; the finish pushes to that neighbour or relabels.
+// Second-pass tasks of the long rows whose first chunk did not settle them,
+// gathered by the first pass's thread 0 and listed with one atomic on the
+// task counter per workgroup (one per row serialised thousands per launch).
+constexpr int TASK_BUF = 64;
+__device__ __forceinline__ void flush_tasks(const SweepQ &q, const int32_t *tu, const int32_t *tc, int *tn) {
+  int32_t tot = 0;
+  for (int i = 0; i < *tn; i++) tot += tc[i] - 1;
+  if (tot > 0) {
+    int32_t base = atomic_add_i32(q.task_cnt, tot);
+    if ((long long)base + tot > (long long)q.tcap) {
+      atomic_add_i32(q.err, 1);
+    } else {
+      for (int i = 0; i < *tn; i++)
+        for (int32_t cc = 1; cc < tc[i]; cc++, base++) {
+          q.task_u[base] = tu[i];
+          q.task_c[base] = cc;
+        }
+    }
+  }
+  *tn = 0;
+}
+
 template <bool FIRST, bool RC>
 __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
   constexpr int PER = CHUNK / BLK;
+  __shared__ int32_t s_tu[TASK_BUF];  // first pass, thread 0 only: rows ...
+  __shared__ int32_t s_tc[TASK_BUF];  // ... and their chunk counts
+  int tn = 0;                         // thread 0's count of them
   __shared__ int s_qbuf[BLK_WAVES][WB_QBUF];
   __shared__ int s_qcnt[BLK_WAVES];
   __shared__ long long s_wsum[BLK_WAVES];
@@ -789,16 +814,11 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
       } else {
         if (key != WB_KEY_NONE) atomic_min_u64(&q.lr_key[u], key);
         if (short_claim) atomic_or_i32(&q.lr_cnt[u], CHUNK_MORE);
-        if (FIRST) {  // the other chunks become second-pass tasks
-          const int32_t base = atomic_add_i32(q.task_cnt, nch - 1);
-          if ((long long)base + nch - 1 > (long long)q.tcap) {
-            atomic_add_i32(q.err, 1);
-          } else {
-            for (int32_t cc = 1; cc < nch; cc++) {
-              q.task_u[base + cc - 1] = u;
-              q.task_c[base + cc - 1] = cc;
-            }
-          }
+        if (FIRST) {  // the other chunks become second-pass tasks (listed at the end)
+          if (tn == TASK_BUF) flush_tasks(q, s_tu, s_tc, &tn);
+          s_tu[tn] = u;
+          s_tc[tn] = nch;
+          tn++;
         }
       }
     }
@@ -808,6 +828,7 @@ __global__ void __launch_bounds__(BLK) k_sweep_chunk(Graph g, SweepQ q) {
     }
     __syncthreads();  // s_take, s_wmin and s_wsum are reused by the next task
   }
+  if (FIRST && threadIdx.x == 0) flush_tasks(q, s_tu, s_tc, &tn);
   {
     __shared__ int s_off[BLK_WAVES + 1];
     block_flush<BLK_WAVES>(wq, s_off);
