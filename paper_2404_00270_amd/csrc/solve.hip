@@ -73,21 +73,24 @@ __device__ __forceinline__ bool push_entry(const Graph &g, int32_t hk, int32_t v
 // atomics per launch), which the control step folds; without slots, to the
 // counters themselves.  Every thread of the workgroup calls it, at the end.
 __device__ __forceinline__ void flush_stats(const SweepQ &q, int kofs, long long scans, int pushes, int relabels,
-                                            long long queued, long long rwork) {
+                                            long long queued, long long rwork, long long gskips = 0) {
   long long *stats = q.stats + q.sofs + kofs;
   long long *rwork_ctr = q.rwork;
+  long long *gskip_ctr = q.gap_skips;
   if (q.part) {
     long long *slot = q.part + (int64_t)(blockIdx.x % PART_SLOTS) * PART_WORDS;
     stats = slot + q.sofs + kofs;
     rwork_ctr = slot + 12;
+    gskip_ctr = slot + 13;
   }
-  __shared__ unsigned long long s_acc[5];
+  __shared__ unsigned long long s_acc[6];
   scans = (long long)group_sum_i64<WB_WAVE>(scans);
   long long p = group_sum_i64<WB_WAVE>((long long)pushes);
   long long r = group_sum_i64<WB_WAVE>((long long)relabels);
   queued = group_sum_i64<WB_WAVE>(queued);
   rwork = group_sum_i64<WB_WAVE>(rwork);
-  if (threadIdx.x < 5) s_acc[threadIdx.x] = 0;
+  gskips = group_sum_i64<WB_WAVE>(gskips);
+  if (threadIdx.x < 6) s_acc[threadIdx.x] = 0;
   __syncthreads();
   if (lane() == 0) {
     if (scans) atomicAdd(&s_acc[0], (unsigned long long)scans);
@@ -95,6 +98,7 @@ __device__ __forceinline__ void flush_stats(const SweepQ &q, int kofs, long long
     if (r) atomicAdd(&s_acc[2], (unsigned long long)r);
     if (queued) atomicAdd(&s_acc[3], (unsigned long long)queued);
     if (rwork) atomicAdd(&s_acc[4], (unsigned long long)rwork);
+    if (gskips) atomicAdd(&s_acc[5], (unsigned long long)gskips);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -103,6 +107,7 @@ __device__ __forceinline__ void flush_stats(const SweepQ &q, int kofs, long long
     if (s_acc[2]) atomic_add_i64(&stats[2], (long long)s_acc[2]);
     if (s_acc[3]) atomic_add_i64(&stats[3], (long long)s_acc[3]);
     if (s_acc[4]) atomic_add_i64(rwork_ctr, (long long)s_acc[4]);
+    if (s_acc[5] && gskip_ctr) atomic_add_i64(gskip_ctr, (long long)s_acc[5]);
   }
 }
 
@@ -188,18 +193,19 @@ __global__ void __launch_bounds__(PART_SLOTS) k_sweep_control(SweepCtl c) {
     // fold the sweep kernels' per-workgroup partial counters: lane i takes
     // slot i, then one sum per counter over the wave
     long long *slot = c.part + (int64_t)threadIdx.x * PART_WORDS;
-    long long x[13];
+    long long x[14];
 #pragma unroll
-    for (int k = 0; k < 13; k++) x[k] = slot[k];
+    for (int k = 0; k < 14; k++) x[k] = slot[k];
 #pragma unroll
-    for (int k = 0; k < 13; k++) slot[k] = 0;
+    for (int k = 0; k < 14; k++) slot[k] = 0;
 #pragma unroll
-    for (int k = 0; k < 13; k++) {
+    for (int k = 0; k < 14; k++) {
       if (__ballot(x[k] != 0) == 0) continue;  // wave-uniform
       const long long t = group_sum_i64<WB_WAVE>(x[k]);
       if (threadIdx.x == 0) {
         if (k < 12) c.stats[k] += t;
-        else *c.rwork_acc += t;
+        else if (k == 12) *c.rwork_acc += t;
+        else c.stats[15] += t;  // entries left to the relabel by the gap heuristic
       }
     }
   }
@@ -569,12 +575,8 @@ __global__ void __launch_bounds__(SWEEP_THREADS) k_sweep_tile(Graph g, SweepQ q)
       block_flush<SWEEP_THREADS / WB_WAVE>(wbig, s_off);
     }
   }
-  flush_stats(q, 0, scans, pushes, relabels, queued, rwork);
+  flush_stats(q, 0, scans, pushes, relabels, queued, rwork, gskips);
   gap_flush_lds(g, s_gap, gbase, gn);
-  if (q.gap_skips) {
-    const int32_t gs = wave_sum_i32(gskips);
-    if (lane() == 0 && gs) atomic_add_i64(q.gap_skips, gs);
-  }
   if (q.wtrace) trace_wave(q, q.kind, wt0, scans, queued);
 }
 

@@ -110,7 +110,8 @@ struct SweepQ {
                         // [4k+2] relabels, [4k+3] queued; [12] bfs scans; [13] nonempty sweeps
   long long *rwork;     // running sum of row lengths scanned by relabels
   // nullable: per-workgroup partial counters, PART_SLOTS slots of PART_WORDS
-  // (one cache line each: [0..11] as stats[0..11], [12] relabel work), which
+  // (one cache line each: [0..11] as stats[0..11], [12] relabel work, [13]
+  // gap skips as stats[15]), which
   // the control step folds into stats and rwork; without it the kernels add
   // to stats and rwork directly
   long long *part;
