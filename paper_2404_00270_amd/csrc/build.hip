@@ -165,48 +165,64 @@ __global__ void __launch_bounds__(BT) k_emit_keys_tiled(const int64_t *rp, const
                                                         const int32_t *col, const int32_t *cap, int32_t V, int64_t E,
                                                         int vb, uint64_t *fkeys, uint64_t *bkeys,
                                                         uint32_t *bvals, int32_t *arc2ent, int32_t *acap,
-                                                        BuildStatus *st) {
+                                                        int32_t *hist, BuildStatus *st) {
+  static_assert(RADIX_TILE % EK_TILE == 0, "a radix tile is whole emission tiles");
+  constexpr int EK_PER_RS = RADIX_TILE / EK_TILE;
+  constexpr int NDIG = 1 << RADIX_BITS;
   __shared__ int64_t s_rp[EK_ROWS];
+  __shared__ int s_dig[NDIG];
   int nself = 0, bad = 0, unsorted = 0, longrun = 0;
-  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {  // workgroup-uniform
-    const int64_t a0 = t * EK_TILE;
-    const int64_t a1 = a0 + EK_TILE < E ? a0 + EK_TILE : E;
-    const int32_t r0 = trow[t];
-    const int32_t r1 = t + 1 < ntiles ? trow[t + 1] : trow[ntiles];  // row of a1 (or of the last arc)
-    const int32_t lo = r0 < r1 ? r0 : r1, hi = r0 < r1 ? r1 : r0;  // ordered even for a malformed row_ptr
-    const bool in_lds = hi - lo + 1 <= EK_ROWS;
-    __syncthreads();  // s_rp of the previous tile is read
-    if (in_lds)
-      for (int32_t r = lo + threadIdx.x; r <= hi; r += BT) s_rp[r - lo] = rp[r];
-    __syncthreads();
-    for (int64_t i = a0 + threadIdx.x; i < a1; i += BT) {
-      int32_t r;
-      if (in_lds) {
-        int32_t l = 0, h = hi - lo;  // largest index with s_rp <= i
-        while (l < h) {
-          const int32_t m = l + (h - l + 1) / 2;
-          if (s_rp[m] <= i) l = m; else h = m - 1;
+  // a workgroup takes the emission tiles of one radix tile at a time and
+  // counts the first digit of their backward keys (the low RADIX_BITS bits
+  // of the row) for the radix sort's first pass
+  const int64_t ngroups = (ntiles + EK_PER_RS - 1) / EK_PER_RS;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {  // workgroup-uniform
+    for (int d = threadIdx.x; d < NDIG; d += BT) s_dig[d] = 0;  // ordered before the counts by the tile's barriers
+    const int64_t tend = (grp + 1) * EK_PER_RS < ntiles ? (grp + 1) * EK_PER_RS : ntiles;
+    for (int64_t t = grp * EK_PER_RS; t < tend; t++) {  // workgroup-uniform
+      const int64_t a0 = t * EK_TILE;
+      const int64_t a1 = a0 + EK_TILE < E ? a0 + EK_TILE : E;
+      const int32_t r0 = trow[t];
+      const int32_t r1 = t + 1 < ntiles ? trow[t + 1] : trow[ntiles];  // row of a1 (or of the last arc)
+      const int32_t lo = r0 < r1 ? r0 : r1, hi = r0 < r1 ? r1 : r0;  // ordered even for a malformed row_ptr
+      const bool in_lds = hi - lo + 1 <= EK_ROWS;
+      __syncthreads();  // s_rp of the previous tile is read
+      if (in_lds)
+        for (int32_t r = lo + threadIdx.x; r <= hi; r += BT) s_rp[r - lo] = rp[r];
+      __syncthreads();
+      for (int64_t i = a0 + threadIdx.x; i < a1; i += BT) {
+        int32_t r;
+        if (in_lds) {
+          int32_t l = 0, h = hi - lo;  // largest index with s_rp <= i
+          while (l < h) {
+            const int32_t m = l + (h - l + 1) / 2;
+            if (s_rp[m] <= i) l = m; else h = m - 1;
+          }
+          r = lo + l;
+        } else {
+          r = row_search(rp, lo, hi, i);
         }
-        r = lo + l;
-      } else {
-        r = row_search(rp, lo, hi, i);
+        const uint64_t u = (uint64_t)r;
+        const int32_t vv = col[i];
+        const int32_t c = cap[i];
+        const bool ok = vv >= 0 && vv < V;
+        if (!ok || c < 0) bad++;
+        const int64_t rs = in_lds ? s_rp[r - lo] : rp[r];
+        if (i > rs && col[i - 1] > vv) unsorted++;
+        if (i - MT_RUN >= rs && i >= MT_RUN && col[i - MT_RUN] == vv) longrun++;
+        const uint64_t v = ok ? (uint64_t)vv : u;
+        if (u == v) nself++;
+        fkeys[i] = (u << vb) | v;
+        bkeys[i] = (v << vb) | u;
+        arc2ent[i] = u == v ? -1 : 0;
+        bvals[i] = (uint32_t)(E + i);
+        acap[i] = c;
+        atomicAdd(&s_dig[(int)(v & (NDIG - 1))], 1);
       }
-      const uint64_t u = (uint64_t)r;
-      const int32_t vv = col[i];
-      const int32_t c = cap[i];
-      const bool ok = vv >= 0 && vv < V;
-      if (!ok || c < 0) bad++;
-      const int64_t rs = in_lds ? s_rp[r - lo] : rp[r];
-      if (i > rs && col[i - 1] > vv) unsorted++;
-      if (i - MT_RUN >= rs && i >= MT_RUN && col[i - MT_RUN] == vv) longrun++;
-      const uint64_t v = ok ? (uint64_t)vv : u;
-      if (u == v) nself++;
-      fkeys[i] = (u << vb) | v;
-      bkeys[i] = (v << vb) | u;
-      arc2ent[i] = u == v ? -1 : 0;
-      bvals[i] = (uint32_t)(E + i);
-      acap[i] = c;
     }
+    __syncthreads();
+    for (int d = threadIdx.x; d < NDIG; d += BT) hist[(int64_t)d * ngroups + grp] = s_dig[d];
+    __syncthreads();  // the counts are read before the next group clears them
   }
   nself = block_reduce_i32<false>(nself);
   bad = block_reduce_i32<false>(bad);
@@ -1011,8 +1027,9 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
   {
     const int64_t ntiles = (E + EK_TILE - 1) / EK_TILE;
     hipLaunchKernelGGL(k_tile_rows, dim3(grid_for(ntiles + 1)), dim3(BT), 0, st, row_ptr, V, E, ntiles, s.hx);
-    hipLaunchKernelGGL(k_emit_keys_tiled, dim3((unsigned)(ntiles < 65535 ? ntiles : 65535)), dim3(BT), 0, st, row_ptr,
-                       s.hx, ntiles, col, cap, V, E, vb, s.k0, bk, bv, arc2ent, acap, status_dev);
+    const int64_t ngroups = (E + RADIX_TILE - 1) / RADIX_TILE;
+    hipLaunchKernelGGL(k_emit_keys_tiled, dim3((unsigned)(ngroups < 65535 ? ngroups : 65535)), dim3(BT), 0, st,
+                       row_ptr, s.hx, ntiles, col, cap, V, E, vb, s.k0, bk, bv, arc2ent, acap, s.hist, status_dev);
   }
   // which path: the host needs the row-order check (and the self-loop count)
   BuildStatus hs;
@@ -1032,7 +1049,7 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
     int alt = 0;
     uint64_t *ok = odd ? s.k0 + E : s.k1 + E;
     uint32_t *ov = odd ? s.v0 + E : s.v1 + E;
-    e = radix_sort_u64_u32(bk, bv, ok, ov, E, vb, s.hist, s.stemp, &alt, st, vb);
+    e = radix_sort_u64_u32(bk, bv, ok, ov, E, vb, s.hist, s.stemp, &alt, st, vb, true);
     if (e != hipSuccess) return e;
     if ((alt ? ok : bk) != s.k0 + E) {  // pass count disagrees with radix_sort_passes
       e = hipMemcpyAsync(s.k0 + E, alt ? ok : bk, 8 * (size_t)E, hipMemcpyDeviceToDevice, st);
@@ -1042,7 +1059,7 @@ hipError_t build_residual(const int64_t *row_ptr, const int32_t *col, const int3
     if (fused) {
       // tile bounds, per-tile entry counts and their prefix sums in the
       // radix histogram's space (free after the sort; its 1,024 bytes per
-      // 4,096 keys hold the 24 ntiles + 16 bytes); each entry's row in head[]
+      // 6,144 keys hold the 24 ntiles + 16 bytes); each entry's row in head[]
       const int64_t ntiles = (N + MT_TILE - 1) / MT_TILE;
       int64_t *split = (int64_t *)s.hist;
       int32_t *heads = (int32_t *)(split + 2 * (ntiles + 1));

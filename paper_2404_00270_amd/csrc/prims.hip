@@ -136,9 +136,10 @@ constexpr int RS_BITS = 8;
 constexpr int RS_BINS = 1 << RS_BITS;
 constexpr int RS_THREADS = 256;
 constexpr int RS_WAVES = RS_THREADS / WB_WAVE;
-constexpr int RS_ITEMS = 16;
+constexpr int RS_ITEMS = 24;  // 6,144 keys a tile: 78 KB of LDS in the scatter, two workgroups a CU
 constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
 static_assert(RS_THREADS == RS_BINS, "one thread per digit in the scatter's set-up");
+static_assert(RS_TILE == RADIX_TILE && RS_BITS == RADIX_BITS, "tile and digit that producers of a first histogram use");
 
 // hist[d * nblocks + b] = number of items of tile b whose digit is d.
 __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t *keys, int64_t n, int shift, int32_t *hist,
@@ -147,10 +148,18 @@ __global__ void __launch_bounds__(RS_THREADS) k_rs_hist(const uint64_t *keys, in
   for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) cnt[d] = 0;
   __syncthreads();
   int64_t base = (int64_t)blockIdx.x * RS_TILE;
-#pragma unroll 4
+  // every key of the thread is loaded before the first count, so all its
+  // loads are in flight together
+  uint64_t kk[RS_ITEMS];
+#pragma unroll
   for (int j = 0; j < RS_ITEMS; j++) {
-    int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (RS_BINS - 1)], 1);
+    const int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
+    kk[j] = i < n ? keys[i] : 0;
+  }
+#pragma unroll
+  for (int j = 0; j < RS_ITEMS; j++) {
+    const int64_t i = base + (int64_t)j * RS_THREADS + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(kk[j] >> shift) & (RS_BINS - 1)], 1);
   }
   __syncthreads();
   for (int d = threadIdx.x; d < RS_BINS; d += RS_THREADS) hist[(int64_t)d * nblocks + blockIdx.x] = cnt[d];
@@ -273,7 +282,8 @@ int64_t radix_hist_elems(int64_t n) { return (int64_t)RS_BINS * ((n + RS_TILE - 
 int radix_sort_passes(int bits) { return (bits + RS_BITS - 1) / RS_BITS; }
 
 hipError_t radix_sort_u64_u32(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int bits,
-                              int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st, int shift0) {
+                              int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st, int shift0,
+                              bool first_hist) {
   *result_in_alt = 0;
   if (n <= 1) return hipSuccess;
   int nblocks = (int)((n + RS_TILE - 1) / RS_TILE);
@@ -281,7 +291,8 @@ hipError_t radix_sort_u64_u32(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t
   uint64_t *ka = k0, *kb = k1;
   uint32_t *va = v0, *vb = v1;
   for (int shift = shift0; shift < shift0 + bits; shift += RS_BITS) {
-    hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, st, ka, n, shift, hist, nblocks);
+    if (!(first_hist && shift == shift0))
+      hipLaunchKernelGGL(k_rs_hist, dim3(nblocks), dim3(RS_THREADS), 0, st, ka, n, shift, hist, nblocks);
     hipError_t e = excl_scan_i32(hist, hist, hn, nullptr, scan_temp, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rs_scatter, dim3(nblocks), dim3(RS_THREADS), 0, st, ka, va, kb, vb, n, shift, hist, nblocks);

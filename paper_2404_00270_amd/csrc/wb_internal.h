@@ -14,8 +14,14 @@ int64_t radix_hist_elems(int64_t n);
 // passes radix_sort_u64_u32 makes over `bits` key bits (for n > 1); an odd
 // count leaves the result in the alternate buffers
 int radix_sort_passes(int bits);
+// Keys per radix tile and key bits per pass.  hist[d * tiles + b] counts
+// the keys of tile b whose digit is d; with first_hist the caller has
+// filled it for the first pass (digit bits [shift0, shift0 + RADIX_BITS)).
+constexpr int RADIX_TILE = 6144;
+constexpr int RADIX_BITS = 8;
 hipError_t radix_sort_u64_u32(uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1, int64_t n, int bits,
-                              int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st, int shift0 = 0);
+                              int32_t *hist, int32_t *scan_temp, int *result_in_alt, hipStream_t st, int shift0 = 0,
+                              bool first_hist = false);
 
 // ---- residual graph: bidirectional CSR with merged entries and explicit
 // mate indices, in a device arena shared by all instances (build.hip)
