@@ -114,6 +114,22 @@ def test_sorted_and_unsorted_rows(solver, V, E, seed):
         check_against_oracle(g, solver.solve(g), ref)
 
 
+@pytest.mark.parametrize("E", [1, 2047, 2048, 2049, 6143, 6144, 6145, 12289])
+def test_arc_counts_at_tile_boundaries(solver, E):
+    """Arc counts around the key emission's tiles (2,048 arcs) and the radix
+    sort's tiles (6,144 keys, three emission tiles): the emission counts the
+    first radix pass's histogram per radix tile, so a last tile that is
+    partial, or holds one emission tile only, must still give the sort's
+    offsets.  Column-sorted rows (the path that uses that histogram) and
+    shuffled rows (the full sort, which counts its own)."""
+    g0 = W.random_graph(max(8, E // 6), E, 1, 100, 7)
+    assert g0.E == E
+    ref = oracle.reference(g0.V, g0.row_ptr, g0.col, g0.cap, g0.s, g0.t)
+    for g in (_reorder_rows(g0), _reorder_rows(g0, 3)):
+        say(f"[tiles] {g.name} E={E}")
+        check_against_oracle(g, solver.solve(g), ref)
+
+
 @pytest.mark.parametrize("seed", [1, 2])
 def test_long_groups_of_parallel_arcs(solver, seed):
     """Pairs joined by hundreds of parallel and antiparallel arcs (groups of
