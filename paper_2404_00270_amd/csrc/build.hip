@@ -459,8 +459,21 @@ __global__ void __launch_bounds__(MT_THREADS) k_merge_count(const uint64_t *ka, 
     int64_t i0, j0;
     int na, nb;
     mt_tile(split, t, &i0, &j0, &na, &nb);
-    const int cnt = na + nb;
-    for (int x = threadIdx.x; x < cnt; x += MT_THREADS) s_k[x] = x < na ? ka[i0 + x] : kb[j0 + x - na];
+    const int cnt = na + nb;  // <= MT_CAP = MT_ITEMS * MT_THREADS
+    {
+      // every load of the thread is issued before the first LDS store
+      uint64_t r[MT_ITEMS];
+#pragma unroll
+      for (int q = 0; q < MT_ITEMS; q++) {
+        const int x = threadIdx.x + q * MT_THREADS;
+        r[q] = x < na ? ka[i0 + x] : x < cnt ? kb[j0 + x - na] : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < MT_ITEMS; q++) {
+        const int x = threadIdx.x + q * MT_THREADS;
+        if (x < cnt) s_k[x] = r[q];
+      }
+    }
     __syncthreads();
     int h = 0;
     for (int x = threadIdx.x; x < cnt; x += MT_THREADS) {
@@ -512,13 +525,30 @@ __global__ void __launch_bounds__(MT_THREADS)
     mt_tile(split, t, &i0, &j0, &na, &nb);
     const int cnt = na + nb;
     const long long P = hpre[t];  // entries of the earlier tiles
-    for (int x = threadIdx.x; x < cnt; x += MT_THREADS) {
-      if (x < na) {
-        s_k[x] = ka[i0 + x];
-        s_v[x] = (uint32_t)cap[i0 + x];
-      } else {
-        s_k[x] = kb[j0 + x - na];
-        s_v[x] = vb[j0 + x - na];
+    {
+      // every load of the thread is issued before the first LDS store
+      uint64_t r[MT_ITEMS];
+      uint32_t rv[MT_ITEMS];
+#pragma unroll
+      for (int q = 0; q < MT_ITEMS; q++) {
+        const int x = threadIdx.x + q * MT_THREADS;
+        r[q] = 0;
+        rv[q] = 0;
+        if (x < na) {
+          r[q] = ka[i0 + x];
+          rv[q] = (uint32_t)cap[i0 + x];
+        } else if (x < cnt) {
+          r[q] = kb[j0 + x - na];
+          rv[q] = vb[j0 + x - na];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < MT_ITEMS; q++) {
+        const int x = threadIdx.x + q * MT_THREADS;
+        if (x < cnt) {
+          s_k[x] = r[q];
+          s_v[x] = rv[q];
+        }
       }
     }
     __syncthreads();
